@@ -1,0 +1,231 @@
+/*
+ * bwt_oracle.c -- plain, slow, obviously correct CPU oracle for the BWT of a
+ * string set (Pantaleoni, "A massively parallel algorithm for constructing the
+ * BWT of large string sets", arXiv:1410.0562).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark load it.  It shares no code with the GPU path.
+ *
+ * Text encoding used throughout: one byte per symbol, 0 = a terminator, and
+ * 1..4 = the bases A,C,G,T in alphabet order.  A string set S_0..S_{m-1} is
+ * laid out as T = S_0 $_0 S_1 $_1 ... S_{m-1} $_{m-1} (Section 2, the
+ * definition of the BWT of a string set), so every terminator is a 0 byte and
+ * the i-th 0 byte from the left is $_i.
+ *
+ * Order (Section 2): $_0 < $_1 < ... < $_{m-1} < A < C < G < T.  Two suffixes
+ * are compared symbol by symbol; at the first pair that differs the byte value
+ * decides; if both walks reach a terminator at the same offset, the terminators
+ * are distinct symbols and the one further left is the smaller (its index is
+ * lower).  A walk never passes a terminator, so it never reads past T[n-1],
+ * which is always $_{m-1}.
+ *
+ * Functions (all single-threaded unless stated):
+ *   oracle_sa            suffix array by comparison sort (definition of SA,
+ *                        Section 2)
+ *   oracle_bwt           B[i] = T[(SA[i]-1) mod n]   (Eq. 1)
+ *   oracle_count_smaller number of suffixes of T smaller than T^p, by brute
+ *                        force against every suffix (rank of one row, O(n))
+ *   oracle_lf_invert     walks B backwards from row j with C[c] + rank(c,r),
+ *                        the LF step of Lemma 1 applied inside one BWT; spells
+ *                        each string reversed.  Used as an invariant check.
+ *   oracle_compute_ranks ComputeRanks (Algorithm 2, with the readings: the walk
+ *                        starts at i = m_ext, and g is indexed off_j + k with
+ *                        off the exclusive prefix sum of |P_j|+1)
+ *   oracle_count_old_smaller  brute-force definition of what ComputeRanks
+ *                        returns: for a new suffix, the number of old suffixes
+ *                        smaller than it (hypothesis of Lemma 1)
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* qsort has no context argument; the oracle is single-threaded, so the text
+ * being sorted is held in file-scope state for the duration of one call. */
+static const uint8_t *g_text;
+
+/* Compare suffixes a and b of g_text under the order stated above. */
+static int cmp_suffix_at(const uint8_t *T, uint64_t a, uint64_t b)
+{
+    if (a == b) return 0;
+    for (uint64_t t = 0;; ++t) {
+        uint8_t x = T[a + t], y = T[b + t];
+        if (x != y) return x < y ? -1 : 1;
+        if (x == 0) return (a + t) < (b + t) ? -1 : 1;
+    }
+}
+
+static int qsort_cmp(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return cmp_suffix_at(g_text, a, b);
+}
+
+/* Suffix array of T[0..n) (T[n-1] must be 0). */
+void oracle_sa(const uint8_t *T, uint64_t n, uint64_t *sa)
+{
+    for (uint64_t i = 0; i < n; ++i) sa[i] = i;
+    g_text = T;
+    qsort(sa, (size_t)n, sizeof(uint64_t), qsort_cmp);
+    g_text = NULL;
+}
+
+/* Eq. 1: B[i] = T[(SA[i]-1) mod n], written as ASCII with every terminator
+ * printed as '$'. */
+void oracle_bwt(const uint8_t *T, uint64_t n, const uint64_t *sa, uint8_t *B)
+{
+    static const char ascii[5] = {'$', 'A', 'C', 'G', 'T'};
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t prev = (sa[i] + n - 1) % n;
+        B[i] = (uint8_t)ascii[T[prev]];
+    }
+}
+
+/* Number of suffixes q of T with T^q < T^p: one row of the suffix array,
+ * computed without sorting anything. */
+uint64_t oracle_count_smaller(const uint8_t *T, uint64_t n, uint64_t p)
+{
+    uint64_t c = 0;
+    for (uint64_t q = 0; q < n; ++q)
+        if (cmp_suffix_at(T, q, p) < 0) ++c;
+    return c;
+}
+
+/* Symbol code of an ASCII BWT byte: '$'->0, A->1, C->2, G->3, T->4, else 255. */
+static int code_of(uint8_t ch)
+{
+    switch (ch) {
+    case '$': return 0;
+    case 'A': return 1;
+    case 'C': return 2;
+    case 'G': return 3;
+    case 'T': return 4;
+    default: return 255;
+    }
+}
+
+/* Occurrence table used by the LF walks below: occ[r*5 + c] = number of code c
+ * in B[0..r) for r a multiple of OCC_STEP; the rest is counted by a scan. */
+#define OCC_STEP 64
+
+static uint64_t *build_occ(const uint8_t *B, uint64_t n)
+{
+    uint64_t ns = n / OCC_STEP + 1;
+    uint64_t *occ = (uint64_t *)calloc((size_t)ns * 5, sizeof(uint64_t));
+    if (!occ) return NULL;
+    uint64_t run[5] = {0, 0, 0, 0, 0};
+    for (uint64_t i = 0; i <= n; ++i) {
+        if (i % OCC_STEP == 0) memcpy(occ + (i / OCC_STEP) * 5, run, sizeof run);
+        if (i < n) run[code_of(B[i])]++;
+    }
+    return occ;
+}
+
+/* rank(c, k, B) of Eq. 2 from the sampled table plus a short scan. */
+static uint64_t occ_rank(const uint8_t *B, const uint64_t *occ, int c, uint64_t k)
+{
+    uint64_t s = k / OCC_STEP;
+    uint64_t r = occ[s * 5 + c];
+    for (uint64_t i = s * OCC_STEP; i < k; ++i)
+        if (code_of(B[i]) == c) ++r;
+    return r;
+}
+
+/*
+ * Invert the BWT B (ASCII, n symbols, m terminators) for the rows listed in
+ * `rows`: from row j, emit B[r] and step r <- C[B[r]] + rank(B[r], r, B) until
+ * B[r] is '$'.  Row j of the BWT of a string set is the suffix $_j..., whose
+ * preceding symbol is the last symbol of S_j, so the walk spells S_j reversed.
+ * Output for row rows[t] goes to out + out_off[t] (ASCII, reversed string),
+ * with at most out_off[t+1]-out_off[t] symbols; lens[t] receives the walk
+ * length (or UINT64_MAX when the walk overran its slot or hit a bad byte).
+ * Returns 0, or -1 on allocation failure.
+ */
+int oracle_lf_invert(const uint8_t *B, uint64_t n, const uint64_t *rows,
+                     uint64_t nrows, const uint64_t *out_off, uint8_t *out,
+                     uint64_t *lens)
+{
+    uint64_t *occ = build_occ(B, n);
+    if (!occ) return -1;
+    uint64_t cnt[5];
+    for (int c = 0; c < 5; ++c) cnt[c] = occ_rank(B, occ, c, n);
+    uint64_t C[5];
+    C[0] = 0;
+    for (int c = 1; c < 5; ++c) C[c] = C[c - 1] + cnt[c - 1];
+    for (uint64_t t = 0; t < nrows; ++t) {
+        uint64_t r = rows[t], cap = out_off[t + 1] - out_off[t], len = 0;
+        for (;;) {
+            if (r >= n) { len = UINT64_MAX; break; }
+            int c = code_of(B[r]);
+            if (c == 255) { len = UINT64_MAX; break; }
+            if (c == 0) break;
+            if (len == cap) { len = UINT64_MAX; break; }
+            out[out_off[t] + len] = B[r];
+            ++len;
+            r = C[c] + occ_rank(B, occ, c, r);
+        }
+        lens[t] = len;
+    }
+    free(occ);
+    return 0;
+}
+
+/*
+ * ComputeRanks (Section 4, Lemma 1 and Algorithm 2).
+ *
+ *   Bext  : the current BWT B_ext, ASCII, n_ext symbols, m_ext of them '$'.
+ *   text  : the block's text, codes as described at the top of this file
+ *           (terminators 0), laid out P_0 $ P_1 $ ... P_{mb-1} $.
+ *   soff  : soff[j] = position of P_j's first symbol in `text` (that is, the
+ *           exclusive prefix sum of |P_j|+1), soff[mb] = length of text.
+ *   g     : output, one entry per position of `text`: g[soff[j]+k] is the
+ *           number of suffixes of B_ext smaller than the suffix P_j^k $_j.
+ *
+ * For each string the walk starts from its terminator suffix, which is larger
+ * than exactly the m_ext old terminator suffixes and smaller than every old
+ * suffix that begins with a base, so i = m_ext; then, going left one symbol at
+ * a time with c = P_j[k-1], i becomes C[c] + rank(c, i, B_ext) (Lemma 1),
+ * where C[c] counts the symbols of B_ext smaller than c (terminators count as
+ * smaller than every base).  Returns 0, or -1 on allocation failure.
+ */
+int oracle_compute_ranks(const uint8_t *Bext, uint64_t n_ext,
+                         const uint8_t *text, const uint64_t *soff, uint64_t mb,
+                         uint64_t *g)
+{
+    uint64_t *occ = build_occ(Bext, n_ext);
+    if (!occ) return -1;
+    uint64_t cnt[5], C[5];
+    for (int c = 0; c < 5; ++c) cnt[c] = occ_rank(Bext, occ, c, n_ext);
+    C[0] = 0;
+    for (int c = 1; c < 5; ++c) C[c] = C[c - 1] + cnt[c - 1];
+    uint64_t m_ext = cnt[0];
+    for (uint64_t j = 0; j < mb; ++j) {
+        uint64_t off = soff[j];
+        uint64_t k = soff[j + 1] - soff[j] - 1;   /* |P_j| */
+        uint64_t i = m_ext;
+        g[off + k] = i;
+        while (k > 0) {
+            k = k - 1;
+            int c = text[off + k];                  /* 1..4 */
+            i = C[c] + occ_rank(Bext, occ, c, i);
+            g[off + k] = i;
+        }
+    }
+    free(occ);
+    return 0;
+}
+
+/*
+ * What ComputeRanks must return, from the definition: the number of old
+ * suffixes smaller than the new suffix starting at text position p.  The old
+ * and new strings are compared inside one global text G = old strings then new
+ * strings (the order in which their terminators are numbered), so this is
+ * simply a count over the first n_old positions of G.
+ */
+uint64_t oracle_count_old_smaller(const uint8_t *G, uint64_t n_old, uint64_t p)
+{
+    uint64_t c = 0;
+    for (uint64_t q = 0; q < n_old; ++q)
+        if (cmp_suffix_at(G, q, p) < 0) ++c;
+    return c;
+}

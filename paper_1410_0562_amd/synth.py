@@ -1,0 +1,163 @@
+"""Seeded synthetic read sets in the library's input format.
+
+This module only draws random DNA and packs it; it holds none of the BWT
+arithmetic, and it is the one piece shared by the tests, the benchmark and the
+CPU oracle's callers.
+
+Input format (the one ``bwt_set_append`` takes):
+
+* ``packed``: uint8, 2 bits per symbol, code = index in "ACGT", symbol s at
+  byte s >> 2, bits 2*(s & 3) and up (LSB first);
+* ``offsets``: uint64[m + 1], non-decreasing; read j is symbols
+  [offsets[j], offsets[j+1]).
+
+Workloads (seed = 14100562 + workload number):
+
+1. ``uniform_reads``: 10,000 reads x 100 bp, i.i.d. uniform bases.
+2. ``short_reads``: 4,000,000 x 100 bp sampled from a uniform random 50 Mbp
+   reference at uniform start positions, either strand with probability 1/2
+   (reverse complement), 1% i.i.d. substitutions to one of the other three
+   bases.  Stands in for a large Illumina short-read set.
+3. ``long_reads``: 250,000 reads, lengths lognormal (mean 5 kbp, sigma of the
+   log 0.5, clipped to [1,000, 50,000]) from a uniform 100 Mbp reference, either
+   strand, 10% noise per base split 6% substitution / 2% insertion / 2%
+   deletion.  Stands in for a long-read (Sanger-like) set.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_BASE = 14100562
+_RC = np.array([3, 2, 1, 0], dtype=np.uint8)
+
+
+def pack_codes(codes: np.ndarray) -> np.ndarray:
+    """Pack codes 0..3 four per byte, LSB first; pads with zero bits."""
+    codes = np.asarray(codes, dtype=np.uint8)
+    n = len(codes)
+    pad = (-n) % 4
+    if pad:
+        codes = np.concatenate([codes, np.zeros(pad, dtype=np.uint8)])
+    c = codes.reshape(-1, 4)
+    return (c[:, 0] | (c[:, 1] << 2) | (c[:, 2] << 4) | (c[:, 3] << 6)).astype(np.uint8)
+
+
+def strings_to_input(reads) -> tuple[np.ndarray, np.ndarray]:
+    """ASCII reads over ACGT -> (packed, offsets)."""
+    lut = np.full(256, 255, dtype=np.uint8)
+    for i, ch in enumerate(b"ACGT"):
+        lut[ch] = i
+    joined = "".join(reads).encode("ascii")
+    codes = lut[np.frombuffer(joined, dtype=np.uint8)] if joined else np.zeros(0, np.uint8)
+    if codes.size and codes.max() > 3:
+        raise ValueError("reads must use only A, C, G, T")
+    offsets = np.zeros(len(reads) + 1, dtype=np.uint64)
+    if len(reads):
+        offsets[1:] = np.cumsum([len(r) for r in reads], dtype=np.uint64)
+    return pack_codes(codes), offsets
+
+
+def random_reads(seed: int, m: int, min_len: int, max_len: int, alphabet: int = 4):
+    """m reads with lengths uniform in [min_len, max_len], i.i.d. bases drawn
+    from the first `alphabet` letters of ACGT.  Returns (packed, offsets)."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(min_len, max_len + 1, size=m, dtype=np.int64)
+    offsets = np.zeros(m + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(lens).astype(np.uint64)
+    codes = rng.integers(0, alphabet, size=int(offsets[-1]), dtype=np.uint8)
+    return pack_codes(codes), offsets
+
+
+def uniform_reads(m: int = 10_000, length: int = 100, seed: int = SEED_BASE + 1):
+    """Workload 1: m reads x length bp, i.i.d. uniform over ACGT."""
+    return random_reads(seed, m, length, length)
+
+
+def _substitute(rng, codes: np.ndarray, rate: float) -> None:
+    hit = rng.random(codes.shape) < rate
+    k = int(hit.sum())
+    if k:
+        codes[hit] = (codes[hit] + rng.integers(1, 4, size=k, dtype=np.uint8)) & 3
+
+
+def short_reads(m: int = 4_000_000, length: int = 100, ref_len: int = 50_000_000,
+                sub_rate: float = 0.01, seed: int = SEED_BASE + 2,
+                chunk: int = 1 << 18):
+    """Workload 2: fixed-length reads sampled from a random reference, both
+    strands, i.i.d. substitutions.  Returns (packed, offsets)."""
+    rng = np.random.default_rng(seed)
+    ref = rng.integers(0, 4, size=ref_len, dtype=np.uint8)
+    total = m * length
+    codes_all = np.empty(total, dtype=np.uint8)
+    ar = np.arange(length, dtype=np.int64)
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        k = r1 - r0
+        starts = rng.integers(0, ref_len - length + 1, size=k, dtype=np.int64)
+        minus = rng.random(k) < 0.5
+        blk = ref[starts[:, None] + ar[None, :]]
+        if minus.any():
+            blk[minus] = _RC[blk[minus][:, ::-1]]
+        _substitute(rng, blk, sub_rate)
+        codes_all[r0 * length:r1 * length] = blk.reshape(-1)
+    offsets = np.arange(m + 1, dtype=np.uint64) * np.uint64(length)
+    return pack_codes(codes_all), offsets
+
+
+def long_reads(m: int = 250_000, mean_len: float = 5000.0, sigma: float = 0.5,
+               min_len: int = 1000, max_len: int = 50_000,
+               ref_len: int = 100_000_000, sub: float = 0.06, ins: float = 0.02,
+               dele: float = 0.02, seed: int = SEED_BASE + 3, chunk: int = 4096):
+    """Workload 3: lognormal-length noisy reads from a random reference.
+    Returns (packed, offsets)."""
+    rng = np.random.default_rng(seed)
+    ref = rng.integers(0, 4, size=ref_len, dtype=np.uint8)
+    mu = np.log(mean_len) - sigma * sigma / 2.0
+    lens = np.clip(np.rint(rng.lognormal(mu, sigma, size=m)), min_len, max_len).astype(np.int64)
+    pieces = []
+    out_lens = np.empty(m, dtype=np.int64)
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        L = lens[r0:r1]
+        starts = rng.integers(0, ref_len - L + 1, dtype=np.int64)
+        minus = rng.random(r1 - r0) < 0.5
+        for t in range(r1 - r0):
+            src = ref[starts[t]:starts[t] + L[t]]
+            if minus[t]:
+                src = _RC[src[::-1]]
+            u = rng.random(len(src))
+            # per source base: deletion -> 0 copies, insertion -> base + random
+            # base, substitution -> changed base, otherwise the base itself
+            copies = np.where(u < dele, 0, np.where(u < dele + ins, 2, 1))
+            base = src.copy()
+            subm = (u >= dele + ins) & (u < dele + ins + sub)
+            ks = int(subm.sum())
+            if ks:
+                base[subm] = (base[subm] + rng.integers(1, 4, size=ks, dtype=np.uint8)) & 3
+            rep = np.repeat(base, copies)
+            ins_pos = np.flatnonzero(copies == 2)
+            if len(ins_pos):
+                # the second copy of an inserted base becomes a random base
+                out_idx = np.cumsum(copies) - 1
+                rep[out_idx[ins_pos]] = rng.integers(0, 4, size=len(ins_pos), dtype=np.uint8)
+            pieces.append(rep)
+            out_lens[r0 + t] = len(rep)
+    offsets = np.zeros(m + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(out_lens).astype(np.uint64)
+    return pack_codes(np.concatenate(pieces) if pieces else np.zeros(0, np.uint8)), offsets
+
+
+def take_reads(packed: np.ndarray, offsets: np.ndarray, j0: int, j1: int):
+    """Reads j0..j1-1 of an input as a new (packed, offsets) pair whose first
+    read starts at symbol 0."""
+    offsets = np.asarray(offsets, dtype=np.uint64)
+    s0, s1 = int(offsets[j0]), int(offsets[j1])
+    n = s1 - s0
+    # unpack the symbol range and repack from symbol 0
+    b0, b1 = s0 // 4, (s1 + 3) // 4
+    sub = np.asarray(packed[b0:b1], dtype=np.uint8)
+    codes = np.empty(len(sub) * 4, dtype=np.uint8)
+    for q in range(4):
+        codes[q::4] = (sub >> (2 * q)) & 3
+    codes = codes[s0 - 4 * b0:s0 - 4 * b0 + n]
+    return pack_codes(codes), (offsets[j0:j1 + 1] - np.uint64(s0)).astype(np.uint64)
