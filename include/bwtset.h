@@ -1,0 +1,172 @@
+/*
+ * bwtset.h -- C ABI of libbwtset: incremental BWT of a DNA string set on an
+ * MI355X (gfx950) GPU, built block by block with set-bwte (Pantaleoni,
+ * "A massively parallel algorithm for constructing the BWT of large string
+ * sets", arXiv:1410.0562, Algorithm 1).
+ *
+ * What is computed (Section 2): for strings S_0..S_{m-1} over A<C<G<T, the BWT
+ * B of T = S_0 $_0 S_1 $_1 ... S_{m-1} $_{m-1} with $_0 < ... < $_{m-1} < A,
+ * B[i] = T[(SA[i]-1) mod n] (Eq. 1), n = sum(|S_j| + 1).  Every terminator is
+ * reported as '$'.  Strings appended later are numbered after all earlier
+ * ones, in array order, so an index built by several appends is the BWT of the
+ * concatenation of all appended sets (new strings can be added at any time,
+ * Section 2).
+ *
+ * Conventions shared by every entry point:
+ *   - Input reads are 2-bit packed: code = index in the alphabet (A=0, C=1,
+ *     G=2, T=3), symbol s at byte s>>2, bits 2*(s&3)..2*(s&3)+1 (LSB first).
+ *   - offsets: m+1 non-decreasing uint64 symbol offsets into `reads`; read j
+ *     is symbols [offsets[j], offsets[j+1]).  Empty reads are allowed and add
+ *     one terminator.  A read may hold at most 2^29 - 2 symbols.
+ *   - Pointers may be host or device memory (detected with
+ *     hipPointerGetAttributes) unless an entry point says "device".  Device
+ *     buffers must be readable by the GPU the handle was created on.
+ *   - `stream` is a hipStream_t (NULL: the handle's own stream).  Unless an
+ *     entry point says otherwise, it returns after the work is done and the
+ *     result is visible to later work on any stream.
+ *   - A handle is not thread-safe.  Distinct handles are independent.
+ *   - Errors are negative return codes (BWT_E*); the last one is kept per
+ *     handle (bwt_set_last_error).  An append that fails leaves the index as it
+ *     was before the call.
+ */
+#ifndef BWTSET_H
+#define BWTSET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bwt_set *bwt_set_t;
+
+enum {
+    BWT_OK = 0,
+    BWT_EINVAL = -1,        /* invalid argument (NULL, bad offsets, bad k/c) */
+    BWT_ENOMEM = -2,        /* device memory could not be allocated */
+    BWT_EHIP = -3,          /* a HIP runtime call failed */
+    BWT_EALPHABET = -4,     /* alphabet other than "ACGT" */
+    BWT_ESTATE = -5         /* handle unusable after an earlier HIP failure */
+};
+
+/* Creates an empty index on the current HIP device.  alphabet: NUL-terminated
+ * list of the sigma symbols in sort order, without '$'; only "ACGT" is
+ * supported (2-bit symbols).  Returns NULL on error; bwt_set_last_error(NULL)
+ * then gives the code. */
+bwt_set_t bwt_set_create(const char *alphabet);
+
+/* Frees the handle and all its device memory.  NULL is ignored. */
+void bwt_set_destroy(bwt_set_t h);
+
+/* Adds m strings to the index (Algorithm 1): the strings are split into
+ * blocks of whole strings of at most M suffixes each (M from
+ * bwt_set_set_block_size; a longer string is a block by itself), and each
+ * block is suffix-sorted (ConstructSA, Section 3), ranked against the index by
+ * LF steps (ComputeRanks, Section 4, Lemma 1 / Algorithm 2), reordered into
+ * suffix order (g_sa) and merged into the index (Insert, Section 5), which
+ * also rebuilds the occurrence counters used by rank.  reads/offsets: host or
+ * device, layout above.  Host buffers are copied before the GPU work starts;
+ * device buffers must stay valid until the call returns.  m == 0 is a no-op.
+ * Returns BWT_OK or a negative code; on error the index is unchanged. */
+int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
+                   uint64_t m, void *stream);
+
+/* rank(c, k, B) = |{ i < k : B[i] = c }| (Eq. 2).  c: 'A','C','G','T' or '$';
+ * 0 <= k <= n.  Returns the count, or UINT64_MAX on error. */
+uint64_t bwt_set_rank(bwt_set_t h, char c, uint64_t k);
+
+/* Batched rank: out[t] = rank(cs[t], ks[t], B) for t < count.  cs, ks, out:
+ * device pointers (cs as ASCII bytes).  An invalid pair yields UINT64_MAX in
+ * its slot.  Enqueued on `stream`; returns without waiting. */
+int bwt_set_rank_many(bwt_set_t h, const uint8_t *cs, const uint64_t *ks,
+                      uint64_t *out, uint64_t count, void *stream);
+
+/* Writes B as n ASCII bytes ('A','C','G','T','$') to out (host or device).
+ * out == NULL: returns n without writing (length query).  Returns n or a
+ * negative code. */
+int64_t bwt_set_export(bwt_set_t h, uint8_t *out);
+
+/* Number of symbols n and strings m in the index. */
+int bwt_set_size(bwt_set_t h, uint64_t *n, uint64_t *m);
+
+/* Empties the index, keeping its device memory for reuse. */
+int bwt_set_reset(bwt_set_t h);
+
+/* Block size M of Algorithm 1, in suffixes (terminators included); default
+ * 2^26.  Must be at least 1.  The result does not depend on M. */
+int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
+
+/* Last error code recorded on h (or, for h == NULL, by bwt_set_create). */
+int bwt_set_last_error(bwt_set_t h);
+
+/* Static description of an error code. */
+const char *bwt_set_strerror(int code);
+
+/* ---- Single steps of Algorithm 1, for checking each step on its own ----- */
+
+/* ConstructSA and B_int of one block made of all m reads (block-local
+ * terminators in read order, Section 3 and Algorithm 1): sa_out[i] (device,
+ * uint32, n_blk = sum(|P_j|+1) entries) is the i-th smallest suffix of the
+ * block text P_0 $ P_1 $ ...; bint_out[i] (device, n_blk bytes) is the symbol
+ * before it as ASCII, '$' when the suffix starts a read.  reads/offsets: host
+ * or device.  Does not change the index. */
+int bwt_set_block_sort(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
+                       uint64_t m, uint32_t *sa_out, uint8_t *bint_out, void *stream);
+
+/* ComputeRanks (Section 4, Lemma 1 / Algorithm 2) of one block made of all m
+ * reads against the current index: g_out[p] (device, uint64, n_blk entries, in
+ * block text order) = number of suffixes in the index smaller than the block
+ * suffix at p.  Does not change the index. */
+int bwt_set_compute_ranks(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
+                          uint64_t m, uint64_t *g_out, void *stream);
+
+/* Insert (Section 5): merges n_new <= 2^29 - 1 symbols bint (device,
+ * ASCII 'A','C','G','T','$') into the index, bint[i] going in front of old
+ * row gsa[i] (device, uint64, non-decreasing, each <= n), and rebuilds the
+ * occurrence counters; every '$' in bint counts as one more string.  Returns
+ * BWT_EINVAL (index unchanged) if gsa decreases or exceeds n, or if bint
+ * holds another byte. */
+int bwt_set_insert(bwt_set_t h, const uint8_t *bint, const uint64_t *gsa,
+                   uint64_t n_new, void *stream);
+
+/* ---- Timing of the GPU steps ------------------------------------------- */
+
+enum {
+    BWT_STAGE_PLAN = 0,     /* offsets check and block split */
+    BWT_STAGE_SORT = 1,     /* ConstructSA: keys, radix passes, doubling */
+    BWT_STAGE_RANKS = 2,    /* ComputeRanks kernel */
+    BWT_STAGE_GATHER = 3,   /* B_int and g_sa from the suffix array */
+    BWT_STAGE_INSERT = 4,   /* Insert + occurrence counters */
+    BWT_NSTAGES = 5
+};
+
+typedef struct {
+    double ms[BWT_NSTAGES];         /* summed GPU time per stage (HIP events) */
+    uint64_t launches[BWT_NSTAGES]; /* timed intervals per stage */
+    double ranks_kernel_ms;         /* ComputeRanks kernel alone */
+    uint64_t ranks_launches;
+    uint64_t ranks_steps;           /* LF steps performed (symbols walked) */
+    double insert_kernel_ms;        /* Insert merge kernel alone */
+    uint64_t insert_launches;
+    uint64_t insert_records_out;    /* index records written by Insert */
+    uint64_t insert_records_in;     /* index records read by Insert */
+    uint64_t insert_new_symbols;    /* symbols merged in */
+    double sort_pass_ms;            /* radix passes alone */
+    uint64_t sort_pass_launches;
+    uint64_t sort_pass_keys;        /* keys moved by radix passes */
+    uint64_t blocks;                /* blocks processed */
+    uint64_t doubling_rounds;       /* prefix-doubling rounds after the first sort */
+} bwt_stats_t;
+
+/* Turns per-stage HIP-event timing on (1) or off (0).  Timing adds event
+ * records around the stages; results are unchanged. */
+int bwt_set_enable_timing(bwt_set_t h, int on);
+
+/* Copies the accumulated timings; clears them when reset != 0. */
+int bwt_set_get_stats(bwt_set_t h, bwt_stats_t *out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BWTSET_H */

@@ -1,0 +1,144 @@
+// bwt_internal.hpp -- layouts and kernel launchers shared by the host runtime
+// (bwtset.cpp) and the HIP kernel files.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bwt {
+
+// ---------------------------------------------------------------------------
+// Index layout in HBM (the partial BWT B_ext plus its occurrence counters).
+//
+// B_ext is cut into records of 128 symbols.  A record is one 64-byte line:
+//   cnt[4]  occurrences of A, C, G, T in [superblock start, record start)
+//   lo[2]   bit t = low bit of the code of symbol t   (A=0 C=1 G=2 T=3)
+//   hi[2]   bit t = high bit of the code of symbol t
+//   dl[2]   bit t = 1 where symbol t is a terminator ('$'; its lo/hi are 0)
+// so rank(c, k) (Eq. 2) is one 64-byte record read plus two popcounts, the
+// counterpart of the per-page counters sampled every 128 symbols that the
+// paper keeps for DNA (Section 5).  Counts are 32-bit and relative to a
+// superblock of 2^32 symbols; `sbc[sb*4 + c]` holds the 64-bit count of c
+// before superblock sb.  An index of n symbols has n/128 + 1 records (the last
+// one may be a sentinel holding only counts, so that rank(c, n) is a plain
+// record lookup) and n/2^32 + 1 superblock entries.
+//
+// `meta` (device, uint64[8]): [0..3] total A, C, G, T; [4] n; [5] m (number of
+// terminators); [6..7] unused.
+// ---------------------------------------------------------------------------
+struct alignas(64) Rec {
+    uint32_t cnt[4];
+    uint64_t lo[2];
+    uint64_t hi[2];
+    uint64_t dl[2];
+};
+static_assert(sizeof(Rec) == 64, "record must be one 64-byte line");
+
+constexpr int REC_SHIFT = 7;
+constexpr uint64_t REC_SYMS = 1ull << REC_SHIFT;
+constexpr int SB_SHIFT = 32;
+constexpr int META_WORDS = 8;
+
+inline uint64_t records_for(uint64_t n) { return (n >> REC_SHIFT) + 1; }
+inline uint64_t superblocks_for(uint64_t n) { return (n >> SB_SHIFT) + 1; }
+
+// ---------------------------------------------------------------------------
+// Block suffix sorting.
+//
+// Position p of a block's text (reads P_0 $ P_1 $ ..., local terminators in
+// read order) is carried in sort values as p | prev << 29, where prev is the
+// code of the symbol before p (0..3) or 4 when p starts a read, so that B_int
+// falls out of the sorted values without a second gather.
+//
+// First sort key of p, with r = number of symbols before the read's
+// terminator and t = min(r, KEY_K):
+//   key = (first t symbols, 2 bits each, first symbol most significant,
+//          zero-padded to KEY_K symbols) << 5 | t
+// Equal keys with t < KEY_K end in their terminators and are ordered by read
+// index, i.e. by position, which the stable sort keeps.
+// ---------------------------------------------------------------------------
+constexpr int KEY_K = 29;
+constexpr int KEY_LEN_BITS = 5;
+constexpr int KEY_BITS0 = 2 * KEY_K + KEY_LEN_BITS;  // 63
+constexpr int POS_BITS = 29;
+constexpr uint32_t POS_MASK = (1u << POS_BITS) - 1u;
+constexpr uint64_t MAX_BLOCK = (1ull << POS_BITS) - 1;  // suffixes per block
+constexpr uint64_t MAX_READ = MAX_BLOCK - 1;            // symbols per read
+
+constexpr int PREP_TILE_SHIFT = 12;  // positions per read-lookup tile
+constexpr int SCAN_TILE = 4096;      // elements per look-back scan tile
+constexpr int RADIX_TILE = 4096;     // keys per radix pass tile
+constexpr int INS_TILE_RECS = 16;    // output records per Insert tile
+constexpr uint64_t INS_TILE_SYMS = INS_TILE_RECS * REC_SYMS;
+constexpr int CHUNK_SHIFT = 6;       // B_int counts sampled every 64 symbols
+
+__host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// ----------------------------------------------------------------- launchers
+// Every launcher enqueues on `s` and returns hipGetLastError().  `err` is a
+// device word into which kernels OR a bit when an internal consistency check
+// fails (a bounded wait timed out, an index would leave its buffer); the host
+// reads it after every append and treats a nonzero value as a failure.
+
+// radix sort pieces (k_radix.hip)
+hipError_t launch_radix_hist(const uint64_t *keys, uint64_t n, int npass, uint32_t *hist,
+                             hipStream_t s);
+hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                             uint32_t *vout, uint64_t n, int shift, const uint32_t *dstart,
+                             uint64_t *status, uint32_t *counter, uint32_t epoch, uint32_t *err,
+                             hipStream_t s);
+
+// block preparation and prefix doubling (k_sa.hip)
+hipError_t launch_block_soff(const uint64_t *off, uint32_t m_blk, uint32_t *soff, hipStream_t s);
+hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
+                                   uint32_t *tile_first, hipStream_t s);
+hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                             const uint32_t *tile_first, uint32_t m_blk, uint32_t n_blk,
+                             uint64_t *keys, uint32_t *vals, hipStream_t s);
+// groups after a sort: round 0 (U == nullptr: element i is SA slot i, keys
+// with a short length field are singletons) or a doubling round (element u
+// goes to SA slot U[u]; its value is stored there)
+hipError_t launch_group_heads(const uint64_t *keys, const uint32_t *vals, const uint32_t *U,
+                              uint32_t n, uint32_t *sa, uint32_t *rank, uint32_t *Uout,
+                              uint32_t *nUout, uint64_t *status, uint32_t *counter,
+                              uint32_t epoch, uint32_t *err, hipStream_t s);
+hipError_t launch_doubling_keys(const uint32_t *U, uint32_t nU, const uint32_t *sa,
+                                const uint32_t *rank, uint32_t h, int rbits, uint32_t n_blk,
+                                uint64_t *keys, uint32_t *vals, uint32_t *err, hipStream_t s);
+hipError_t launch_gather(const uint32_t *sa, const uint64_t *g, uint32_t n, uint8_t *bint,
+                         uint64_t *gsa, hipStream_t s);
+hipError_t launch_sa_strip(const uint32_t *sa, uint32_t n, uint32_t *out, hipStream_t s);
+
+// ComputeRanks (k_ranks.hip)
+hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                                uint32_t m_blk, const Rec *recs, const uint64_t *sbc,
+                                const uint64_t *meta, int big, uint64_t *g, hipStream_t s);
+
+// Insert and index bookkeeping (k_insert.hip)
+hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream_t s);
+hipError_t launch_count_bint(const uint8_t *bint, uint32_t n, uint32_t *bcnt, uint64_t *status,
+                             uint32_t *counter, uint32_t epoch, uint32_t *bad, uint32_t *err,
+                             hipStream_t s);
+hipError_t launch_check_gsa(const uint64_t *gsa, uint64_t n_new, uint64_t n_ext, uint32_t *bad,
+                            hipStream_t s);
+hipError_t launch_ins_tile_first(const uint64_t *gsa, uint64_t n_new, uint64_t ntiles,
+                                 uint64_t *first_new, hipStream_t s);
+hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
+                           const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
+                           uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta, hipStream_t s);
+hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
+                         const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
+                         uint64_t n_new, const uint64_t *first_new, Rec *nrecs,
+                         const uint64_t *nsbc, uint32_t *err, hipStream_t s);
+
+// queries and input checks (k_query.hip)
+hipError_t launch_rank_many(const Rec *recs, const uint64_t *sbc, const uint64_t *meta,
+                            const uint8_t *cs, const uint64_t *ks, uint64_t *out, uint64_t count,
+                            hipStream_t s);
+hipError_t launch_export(const Rec *recs, uint64_t n, uint8_t *out, hipStream_t s);
+hipError_t launch_check_offsets(const uint64_t *off, uint64_t m, uint64_t *res, hipStream_t s);
+hipError_t launch_plan_blocks(const uint64_t *off, uint64_t m, uint64_t M, uint64_t *cuts,
+                              uint64_t *res, hipStream_t s);
+
+}  // namespace bwt

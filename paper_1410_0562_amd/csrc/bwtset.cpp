@@ -1,0 +1,921 @@
+// bwtset.cpp -- host runtime of libbwtset: handle state, device memory, the
+// per-block driver of set-bwte (Algorithm 1) and the C ABI of bwtset.h.
+//
+// One handle owns three index buffers: the current index is only ever read
+// during an append, and the blocks of the append alternate between the two
+// others, so a failed append leaves the index untouched.  A workspace sized
+// for the largest block holds the suffix sort, the ranks and the merge inputs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "../../include/bwtset.h"
+#include "bwt_internal.hpp"
+
+using namespace bwt;
+
+namespace {
+
+thread_local int g_create_error = BWT_OK;
+std::atomic<uint32_t> g_epoch{1};
+
+// Every look-back launch gets a fresh epoch (30 bits, never 0).
+uint32_t next_epoch() {
+    uint32_t e = g_epoch.fetch_add(1) & 0x3fffffffu;
+    if (e == 0) e = g_epoch.fetch_add(1) & 0x3fffffffu;
+    return e;
+}
+
+struct IndexBuf {
+    Rec *recs = nullptr;
+    uint64_t rec_cap = 0;
+    uint64_t *sbc = nullptr;
+    uint64_t sbc_cap = 0;
+    uint64_t *meta = nullptr;
+};
+
+// Device scratch for one block of at most `cap` suffixes.
+struct Workspace {
+    uint64_t cap = 0;
+    uint64_t *kA = nullptr, *kB = nullptr;   // sort keys (ping-pong)
+    uint32_t *v[3] = {nullptr, nullptr, nullptr};  // sort values / suffix array
+    uint32_t *U[2] = {nullptr, nullptr};     // unresolved SA slots
+    uint32_t *rank = nullptr;                // group rank per block position
+    uint64_t *g = nullptr, *gsa = nullptr;   // ranks in text order / in SA order
+    uint8_t *bint = nullptr;
+    uint32_t *bcnt = nullptr;                // B_int counts per 64 symbols
+    uint32_t *soff = nullptr;                // block position of each read
+    uint32_t *tile_first = nullptr;
+    uint64_t *status_radix = nullptr;        // radix look-back words
+    uint64_t *status_scan = nullptr;         // scan look-back words
+    uint32_t *misc = nullptr;                // counters, histograms, flags
+};
+
+// layout of Workspace::misc (uint32 words)
+constexpr int MISC_CNT_RADIX = 0;
+constexpr int MISC_CNT_HEADS = 1;
+constexpr int MISC_CNT_BINT = 2;
+constexpr int MISC_NU = 4;
+constexpr int MISC_BAD = 5;
+constexpr int MISC_ERR = 6;
+constexpr int MISC_HIST = 64;                 // 8*256 + 1 words
+constexpr int MISC_WORDS = MISC_HIST + 8 * 256 + 64;
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Span {
+        int stage;      // BWT_STAGE_* or 100+ for kernel-level spans
+        hipEvent_t a, b;
+        uint64_t units;
+    };
+    std::vector<Span> open;
+    bwt_stats_t acc;
+    Timer() { memset(&acc, 0, sizeof acc); }
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+enum { SPAN_RANKS_K = 100, SPAN_INSERT_K = 101, SPAN_RADIX_PASS = 102 };
+
+}  // namespace
+
+struct bwt_set {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t n = 0, m = 0;
+    IndexBuf buf[3];
+    int cur = 0;
+    Workspace ws;
+    uint64_t M = 1ull << 26;
+    uint64_t *first_new = nullptr;
+    uint64_t first_new_cap = 0;
+    // staging for host inputs / outputs
+    uint8_t *stage_reads = nullptr;
+    uint64_t stage_reads_cap = 0;
+    uint64_t *stage_off = nullptr;
+    uint64_t stage_off_cap = 0;
+    uint64_t *cuts = nullptr;
+    uint64_t cuts_cap = 0;
+    uint8_t *stage_out = nullptr;
+    uint64_t stage_out_cap = 0;
+    uint64_t *res = nullptr;       // 4 words of device results
+    uint64_t *pinned = nullptr;    // small pinned host area (512 words)
+    int last_error = BWT_OK;
+    bool broken = false;
+    Timer timer;
+};
+
+namespace {
+
+int fail(bwt_set *h, int code) {
+    if (h) {
+        h->last_error = code;
+        if (code == BWT_EHIP) h->broken = true;
+    }
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                     \
+    do {                                                                    \
+        hipError_t _e = (expr);                                             \
+        if (_e != hipSuccess) {                                             \
+            if (getenv("BWTSET_DEBUG"))                                     \
+                fprintf(stderr, "bwtset: %s failed: %s (%s:%d)\n", #expr,  \
+                        hipGetErrorString(_e), __FILE__, __LINE__);         \
+            return fail((h), BWT_EHIP);                                     \
+        }                                                                   \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, uint64_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+template <class T>
+void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// ---- timing ---------------------------------------------------------------
+struct Scope {
+    bwt_set *h;
+    hipStream_t s;
+    int stage;
+    uint64_t units;
+    hipEvent_t a = nullptr;
+    Scope(bwt_set *h_, hipStream_t s_, int stage_, uint64_t units_ = 0)
+        : h(h_), s(s_), stage(stage_), units(units_) {
+        if (h->timer.on) {
+            a = h->timer.get();
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~Scope() {
+        if (h->timer.on && a) {
+            hipEvent_t b = h->timer.get();
+            if (b) {
+                (void)hipEventRecord(b, s);
+                h->timer.open.push_back({stage, a, b, units});
+            }
+        }
+    }
+};
+
+// Called after the stream has been synchronized.
+void timer_collect(bwt_set *h) {
+    Timer &T = h->timer;
+    for (auto &sp : T.open) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) {
+            (void)hipGetLastError();
+            ms = 0.f;
+        }
+        if (sp.stage < BWT_NSTAGES) {
+            T.acc.ms[sp.stage] += ms;
+            T.acc.launches[sp.stage] += 1;
+        } else if (sp.stage == SPAN_RANKS_K) {
+            T.acc.ranks_kernel_ms += ms;
+            T.acc.ranks_launches += 1;
+            T.acc.ranks_steps += sp.units;
+        } else if (sp.stage == SPAN_INSERT_K) {
+            T.acc.insert_kernel_ms += ms;
+            T.acc.insert_launches += 1;
+        } else if (sp.stage == SPAN_RADIX_PASS) {
+            T.acc.sort_pass_ms += ms;
+            T.acc.sort_pass_launches += 1;
+            T.acc.sort_pass_keys += sp.units;
+        }
+        T.pool.push_back(sp.a);
+        T.pool.push_back(sp.b);
+    }
+    T.open.clear();
+}
+
+// ---- memory ---------------------------------------------------------------
+int ensure_index(bwt_set *h, IndexBuf &b, uint64_t n) {
+    uint64_t nr = records_for(n), ns = superblocks_for(n);
+    if (b.rec_cap < nr) {
+        uint64_t cap = std::max<uint64_t>(nr, b.rec_cap + b.rec_cap / 2);
+        dfree(b.recs);
+        b.rec_cap = 0;
+        if (dalloc(&b.recs, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, BWT_ENOMEM);
+        }
+        b.rec_cap = cap;
+    }
+    if (b.sbc_cap < ns) {
+        uint64_t cap = std::max<uint64_t>(ns, 4);
+        dfree(b.sbc);
+        b.sbc_cap = 0;
+        if (dalloc(&b.sbc, cap * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, BWT_ENOMEM);
+        }
+        b.sbc_cap = cap;
+    }
+    if (!b.meta) {
+        if (dalloc(&b.meta, META_WORDS) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, BWT_ENOMEM);
+        }
+    }
+    return BWT_OK;
+}
+
+void free_ws(Workspace &w) {
+    dfree(w.kA);
+    dfree(w.kB);
+    for (auto &p : w.v) dfree(p);
+    for (auto &p : w.U) dfree(p);
+    dfree(w.rank);
+    dfree(w.g);
+    dfree(w.gsa);
+    dfree(w.bint);
+    dfree(w.bcnt);
+    dfree(w.soff);
+    dfree(w.tile_first);
+    dfree(w.status_radix);
+    dfree(w.status_scan);
+    dfree(w.misc);
+    w.cap = 0;
+}
+
+int ensure_ws(bwt_set *h, uint64_t need) {
+    Workspace &w = h->ws;
+    if (w.cap >= need && w.misc) return BWT_OK;
+    uint64_t cap = std::max<uint64_t>(need, w.cap + w.cap / 4);
+    cap = std::min<uint64_t>(std::max<uint64_t>(cap, 4096), MAX_BLOCK + 1);
+    free_ws(w);
+    bool ok = true;
+    uint64_t tiles = div_up(cap, 4096) + 1;
+    ok &= dalloc(&w.kA, cap) == hipSuccess;
+    ok &= dalloc(&w.kB, cap) == hipSuccess;
+    for (auto &p : w.v) ok &= dalloc(&p, cap) == hipSuccess;
+    for (auto &p : w.U) ok &= dalloc(&p, cap) == hipSuccess;
+    ok &= dalloc(&w.rank, cap) == hipSuccess;
+    ok &= dalloc(&w.g, cap) == hipSuccess;
+    ok &= dalloc(&w.gsa, cap) == hipSuccess;
+    ok &= dalloc(&w.bint, cap + 64) == hipSuccess;
+    ok &= dalloc(&w.bcnt, (div_up(cap, 64) + 2) * 4) == hipSuccess;
+    ok &= dalloc(&w.soff, cap + 2) == hipSuccess;
+    ok &= dalloc(&w.tile_first, div_up(cap, 1u << PREP_TILE_SHIFT) + 2) == hipSuccess;
+    ok &= dalloc(&w.status_radix, tiles * 256) == hipSuccess;
+    ok &= dalloc(&w.status_scan, tiles * 8) == hipSuccess;
+    ok &= dalloc(&w.misc, MISC_WORDS) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_ws(w);
+        return fail(h, BWT_ENOMEM);
+    }
+    // counters start at zero; status words never need clearing (epoch tags),
+    // zeroing them once makes the first launches read "not ready" cleanly
+    HIPCHK(h, hipMemsetAsync(w.misc, 0, MISC_WORDS * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(w.status_radix, 0, tiles * 256 * 8, h->stream));
+    HIPCHK(h, hipMemsetAsync(w.status_scan, 0, tiles * 8 * 8, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    w.cap = cap;
+    return BWT_OK;
+}
+
+template <class T>
+int ensure_buf(bwt_set *h, T *&p, uint64_t &cap, uint64_t need) {
+    if (cap >= need && p) return BWT_OK;
+    uint64_t c = std::max<uint64_t>(need, cap + cap / 2);
+    dfree(p);
+    cap = 0;
+    if (dalloc(&p, c) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, BWT_ENOMEM);
+    }
+    cap = c;
+    return BWT_OK;
+}
+
+int bits_for(uint64_t v) {  // bits needed to hold values < v (at least 1)
+    int b = 1;
+    while (b < 63 && (1ull << b) < v) ++b;
+    return b;
+}
+
+// ---- radix sort -------------------------------------------------------------
+// Sorts (kin, vin) by the low `bits` bits of the keys, ping-ponging with
+// (kalt, valt); returns via *ko / *vo where the sorted data ended up.
+int radix_sort(bwt_set *h, hipStream_t s, uint64_t *kin, uint32_t *vin, uint64_t *kalt,
+               uint32_t *valt, uint64_t n, int bits, uint64_t **ko, uint32_t **vo) {
+    Workspace &w = h->ws;
+    int npass = (bits + 7) / 8;
+    *ko = kin;
+    *vo = vin;
+    if (n <= 1) return BWT_OK;
+    HIPCHK(h, launch_radix_hist(kin, n, npass, w.misc + MISC_HIST, s));
+    uint64_t *ka = kin, *kb = kalt;
+    uint32_t *va = vin, *vb = valt;
+    for (int p = 0; p < npass; ++p) {
+        {
+            Scope sc(h, s, SPAN_RADIX_PASS, n);
+            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, 8 * p, w.misc + MISC_HIST + 256 * p,
+                                        w.status_radix, w.misc + MISC_CNT_RADIX, next_epoch(),
+                                        w.misc + MISC_ERR, s));
+        }
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    *ko = ka;
+    *vo = va;
+    return BWT_OK;
+}
+
+int read_u32(bwt_set *h, hipStream_t s, const uint32_t *dptr, uint32_t *out) {
+    HIPCHK(h, hipMemcpyAsync(h->pinned, dptr, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    *out = *reinterpret_cast<uint32_t *>(h->pinned);
+    return BWT_OK;
+}
+
+// Clears the device consistency word (before a call that launches kernels).
+int clear_err(bwt_set *h, hipStream_t s) {
+    HIPCHK(h, hipMemsetAsync(h->ws.misc + MISC_ERR, 0, 4, s));
+    return BWT_OK;
+}
+
+// After the stream is synchronized: a nonzero consistency word means a kernel
+// met an impossible state; the call fails and the tile counters are reset.
+int check_err(bwt_set *h, hipStream_t s) {
+    uint32_t e = 0;
+    int rc = read_u32(h, s, h->ws.misc + MISC_ERR, &e);
+    if (rc) return rc;
+    if (e) {
+        if (getenv("BWTSET_DEBUG")) fprintf(stderr, "bwtset: device check failed: 0x%x\n", e);
+        HIPCHK(h, hipMemsetAsync(h->ws.misc, 0, MISC_HIST * 4, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        h->last_error = BWT_EHIP;
+        return BWT_EHIP;
+    }
+    return BWT_OK;
+}
+
+// ---- ConstructSA of one block --------------------------------------------
+// reads/off: device; off points at the block's first read (m_blk + 1
+// entries).  On return *sa_out points at the block's suffix array (values
+// carry the preceding symbol in bits 29..31).
+int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *off,
+               uint32_t m_blk, uint32_t n_blk, uint32_t **sa_out) {
+    Workspace &w = h->ws;
+    Scope sc(h, s, BWT_STAGE_SORT);
+    HIPCHK(h, launch_block_soff(off, m_blk, w.soff, s));
+    HIPCHK(h, launch_block_tile_first(w.soff, m_blk, n_blk, w.tile_first, s));
+    HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, m_blk, n_blk, w.kA, w.v[0], s));
+    uint64_t *ks;
+    uint32_t *vs;
+    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, KEY_BITS0, &ks, &vs);
+    if (rc) return rc;
+    uint32_t *sa = vs;
+    uint32_t *spare[2];
+    {
+        int k = 0;
+        for (auto *p : w.v)
+            if (p != sa) spare[k++] = p;
+    }
+    int ui = 0;
+    HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, sa, w.rank, w.U[ui], w.misc + MISC_NU,
+                                 w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
+                                 w.misc + MISC_ERR, s));
+    uint32_t nU = 0;
+    if (n_blk > 0 && (rc = read_u32(h, s, w.misc + MISC_NU, &nU))) return rc;
+    const int rbits = bits_for(n_blk);
+    uint32_t hlen = KEY_K;
+    int rounds = 0;
+    while (nU > 0) {
+        // h doubles every round and no suffix is longer than a block
+        if (++rounds > 32 || hlen > n_blk) return fail(h, BWT_EHIP);
+        h->timer.acc.doubling_rounds += 1;
+        HIPCHK(h, launch_doubling_keys(w.U[ui], nU, sa, w.rank, hlen, rbits, n_blk, w.kA,
+                                       spare[0], w.misc + MISC_ERR, s));
+        rc = radix_sort(h, s, w.kA, spare[0], w.kB, spare[1], nU, 2 * rbits, &ks, &vs);
+        if (rc) return rc;
+        HIPCHK(h, launch_group_heads(ks, vs, w.U[ui], nU, sa, w.rank, w.U[ui ^ 1],
+                                     w.misc + MISC_NU, w.status_scan, w.misc + MISC_CNT_HEADS,
+                                     next_epoch(), w.misc + MISC_ERR, s));
+        ui ^= 1;
+        if ((rc = read_u32(h, s, w.misc + MISC_NU, &nU))) return rc;
+        hlen *= 2;
+    }
+    *sa_out = sa;
+    return BWT_OK;
+}
+
+// ---- Insert ------------------------------------------------------------------
+int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, uint64_t n_ext,
+                 const uint8_t *bint, const uint64_t *gsa, uint64_t n_new, bool check) {
+    Workspace &w = h->ws;
+    const uint64_t n_out = n_ext + n_new;
+    const uint64_t ntiles = div_up(records_for(n_out), INS_TILE_RECS);
+    int rc = ensure_buf(h, h->first_new, h->first_new_cap, ntiles + 2);
+    if (rc) return rc;
+    Scope sc(h, s, BWT_STAGE_INSERT);
+    if (check) {
+        HIPCHK(h, hipMemsetAsync(w.misc + MISC_BAD, 0, 4, s));
+        HIPCHK(h, launch_check_gsa(gsa, n_new, n_ext, w.misc + MISC_BAD, s));
+    }
+    HIPCHK(h, launch_count_bint(bint, (uint32_t)n_new, w.bcnt, w.status_scan,
+                                w.misc + MISC_CNT_BINT, next_epoch(), w.misc + MISC_BAD,
+                                w.misc + MISC_ERR, s));
+    if (check) {
+        uint32_t bad = 0;
+        if ((rc = read_u32(h, s, w.misc + MISC_BAD, &bad))) return rc;
+        if (bad) return fail(h, BWT_EINVAL);
+    }
+    HIPCHK(h, launch_ins_tile_first(gsa, n_new, ntiles, h->first_new, s));
+    HIPCHK(h, launch_ins_meta(src.recs, src.sbc, src.meta, bint, w.bcnt, gsa, n_new, dst.sbc,
+                              dst.meta, s));
+    {
+        Scope sk(h, s, SPAN_INSERT_K);
+        HIPCHK(h, launch_insert(src.recs, src.sbc, n_ext, bint, w.bcnt, gsa, n_new, h->first_new,
+                                dst.recs, dst.sbc, w.misc + MISC_ERR, s));
+    }
+    if (h->timer.on) {
+        h->timer.acc.insert_records_out += records_for(n_out);
+        h->timer.acc.insert_records_in += records_for(n_ext);
+        h->timer.acc.insert_new_symbols += n_new;
+    }
+    return BWT_OK;
+}
+
+// ---- input planning -----------------------------------------------------------
+struct Plan {
+    const uint8_t *reads = nullptr;   // device
+    const uint64_t *off = nullptr;    // device, m + 1 entries
+    std::vector<uint64_t> cut_j;      // block boundaries (read indices), K + 1
+    std::vector<uint64_t> cut_s;      // block-text position S(j) of each boundary
+    uint64_t total_suffixes = 0;
+};
+
+int plan_input(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *offsets,
+               uint64_t m, uint64_t M, Plan &P) {
+    const bool off_dev = is_device_ptr(offsets);
+    const bool reads_dev = is_device_ptr(reads);
+    std::vector<uint64_t> hoff;
+    if (!off_dev || !reads_dev) {
+        // bring the offsets to the host and plan there
+        hoff.resize(m + 1);
+        if (off_dev) {
+            HIPCHK(h, hipMemcpyAsync(hoff.data(), offsets, (m + 1) * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+        } else {
+            memcpy(hoff.data(), offsets, (m + 1) * 8);
+        }
+        uint64_t maxlen = 0;
+        for (uint64_t j = 0; j < m; ++j) {
+            if (hoff[j + 1] < hoff[j]) return fail(h, BWT_EINVAL);
+            maxlen = std::max(maxlen, hoff[j + 1] - hoff[j]);
+        }
+        if (maxlen > MAX_READ) return fail(h, BWT_EINVAL);
+        const uint64_t o0 = hoff[0];
+        P.cut_j.assign(1, 0);
+        P.cut_s.assign(1, 0);
+        uint64_t j = 0;
+        while (j < m) {
+            uint64_t Sj = hoff[j] - o0 + j, k = j + 1;
+            // largest k with S(k) - S(j) <= M (at least j + 1)
+            uint64_t lo = j + 1, hi = m;
+            while (lo < hi) {
+                uint64_t mid = lo + (hi - lo + 1) / 2;
+                if (hoff[mid] - o0 + mid - Sj <= M) lo = mid;
+                else hi = mid - 1;
+            }
+            k = lo;
+            P.cut_j.push_back(k);
+            P.cut_s.push_back(hoff[k] - o0 + k);
+            j = k;
+        }
+        P.total_suffixes = hoff[m] - o0 + m;
+        // device copies
+        uint64_t base_sym = o0 & ~3ull;
+        if (!reads_dev) {
+            uint64_t nbytes = (hoff[m] + 3) / 4 - base_sym / 4;
+            int rc = ensure_buf(h, h->stage_reads, h->stage_reads_cap, nbytes + 16);
+            if (rc) return rc;
+            HIPCHK(h, hipMemcpyAsync(h->stage_reads, reads + base_sym / 4, nbytes,
+                                     hipMemcpyHostToDevice, s));
+            for (auto &x : hoff) x -= base_sym;
+            P.reads = h->stage_reads;
+        } else {
+            P.reads = reads;
+        }
+        int rc = ensure_buf(h, h->stage_off, h->stage_off_cap, m + 1);
+        if (rc) return rc;
+        HIPCHK(h, hipMemcpyAsync(h->stage_off, hoff.data(), (m + 1) * 8, hipMemcpyHostToDevice, s));
+        // the host vector must outlive the copy
+        HIPCHK(h, hipStreamSynchronize(s));
+        P.off = h->stage_off;
+        return BWT_OK;
+    }
+    // both on the device: check and split there, read back only the cuts
+    HIPCHK(h, launch_check_offsets(offsets, m, h->res, s));
+    int rc = ensure_buf(h, h->cuts, h->cuts_cap, 2 * (m + 1) + 2);
+    if (rc) return rc;
+    HIPCHK(h, launch_plan_blocks(offsets, m, M, h->cuts, h->res, s));
+    HIPCHK(h, hipMemcpyAsync(h->pinned, h->res, 4 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    uint64_t bad = h->pinned[0], maxlen = h->pinned[1], K = h->pinned[2];
+    if (bad || maxlen > MAX_READ) return fail(h, BWT_EINVAL);
+    std::vector<uint64_t> cuts(2 * (K + 1));
+    HIPCHK(h, hipMemcpyAsync(cuts.data(), h->cuts, cuts.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    P.cut_j.resize(K + 1);
+    P.cut_s.resize(K + 1);
+    for (uint64_t k = 0; k <= K; ++k) {
+        P.cut_j[k] = cuts[2 * k];
+        P.cut_s[k] = cuts[2 * k + 1];
+    }
+    P.total_suffixes = P.cut_s[K];
+    P.reads = reads;
+    P.off = offsets;
+    return BWT_OK;
+}
+
+uint64_t max_block(const Plan &P) {
+    uint64_t mb = 0;
+    for (size_t k = 0; k + 1 < P.cut_s.size(); ++k) mb = std::max(mb, P.cut_s[k + 1] - P.cut_s[k]);
+    return mb;
+}
+
+int set_device(bwt_set *h) {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, BWT_EHIP);
+    }
+    if (d != h->device) HIPCHK(h, hipSetDevice(h->device));
+    return BWT_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+bwt_set_t bwt_set_create(const char *alphabet) {
+    if (!alphabet) {
+        g_create_error = BWT_EINVAL;
+        return nullptr;
+    }
+    if (strcmp(alphabet, "ACGT") != 0) {
+        g_create_error = BWT_EALPHABET;
+        return nullptr;
+    }
+    bwt_set *h = new (std::nothrow) bwt_set();
+    if (!h) {
+        g_create_error = BWT_ENOMEM;
+        return nullptr;
+    }
+    bool ok = hipGetDevice(&h->device) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&h->pinned, 512 * 8, hipHostMallocDefault) == hipSuccess;
+    ok = ok && dalloc(&h->res, 4) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        g_create_error = BWT_EHIP;
+        bwt_set_destroy(h);
+        return nullptr;
+    }
+    for (int b = 0; b < 3; ++b) {
+        if (ensure_index(h, h->buf[b], 1024 * REC_SYMS) != BWT_OK) {
+            g_create_error = BWT_ENOMEM;
+            bwt_set_destroy(h);
+            return nullptr;
+        }
+    }
+    if (launch_index_init(h->buf[0].recs, h->buf[0].sbc, h->buf[0].meta, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        g_create_error = BWT_EHIP;
+        bwt_set_destroy(h);
+        return nullptr;
+    }
+    h->cur = 0;
+    g_create_error = BWT_OK;
+    return h;
+}
+
+void bwt_set_destroy(bwt_set_t h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto &b : h->buf) {
+        dfree(b.recs);
+        dfree(b.sbc);
+        dfree(b.meta);
+    }
+    free_ws(h->ws);
+    dfree(h->first_new);
+    dfree(h->stage_reads);
+    dfree(h->stage_off);
+    dfree(h->cuts);
+    dfree(h->stage_out);
+    dfree(h->res);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    for (auto e : h->timer.pool) (void)hipEventDestroy(e);
+    for (auto &sp : h->timer.open) {
+        (void)hipEventDestroy(sp.a);
+        (void)hipEventDestroy(sp.b);
+    }
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, uint64_t m,
+                   void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (m == 0) return BWT_OK;
+    if (!reads || !offsets) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    Plan P;
+    {
+        Scope sc(h, s, BWT_STAGE_PLAN);
+        rc = plan_input(h, s, reads, offsets, m, h->M, P);
+    }
+    if (rc) {
+        if (h->timer.on) {
+            (void)hipStreamSynchronize(s);
+            timer_collect(h);
+        }
+        return rc;
+    }
+    const uint64_t n_final = h->n + P.total_suffixes;
+    // the two buffers other than the current one receive the blocks
+    int other[2], k = 0;
+    for (int b = 0; b < 3; ++b)
+        if (b != h->cur) other[k++] = b;
+    for (int b : other)
+        if ((rc = ensure_index(h, h->buf[b], n_final))) return rc;
+    if ((rc = ensure_ws(h, max_block(P)))) return rc;
+    Workspace &w = h->ws;
+    if ((rc = clear_err(h, s))) return rc;
+
+    // block b reads the index written by block b-1 (the current one for
+    // b = 0) and writes other[b & 1]
+    int src = h->cur;
+    uint64_t n_cur = h->n;
+    const size_t K = P.cut_j.size() - 1;
+    for (size_t b = 0; b < K; ++b) {
+        const uint64_t j0 = P.cut_j[b], j1 = P.cut_j[b + 1];
+        const uint32_t m_blk = (uint32_t)(j1 - j0);
+        const uint32_t n_blk = (uint32_t)(P.cut_s[b + 1] - P.cut_s[b]);
+        const uint64_t *off = P.off + j0;
+        uint32_t *sa = nullptr;
+        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, &sa))) return rc;
+        IndexBuf &S = h->buf[src];
+        {
+            Scope sc(h, s, BWT_STAGE_RANKS);
+            Scope sk(h, s, SPAN_RANKS_K, n_blk - m_blk);
+            HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, S.recs, S.sbc, S.meta,
+                                           n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, s));
+        }
+        {
+            Scope sc(h, s, BWT_STAGE_GATHER);
+            HIPCHK(h, launch_gather(sa, w.g, n_blk, w.bint, w.gsa, s));
+        }
+        const int dst = other[b & 1];
+        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, w.bint, w.gsa, n_blk, false)))
+            return rc;
+        n_cur += n_blk;
+        h->timer.acc.blocks += 1;
+        src = dst;
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (h->timer.on) timer_collect(h);
+    if ((rc = check_err(h, s))) return rc;
+    h->cur = src;
+    h->n = n_final;
+    h->m += m;
+    return BWT_OK;
+}
+
+uint64_t bwt_set_rank(bwt_set_t h, char c, uint64_t k) {
+    if (!h) return UINT64_MAX;
+    if (h->broken) {
+        fail(h, BWT_ESTATE);
+        return UINT64_MAX;
+    }
+    if (!(c == 'A' || c == 'C' || c == 'G' || c == 'T' || c == '$') || k > h->n) {
+        fail(h, BWT_EINVAL);
+        return UINT64_MAX;
+    }
+    if (set_device(h)) return UINT64_MAX;
+    // device scratch: res[0] = query k, res[1] = result, byte query in res[2]
+    uint64_t *hp = h->pinned;
+    hp[0] = k;
+    hp[2] = (uint64_t)(uint8_t)c;
+    IndexBuf &B = h->buf[h->cur];
+    if (hipMemcpyAsync(h->res, hp, 3 * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        launch_rank_many(B.recs, B.sbc, B.meta, reinterpret_cast<const uint8_t *>(h->res + 2),
+                         h->res, h->res + 1, 1, h->stream) != hipSuccess ||
+        hipMemcpyAsync(hp + 8, h->res + 1, 8, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(h, BWT_EHIP);
+        return UINT64_MAX;
+    }
+    return hp[8];
+}
+
+int bwt_set_rank_many(bwt_set_t h, const uint8_t *cs, const uint64_t *ks, uint64_t *out,
+                      uint64_t count, void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (count == 0) return BWT_OK;
+    if (!cs || !ks || !out) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    IndexBuf &B = h->buf[h->cur];
+    HIPCHK(h, launch_rank_many(B.recs, B.sbc, B.meta, cs, ks, out, count, s));
+    return BWT_OK;
+}
+
+int64_t bwt_set_export(bwt_set_t h, uint8_t *out) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (!out || h->n == 0) return (int64_t)h->n;
+    int rc = set_device(h);
+    if (rc) return rc;
+    IndexBuf &B = h->buf[h->cur];
+    if (is_device_ptr(out)) {
+        HIPCHK(h, launch_export(B.recs, h->n, out, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return (int64_t)h->n;
+    }
+    if ((rc = ensure_buf(h, h->stage_out, h->stage_out_cap, h->n))) return rc;
+    HIPCHK(h, launch_export(B.recs, h->n, h->stage_out, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out, h->stage_out, h->n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return (int64_t)h->n;
+}
+
+int bwt_set_size(bwt_set_t h, uint64_t *n, uint64_t *m) {
+    if (!h) return BWT_EINVAL;
+    if (n) *n = h->n;
+    if (m) *m = h->m;
+    return BWT_OK;
+}
+
+int bwt_set_reset(bwt_set_t h) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    int rc = set_device(h);
+    if (rc) return rc;
+    IndexBuf &B = h->buf[h->cur];
+    HIPCHK(h, launch_index_init(B.recs, B.sbc, B.meta, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->n = 0;
+    h->m = 0;
+    return BWT_OK;
+}
+
+int bwt_set_set_block_size(bwt_set_t h, uint64_t M) {
+    if (!h) return BWT_EINVAL;
+    if (M < 1) return fail(h, BWT_EINVAL);
+    h->M = std::min<uint64_t>(M, MAX_BLOCK);
+    return BWT_OK;
+}
+
+int bwt_set_last_error(bwt_set_t h) { return h ? h->last_error : g_create_error; }
+
+const char *bwt_set_strerror(int code) {
+    switch (code) {
+    case BWT_OK: return "ok";
+    case BWT_EINVAL: return "invalid argument";
+    case BWT_ENOMEM: return "out of device memory";
+    case BWT_EHIP: return "HIP runtime error";
+    case BWT_EALPHABET: return "unsupported alphabet (only \"ACGT\")";
+    case BWT_ESTATE: return "handle unusable after an earlier HIP error";
+    default: return "unknown error";
+    }
+}
+
+int bwt_set_block_sort(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, uint64_t m,
+                       uint32_t *sa_out, uint8_t *bint_out, void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (m == 0) return BWT_OK;
+    if (!reads || !offsets || !sa_out || !bint_out) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    Plan P;
+    if ((rc = plan_input(h, s, reads, offsets, m, MAX_BLOCK, P))) return rc;
+    if (P.total_suffixes > MAX_BLOCK) return fail(h, BWT_EINVAL);
+    if ((rc = ensure_ws(h, P.total_suffixes))) return rc;
+    if ((rc = clear_err(h, s))) return rc;
+    uint32_t *sa = nullptr;
+    const uint32_t n_blk = (uint32_t)P.total_suffixes;
+    if ((rc = block_sort(h, s, P.reads, P.off, (uint32_t)m, n_blk, &sa))) return rc;
+    // B_int from the value bits, then the plain suffix array
+    HIPCHK(h, launch_gather(sa, h->ws.g, n_blk, bint_out, h->ws.gsa, s));
+    HIPCHK(h, launch_sa_strip(sa, n_blk, sa_out, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (h->timer.on) timer_collect(h);
+    return check_err(h, s);
+}
+
+int bwt_set_compute_ranks(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, uint64_t m,
+                          uint64_t *g_out, void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (m == 0) return BWT_OK;
+    if (!reads || !offsets || !g_out) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    Plan P;
+    if ((rc = plan_input(h, s, reads, offsets, m, MAX_BLOCK, P))) return rc;
+    if (P.total_suffixes > MAX_BLOCK) return fail(h, BWT_EINVAL);
+    if ((rc = ensure_ws(h, P.total_suffixes))) return rc;
+    IndexBuf &B = h->buf[h->cur];
+    HIPCHK(h, launch_block_soff(P.off, (uint32_t)m, h->ws.soff, s));
+    {
+        Scope sk(h, s, SPAN_RANKS_K, P.total_suffixes - m);
+        HIPCHK(h, launch_compute_ranks(P.reads, P.off, h->ws.soff, (uint32_t)m, B.recs, B.sbc,
+                                       B.meta, h->n >= (1ull << SB_SHIFT) ? 1 : 0, g_out, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (h->timer.on) timer_collect(h);
+    return BWT_OK;
+}
+
+int bwt_set_insert(bwt_set_t h, const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
+                   void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (n_new == 0) return BWT_OK;
+    if (!bint || !gsa || n_new > MAX_BLOCK) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    const uint64_t n_final = h->n + n_new;
+    int dst = (h->cur + 1) % 3;
+    if ((rc = ensure_index(h, h->buf[dst], n_final))) return rc;
+    if ((rc = ensure_ws(h, n_new))) return rc;
+    if ((rc = clear_err(h, s))) return rc;
+    if ((rc = insert_block(h, s, h->buf[h->cur], h->buf[dst], h->n, bint, gsa, n_new, true)))
+        return rc;
+    // the number of terminators merged in comes from the new counts
+    HIPCHK(h, hipMemcpyAsync(h->pinned, h->buf[dst].meta, META_WORDS * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (h->timer.on) timer_collect(h);
+    uint64_t new_n = h->pinned[4], new_m = h->pinned[5];
+    if ((rc = check_err(h, s))) return rc;
+    h->cur = dst;
+    h->n = new_n;
+    h->m = new_m;
+    return BWT_OK;
+}
+
+int bwt_set_enable_timing(bwt_set_t h, int on) {
+    if (!h) return BWT_EINVAL;
+    h->timer.on = on != 0;
+    return BWT_OK;
+}
+
+int bwt_set_get_stats(bwt_set_t h, bwt_stats_t *out, int reset) {
+    if (!h || !out) return BWT_EINVAL;
+    *out = h->timer.acc;
+    if (reset) memset(&h->timer.acc, 0, sizeof h->timer.acc);
+    return BWT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,347 @@
+// k_insert.hip -- Insert of Algorithm 1 / Section 5 and the rebuild of the
+// occurrence counters, as one streaming merge from the old index into a new
+// one in HBM.
+//
+// New symbol i (in suffix order) lands at output row g_sa[i] + i: g_sa is
+// non-decreasing, so g_sa[i] + i is strictly increasing, and old row r lands at
+// r + |{i : g_sa[i] <= r}|.  The output is cut into tiles of 16 records (2048
+// rows); a tile finds by binary search how many new symbols precede it (a0),
+// so it knows that old rows o0 = q0 - a0 ... follow, marks its new rows in an
+// LDS bitmap, and fills every row from either B_int or the old records.  The
+// counts stored in each record follow from the counts at the tile start,
+//   count(c, q0) = rank(c, o0, B_ext) + rank(c, a0, B_int),
+// plus popcounts inside the tile, so tiles never wait on each other.
+// rank(c, a, B_int) comes from counts sampled every 64 symbols of B_int.
+#include "dev_util.hpp"
+
+namespace bwt {
+
+namespace {
+
+// ASCII symbol -> 0..3 for A,C,G,T, 4 for '$', 5 otherwise
+__device__ __forceinline__ int code_of_ascii(uint8_t ch) {
+    switch (ch) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'T': return 3;
+    case '$': return 4;
+    default: return 5;
+    }
+}
+
+__global__ void index_init_kernel(Rec *recs, uint64_t *sbc, uint64_t *meta) {
+    int t = threadIdx.x;
+    if (t < 16) reinterpret_cast<uint32_t *>(recs)[t] = 0;
+    if (t < 4) sbc[t] = 0;
+    if (t < META_WORDS) meta[t] = 0;
+}
+
+// bcnt[k*4 + c] = occurrences of c in bint[0 .. 64k) for k = 0 .. ceil(n/64)
+// (the last entry holds the totals).  Tile of 4096 symbols = 64 chunks, one
+// look-back chain per base.  Any byte outside "ACGT$" sets *bad.
+__global__ __launch_bounds__(256) void count_bint_kernel(const uint8_t *__restrict__ bint,
+                                                         uint32_t n, uint32_t *__restrict__ bcnt,
+                                                         uint64_t *__restrict__ status,
+                                                         uint32_t *__restrict__ counter,
+                                                         uint32_t ntiles, uint32_t epoch,
+                                                         uint32_t *__restrict__ bad,
+                                                         uint32_t *__restrict__ err) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wtot[4][4];
+    __shared__ uint32_t s_pre[4];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint32_t tile = acquire_tile(counter, ntiles, &s_tile);
+    if (tile >= ntiles) {
+        if (tid == 0) atomicOr(err, 2u);
+        return;
+    }
+    const uint64_t wbase = (uint64_t)tile * SCAN_TILE + (uint64_t)wave * 1024;
+    uint32_t run[4] = {0, 0, 0, 0};
+    uint32_t loc[16][4];
+    bool badl = false;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        uint64_t x = wbase + (uint64_t)e * 64 + lane;
+        int c = x < n ? code_of_ascii(bint[x]) : 6;
+        badl |= (c == 5);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            loc[e][b] = run[b];
+            run[b] += (uint32_t)__popcll(__ballot(c == b));
+        }
+    }
+    if (badl) atomicOr(bad, 1u);
+    // the counts are uniform across the wave; lane b < 4 keeps base b
+    auto pick = [lane](const uint32_t *v) {
+        return lane == 0 ? v[0] : lane == 1 ? v[1] : lane == 2 ? v[2] : v[3];
+    };
+    if (lane < 4) s_wtot[wave][lane] = pick(run);
+    __syncthreads();
+    if (wave == 0 && lane < 4) {
+        uint32_t tot = s_wtot[0][lane] + s_wtot[1][lane] + s_wtot[2][lane] + s_wtot[3][lane];
+        uint32_t p = lookback(status + lane, 4u, tile, epoch, tot, OpSum(), 0u, err);
+        s_pre[lane] = p;
+        if (tile == ntiles - 1) {
+            uint64_t nch = div_up(n, 64);
+            bcnt[nch * 4 + lane] = p + tot;
+        }
+    }
+    __syncthreads();
+    if (lane < 4) {
+        uint32_t wpre = s_pre[lane];
+        for (int w = 0; w < wave; ++w) wpre += s_wtot[w][lane];
+        for (int e = 0; e < 16; ++e) {
+            uint64_t x0 = wbase + (uint64_t)e * 64;
+            if (x0 < n) bcnt[(x0 >> 6) * 4 + lane] = wpre + pick(loc[e]);
+        }
+    }
+}
+
+__global__ void check_gsa_kernel(const uint64_t *__restrict__ gsa, uint64_t n_new, uint64_t n_ext,
+                                 uint32_t *__restrict__ bad) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_new) return;
+    uint64_t v = gsa[i];
+    if (v > n_ext || (i > 0 && gsa[i - 1] > v)) atomicOr(bad, 2u);
+}
+
+// first_new[t] = number of new symbols whose output row is below t * 2048
+__global__ void ins_tile_first_kernel(const uint64_t *__restrict__ gsa, uint64_t n_new,
+                                      uint64_t ntiles, uint64_t *__restrict__ first_new) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    uint64_t Q = t * INS_TILE_SYMS;
+    uint64_t lo = 0, hi = n_new;
+    while (lo < hi) {  // first i with gsa[i] + i >= Q
+        uint64_t mid = (lo + hi) >> 1;
+        if (gsa[mid] + mid >= Q) hi = mid;
+        else lo = mid + 1;
+    }
+    first_new[t] = lo;
+}
+
+__device__ uint64_t rank_bint(const uint8_t *__restrict__ bint, const uint32_t *__restrict__ bcnt,
+                              uint64_t a, int c) {
+    uint64_t r = bcnt[(a >> CHUNK_SHIFT) * 4 + c];
+    for (uint64_t x = a & ~63ull; x < a; ++x) r += (code_of_ascii(bint[x]) == c);
+    return r;
+}
+
+// New totals, n, m and superblock base counts of the merged index (one
+// thread; the number of superblocks is n / 2^32 + 1).
+__global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
+                                const uint64_t *__restrict__ ometa,
+                                const uint8_t *__restrict__ bint, const uint32_t *__restrict__ bcnt,
+                                const uint64_t *__restrict__ gsa, uint64_t n_new,
+                                uint64_t *__restrict__ nsbc, uint64_t *__restrict__ nmeta) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t nch = div_up(n_new, 64);
+    uint64_t add = 0;
+    for (int c = 0; c < 4; ++c) {
+        uint64_t t = bcnt[nch * 4 + c];
+        nmeta[c] = ometa[c] + t;
+        add += t;
+    }
+    const uint64_t n_out = ometa[4] + n_new;
+    nmeta[4] = n_out;
+    nmeta[5] = ometa[5] + (n_new - add);
+    nmeta[6] = 0;
+    nmeta[7] = 0;
+    const uint64_t nsb = (n_out >> SB_SHIFT) + 1;
+    for (int c = 0; c < 4; ++c) nsbc[c] = 0;
+    for (uint64_t sb = 1; sb < nsb; ++sb) {
+        uint64_t Q = sb << SB_SHIFT;
+        uint64_t lo = 0, hi = n_new;
+        while (lo < hi) {
+            uint64_t mid = (lo + hi) >> 1;
+            if (gsa[mid] + mid >= Q) hi = mid;
+            else lo = mid + 1;
+        }
+        uint64_t o = Q - lo;
+        for (int c = 0; c < 4; ++c)
+            nsbc[sb * 4 + c] = rank_base(orecs, osbc, o, c, true) + rank_bint(bint, bcnt, lo, c);
+    }
+}
+
+__global__ __launch_bounds__(256) void insert_kernel(
+    const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
+    const uint8_t *__restrict__ bint, const uint32_t *__restrict__ bcnt,
+    const uint64_t *__restrict__ gsa, const uint64_t *__restrict__ first_new,
+    Rec *__restrict__ nrecs, const uint64_t *__restrict__ nsbc, uint64_t n_out, uint64_t nrec_out,
+    uint64_t nrec_in, uint32_t *__restrict__ err) {
+    __shared__ uint32_t s_bm[INS_TILE_SYMS / 32];
+    __shared__ uint8_t s_new[INS_TILE_SYMS];
+    __shared__ uint64_t s_old[(INS_TILE_RECS + 1) * 6];
+    __shared__ alignas(16) uint8_t s_lo[256];
+    __shared__ alignas(16) uint8_t s_hi[256];
+    __shared__ alignas(16) uint8_t s_dl[256];
+    __shared__ uint32_t s_rc[INS_TILE_RECS][4];
+    __shared__ uint64_t s_base[4];
+    __shared__ uint32_t s_tmp[4];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint64_t t = blockIdx.x;
+    const uint64_t R0 = t * INS_TILE_RECS;
+    const uint64_t nrec = (nrec_out - R0) < (uint64_t)INS_TILE_RECS ? (nrec_out - R0) : INS_TILE_RECS;
+    const uint64_t q0 = R0 * REC_SYMS;
+    const uint64_t q1 = (q0 + INS_TILE_SYMS) < n_out ? (q0 + INS_TILE_SYMS) : n_out;
+    const uint64_t a0 = first_new[t], a1 = first_new[t + 1];
+    const uint64_t o0 = q0 - a0;                     // old rows before the tile
+    const uint64_t nold = (q1 - q0) - (a1 - a0);     // old rows inside it
+    const uint64_t r_lo = o0 >> REC_SHIFT;
+    uint32_t nr_old = nold ? (uint32_t)(((o0 + nold - 1) >> REC_SHIFT) - r_lo + 1) : 0u;
+    // a consistent split never trips these; they keep a broken one in bounds
+    if (a1 < a0 || a1 - a0 > INS_TILE_SYMS || nr_old > INS_TILE_RECS + 1 ||
+        (nr_old && r_lo + nr_old > nrec_in)) {
+        if (tid == 0) atomicOr(err, 32u);
+        return;
+    }
+
+    if (tid < (int)(INS_TILE_SYMS / 32)) s_bm[tid] = 0;
+    if (tid < (int)nr_old * 6) {
+        const uint64_t *rw = reinterpret_cast<const uint64_t *>(orecs + r_lo + tid / 6);
+        s_old[tid] = rw[2 + tid % 6];
+    }
+    __syncthreads();
+    for (uint64_t i = a0 + tid; i < a1; i += 256) {
+        uint64_t pos = gsa[i] + i - q0;
+        if (pos < INS_TILE_SYMS) atomicOr(&s_bm[pos >> 5], 1u << (pos & 31));
+        else atomicOr(err, 32u);
+        s_new[i - a0] = (uint8_t)code_of_ascii(bint[i]);
+    }
+    if (wave == 1) {
+        // counts at the tile start: old part by a rank on B_ext, new part from
+        // the sampled B_int counts plus the < 64 symbols since the sample
+        uint64_t x = (a0 & ~63ull) + lane;
+        int c = x < a0 ? code_of_ascii(bint[x]) : 6;
+        uint32_t cA = __popcll(__ballot(c == 0)), cC = __popcll(__ballot(c == 1));
+        uint32_t cG = __popcll(__ballot(c == 2)), cT = __popcll(__ballot(c == 3));
+        if (lane < 4) {
+            uint32_t part = lane == 0 ? cA : lane == 1 ? cC : lane == 2 ? cG : cT;
+            s_base[lane] = (uint64_t)bcnt[(a0 >> CHUNK_SHIFT) * 4 + lane] + part +
+                           rank_base(orecs, osbc, o0, lane, true);
+        }
+    }
+    __syncthreads();
+    // this thread's 8 output rows: q0 + 8*tid .. +7
+    const uint32_t byte = (s_bm[tid >> 2] >> (8 * (tid & 3))) & 255u;
+    uint32_t tot;
+    uint32_t nb = block_excl_sum256((uint32_t)__popc(byte), s_tmp, &tot);
+    uint64_t ob = o0 + 8ull * tid - nb - r_lo * REC_SYMS;  // old row, relative to record r_lo
+    uint32_t lo_b = 0, hi_b = 0, dl_b = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        uint64_t q = q0 + 8ull * tid + u;
+        if (q < q1) {
+            int sym;
+            if ((byte >> u) & 1u) {
+                sym = s_new[nb < INS_TILE_SYMS ? nb : INS_TILE_SYMS - 1];
+                ++nb;
+            } else {
+                uint32_t rr = (uint32_t)(ob >> REC_SHIFT), bit = (uint32_t)(ob & 127), w = bit >> 6,
+                         b = bit & 63;
+                ++ob;
+                if (rr > INS_TILE_RECS) rr = INS_TILE_RECS;
+                const uint64_t *R = s_old + rr * 6;
+                sym = ((R[4 + w] >> b) & 1) ? 4 : (int)(((R[w] >> b) & 1) | (((R[2 + w] >> b) & 1) << 1));
+            }
+            if (sym == 4) dl_b |= 1u << u;
+            else {
+                lo_b |= (uint32_t)(sym & 1) << u;
+                hi_b |= (uint32_t)(sym >> 1) << u;
+            }
+        }
+    }
+    s_lo[tid] = (uint8_t)lo_b;
+    s_hi[tid] = (uint8_t)hi_b;
+    s_dl[tid] = (uint8_t)dl_b;
+    __syncthreads();
+    if (tid < INS_TILE_RECS * 4) {
+        int r = tid >> 2, c = tid & 3;
+        uint64_t rq = q0 + (uint64_t)r * REC_SYMS;
+        uint64_t valid = rq < q1 ? (q1 - rq < REC_SYMS ? q1 - rq : REC_SYMS) : 0;
+        const uint64_t *L = reinterpret_cast<const uint64_t *>(s_lo + 16 * r);
+        const uint64_t *H = reinterpret_cast<const uint64_t *>(s_hi + 16 * r);
+        const uint64_t *D = reinterpret_cast<const uint64_t *>(s_dl + 16 * r);
+        uint64_t v0 = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+        uint64_t v1 = valid > 64 ? (valid >= 128 ? ~0ull : ((1ull << (valid - 64)) - 1ull)) : 0ull;
+        s_rc[r][c] = (uint32_t)(__popcll(match_bits(L[0], H[0], D[0], c) & v0) +
+                                __popcll(match_bits(L[1], H[1], D[1], c) & v1));
+    }
+    __syncthreads();
+    if (tid < 4) {
+        uint32_t run = 0;
+        for (int r = 0; r < INS_TILE_RECS; ++r) {
+            uint32_t x = s_rc[r][tid];
+            s_rc[r][tid] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    const int r = tid >> 4, w = tid & 15;
+    if ((uint64_t)r < nrec) {
+        const uint64_t R = R0 + r;
+        uint32_t val;
+        if (w < 4) {
+            uint64_t abs = s_base[w] + s_rc[r][w];
+            val = (uint32_t)(abs - nsbc[((R * REC_SYMS) >> SB_SHIFT) * 4 + w]);
+        } else {
+            const uint8_t *plane = (w < 8) ? s_lo : (w < 12) ? s_hi : s_dl;
+            val = *reinterpret_cast<const uint32_t *>(plane + 16 * r + 4 * ((w - 4) & 3));
+        }
+        reinterpret_cast<uint32_t *>(nrecs)[R * 16 + w] = val;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream_t s) {
+    index_init_kernel<<<1, 64, 0, s>>>(recs, sbc, meta);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_bint(const uint8_t *bint, uint32_t n, uint32_t *bcnt, uint64_t *status,
+                             uint32_t *counter, uint32_t epoch, uint32_t *bad, uint32_t *err,
+                             hipStream_t s) {
+    uint32_t ntiles = (uint32_t)div_up(n, SCAN_TILE);
+    if (ntiles == 0) return hipSuccess;
+    count_bint_kernel<<<ntiles, 256, 0, s>>>(bint, n, bcnt, status, counter, ntiles, epoch, bad,
+                                             err);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_gsa(const uint64_t *gsa, uint64_t n_new, uint64_t n_ext, uint32_t *bad,
+                            hipStream_t s) {
+    if (n_new == 0) return hipSuccess;
+    check_gsa_kernel<<<(unsigned)div_up(n_new, 256), 256, 0, s>>>(gsa, n_new, n_ext, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_ins_tile_first(const uint64_t *gsa, uint64_t n_new, uint64_t ntiles,
+                                 uint64_t *first_new, hipStream_t s) {
+    ins_tile_first_kernel<<<(unsigned)div_up(ntiles + 1, 256), 256, 0, s>>>(gsa, n_new, ntiles,
+                                                                           first_new);
+    return hipGetLastError();
+}
+
+hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
+                           const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
+                           uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta, hipStream_t s) {
+    ins_meta_kernel<<<1, 64, 0, s>>>(orecs, osbc, ometa, bint, bcnt, gsa, n_new, nsbc, nmeta);
+    return hipGetLastError();
+}
+
+hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
+                         const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
+                         uint64_t n_new, const uint64_t *first_new, Rec *nrecs,
+                         const uint64_t *nsbc, uint32_t *err, hipStream_t s) {
+    const uint64_t n_out = n_ext + n_new;
+    const uint64_t nrec_out = records_for(n_out);
+    const uint64_t ntiles = div_up(nrec_out, INS_TILE_RECS);
+    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(orecs, osbc, bint, bcnt, gsa, first_new, nrecs,
+                                                   nsbc, n_out, nrec_out, records_for(n_ext), err);
+    return hipGetLastError();
+}
+
+}  // namespace bwt

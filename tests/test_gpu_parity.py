@@ -1,0 +1,313 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, through the
+C ABI.  Integer work, so the bar is bit-exact equality everywhere."""
+import random
+
+import numpy as np
+import pytest
+
+from paper_1410_0562_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def B(torch_dev):
+    from paper_1410_0562_amd import bwtset
+    return bwtset
+
+
+def _pins():
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "set_bwt_pins.tsv")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip("\n"):
+                continue
+            reads_s, Bs, _ = line.rstrip("\n").split("\t")
+            rows.append((reads_s.split(","), Bs))
+    return rows
+
+
+def _dev(torch, arr, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(arr).view(np.int64) if arr.dtype == np.uint64
+                         else np.ascontiguousarray(arr))
+    return t.cuda()
+
+
+def _oracle_inputs(O, packed, offsets):
+    codes, offs = O.reads_from_packed(packed, offsets)
+    return codes, offs
+
+
+@pytest.mark.parametrize("row", _pins(), ids=lambda r: ",".join(r[0]) or "empty")
+def test_pins_host_inputs(B, oracle_mod, row):
+    reads, want = row
+    packed, offs = synth.strings_to_input(reads)
+    with B.BwtSet() as idx:
+        idx.append(packed, offs)
+        assert idx.export().decode() == want
+        assert idx.size() == (len(want), len(reads))
+
+
+def test_pins_device_inputs(B, torch_dev, oracle_mod):
+    for reads, want in _pins():
+        packed, offs = synth.strings_to_input(reads)
+        with B.BwtSet() as idx:
+            idx.append(_dev(torch_dev, np.concatenate([packed, np.zeros(8, np.uint8)])),
+                       _dev(torch_dev, offs))
+            assert idx.export().decode() == want, reads
+
+
+def _random_set(rng, m, lo, hi, alpha="ACGT"):
+    return ["".join(rng.choice(alpha) for _ in range(rng.randint(lo, hi))) for _ in range(m)]
+
+
+def test_random_small_sets(B, oracle_mod):
+    rng = random.Random(20)
+    for trial in range(40):
+        reads = _random_set(rng, rng.randint(1, 60), 0, rng.choice([3, 12, 40]),
+                            rng.choice(["ACGT", "AC", "A", "GT"]))
+        packed, offs = synth.strings_to_input(reads)
+        with B.BwtSet(block_size=rng.randint(1, 200)) as idx:
+            idx.append(packed, offs)
+            got = idx.export()
+        assert got == oracle_mod.bwt(reads), (trial, reads)
+
+
+def test_uniform_reads_workload(B, oracle_mod):
+    # 10,000 reads x 100 bp, block size 262,144 suffixes (4 blocks, ragged last)
+    packed, offs = synth.uniform_reads()
+    codes, o = _oracle_inputs(oracle_mod, packed, offs)
+    want = oracle_mod.bwt_of_codes(codes, o)
+    with B.BwtSet(block_size=262_144) as idx:
+        idx.enable_timing(True)
+        idx.append(packed, offs)
+        got = idx.export()
+        st = idx.stats()
+    assert st["blocks"] == 4
+    assert got == want
+
+
+def test_block_sort_vs_oracle(B, torch_dev, oracle_mod):
+    torch = torch_dev
+    cases = [
+        synth.random_reads(31, 2595, 100, 100),            # one block of the 10k x 100 workload
+        synth.random_reads(32, 3000, 0, 300),              # ragged, empty reads included
+        synth.random_reads(33, 500, 0, 40, alphabet=2),    # long common prefixes
+        synth.short_reads(m=20_000, length=100, ref_len=200_000, seed=34),  # 10x coverage
+    ]
+    for packed, offs in cases:
+        codes, o = _oracle_inputs(oracle_mod, packed, offs)
+        sa_want, T = oracle_mod.construct_sa(codes, o)
+        bint_want = oracle_mod.b_int(T, sa_want)
+        n = len(T)
+        sa = torch.empty(n, dtype=torch.int32, device="cuda")
+        bint = torch.empty(n, dtype=torch.uint8, device="cuda")
+        with B.BwtSet() as idx:
+            idx.block_sort(packed, offs, sa, bint)
+        assert np.array_equal(sa.cpu().numpy().astype(np.uint64), sa_want)
+        assert bint.cpu().numpy().tobytes() == bint_want
+
+
+def test_block_sort_repeats(B, torch_dev, oracle_mod):
+    # identical reads and reads that are shifts of one long string: long LCPs,
+    # many prefix-doubling rounds, groups spanning several scan tiles
+    torch = torch_dev
+    rng = np.random.default_rng(35)
+    ref = rng.integers(0, 4, 3000, dtype=np.uint8)
+    reads = []
+    for k in range(400):
+        a = int(rng.integers(0, 200))
+        reads.append(ref[a:a + 2500])
+    for k in range(5000):
+        reads.append(ref[:37])
+    codes = np.concatenate(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(r) for r in reads])
+    packed = synth.pack_codes(codes)
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    sa_want, T = oracle_mod.construct_sa(c1, o1)
+    n = len(T)
+    sa = torch.empty(n, dtype=torch.int32, device="cuda")
+    bint = torch.empty(n, dtype=torch.uint8, device="cuda")
+    with B.BwtSet() as idx:
+        idx.block_sort(packed, offs, sa, bint)
+    assert np.array_equal(sa.cpu().numpy().astype(np.uint64), sa_want)
+    assert bint.cpu().numpy().tobytes() == oracle_mod.b_int(T, sa_want)
+
+
+def _split(packed, offs, j):
+    return synth.take_reads(packed, offs, 0, j), synth.take_reads(packed, offs, j, len(offs) - 1)
+
+
+def test_compute_ranks_vs_oracle(B, torch_dev, oracle_mod):
+    torch = torch_dev
+    packed, offs = synth.short_reads(m=12_000, length=100, ref_len=300_000, seed=36)
+    (pa, oa), (pb, ob) = _split(packed, offs, 9_000)
+    ca, oa2 = _oracle_inputs(oracle_mod, pa, oa)
+    B_ext = oracle_mod.bwt_of_codes(ca, oa2)
+    cb, ob2 = _oracle_inputs(oracle_mod, pb, ob)
+    T, soff = oracle_mod.concat_text(cb, ob2)
+    want = oracle_mod.compute_ranks(B_ext, T, soff)
+    g = torch.empty(len(T), dtype=torch.int64, device="cuda")
+    with B.BwtSet() as idx:
+        idx.append(pa, oa)
+        assert idx.export() == B_ext
+        idx.compute_ranks(pb, ob, g)
+    assert np.array_equal(g.cpu().numpy().astype(np.uint64), want)
+
+
+def test_insert_vs_oracle(B, torch_dev, oracle_mod):
+    torch = torch_dev
+    packed, offs = synth.random_reads(37, 5000, 20, 180)
+    (pa, oa), (pb, ob) = _split(packed, offs, 3000)
+    ca, oa2 = _oracle_inputs(oracle_mod, pa, oa)
+    B_ext = oracle_mod.bwt_of_codes(ca, oa2)
+    cb, ob2 = _oracle_inputs(oracle_mod, pb, ob)
+    sa_int, T = oracle_mod.construct_sa(cb, ob2)
+    bint = oracle_mod.b_int(T, sa_int)
+    _, soff = oracle_mod.concat_text(cb, ob2)
+    g = oracle_mod.compute_ranks(B_ext, T, soff)
+    gsa = oracle_mod.reorder(g, sa_int)
+    want = oracle_mod.insert(B_ext, bint, gsa)
+    codes_all, o_all = _oracle_inputs(oracle_mod, packed, offs)
+    assert want == oracle_mod.bwt_of_codes(codes_all, o_all)
+    with B.BwtSet() as idx:
+        idx.append(pa, oa)
+        idx.insert(_dev(torch, np.frombuffer(bint, np.uint8).copy()), _dev(torch, gsa))
+        assert idx.export() == want
+        assert idx.size() == (len(want), 5000)
+
+
+def test_rank_queries(B, torch_dev, oracle_mod):
+    torch = torch_dev
+    packed, offs = synth.random_reads(38, 3000, 0, 150)
+    codes, o = _oracle_inputs(oracle_mod, packed, offs)
+    Bw = oracle_mod.bwt_of_codes(codes, o)
+    n = len(Bw)
+    rng = np.random.default_rng(39)
+    ks = np.concatenate([[0, 1, 127, 128, 129, n - 1, n], rng.integers(0, n + 1, 500)]).astype(np.int64)
+    with B.BwtSet() as idx:
+        idx.append(packed, offs)
+        tables = {c: oracle_mod.bwt_rank_all(Bw, c) for c in "$ACGT"}
+        for c in "$ACGT":
+            for k in ks[:40]:
+                assert idx.rank(c, int(k)) == int(tables[c][k])
+        cs = np.array([ord(c) for c in "$ACGT"] * len(ks), np.uint8)
+        kk = np.repeat(ks, 5)
+        out = torch.empty(len(kk), dtype=torch.int64, device="cuda")
+        idx.rank_many(_dev(torch, cs), _dev(torch, kk), out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        want = np.array([tables[chr(c)][k] for c, k in zip(cs, kk)], dtype=np.int64)
+        assert np.array_equal(got, want)
+
+
+def test_blocking_and_append_split_invariance(B, oracle_mod):
+    packed, offs = synth.random_reads(40, 4000, 0, 120)
+    codes, o = _oracle_inputs(oracle_mod, packed, offs)
+    want = oracle_mod.bwt_of_codes(codes, o)
+    for M in (1, 97, 4096, 1 << 20):
+        with B.BwtSet(block_size=M) as idx:
+            idx.append(packed, offs)
+            assert idx.export() == want, M
+    with B.BwtSet(block_size=5000) as idx:
+        for j0, j1 in ((0, 1), (1, 1000), (1000, 1001), (1001, 4000)):
+            p, oo = synth.take_reads(packed, offs, j0, j1)
+            idx.append(p, oo)
+        assert idx.export() == want
+
+
+def test_long_reads(B, oracle_mod):
+    # reads of 5k-60k symbols cut from one reference: long LF walks and long
+    # shared prefixes (many doubling rounds)
+    rng = np.random.default_rng(41)
+    ref = rng.integers(0, 4, 120_000, dtype=np.uint8)
+    reads = []
+    for _ in range(12):
+        a = int(rng.integers(0, 50_000))
+        L = int(rng.integers(5_000, 60_000))
+        r = ref[a:a + L].copy()
+        hit = rng.random(len(r)) < 0.001
+        r[hit] = (r[hit] + 1) & 3
+        reads.append(r)
+    codes = np.concatenate(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(r) for r in reads])
+    packed = synth.pack_codes(codes)
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    want = oracle_mod.bwt_of_codes(c1, o1)
+    with B.BwtSet(block_size=100_000) as idx:
+        idx.append(packed, offs)
+        assert idx.export() == want
+
+
+def test_misaligned_device_reads(B, torch_dev, oracle_mod):
+    # reads starting at an odd symbol offset inside an unaligned device buffer
+    torch = torch_dev
+    packed, offs = synth.random_reads(42, 700, 1, 90)
+    shift = 5  # symbols
+    codes = oracle_mod.unpack_2bit(packed, int(offs[-1]))
+    shifted = synth.pack_codes(np.concatenate([np.zeros(shift, np.uint8), codes]))
+    offs2 = offs + np.uint64(shift)
+    buf = torch.zeros(len(shifted) + 16, dtype=torch.uint8, device="cuda")
+    buf[3:3 + len(shifted)] = torch.from_numpy(shifted).cuda()
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    with B.BwtSet(block_size=9999) as idx:
+        idx.append(buf[3:], _dev(torch, offs2))
+        assert idx.export() == oracle_mod.bwt_of_codes(c1, o1)
+
+
+def test_errors_leave_index_unchanged(B, torch_dev, oracle_mod):
+    torch = torch_dev
+    with pytest.raises(B.BwtSetError) as e:
+        B.BwtSet("ACGU")
+    assert e.value.code == B.BWT_EALPHABET
+    packed, offs = synth.random_reads(43, 200, 0, 50)
+    with B.BwtSet() as idx:
+        idx.append(packed, offs)
+        before = idx.export()
+        bad = offs.copy()
+        bad[5], bad[6] = bad[6] + 3, bad[5]
+        with pytest.raises(B.BwtSetError) as e:
+            idx.append(packed, bad)
+        assert e.value.code == B.BWT_EINVAL
+        with pytest.raises(B.BwtSetError):
+            idx.append(_dev(torch, packed), _dev(torch, bad))
+        n, m = idx.size()
+        with pytest.raises(B.BwtSetError):
+            idx.rank("A", n + 1)
+        with pytest.raises(B.BwtSetError):
+            idx.rank("N", 0)
+        gsa = np.array([3, 2], np.uint64)
+        with pytest.raises(B.BwtSetError):
+            idx.insert(_dev(torch, np.frombuffer(b"A$", np.uint8).copy()), _dev(torch, gsa))
+        with pytest.raises(B.BwtSetError):
+            idx.insert(_dev(torch, np.frombuffer(b"AX", np.uint8).copy()),
+                       _dev(torch, np.array([0, 1], np.uint64)))
+        assert idx.export() == before
+        assert idx.size() == (n, m)
+        idx.reset()
+        assert idx.size() == (0, 0) and idx.export() == b""
+        idx.append(packed, offs)
+        assert idx.export() == before
+
+
+def test_deterministic(B, oracle_mod):
+    packed, offs = synth.short_reads(m=30_000, length=100, ref_len=500_000, seed=44)
+    outs = []
+    for _ in range(2):
+        with B.BwtSet(block_size=1 << 20) as idx:
+            idx.append(packed, offs)
+            outs.append(idx.export())
+    assert outs[0] == outs[1]
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    assert outs[0] == oracle_mod.bwt_of_codes(c1, o1)
