@@ -1,0 +1,209 @@
+"""Benchmark: incremental BWT construction (set-bwte, Algorithm 1) on one GPU.
+
+One step = build the index of the whole short-read workload from empty:
+4,000,000 reads x 100 bp sampled from a random 50 Mbp reference (both strands,
+1% substitutions), appended in blocks of M = 2^26 suffixes (7 blocks), i.e.
+every stage of the hot path -- suffix sort, ComputeRanks, g_sa gather, Insert
+with the occurrence-counter rebuild -- over 400 Mbp.  Inputs are resident in
+HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "input bases indexed/sec (incremental BWT) + HBM GB/s fraction; p99 append latency"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+RANKS_BYTES_PER_STEP = 64 + 8 + 0.25   # one index record, one g write, one 2-bit symbol
+RADIX_BYTES_PER_KEY = 24               # read and write a 64-bit key and a 32-bit value
+INSERT_BYTES_PER_RECORD = 64           # each index record read (old) or written (new)
+INSERT_BYTES_PER_NEW = 9               # one B_int byte and one 64-bit g_sa per new symbol
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def source_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "compute_ranks_kernel": ["paper_1410_0562_amd/csrc/k_ranks.hip",
+                             "paper_1410_0562_amd/csrc/dev_util.hpp"],
+    "radix_pass_kernel": ["paper_1410_0562_amd/csrc/k_radix.hip",
+                          "paper_1410_0562_amd/csrc/dev_util.hpp"],
+    "insert_kernel": ["paper_1410_0562_amd/csrc/k_insert.hip",
+                      "paper_1410_0562_amd/csrc/dev_util.hpp"],
+}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel)
+    if not e or e.get("source_digest") != source_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(packed, offs, nreads):
+    from oracle import oracle
+    from paper_1410_0562_amd import synth
+    p, o = synth.take_reads(packed, offs, 0, nreads)
+    codes, oo = oracle.reads_from_packed(p, o)
+    bases = int(oo[-1])
+    t0 = time.perf_counter()
+    oracle.bwt_of_codes(codes, oo)
+    dt = time.perf_counter() - t0
+    return {"value": bases / dt, "unit": "bases/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d reads (%d bases) of the same workload; single-threaded "
+                      "comparison sort of all suffixes (%.1f s)" % (nreads, bases, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--reads", type=int, default=4_000_000)
+    ap.add_argument("--block", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the per-block path on a single "
+              "MI355X (sharding across GPUs is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1410_0562_amd import bwtset, synth
+
+    if not os.path.exists(bwtset.LIB_PATH):
+        from paper_1410_0562_amd import build
+        build.build()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    if args.calibrate_copy:
+        # a plain copy of known size: the HBM byte counters read on it give the
+        # factor between counter units and bytes moved (1 GiB read + 1 GiB written)
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "launches": 3}))
+        return
+
+    log("generating workload")
+    packed, offs = synth.short_reads(m=args.reads)
+    bases = int(offs[-1]) - int(offs[0])
+    m = len(offs) - 1
+    dev_reads = torch.from_numpy(packed).cuda()
+    dev_offs = torch.from_numpy(offs.view(np.int64)).cuda()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    idx = bwtset.BwtSet(block_size=args.block)
+    for w in range(args.warmup):
+        idx.reset()
+        idx.append(dev_reads, dev_offs, stream)
+        log("warmup %d done" % w)
+    idx.stats(reset=True)
+    idx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        idx.reset()
+        idx.append(dev_reads, dev_offs, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = idx.stats()
+    n, mm = idx.size()
+    assert n == bases + m and mm == m
+    dt = t1 - t0
+    log("timed %d steps in %.3f s" % (args.steps, dt))
+
+    kernels = {}
+    if st["ranks_launches"]:
+        kernels["compute_ranks_kernel"] = (st["ranks_kernel_ms"], st["ranks_launches"],
+                                           st["ranks_steps"] * RANKS_BYTES_PER_STEP)
+    if st["sort_pass_launches"]:
+        kernels["radix_pass_kernel"] = (st["sort_pass_ms"], st["sort_pass_launches"],
+                                        st["sort_pass_keys"] * RADIX_BYTES_PER_KEY)
+    if st["insert_launches"]:
+        kernels["insert_kernel"] = (
+            st["insert_kernel_ms"], st["insert_launches"],
+            (st["insert_records_in"] + st["insert_records_out"]) * INSERT_BYTES_PER_RECORD +
+            st["insert_new_symbols"] * INSERT_BYTES_PER_NEW)
+    kinfo = {}
+    for name, (ms, launches, nbytes) in kernels.items():
+        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        kinfo[name] = {"ms_per_step": ms / args.steps, "launches_per_step": launches / args.steps,
+                       "avg_launch_ms": ms / launches, "bytes_per_launch": nbytes / launches,
+                       "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    dom = max(kinfo, key=lambda k: kinfo[k]["ms_per_step"])
+    d = kinfo[dom]
+    traffic = measured_traffic(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["achieved_GBs"], 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["frac"], 4),
+                "traffic": traffic}
+
+    out = {
+        "metric": METRIC,
+        "value": bases * args.steps / dt,
+        "unit": "bases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "short reads: %d x 100 bp from a random 50 Mbp reference, both "
+                               "strands, 1%% substitutions; block M=%d suffixes" % (m, args.block),
+                   "reads": m, "bases": bases, "block_suffixes": args.block,
+                   "blocks": st["blocks"] // args.steps},
+        "roofline": roofline,
+        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
+        "stages_ms_per_step": {s: round(st["ms"][s] / args.steps, 3) for s in bwtset.STAGES},
+        "doubling_rounds_per_step": st["doubling_rounds"] / args.steps,
+    }
+    idx.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(packed, offs, min(args.cpu_sample_reads, m))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
