@@ -51,20 +51,34 @@ inline uint64_t superblocks_for(uint64_t n) { return (n >> SB_SHIFT) + 1; }
 // code of the symbol before p (0..3) or 4 when p starts a read, so that B_int
 // falls out of the sorted values without a second gather.
 //
-// First sort key of p, with r = number of symbols before the read's
-// terminator and t = min(r, KEY_K):
-//   key = (first t symbols, 2 bits each, first symbol most significant,
-//          zero-padded to KEY_K symbols) << 5 | t
-// Equal keys with t < KEY_K end in their terminators and are ordered by read
-// index, i.e. by position, which the stable sort keeps.
+// First sort key of p.  g[p] (ComputeRanks: old suffixes smaller than the
+// block suffix at p) is non-decreasing in suffix order, so it can lead the
+// key without changing the order, and g_sa comes out of the sort with it:
+//   key = g[p] << (64 - gbits) | sym << 5 | t,
+// gbits = bits needed for values up to n_ext (0 for an empty index),
+// K' = min(29, (59 - gbits) / 2) symbols, r = symbols of p's read before its
+// terminator, t = min(r, K'), sym = the first t symbols, 2 bits each, first
+// symbol most significant, zero-padded to K' symbols.  Equal keys with t < K'
+// end in their terminators and are ordered by read index, i.e. by position,
+// which the stable sort keeps.  Later chunks of 29 symbols at depth d use the
+// same layout without g (chunk keys).
 // ---------------------------------------------------------------------------
-constexpr int KEY_K = 29;
+constexpr int KEY_K = 29;            // symbols in a chunk key
 constexpr int KEY_LEN_BITS = 5;
-constexpr int KEY_BITS0 = 2 * KEY_K + KEY_LEN_BITS;  // 63
 constexpr int POS_BITS = 29;
 constexpr uint32_t POS_MASK = (1u << POS_BITS) - 1u;
 constexpr uint64_t MAX_BLOCK = (1ull << POS_BITS) - 1;  // suffixes per block
 constexpr uint64_t MAX_READ = MAX_BLOCK - 1;            // symbols per read
+
+__host__ __device__ inline int first_key_syms(int gbits) {
+    int k = (64 - KEY_LEN_BITS - gbits) / 2;
+    return k < KEY_K ? k : KEY_K;
+}
+
+// groups of tied suffixes up to this size are finished in LDS by comparing
+// successive chunks; a block with a larger group uses prefix doubling
+constexpr int REFINE_LIMIT = 256;
+constexpr int REFINE_WINDOW = 1024;
 
 constexpr int PREP_TILE_SHIFT = 12;  // positions per read-lookup tile
 constexpr int SCAN_TILE = 4096;      // elements per look-back scan tile
@@ -72,6 +86,12 @@ constexpr int RADIX_TILE = 4096;     // keys per radix pass tile
 constexpr int INS_TILE_RECS = 16;    // output records per Insert tile
 constexpr uint64_t INS_TILE_SYMS = INS_TILE_RECS * REC_SYMS;
 constexpr int CHUNK_SHIFT = 6;       // B_int counts sampled every 64 symbols
+
+__host__ __device__ inline int bits_for_value(uint64_t v) {  // bits to hold 0..v
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
 
 __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
@@ -89,25 +109,33 @@ hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t 
                              uint64_t *status, uint32_t *counter, uint32_t epoch, uint32_t *err,
                              hipStream_t s);
 
-// block preparation and prefix doubling (k_sa.hip)
+// block preparation, suffix sorting and refinement (k_sa.hip)
 hipError_t launch_block_soff(const uint64_t *off, uint32_t m_blk, uint32_t *soff, hipStream_t s);
 hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
                                    uint32_t *tile_first, hipStream_t s);
+// g may be null when gbits == 0
 hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
-                             const uint32_t *tile_first, uint32_t m_blk, uint32_t n_blk,
-                             uint64_t *keys, uint32_t *vals, hipStream_t s);
-// groups after a sort: round 0 (U == nullptr: element i is SA slot i, keys
-// with a short length field are singletons) or a doubling round (element u
-// goes to SA slot U[u]; its value is stored there)
+                             const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
+                             int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s);
+// Groups after a sort.  Round 0 (U == nullptr): element i is SA slot i, and a
+// key whose length field is below kshort is a singleton.  Doubling round:
+// element u is SA slot U[u] and its value is stored there.  rank == nullptr
+// skips the rank scatter.  A group larger than `limit` sets *large.
 hipError_t launch_group_heads(const uint64_t *keys, const uint32_t *vals, const uint32_t *U,
-                              uint32_t n, uint32_t *sa, uint32_t *rank, uint32_t *Uout,
-                              uint32_t *nUout, uint64_t *status, uint32_t *counter,
-                              uint32_t epoch, uint32_t *err, hipStream_t s);
+                              uint32_t n, int kshort, uint32_t *sa, uint32_t *rank,
+                              uint32_t *Uout, uint32_t *nUout, uint32_t limit, uint32_t *large,
+                              uint64_t *status, uint32_t *counter, uint32_t epoch, uint32_t *err,
+                              hipStream_t s);
 hipError_t launch_doubling_keys(const uint32_t *U, uint32_t nU, const uint32_t *sa,
                                 const uint32_t *rank, uint32_t h, int rbits, uint32_t n_blk,
                                 uint64_t *keys, uint32_t *vals, uint32_t *err, hipStream_t s);
-hipError_t launch_gather(const uint32_t *sa, const uint64_t *g, uint32_t n, uint8_t *bint,
-                         uint64_t *gsa, hipStream_t s);
+// finishes every group of U (all of size <= REFINE_LIMIT) by chunk keys
+hipError_t launch_refine(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                         const uint32_t *tile_first, const uint64_t *keys, const uint32_t *U,
+                         uint32_t nU, uint32_t *sa, int kfirst, uint32_t max_iter, uint32_t *err,
+                         hipStream_t s);
+// B_int as ASCII from sorted values, and the plain suffix array
+hipError_t launch_vals_to_ascii(const uint32_t *sa, uint32_t n, uint8_t *bint, hipStream_t s);
 hipError_t launch_sa_strip(const uint32_t *sa, uint32_t n, uint32_t *out, hipStream_t s);
 
 // ComputeRanks (k_ranks.hip)
@@ -115,22 +143,29 @@ hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const
                                 uint32_t m_blk, const Rec *recs, const uint64_t *sbc,
                                 const uint64_t *meta, int big, uint64_t *g, hipStream_t s);
 
-// Insert and index bookkeeping (k_insert.hip)
+// Insert and index bookkeeping (k_insert.hip).  The new symbols come in
+// suffix order as the sorted (key, value) pairs of ConstructSA: g_sa[i] is the
+// top gbits bits of gkeys[i] (0 when gbits == 0) and the symbol code (0..3
+// for A..T, 4 for '$') is vals[i] >> 29.
 hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream_t s);
-hipError_t launch_count_bint(const uint8_t *bint, uint32_t n, uint32_t *bcnt, uint64_t *status,
-                             uint32_t *counter, uint32_t epoch, uint32_t *bad, uint32_t *err,
-                             hipStream_t s);
-hipError_t launch_check_gsa(const uint64_t *gsa, uint64_t n_new, uint64_t n_ext, uint32_t *bad,
-                            hipStream_t s);
-hipError_t launch_ins_tile_first(const uint64_t *gsa, uint64_t n_new, uint64_t ntiles,
-                                 uint64_t *first_new, hipStream_t s);
+hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *bcnt, uint64_t *status,
+                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s);
+// user-supplied B_int (ASCII) and g_sa: *bad |= 1 for a byte outside "ACGT$",
+// 2 for a g_sa that decreases or exceeds n_ext; then packed as keys/values
+hipError_t launch_check_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
+                                   uint64_t n_ext, uint32_t *bad, hipStream_t s);
+hipError_t launch_pack_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
+                                  int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gbits, uint64_t n_new,
+                                 uint64_t ntiles, uint64_t *first_new, hipStream_t s);
 hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
-                           const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
-                           uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta, hipStream_t s);
+                           const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                           const uint32_t *bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
+                           hipStream_t s);
 hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
-                         const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
-                         uint64_t n_new, const uint64_t *first_new, Rec *nrecs,
-                         const uint64_t *nsbc, uint32_t *err, hipStream_t s);
+                         const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                         const uint32_t *bcnt, uint64_t n_new, const uint64_t *first_new,
+                         Rec *nrecs, const uint64_t *nsbc, uint32_t *err, hipStream_t s);
 
 // queries and input checks (k_query.hip)
 hipError_t launch_rank_many(const Rec *recs, const uint64_t *sbc, const uint64_t *meta,

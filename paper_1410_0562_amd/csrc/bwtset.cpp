@@ -61,9 +61,10 @@ struct Workspace {
 constexpr int MISC_CNT_RADIX = 0;
 constexpr int MISC_CNT_HEADS = 1;
 constexpr int MISC_CNT_BINT = 2;
-constexpr int MISC_NU = 4;
-constexpr int MISC_BAD = 5;
-constexpr int MISC_ERR = 6;
+constexpr int MISC_NU = 4;       // followed by MISC_LARGE (read together)
+constexpr int MISC_LARGE = 5;
+constexpr int MISC_BAD = 6;
+constexpr int MISC_ERR = 7;
 constexpr int MISC_HIST = 64;                 // 8*256 + 1 words
 constexpr int MISC_WORDS = MISC_HIST + 8 * 256 + 64;
 
@@ -384,21 +385,56 @@ int check_err(bwt_set *h, hipStream_t s) {
 }
 
 // ---- ConstructSA of one block --------------------------------------------
-// reads/off: device; off points at the block's first read (m_blk + 1
-// entries).  On return *sa_out points at the block's suffix array (values
-// carry the preceding symbol in bits 29..31).
-int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *off,
-               uint32_t m_blk, uint32_t n_blk, uint32_t **sa_out) {
+// soff (block position of each read) and the read-lookup tiles of a block.
+int block_prep(bwt_set *h, hipStream_t s, const uint64_t *off, uint32_t m_blk, uint32_t n_blk) {
     Workspace &w = h->ws;
-    Scope sc(h, s, BWT_STAGE_SORT);
     HIPCHK(h, launch_block_soff(off, m_blk, w.soff, s));
     HIPCHK(h, launch_block_tile_first(w.soff, m_blk, n_blk, w.tile_first, s));
-    HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, m_blk, n_blk, w.kA, w.v[0], s));
+    return BWT_OK;
+}
+
+// Suffix array of one block (after block_prep).  reads/off: device; off
+// points at the block's first read (m_blk + 1 entries).  g (text order, may be
+// null when gbits == 0) leads the first sort key.  On return *sa_out holds the
+// suffix array (values carry the preceding symbol in bits 29..31) and
+// *gkeys_out keys whose top gbits bits are g_sa, both indexed by SA slot.
+int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *off,
+               uint32_t m_blk, uint32_t n_blk, uint64_t maxlen, const uint64_t *g, int gbits,
+               uint32_t **sa_out, const uint64_t **gkeys_out) {
+    (void)m_blk;
+    Workspace &w = h->ws;
+    Scope sc(h, s, BWT_STAGE_SORT);
+    const int kfirst = first_key_syms(gbits);
+    HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, g, gbits, w.kA, w.v[0], s));
     uint64_t *ks;
     uint32_t *vs;
-    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, KEY_BITS0, &ks, &vs);
+    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, gbits ? 64 : 2 * kfirst + 5,
+                        &ks, &vs);
     if (rc) return rc;
     uint32_t *sa = vs;
+    *sa_out = sa;
+    *gkeys_out = ks;
+    HIPCHK(h, hipMemsetAsync(w.misc + MISC_LARGE, 0, 4, s));
+    HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, kfirst, sa, nullptr, w.U[0],
+                                 w.misc + MISC_NU, REFINE_LIMIT, w.misc + MISC_LARGE,
+                                 w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
+                                 w.misc + MISC_ERR, s));
+    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    uint32_t nU = reinterpret_cast<uint32_t *>(h->pinned)[0];
+    const bool large = reinterpret_cast<uint32_t *>(h->pinned)[1] != 0;
+    if (nU == 0) return BWT_OK;
+    if (!large) {
+        // every tied group is small: finish them in LDS by chunk keys
+        const uint32_t max_iter = (uint32_t)(maxlen / KEY_K + 2);
+        HIPCHK(h, launch_refine(reads, off, w.soff, w.tile_first, ks, w.U[0], nU, sa, kfirst,
+                                max_iter, w.misc + MISC_ERR, s));
+        return BWT_OK;
+    }
+    // A group too large for LDS: prefix doubling over all tied suffixes.
+    // The doubling sorts reuse both key buffers, so g_sa moves to w.g first.
+    HIPCHK(h, hipMemcpyAsync(w.g, ks, (uint64_t)n_blk * 8, hipMemcpyDeviceToDevice, s));
+    *gkeys_out = w.g;
     uint32_t *spare[2];
     {
         int k = 0;
@@ -406,61 +442,53 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
             if (p != sa) spare[k++] = p;
     }
     int ui = 0;
-    HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, sa, w.rank, w.U[ui], w.misc + MISC_NU,
+    HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, kfirst, sa, w.rank, w.U[ui],
+                                 w.misc + MISC_NU, 0xffffffffu, w.misc + MISC_LARGE,
                                  w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
                                  w.misc + MISC_ERR, s));
-    uint32_t nU = 0;
-    if (n_blk > 0 && (rc = read_u32(h, s, w.misc + MISC_NU, &nU))) return rc;
+    if ((rc = read_u32(h, s, w.misc + MISC_NU, &nU))) return rc;
     const int rbits = bits_for(n_blk);
-    uint32_t hlen = KEY_K;
+    uint32_t hlen = (uint32_t)kfirst;
     int rounds = 0;
     while (nU > 0) {
         // h doubles every round and no suffix is longer than a block
-        if (++rounds > 32 || hlen > n_blk) return fail(h, BWT_EHIP);
+        if (++rounds > 40 || hlen > n_blk) return fail(h, BWT_EHIP);
         h->timer.acc.doubling_rounds += 1;
         HIPCHK(h, launch_doubling_keys(w.U[ui], nU, sa, w.rank, hlen, rbits, n_blk, w.kA,
                                        spare[0], w.misc + MISC_ERR, s));
         rc = radix_sort(h, s, w.kA, spare[0], w.kB, spare[1], nU, 2 * rbits, &ks, &vs);
         if (rc) return rc;
-        HIPCHK(h, launch_group_heads(ks, vs, w.U[ui], nU, sa, w.rank, w.U[ui ^ 1],
-                                     w.misc + MISC_NU, w.status_scan, w.misc + MISC_CNT_HEADS,
-                                     next_epoch(), w.misc + MISC_ERR, s));
+        HIPCHK(h, launch_group_heads(ks, vs, w.U[ui], nU, 0, sa, w.rank, w.U[ui ^ 1],
+                                     w.misc + MISC_NU, 0xffffffffu, w.misc + MISC_LARGE,
+                                     w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
+                                     w.misc + MISC_ERR, s));
         ui ^= 1;
         if ((rc = read_u32(h, s, w.misc + MISC_NU, &nU))) return rc;
         hlen *= 2;
     }
-    *sa_out = sa;
     return BWT_OK;
 }
 
 // ---- Insert ------------------------------------------------------------------
+// Merges the n_new sorted block symbols (gkeys/gbits give g_sa, vals the
+// symbol codes) into src, writing dst.
 int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, uint64_t n_ext,
-                 const uint8_t *bint, const uint64_t *gsa, uint64_t n_new, bool check) {
+                 const uint64_t *gkeys, int gbits, const uint32_t *vals, uint64_t n_new) {
     Workspace &w = h->ws;
     const uint64_t n_out = n_ext + n_new;
     const uint64_t ntiles = div_up(records_for(n_out), INS_TILE_RECS);
     int rc = ensure_buf(h, h->first_new, h->first_new_cap, ntiles + 2);
     if (rc) return rc;
     Scope sc(h, s, BWT_STAGE_INSERT);
-    if (check) {
-        HIPCHK(h, hipMemsetAsync(w.misc + MISC_BAD, 0, 4, s));
-        HIPCHK(h, launch_check_gsa(gsa, n_new, n_ext, w.misc + MISC_BAD, s));
-    }
-    HIPCHK(h, launch_count_bint(bint, (uint32_t)n_new, w.bcnt, w.status_scan,
-                                w.misc + MISC_CNT_BINT, next_epoch(), w.misc + MISC_BAD,
-                                w.misc + MISC_ERR, s));
-    if (check) {
-        uint32_t bad = 0;
-        if ((rc = read_u32(h, s, w.misc + MISC_BAD, &bad))) return rc;
-        if (bad) return fail(h, BWT_EINVAL);
-    }
-    HIPCHK(h, launch_ins_tile_first(gsa, n_new, ntiles, h->first_new, s));
-    HIPCHK(h, launch_ins_meta(src.recs, src.sbc, src.meta, bint, w.bcnt, gsa, n_new, dst.sbc,
-                              dst.meta, s));
+    HIPCHK(h, launch_count_bint(vals, (uint32_t)n_new, w.bcnt, w.status_scan,
+                                w.misc + MISC_CNT_BINT, next_epoch(), w.misc + MISC_ERR, s));
+    HIPCHK(h, launch_ins_tile_first(gkeys, gbits, n_new, ntiles, h->first_new, s));
+    HIPCHK(h, launch_ins_meta(src.recs, src.sbc, src.meta, gkeys, gbits, vals, w.bcnt, n_new,
+                              dst.sbc, dst.meta, s));
     {
         Scope sk(h, s, SPAN_INSERT_K);
-        HIPCHK(h, launch_insert(src.recs, src.sbc, n_ext, bint, w.bcnt, gsa, n_new, h->first_new,
-                                dst.recs, dst.sbc, w.misc + MISC_ERR, s));
+        HIPCHK(h, launch_insert(src.recs, src.sbc, n_ext, gkeys, gbits, vals, w.bcnt, n_new,
+                                h->first_new, dst.recs, dst.sbc, w.misc + MISC_ERR, s));
     }
     if (h->timer.on) {
         h->timer.acc.insert_records_out += records_for(n_out);
@@ -477,6 +505,7 @@ struct Plan {
     std::vector<uint64_t> cut_j;      // block boundaries (read indices), K + 1
     std::vector<uint64_t> cut_s;      // block-text position S(j) of each boundary
     uint64_t total_suffixes = 0;
+    uint64_t maxlen = 0;              // longest read
 };
 
 int plan_input(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *offsets,
@@ -499,6 +528,7 @@ int plan_input(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
             maxlen = std::max(maxlen, hoff[j + 1] - hoff[j]);
         }
         if (maxlen > MAX_READ) return fail(h, BWT_EINVAL);
+        P.maxlen = maxlen;
         const uint64_t o0 = hoff[0];
         P.cut_j.assign(1, 0);
         P.cut_s.assign(1, 0);
@@ -548,6 +578,7 @@ int plan_input(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     HIPCHK(h, hipStreamSynchronize(s));
     uint64_t bad = h->pinned[0], maxlen = h->pinned[1], K = h->pinned[2];
     if (bad || maxlen > MAX_READ) return fail(h, BWT_EINVAL);
+    P.maxlen = maxlen;
     std::vector<uint64_t> cuts(2 * (K + 1));
     HIPCHK(h, hipMemcpyAsync(cuts.data(), h->cuts, cuts.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
@@ -696,22 +727,23 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
         const uint32_t m_blk = (uint32_t)(j1 - j0);
         const uint32_t n_blk = (uint32_t)(P.cut_s[b + 1] - P.cut_s[b]);
         const uint64_t *off = P.off + j0;
-        uint32_t *sa = nullptr;
-        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, &sa))) return rc;
         IndexBuf &S = h->buf[src];
-        {
+        if ((rc = block_prep(h, s, off, m_blk, n_blk))) return rc;
+        // ComputeRanks first: g leads the suffix sort key (an empty index
+        // ranks every suffix 0, so the first block skips it)
+        const int gbits = bits_for_value(n_cur);
+        if (gbits > 0) {
             Scope sc(h, s, BWT_STAGE_RANKS);
             Scope sk(h, s, SPAN_RANKS_K, n_blk - m_blk);
             HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, S.recs, S.sbc, S.meta,
                                            n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, s));
         }
-        {
-            Scope sc(h, s, BWT_STAGE_GATHER);
-            HIPCHK(h, launch_gather(sa, w.g, n_blk, w.bint, w.gsa, s));
-        }
-        const int dst = other[b & 1];
-        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, w.bint, w.gsa, n_blk, false)))
+        uint32_t *sa = nullptr;
+        const uint64_t *gkeys = nullptr;
+        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, &sa, &gkeys)))
             return rc;
+        const int dst = other[b & 1];
+        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gbits, sa, n_blk))) return rc;
         n_cur += n_blk;
         h->timer.acc.blocks += 1;
         src = dst;
@@ -842,10 +874,13 @@ int bwt_set_block_sort(bwt_set_t h, const uint8_t *reads, const uint64_t *offset
     if ((rc = ensure_ws(h, P.total_suffixes))) return rc;
     if ((rc = clear_err(h, s))) return rc;
     uint32_t *sa = nullptr;
+    const uint64_t *gkeys = nullptr;
     const uint32_t n_blk = (uint32_t)P.total_suffixes;
-    if ((rc = block_sort(h, s, P.reads, P.off, (uint32_t)m, n_blk, &sa))) return rc;
-    // B_int from the value bits, then the plain suffix array
-    HIPCHK(h, launch_gather(sa, h->ws.g, n_blk, bint_out, h->ws.gsa, s));
+    if ((rc = block_prep(h, s, P.off, (uint32_t)m, n_blk))) return rc;
+    if ((rc = block_sort(h, s, P.reads, P.off, (uint32_t)m, n_blk, P.maxlen, nullptr, 0, &sa,
+                         &gkeys)))
+        return rc;
+    HIPCHK(h, launch_vals_to_ascii(sa, n_blk, bint_out, s));
     HIPCHK(h, launch_sa_strip(sa, n_blk, sa_out, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (h->timer.on) timer_collect(h);
@@ -891,7 +926,15 @@ int bwt_set_insert(bwt_set_t h, const uint8_t *bint, const uint64_t *gsa, uint64
     if ((rc = ensure_index(h, h->buf[dst], n_final))) return rc;
     if ((rc = ensure_ws(h, n_new))) return rc;
     if ((rc = clear_err(h, s))) return rc;
-    if ((rc = insert_block(h, s, h->buf[h->cur], h->buf[dst], h->n, bint, gsa, n_new, true)))
+    Workspace &w = h->ws;
+    HIPCHK(h, hipMemsetAsync(w.misc + MISC_BAD, 0, 4, s));
+    HIPCHK(h, launch_check_user_insert(bint, gsa, n_new, h->n, w.misc + MISC_BAD, s));
+    uint32_t bad = 0;
+    if ((rc = read_u32(h, s, w.misc + MISC_BAD, &bad))) return rc;
+    if (bad) return fail(h, BWT_EINVAL);
+    const int gbits = bits_for_value(h->n);
+    HIPCHK(h, launch_pack_user_insert(bint, gsa, n_new, gbits, w.kA, w.v[0], s));
+    if ((rc = insert_block(h, s, h->buf[h->cur], h->buf[dst], h->n, w.kA, gbits, w.v[0], n_new)))
         return rc;
     // the number of terminators merged in comes from the new counts
     HIPCHK(h, hipMemcpyAsync(h->pinned, h->buf[dst].meta, META_WORDS * 8, hipMemcpyDeviceToHost, s));

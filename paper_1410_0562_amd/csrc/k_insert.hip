@@ -37,15 +37,23 @@ __global__ void index_init_kernel(Rec *recs, uint64_t *sbc, uint64_t *meta) {
     if (t < META_WORDS) meta[t] = 0;
 }
 
-// bcnt[k*4 + c] = occurrences of c in bint[0 .. 64k) for k = 0 .. ceil(n/64)
-// (the last entry holds the totals).  Tile of 4096 symbols = 64 chunks, one
-// look-back chain per base.  Any byte outside "ACGT$" sets *bad.
-__global__ __launch_bounds__(256) void count_bint_kernel(const uint8_t *__restrict__ bint,
+__device__ __forceinline__ uint64_t gsa_at(const uint64_t *__restrict__ gkeys, int gbits,
+                                           uint64_t i) {
+    return gbits ? gkeys[i] >> (64 - gbits) : 0ull;
+}
+
+__device__ __forceinline__ int code_at(const uint32_t *__restrict__ vals, uint64_t i) {
+    return (int)(vals[i] >> POS_BITS);
+}
+
+// bcnt[k*4 + c] = occurrences of base c among the first 64k new symbols, for
+// k = 0 .. ceil(n/64) (the last entry holds the totals).  Tile of 4096
+// symbols = 64 chunks, one look-back chain per base.
+__global__ __launch_bounds__(256) void count_bint_kernel(const uint32_t *__restrict__ vals,
                                                          uint32_t n, uint32_t *__restrict__ bcnt,
                                                          uint64_t *__restrict__ status,
                                                          uint32_t *__restrict__ counter,
                                                          uint32_t ntiles, uint32_t epoch,
-                                                         uint32_t *__restrict__ bad,
                                                          uint32_t *__restrict__ err) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wtot[4][4];
@@ -59,19 +67,16 @@ __global__ __launch_bounds__(256) void count_bint_kernel(const uint8_t *__restri
     const uint64_t wbase = (uint64_t)tile * SCAN_TILE + (uint64_t)wave * 1024;
     uint32_t run[4] = {0, 0, 0, 0};
     uint32_t loc[16][4];
-    bool badl = false;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         uint64_t x = wbase + (uint64_t)e * 64 + lane;
-        int c = x < n ? code_of_ascii(bint[x]) : 6;
-        badl |= (c == 5);
+        int c = x < n ? code_at(vals, x) : 6;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             loc[e][b] = run[b];
             run[b] += (uint32_t)__popcll(__ballot(c == b));
         }
     }
-    if (badl) atomicOr(bad, 1u);
     // the counts are uniform across the wave; lane b < 4 keeps base b
     auto pick = [lane](const uint32_t *v) {
         return lane == 0 ? v[0] : lane == 1 ? v[1] : lane == 2 ? v[2] : v[3];
@@ -98,33 +103,47 @@ __global__ __launch_bounds__(256) void count_bint_kernel(const uint8_t *__restri
     }
 }
 
-__global__ void check_gsa_kernel(const uint64_t *__restrict__ gsa, uint64_t n_new, uint64_t n_ext,
-                                 uint32_t *__restrict__ bad) {
+// user-supplied Insert input: *bad |= 1 for a byte outside "ACGT$", 2 for a
+// g_sa value that decreases or exceeds n_ext
+__global__ void check_user_insert_kernel(const uint8_t *__restrict__ bint,
+                                         const uint64_t *__restrict__ gsa, uint64_t n_new,
+                                         uint64_t n_ext, uint32_t *__restrict__ bad) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_new) return;
     uint64_t v = gsa[i];
     if (v > n_ext || (i > 0 && gsa[i - 1] > v)) atomicOr(bad, 2u);
+    if (code_of_ascii(bint[i]) > 4) atomicOr(bad, 1u);
+}
+
+__global__ void pack_user_insert_kernel(const uint8_t *__restrict__ bint,
+                                        const uint64_t *__restrict__ gsa, uint64_t n_new, int gbits,
+                                        uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_new) return;
+    keys[i] = gbits ? gsa[i] << (64 - gbits) : 0ull;
+    vals[i] = (uint32_t)code_of_ascii(bint[i]) << POS_BITS;
 }
 
 // first_new[t] = number of new symbols whose output row is below t * 2048
-__global__ void ins_tile_first_kernel(const uint64_t *__restrict__ gsa, uint64_t n_new,
-                                      uint64_t ntiles, uint64_t *__restrict__ first_new) {
+__global__ void ins_tile_first_kernel(const uint64_t *__restrict__ gkeys, int gbits,
+                                      uint64_t n_new, uint64_t ntiles,
+                                      uint64_t *__restrict__ first_new) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > ntiles) return;
     uint64_t Q = t * INS_TILE_SYMS;
     uint64_t lo = 0, hi = n_new;
-    while (lo < hi) {  // first i with gsa[i] + i >= Q
+    while (lo < hi) {  // first i with g_sa[i] + i >= Q
         uint64_t mid = (lo + hi) >> 1;
-        if (gsa[mid] + mid >= Q) hi = mid;
+        if (gsa_at(gkeys, gbits, mid) + mid >= Q) hi = mid;
         else lo = mid + 1;
     }
     first_new[t] = lo;
 }
 
-__device__ uint64_t rank_bint(const uint8_t *__restrict__ bint, const uint32_t *__restrict__ bcnt,
+__device__ uint64_t rank_bint(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ bcnt,
                               uint64_t a, int c) {
     uint64_t r = bcnt[(a >> CHUNK_SHIFT) * 4 + c];
-    for (uint64_t x = a & ~63ull; x < a; ++x) r += (code_of_ascii(bint[x]) == c);
+    for (uint64_t x = a & ~63ull; x < a; ++x) r += (code_at(vals, x) == c);
     return r;
 }
 
@@ -132,8 +151,9 @@ __device__ uint64_t rank_bint(const uint8_t *__restrict__ bint, const uint32_t *
 // thread; the number of superblocks is n / 2^32 + 1).
 __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
                                 const uint64_t *__restrict__ ometa,
-                                const uint8_t *__restrict__ bint, const uint32_t *__restrict__ bcnt,
-                                const uint64_t *__restrict__ gsa, uint64_t n_new,
+                                const uint64_t *__restrict__ gkeys, int gbits,
+                                const uint32_t *__restrict__ vals,
+                                const uint32_t *__restrict__ bcnt, uint64_t n_new,
                                 uint64_t *__restrict__ nsbc, uint64_t *__restrict__ nmeta) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     uint64_t nch = div_up(n_new, 64);
@@ -155,19 +175,19 @@ __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *_
         uint64_t lo = 0, hi = n_new;
         while (lo < hi) {
             uint64_t mid = (lo + hi) >> 1;
-            if (gsa[mid] + mid >= Q) hi = mid;
+            if (gsa_at(gkeys, gbits, mid) + mid >= Q) hi = mid;
             else lo = mid + 1;
         }
         uint64_t o = Q - lo;
         for (int c = 0; c < 4; ++c)
-            nsbc[sb * 4 + c] = rank_base(orecs, osbc, o, c, true) + rank_bint(bint, bcnt, lo, c);
+            nsbc[sb * 4 + c] = rank_base(orecs, osbc, o, c, true) + rank_bint(vals, bcnt, lo, c);
     }
 }
 
 __global__ __launch_bounds__(256) void insert_kernel(
     const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
-    const uint8_t *__restrict__ bint, const uint32_t *__restrict__ bcnt,
-    const uint64_t *__restrict__ gsa, const uint64_t *__restrict__ first_new,
+    const uint64_t *__restrict__ gkeys, int gbits, const uint32_t *__restrict__ vals,
+    const uint32_t *__restrict__ bcnt, const uint64_t *__restrict__ first_new,
     Rec *__restrict__ nrecs, const uint64_t *__restrict__ nsbc, uint64_t n_out, uint64_t nrec_out,
     uint64_t nrec_in, uint32_t *__restrict__ err) {
     __shared__ uint32_t s_bm[INS_TILE_SYMS / 32];
@@ -205,16 +225,16 @@ __global__ __launch_bounds__(256) void insert_kernel(
     }
     __syncthreads();
     for (uint64_t i = a0 + tid; i < a1; i += 256) {
-        uint64_t pos = gsa[i] + i - q0;
+        uint64_t pos = gsa_at(gkeys, gbits, i) + i - q0;
         if (pos < INS_TILE_SYMS) atomicOr(&s_bm[pos >> 5], 1u << (pos & 31));
         else atomicOr(err, 32u);
-        s_new[i - a0] = (uint8_t)code_of_ascii(bint[i]);
+        s_new[i - a0] = (uint8_t)code_at(vals, i);
     }
     if (wave == 1) {
         // counts at the tile start: old part by a rank on B_ext, new part from
         // the sampled B_int counts plus the < 64 symbols since the sample
         uint64_t x = (a0 & ~63ull) + lane;
-        int c = x < a0 ? code_of_ascii(bint[x]) : 6;
+        int c = x < a0 ? code_at(vals, x) : 6;
         uint32_t cA = __popcll(__ballot(c == 0)), cC = __popcll(__ballot(c == 1));
         uint32_t cG = __popcll(__ballot(c == 2)), cT = __popcll(__ballot(c == 3));
         if (lane < 4) {
@@ -301,46 +321,56 @@ hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_count_bint(const uint8_t *bint, uint32_t n, uint32_t *bcnt, uint64_t *status,
-                             uint32_t *counter, uint32_t epoch, uint32_t *bad, uint32_t *err,
-                             hipStream_t s) {
+hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *bcnt, uint64_t *status,
+                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s) {
     uint32_t ntiles = (uint32_t)div_up(n, SCAN_TILE);
     if (ntiles == 0) return hipSuccess;
-    count_bint_kernel<<<ntiles, 256, 0, s>>>(bint, n, bcnt, status, counter, ntiles, epoch, bad,
-                                             err);
+    count_bint_kernel<<<ntiles, 256, 0, s>>>(vals, n, bcnt, status, counter, ntiles, epoch, err);
     return hipGetLastError();
 }
 
-hipError_t launch_check_gsa(const uint64_t *gsa, uint64_t n_new, uint64_t n_ext, uint32_t *bad,
-                            hipStream_t s) {
+hipError_t launch_check_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
+                                   uint64_t n_ext, uint32_t *bad, hipStream_t s) {
     if (n_new == 0) return hipSuccess;
-    check_gsa_kernel<<<(unsigned)div_up(n_new, 256), 256, 0, s>>>(gsa, n_new, n_ext, bad);
+    check_user_insert_kernel<<<(unsigned)div_up(n_new, 256), 256, 0, s>>>(bint, gsa, n_new, n_ext,
+                                                                          bad);
     return hipGetLastError();
 }
 
-hipError_t launch_ins_tile_first(const uint64_t *gsa, uint64_t n_new, uint64_t ntiles,
-                                 uint64_t *first_new, hipStream_t s) {
-    ins_tile_first_kernel<<<(unsigned)div_up(ntiles + 1, 256), 256, 0, s>>>(gsa, n_new, ntiles,
-                                                                           first_new);
+hipError_t launch_pack_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
+                                  int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+    if (n_new == 0) return hipSuccess;
+    pack_user_insert_kernel<<<(unsigned)div_up(n_new, 256), 256, 0, s>>>(bint, gsa, n_new, gbits,
+                                                                         keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gbits, uint64_t n_new,
+                                 uint64_t ntiles, uint64_t *first_new, hipStream_t s) {
+    ins_tile_first_kernel<<<(unsigned)div_up(ntiles + 1, 256), 256, 0, s>>>(gkeys, gbits, n_new,
+                                                                           ntiles, first_new);
     return hipGetLastError();
 }
 
 hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
-                           const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
-                           uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta, hipStream_t s) {
-    ins_meta_kernel<<<1, 64, 0, s>>>(orecs, osbc, ometa, bint, bcnt, gsa, n_new, nsbc, nmeta);
+                           const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                           const uint32_t *bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
+                           hipStream_t s) {
+    ins_meta_kernel<<<1, 64, 0, s>>>(orecs, osbc, ometa, gkeys, gbits, vals, bcnt, n_new, nsbc,
+                                     nmeta);
     return hipGetLastError();
 }
 
 hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
-                         const uint8_t *bint, const uint32_t *bcnt, const uint64_t *gsa,
-                         uint64_t n_new, const uint64_t *first_new, Rec *nrecs,
-                         const uint64_t *nsbc, uint32_t *err, hipStream_t s) {
+                         const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                         const uint32_t *bcnt, uint64_t n_new, const uint64_t *first_new,
+                         Rec *nrecs, const uint64_t *nsbc, uint32_t *err, hipStream_t s) {
     const uint64_t n_out = n_ext + n_new;
     const uint64_t nrec_out = records_for(n_out);
     const uint64_t ntiles = div_up(nrec_out, INS_TILE_RECS);
-    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(orecs, osbc, bint, bcnt, gsa, first_new, nrecs,
-                                                   nsbc, n_out, nrec_out, records_for(n_ext), err);
+    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(orecs, osbc, gkeys, gbits, vals, bcnt, first_new,
+                                                   nrecs, nsbc, n_out, nrec_out, records_for(n_ext),
+                                                   err);
     return hipGetLastError();
 }
 

@@ -45,13 +45,20 @@ __global__ void zero_words_kernel(uint64_t *p, int n) {
 __global__ void check_offsets_kernel(const uint64_t *__restrict__ off, uint64_t m,
                                      uint64_t *__restrict__ res) {
     uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    uint64_t a = off[j], b = off[j + 1];
-    if (b < a) {
-        atomicOr((unsigned long long *)&res[0], 1ull);
-    } else {
-        atomicMax((unsigned long long *)&res[1], (unsigned long long)(b - a));
+    uint64_t len = 0;
+    bool bad = false;
+    if (j < m) {
+        uint64_t a = off[j], b = off[j + 1];
+        bad = b < a;
+        len = bad ? 0 : b - a;
     }
+    // one atomic per wave
+    if (__ballot(bad) != 0 && lane_id() == 0) atomicOr((unsigned long long *)&res[0], 1ull);
+    for (int d = 32; d > 0; d >>= 1) {
+        uint64_t o = __shfl_xor(len, d, 64);
+        len = o > len ? o : len;
+    }
+    if (lane_id() == 0 && len) atomicMax((unsigned long long *)&res[1], (unsigned long long)len);
 }
 
 // Greedy block split (Algorithm 1 blocks: whole reads, at most M suffixes,

@@ -15,6 +15,40 @@ namespace bwt {
 
 namespace {
 
+// The values of one lane are written in descending order; they are kept in
+// an 8-entry shift register and written as one aligned 64-byte chunk when the
+// register covers indices [8q, 8q + 8), so the writes are whole half-lines
+// instead of single words spread over the cache (partial chunks at both ends
+// of a read are written word by word).
+struct GBuf {
+    uint64_t r0, r1, r2, r3, r4, r5, r6, r7;  // r0 = lowest index held
+    uint32_t cnt;
+    __device__ void push(uint64_t v) {
+        r7 = r6; r6 = r5; r5 = r4; r4 = r3; r3 = r2; r2 = r1; r1 = r0; r0 = v;
+        cnt = cnt < 8 ? cnt + 1 : 8;
+    }
+    // write the held values to g[idx .. idx + cnt)
+    __device__ void flush(uint64_t *__restrict__ g, uint64_t idx, bool vec) {
+        if (cnt == 8 && vec) {
+            uint4 *q = reinterpret_cast<uint4 *>(g + idx);
+            q[0] = make_uint4((uint32_t)r0, (uint32_t)(r0 >> 32), (uint32_t)r1, (uint32_t)(r1 >> 32));
+            q[1] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), (uint32_t)r3, (uint32_t)(r3 >> 32));
+            q[2] = make_uint4((uint32_t)r4, (uint32_t)(r4 >> 32), (uint32_t)r5, (uint32_t)(r5 >> 32));
+            q[3] = make_uint4((uint32_t)r6, (uint32_t)(r6 >> 32), (uint32_t)r7, (uint32_t)(r7 >> 32));
+        } else {
+            if (cnt > 0) g[idx] = r0;
+            if (cnt > 1) g[idx + 1] = r1;
+            if (cnt > 2) g[idx + 2] = r2;
+            if (cnt > 3) g[idx + 3] = r3;
+            if (cnt > 4) g[idx + 4] = r4;
+            if (cnt > 5) g[idx + 5] = r5;
+            if (cnt > 6) g[idx + 6] = r6;
+            if (cnt > 7) g[idx + 7] = r7;
+        }
+        cnt = 0;
+    }
+};
+
 __global__ __launch_bounds__(256) void compute_ranks_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, uint32_t m_blk, const Rec *__restrict__ recs,
@@ -25,11 +59,15 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
     const uint64_t C0 = m_ext, C1 = C0 + meta[0], C2 = C1 + meta[1], C3 = C2 + meta[2];
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m_blk) return;
+    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;  // uniform
     const uint64_t s0 = off[j];
     uint32_t k = (uint32_t)(off[j + 1] - s0);
-    uint64_t *gj = g + soff[j];
+    const uint64_t gb = soff[j];
+    GBuf buf;
+    buf.cnt = 0;
     uint64_t i = m_ext;
-    gj[k] = i;
+    buf.push(i);
+    if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
     // the 8-byte word of packed input holding the current symbol
     uintptr_t wa = 0;
     uint64_t word = 0;
@@ -47,8 +85,10 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
         uint64_t Cc = c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : C3;
         i = Cc + rank_base(recs, sbc, i, c, isbig);
         i = i < n_ext ? i : n_ext;  // a consistent index never needs the clamp
-        gj[k] = i;
+        buf.push(i);
+        if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
     }
+    buf.flush(g, gb, false);  // what is left below the last aligned index
 }
 
 }  // namespace

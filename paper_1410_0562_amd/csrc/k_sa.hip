@@ -1,16 +1,20 @@
-// k_sa.hip -- ConstructSA of one block (Section 3) by prefix doubling over
-// radix-sorted keys, and the B_int / g_sa gather of Algorithm 1.
+// k_sa.hip -- ConstructSA of one block (Section 3) and the pieces of
+// Algorithm 1 that come out of it (B_int, g_sa).
 //
-// Round 0 sorts every block suffix by a 63-bit key made of its first KEY_K
-// symbols (terminator-aware, see bwt_internal.hpp).  After a sort, groups of
-// equal keys get the SA index of their first member as rank; singletons and
-// keys that reach their terminator are final.  Each later round sorts only
-// the still-unresolved suffixes by (rank[p], rank[p + h]) -- the sort
-// doubles the compared prefix from h to 2h, as in Larsson-Sadakane prefix
-// doubling (the paper's GPU sorter also discards resolved suffixes between
-// iterations) -- and writes them back into their group's SA slots.  Since an
-// unresolved suffix has at least h symbols before its terminator, p + h never
-// leaves its read.
+// Round 0 radix-sorts every block suffix by (g, first K' symbols), see
+// bwt_internal.hpp: g is non-decreasing in suffix order, so it may lead the
+// key, and it splits ties that symbols alone would leave.  Groups of equal
+// keys that do not end at a terminator are still tied.  The usual case --
+// every tied group has at most REFINE_LIMIT members -- is finished in LDS:
+// one workgroup takes a window of groups and sorts each group by successive
+// 29-symbol chunks of its suffixes, splitting it until every subgroup is a
+// single suffix or ends at its terminator (the paper's GPU sorter likewise
+// compares suffixes as strings of fixed-size words and drops settled ones
+// between iterations).  A block with a larger group instead runs prefix
+// doubling (Larsson-Sadakane) over all its tied suffixes: sort by
+// (rank[p], rank[p + h]) so the compared prefix doubles from h to 2h; an
+// unresolved suffix has at least h symbols before its terminator, so p + h
+// never leaves its read.
 #include "dev_util.hpp"
 
 namespace bwt {
@@ -45,12 +49,10 @@ __global__ void block_tile_first_kernel(const uint32_t *__restrict__ soff, uint3
     tile_first[T] = lo;
 }
 
-__global__ __launch_bounds__(256) void block_keys_kernel(
-    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first, uint32_t n_blk,
-    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_blk) return;
+// read containing block position p
+__device__ __forceinline__ uint32_t find_read(const uint32_t *__restrict__ soff,
+                                              const uint32_t *__restrict__ tile_first,
+                                              uint32_t p) {
     uint32_t T = p >> PREP_TILE_SHIFT;
     uint32_t lo = tile_first[T], hi = tile_first[T + 1];
     while (lo < hi) {  // largest j in [lo, hi] with soff[j] <= p
@@ -58,42 +60,61 @@ __global__ __launch_bounds__(256) void block_keys_kernel(
         if (soff[mid] <= p) lo = mid;
         else hi = mid - 1;
     }
-    const uint32_t j = lo;
-    const uint32_t sj = soff[j];
-    const uint32_t len = soff[j + 1] - sj - 1;
-    const uint32_t t = p - sj;
-    const uint32_t r = len - t;  // symbols before the terminator
-    const uint64_t s = off[j] + t;
-    const int take = r < (uint32_t)KEY_K ? (int)r : KEY_K;
+    return lo;
+}
+
+// Chunk key of the suffix whose first symbol is global symbol s and which
+// has r symbols before its terminator: min(r, K) symbols, first one most
+// significant, zero-padded to K symbols, then the count in the low 5 bits.
+__device__ __forceinline__ uint64_t chunk_key(const uint8_t *__restrict__ reads, uint64_t s,
+                                              uint32_t r, int K) {
+    const int take = r < (uint32_t)K ? (int)r : K;
     uint64_t sym = 0;
     if (take > 0) {
         uint64_t v = load_sym_window(reads, s, take);
         v &= (1ull << (2 * take)) - 1ull;
-        sym = reverse_pairs(v) >> (64 - 2 * KEY_K);
+        sym = reverse_pairs(v) >> (64 - 2 * K);
     }
-    keys[p] = (sym << KEY_LEN_BITS) | (uint64_t)take;
+    return (sym << KEY_LEN_BITS) | (uint64_t)take;
+}
+
+__global__ __launch_bounds__(256) void block_keys_kernel(
+    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first, uint32_t n_blk,
+    const uint64_t *__restrict__ g, int gbits, uint64_t *__restrict__ keys,
+    uint32_t *__restrict__ vals) {
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_blk) return;
+    const uint32_t j = find_read(soff, tile_first, p);
+    const uint32_t sj = soff[j];
+    const uint32_t t = p - sj;
+    const uint32_t r = soff[j + 1] - 1 - p;  // symbols before the terminator
+    const uint64_t s = off[j] + t;
+    uint64_t key = chunk_key(reads, s, r, first_key_syms(gbits));
+    if (gbits > 0) key |= g[p] << (64 - gbits);
+    keys[p] = key;
     uint32_t prev = t == 0 ? 4u : (uint32_t)load_sym(reads, s - 1);
     vals[p] = p | (prev << POS_BITS);
 }
 
-constexpr int GH_ITEMS = SCAN_TILE / 256;  // 16 rows of 64 per wave... per thread
+constexpr int GH_ITEMS = SCAN_TILE / 256;  // 16 rows of 64 elements per wave
 
 // Group heads after a sort, with one look-back chain for the last head index
 // (max) and one for the number of unresolved elements (sum).
 //
 // Element x (sorted order) has slot = x in round 0, U[x] in a doubling round.
 //   head(x)   : x == 0, or its key differs from x-1's, or (round 0) its key
-//               ends at the terminator (length field < KEY_K)
+//               ends at the terminator (length field < kshort)
 //   unresolved: in a group of two or more
-//   rank[p]   = slot of the first element of x's group
+//   rank[p]   = slot of the first element of x's group (when rank != null)
 //   Uout[...] = slots of unresolved elements, in increasing order
 // A doubling round also stores the sorted value into SA slot U[x].
 __global__ __launch_bounds__(256) void group_heads_kernel(
     const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-    const uint32_t *__restrict__ U, uint32_t n, uint32_t *__restrict__ sa,
+    const uint32_t *__restrict__ U, uint32_t n, int kshort, uint32_t *__restrict__ sa,
     uint32_t *__restrict__ rank, uint32_t *__restrict__ Uout, uint32_t *__restrict__ nUout,
-    uint64_t *__restrict__ status, uint32_t *__restrict__ counter, uint32_t ntiles,
-    uint32_t epoch, uint32_t *__restrict__ err) {
+    uint32_t limit, uint32_t *__restrict__ large, uint64_t *__restrict__ status,
+    uint32_t *__restrict__ counter, uint32_t ntiles, uint32_t epoch, uint32_t *__restrict__ err) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wmax[4], s_wsum[4];
     __shared__ uint32_t s_pmax, s_psum;
@@ -107,7 +128,7 @@ __global__ __launch_bounds__(256) void group_heads_kernel(
     const bool round0 = (U == nullptr);
 
     uint32_t hx[GH_ITEMS], ui[GH_ITEMS];
-    uint32_t unres_bits = 0;
+    uint32_t unres_bits = 0, last_bits = 0;
     uint32_t carry_max = 0, carry_sum = 0;
 #pragma unroll
     for (int e = 0; e < GH_ITEMS; ++e) {
@@ -116,13 +137,15 @@ __global__ __launch_bounds__(256) void group_heads_kernel(
         uint32_t hv = 0, uv = 0;
         if (ok) {
             uint64_t key = keys[x];
-            bool is_short = round0 && (key & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)KEY_K;
+            bool is_short =
+                round0 && (key & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)kshort;
             bool head = (x == 0) || keys[x - 1] != key || is_short;
             bool nhead = (x + 1 == n) || keys[x + 1] != key || is_short;
             bool unres = !(head && nhead);
             hv = head ? (uint32_t)x : 0u;
             uv = unres ? 1u : 0u;
             unres_bits |= (unres ? 1u : 0u) << e;
+            last_bits |= (unres && nhead ? 1u : 0u) << e;
         }
         uint32_t im = wave_incl_max(hv);
         im = im > carry_max ? im : carry_max;
@@ -164,21 +187,19 @@ __global__ __launch_bounds__(256) void group_heads_kernel(
         uint64_t x = wbase + (uint64_t)e * 64 + lane;
         if (x >= n) continue;
         uint32_t head_x = hx[e] > pmax ? hx[e] : pmax;
-        uint32_t v = vals[x];
-        uint32_t slot, gs;
         if (head_x > (uint32_t)x) {  // cannot happen; guards the indexing below
             atomicOr(err, 8u);
             head_x = (uint32_t)x;
         }
-        if (round0) {
-            slot = (uint32_t)x;
-            gs = head_x;
-        } else {
-            slot = U[x];
-            gs = U[head_x];
-            sa[slot] = v;
+        if ((last_bits >> e) & 1u) {
+            if ((uint32_t)x - head_x + 1 > limit) atomicOr(large, 1u);
         }
-        rank[v & POS_MASK] = gs;
+        uint32_t slot = round0 ? (uint32_t)x : U[x];
+        if (!round0 || rank) {
+            uint32_t v = vals[x];
+            if (!round0) sa[slot] = v;
+            if (rank) rank[v & POS_MASK] = round0 ? head_x : U[head_x];
+        }
         uint32_t dst = psum + ui[e];
         if ((unres_bits >> e) & 1u) {
             if (dst < n) Uout[dst] = slot;
@@ -208,16 +229,195 @@ __global__ void doubling_keys_kernel(const uint32_t *__restrict__ U, uint32_t nU
     vals[u] = v;
 }
 
-// Algorithm 1: B_int[i] = symbol before suffix SA_int[i] ('$' at a read
-// start), g_sa[i] = g[SA_int[i]]
-__global__ void gather_kernel(const uint32_t *__restrict__ sa, const uint64_t *__restrict__ g,
-                              uint32_t n, uint8_t *__restrict__ bint, uint64_t *__restrict__ gsa) {
+// ---------------------------------------------------------------- refinement
+constexpr int RF_CAP = REFINE_WINDOW + REFINE_LIMIT;
+constexpr int RF_PER_THREAD = (RF_CAP + 255) / 256;
+
+// U[x] starts a tied group: groups are runs of consecutive slots with equal
+// round-0 keys
+__device__ __forceinline__ bool group_start(const uint32_t *__restrict__ U,
+                                            const uint64_t *__restrict__ keys, uint32_t x) {
+    if (x == 0) return true;
+    uint32_t a = U[x - 1], b = U[x];
+    return a + 1 != b || keys[a] != keys[b];
+}
+
+// One workgroup per window of REFINE_WINDOW unresolved elements, extended to
+// whole groups.  Every member of a group shares g and the first kfirst
+// symbols.  Each pass takes, for every member of a still-tied subgroup, the
+// chunk key of its suffix at depth d, reorders the subgroup by (chunk key,
+// current order) -- stable, so members equal up to their terminators stay in
+// position order, which is terminator order -- and splits it where the key
+// changes.  A subgroup is settled when it has one member or its key reaches
+// the terminator.  d grows by 29 per pass, so a group settles within
+// (longest read / 29) + 1 passes.
+__global__ __launch_bounds__(256) void refine_kernel(
+    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first,
+    const uint64_t *__restrict__ keys, const uint32_t *__restrict__ U, uint32_t nU,
+    uint32_t *__restrict__ sa, int kfirst, uint32_t max_iter, uint32_t *__restrict__ err) {
+    __shared__ uint32_t s_val[RF_CAP];
+    __shared__ uint64_t s_pos[RF_CAP];   // global symbol index of the suffix start
+    __shared__ uint32_t s_rem[RF_CAP];   // symbols before its terminator
+    __shared__ uint64_t s_key[RF_CAP];
+    __shared__ uint16_t s_gs[RF_CAP], s_ge[RF_CAP];  // subgroup [start, end)
+    __shared__ uint32_t s_win[2];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        uint64_t a = (uint64_t)blockIdx.x * REFINE_WINDOW, b = a + REFINE_WINDOW;
+        a = a < nU ? a : nU;
+        b = b < nU ? b : nU;
+        int guard = 0;
+        while (a < nU && !group_start(U, keys, (uint32_t)a) && guard++ < REFINE_LIMIT) ++a;
+        guard = 0;
+        while (b < nU && !group_start(U, keys, (uint32_t)b) && guard++ < REFINE_LIMIT) ++b;
+        s_win[0] = (uint32_t)a;
+        s_win[1] = (uint32_t)b;
+    }
+    __syncthreads();
+    const uint32_t a = s_win[0], b = s_win[1];
+    if (a >= b) return;
+    const uint32_t W = b - a;
+    if (W > (uint32_t)RF_CAP) {
+        if (tid == 0) atomicOr(err, 64u);
+        return;
+    }
+    // load the members
+    for (int t = 0; t < RF_PER_THREAD; ++t) {
+        uint32_t x = tid + 256 * t;
+        if (x < W) {
+            uint32_t v = sa[U[a + x]];
+            uint32_t p = v & POS_MASK;
+            uint32_t j = find_read(soff, tile_first, p);
+            s_val[x] = v;
+            s_pos[x] = off[j] + (p - soff[j]);
+            s_rem[x] = soff[j + 1] - 1 - p;
+            s_gs[x] = group_start(U, keys, a + x) ? 1 : 0;  // head flag for now
+        }
+    }
+    __syncthreads();
+    uint16_t gs_r[RF_PER_THREAD], ge_r[RF_PER_THREAD];
+    for (int t = 0; t < RF_PER_THREAD; ++t) {
+        uint32_t x = tid + 256 * t;
+        if (x < W) {
+            uint32_t y = x;
+            while (y > 0 && !s_gs[y]) --y;
+            uint32_t z = x + 1;
+            while (z < W && !s_gs[z]) ++z;
+            gs_r[t] = (uint16_t)y;
+            ge_r[t] = (uint16_t)z;
+        }
+    }
+    __syncthreads();
+    for (int t = 0; t < RF_PER_THREAD; ++t) {
+        uint32_t x = tid + 256 * t;
+        if (x < W) {
+            s_gs[x] = gs_r[t];
+            s_ge[x] = ge_r[t];
+        }
+    }
+    __syncthreads();
+
+    uint64_t d = (uint64_t)kfirst;
+    for (uint32_t iter = 0;; ++iter) {
+        int any = 0;
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            if (x < W && s_ge[x] - s_gs[x] >= 2) {
+                uint32_t rem = s_rem[x];
+                uint32_t rd = rem >= d ? (uint32_t)(rem - d) : 0u;
+                s_key[x] = chunk_key(reads, s_pos[x] + d, rd, KEY_K);
+                any = 1;
+            }
+        }
+        any = __syncthreads_or(any);
+        if (!any) break;
+        if (iter >= max_iter) {
+            if (tid == 0) atomicOr(err, 64u);
+            break;
+        }
+        // new place of every member inside its subgroup
+        uint32_t np[RF_PER_THREAD], v_r[RF_PER_THREAD], rem_r[RF_PER_THREAD];
+        uint64_t pos_r[RF_PER_THREAD], key_r[RF_PER_THREAD];
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            np[t] = x;
+            if (x < W) {
+                uint32_t gs = s_gs[x], ge = s_ge[x];
+                if (ge - gs >= 2) {
+                    uint64_t kx = s_key[x];
+                    uint32_t c = 0;
+                    for (uint32_t y = gs; y < ge; ++y) {
+                        uint64_t ky = s_key[y];
+                        c += (ky < kx) || (ky == kx && y < x);
+                    }
+                    np[t] = gs + c;
+                }
+                v_r[t] = s_val[x];
+                pos_r[t] = s_pos[x];
+                rem_r[t] = s_rem[x];
+                key_r[t] = s_key[x];
+            }
+        }
+        __syncthreads();
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            if (x < W) {
+                uint32_t q = np[t];
+                s_val[q] = v_r[t];
+                s_pos[q] = pos_r[t];
+                s_rem[q] = rem_r[t];
+                s_key[q] = key_r[t];
+            }
+        }
+        __syncthreads();
+        // split every reordered subgroup where the chunk key changes; a key
+        // that reaches the terminator settles its members where they are
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            if (x < W) {
+                uint32_t gs = s_gs[x], ge = s_ge[x];
+                gs_r[t] = (uint16_t)gs;
+                ge_r[t] = (uint16_t)ge;
+                if (ge - gs >= 2) {
+                    uint64_t k = s_key[x];
+                    if ((k & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)KEY_K) {
+                        gs_r[t] = (uint16_t)x;
+                        ge_r[t] = (uint16_t)(x + 1);
+                    } else {
+                        uint32_t y = x;
+                        while (y > gs && s_key[y - 1] == k) --y;
+                        uint32_t z = x + 1;
+                        while (z < ge && s_key[z] == k) ++z;
+                        gs_r[t] = (uint16_t)y;
+                        ge_r[t] = (uint16_t)z;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            if (x < W) {
+                s_gs[x] = gs_r[t];
+                s_ge[x] = ge_r[t];
+            }
+        }
+        __syncthreads();
+        d += KEY_K;
+    }
+    for (int t = 0; t < RF_PER_THREAD; ++t) {
+        uint32_t x = tid + 256 * t;
+        if (x < W) sa[U[a + x]] = s_val[x];
+    }
+}
+
+__global__ void vals_to_ascii_kernel(const uint32_t *__restrict__ sa, uint32_t n,
+                                     uint8_t *__restrict__ bint) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t v = sa[i];
     const char ascii[5] = {'A', 'C', 'G', 'T', '$'};
-    bint[i] = (uint8_t)ascii[v >> POS_BITS];
-    gsa[i] = g[v & POS_MASK];
+    bint[i] = (uint8_t)ascii[sa[i] >> POS_BITS];
 }
 
 __global__ void sa_strip_kernel(const uint32_t *__restrict__ sa, uint32_t n,
@@ -244,22 +444,22 @@ hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_
 }
 
 hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
-                             const uint32_t *tile_first, uint32_t m_blk, uint32_t n_blk,
-                             uint64_t *keys, uint32_t *vals, hipStream_t s) {
-    (void)m_blk;
-    block_keys_kernel<<<grid_for(n_blk, 256), 256, 0, s>>>(reads, off, soff, tile_first, n_blk,
-                                                          keys, vals);
+                             const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
+                             int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+    block_keys_kernel<<<grid_for(n_blk, 256), 256, 0, s>>>(reads, off, soff, tile_first, n_blk, g,
+                                                          gbits, keys, vals);
     return hipGetLastError();
 }
 
 hipError_t launch_group_heads(const uint64_t *keys, const uint32_t *vals, const uint32_t *U,
-                              uint32_t n, uint32_t *sa, uint32_t *rank, uint32_t *Uout,
-                              uint32_t *nUout, uint64_t *status, uint32_t *counter,
-                              uint32_t epoch, uint32_t *err, hipStream_t s) {
+                              uint32_t n, int kshort, uint32_t *sa, uint32_t *rank,
+                              uint32_t *Uout, uint32_t *nUout, uint32_t limit, uint32_t *large,
+                              uint64_t *status, uint32_t *counter, uint32_t epoch, uint32_t *err,
+                              hipStream_t s) {
     uint32_t ntiles = (uint32_t)div_up(n, SCAN_TILE);
     if (ntiles == 0) return hipSuccess;
-    group_heads_kernel<<<ntiles, 256, 0, s>>>(keys, vals, U, n, sa, rank, Uout, nUout, status,
-                                              counter, ntiles, epoch, err);
+    group_heads_kernel<<<ntiles, 256, 0, s>>>(keys, vals, U, n, kshort, sa, rank, Uout, nUout,
+                                              limit, large, status, counter, ntiles, epoch, err);
     return hipGetLastError();
 }
 
@@ -271,9 +471,18 @@ hipError_t launch_doubling_keys(const uint32_t *U, uint32_t nU, const uint32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const uint32_t *sa, const uint64_t *g, uint32_t n, uint8_t *bint,
-                         uint64_t *gsa, hipStream_t s) {
-    gather_kernel<<<grid_for(n, 256), 256, 0, s>>>(sa, g, n, bint, gsa);
+hipError_t launch_refine(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                         const uint32_t *tile_first, const uint64_t *keys, const uint32_t *U,
+                         uint32_t nU, uint32_t *sa, int kfirst, uint32_t max_iter, uint32_t *err,
+                         hipStream_t s) {
+    if (nU == 0) return hipSuccess;
+    refine_kernel<<<grid_for(nU, REFINE_WINDOW), 256, 0, s>>>(reads, off, soff, tile_first, keys, U,
+                                                              nU, sa, kfirst, max_iter, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_vals_to_ascii(const uint32_t *sa, uint32_t n, uint8_t *bint, hipStream_t s) {
+    vals_to_ascii_kernel<<<grid_for(n, 256), 256, 0, s>>>(sa, n, bint);
     return hipGetLastError();
 }
 

@@ -104,47 +104,69 @@ def short_reads(m: int = 4_000_000, length: int = 100, ref_len: int = 50_000_000
     return pack_codes(codes_all), offsets
 
 
+def _long_chunk(child_seed, ref, L, sub, ins, dele):
+    rng = np.random.default_rng(child_seed)
+    ref_len = len(ref)
+    k = len(L)
+    starts = rng.integers(0, ref_len - L + 1, dtype=np.int64)
+    minus = rng.random(k) < 0.5
+    seg = np.zeros(k + 1, dtype=np.int64)
+    seg[1:] = np.cumsum(L)
+    total = int(seg[-1])
+    # source index of every base; a minus-strand read walks its window
+    # backwards and is complemented
+    step = np.where(minus, -1, 1)
+    first = np.where(minus, starts + L - 1, starts)
+    idx = np.repeat(first - step * seg[:-1], L) + np.repeat(step, L) * np.arange(total, dtype=np.int64)
+    base = ref[idx]
+    mrep = np.repeat(minus, L)
+    base[mrep] = _RC[base[mrep]]
+    # per-base event drawn at a resolution of 1/10,000
+    u = rng.integers(0, 10_000, size=total, dtype=np.uint16)
+    t_del, t_ins = int(round(dele * 1e4)), int(round((dele + ins) * 1e4))
+    t_sub = int(round((dele + ins + sub) * 1e4))
+    copies = np.ones(total, dtype=np.int8)
+    copies[u < t_del] = 0
+    copies[(u >= t_del) & (u < t_ins)] = 2
+    subm = (u >= t_ins) & (u < t_sub)
+    ks = int(subm.sum())
+    if ks:
+        base[subm] = (base[subm] + rng.integers(1, 4, size=ks, dtype=np.uint8)) & 3
+    rep = np.repeat(base, copies)
+    ins_pos = np.flatnonzero(copies == 2)
+    if len(ins_pos):
+        # the second copy of an inserted base becomes a random base
+        out_idx = np.cumsum(copies, dtype=np.int64) - 1
+        rep[out_idx[ins_pos]] = rng.integers(0, 4, size=len(ins_pos), dtype=np.uint8)
+    return rep, np.add.reduceat(copies.astype(np.int64), seg[:-1])
+
+
 def long_reads(m: int = 250_000, mean_len: float = 5000.0, sigma: float = 0.5,
                min_len: int = 1000, max_len: int = 50_000,
                ref_len: int = 100_000_000, sub: float = 0.06, ins: float = 0.02,
-               dele: float = 0.02, seed: int = SEED_BASE + 3, chunk: int = 4096):
+               dele: float = 0.02, seed: int = SEED_BASE + 3, chunk: int = 4096,
+               threads: int = 8):
     """Workload 3: lognormal-length noisy reads from a random reference.
-    Returns (packed, offsets)."""
-    rng = np.random.default_rng(seed)
-    ref = rng.integers(0, 4, size=ref_len, dtype=np.uint8)
+    Each source base is deleted (prob. dele), followed by an inserted random
+    base (ins), substituted (sub) or kept.  Chunks of reads draw from child
+    seeds, so the output does not depend on `threads`.  Returns (packed, offsets)."""
+    from concurrent.futures import ThreadPoolExecutor
+    ss = np.random.SeedSequence(seed)
+    s_ref, s_len, s_chunks = ss.spawn(3)
+    ref = np.random.default_rng(s_ref).integers(0, 4, size=ref_len, dtype=np.uint8)
     mu = np.log(mean_len) - sigma * sigma / 2.0
-    lens = np.clip(np.rint(rng.lognormal(mu, sigma, size=m)), min_len, max_len).astype(np.int64)
-    pieces = []
-    out_lens = np.empty(m, dtype=np.int64)
-    for r0 in range(0, m, chunk):
-        r1 = min(m, r0 + chunk)
-        L = lens[r0:r1]
-        starts = rng.integers(0, ref_len - L + 1, dtype=np.int64)
-        minus = rng.random(r1 - r0) < 0.5
-        for t in range(r1 - r0):
-            src = ref[starts[t]:starts[t] + L[t]]
-            if minus[t]:
-                src = _RC[src[::-1]]
-            u = rng.random(len(src))
-            # per source base: deletion -> 0 copies, insertion -> base + random
-            # base, substitution -> changed base, otherwise the base itself
-            copies = np.where(u < dele, 0, np.where(u < dele + ins, 2, 1))
-            base = src.copy()
-            subm = (u >= dele + ins) & (u < dele + ins + sub)
-            ks = int(subm.sum())
-            if ks:
-                base[subm] = (base[subm] + rng.integers(1, 4, size=ks, dtype=np.uint8)) & 3
-            rep = np.repeat(base, copies)
-            ins_pos = np.flatnonzero(copies == 2)
-            if len(ins_pos):
-                # the second copy of an inserted base becomes a random base
-                out_idx = np.cumsum(copies) - 1
-                rep[out_idx[ins_pos]] = rng.integers(0, 4, size=len(ins_pos), dtype=np.uint8)
-            pieces.append(rep)
-            out_lens[r0 + t] = len(rep)
+    lens = np.clip(np.rint(np.random.default_rng(s_len).lognormal(mu, sigma, size=m)),
+                   min_len, max_len).astype(np.int64)
+    bounds = list(range(0, m, chunk))
+    seeds = s_chunks.spawn(len(bounds))
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        res = list(ex.map(lambda a: _long_chunk(seeds[a[0]], ref, lens[a[1]:min(m, a[1] + chunk)],
+                                                sub, ins, dele), enumerate(bounds)))
+    out_lens = np.concatenate([r[1] for r in res]) if res else np.zeros(0, np.int64)
     offsets = np.zeros(m + 1, dtype=np.uint64)
     offsets[1:] = np.cumsum(out_lens).astype(np.uint64)
-    return pack_codes(np.concatenate(pieces) if pieces else np.zeros(0, np.uint8)), offsets
+    codes = np.concatenate([r[0] for r in res]) if res else np.zeros(0, np.uint8)
+    return pack_codes(codes), offsets
 
 
 def take_reads(packed: np.ndarray, offsets: np.ndarray, j0: int, j1: int):

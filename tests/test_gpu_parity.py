@@ -311,3 +311,48 @@ def test_deterministic(B, oracle_mod):
     assert outs[0] == outs[1]
     c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
     assert outs[0] == oracle_mod.bwt_of_codes(c1, o1)
+
+
+@pytest.mark.parametrize("copies", [255, 256, 257, 600])
+def test_group_size_around_refine_limit(B, torch_dev, oracle_mod, copies):
+    # `copies` identical reads give tied groups of exactly that size: up to
+    # 256 they are finished in LDS, above that by prefix doubling
+    torch = torch_dev
+    rng = np.random.default_rng(100 + copies)
+    base = rng.integers(0, 4, 80, dtype=np.uint8)
+    other = [rng.integers(0, 4, int(rng.integers(0, 120)), dtype=np.uint8) for _ in range(300)]
+    reads = [base] * copies + other
+    codes = np.concatenate(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(r) for r in reads])
+    packed = synth.pack_codes(codes)
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    sa_want, T = oracle_mod.construct_sa(c1, o1)
+    n = len(T)
+    sa = torch.empty(n, dtype=torch.int32, device="cuda")
+    bint = torch.empty(n, dtype=torch.uint8, device="cuda")
+    with B.BwtSet() as idx:
+        idx.block_sort(packed, offs, sa, bint)
+        assert np.array_equal(sa.cpu().numpy().astype(np.uint64), sa_want)
+        # and through the whole path, split so that later blocks rank against
+        # an index that already holds copies of the same read
+        idx.set_block_size(9000)
+        idx.append(packed, offs)
+        assert idx.export() == oracle_mod.bwt_of_codes(c1, o1)
+
+
+def test_identical_long_reads(B, oracle_mod):
+    # three copies of a 6,000-symbol read: the tied group needs ~200 chunk passes
+    rng = np.random.default_rng(45)
+    r = rng.integers(0, 4, 6000, dtype=np.uint8)
+    reads = [r, r[:5000], r, rng.integers(0, 4, 3000, dtype=np.uint8), r]
+    codes = np.concatenate(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(x) for x in reads])
+    packed = synth.pack_codes(codes)
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    want = oracle_mod.bwt_of_codes(c1, o1)
+    for M in (1 << 20, 7000):
+        with B.BwtSet(block_size=M) as idx:
+            idx.append(packed, offs)
+            assert idx.export() == want, M
