@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--reads", type=int, default=4_000_000)
     ap.add_argument("--block", type=int, default=1 << 26)
+    ap.add_argument("--key-bits", type=int, default=None,
+                    help="width of the first suffix-sort key (library default if omitted)")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -130,6 +132,8 @@ def main():
     torch.cuda.synchronize()
 
     idx = bwtset.BwtSet(block_size=args.block)
+    if args.key_bits is not None:
+        idx.set_key_bits(args.key_bits)
     for w in range(args.warmup):
         idx.reset()
         idx.append(dev_reads, dev_offs, stream)
@@ -190,10 +194,17 @@ def main():
         "config": {"workload": "short reads: %d x 100 bp from a random 50 Mbp reference, both "
                                "strands, 1%% substitutions; block M=%d suffixes" % (m, args.block),
                    "reads": m, "bases": bases, "block_suffixes": args.block,
-                   "blocks": st["blocks"] // args.steps},
+                   "blocks": st["blocks"] // args.steps, "key_bits": args.key_bits},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
         "stages_ms_per_step": {s: round(st["ms"][s] / args.steps, 3) for s in bwtset.STAGES},
+        "sort_detail_ms_per_step": {
+            "keys": round(st["keys_ms"] / args.steps, 3),
+            "radix_passes": round(st["sort_pass_ms"] / args.steps, 3),
+            "tie_detection": round(st["heads_ms"] / args.steps, 3),
+            "refine": round(st["refine_ms"] / args.steps, 3)},
+        "tied_fraction": st["tied_suffixes"] / float(args.steps * (bases + m)),
+        "fallback_blocks_per_step": st["fallback_blocks"] / args.steps,
         "doubling_rounds_per_step": st["doubling_rounds"] / args.steps,
     }
     idx.close()

@@ -96,6 +96,14 @@ int bwt_set_reset(bwt_set_t h);
  * 2^26.  Must be at least 1.  The result does not depend on M. */
 int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
 
+/* Tuning knobs; none changes the result.
+ *   BWT_PARAM_KEY_BITS: width in bits (16..64, default 64) of the first
+ *     suffix-sort key, which holds g (the rank among the old suffixes, from
+ *     ComputeRanks) above as many 2-bit symbols as fit.  Fewer bits mean fewer
+ *     8-bit radix passes and more ties left to the LDS refinement. */
+enum { BWT_PARAM_KEY_BITS = 1 };
+int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
+
 /* Last error code recorded on h (or, for h == NULL, by bwt_set_create). */
 int bwt_set_last_error(bwt_set_t h);
 
@@ -155,7 +163,12 @@ typedef struct {
     uint64_t sort_pass_launches;
     uint64_t sort_pass_keys;        /* keys moved by radix passes */
     uint64_t blocks;                /* blocks processed */
-    uint64_t doubling_rounds;       /* prefix-doubling rounds after the first sort */
+    uint64_t doubling_rounds;       /* prefix-doubling rounds (large tied groups only) */
+    double keys_ms;                 /* first-key build */
+    double heads_ms;                /* tied-group detection after the first sort */
+    double refine_ms;               /* LDS refinement of tied groups */
+    uint64_t tied_suffixes;         /* suffixes left tied by the first sort */
+    uint64_t fallback_blocks;       /* blocks sorted by prefix doubling */
 } bwt_stats_t;
 
 /* Turns per-stage HIP-event timing on (1) or off (0).  Timing adds event

@@ -45,6 +45,11 @@ class Stats(ctypes.Structure):
         ("sort_pass_keys", ctypes.c_uint64),
         ("blocks", ctypes.c_uint64),
         ("doubling_rounds", ctypes.c_uint64),
+        ("keys_ms", ctypes.c_double),
+        ("heads_ms", ctypes.c_double),
+        ("refine_ms", ctypes.c_double),
+        ("tied_suffixes", ctypes.c_uint64),
+        ("fallback_blocks", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -63,8 +68,9 @@ EXPORTED = [
     "bwt_set_rank_many", "bwt_set_export", "bwt_set_size", "bwt_set_reset",
     "bwt_set_set_block_size", "bwt_set_last_error", "bwt_set_strerror",
     "bwt_set_block_sort", "bwt_set_compute_ranks", "bwt_set_insert",
-    "bwt_set_enable_timing", "bwt_set_get_stats",
+    "bwt_set_enable_timing", "bwt_set_get_stats", "bwt_set_set_param",
 ]
+BWT_PARAM_KEY_BITS = 1
 
 _lib = None
 
@@ -111,6 +117,8 @@ def load(path: str = LIB_PATH):
     L.bwt_set_enable_timing.restype = i32
     L.bwt_set_get_stats.argtypes = [vp, ctypes.POINTER(Stats), i32]
     L.bwt_set_get_stats.restype = i32
+    L.bwt_set_set_param.argtypes = [vp, i32, ctypes.c_int64]
+    L.bwt_set_set_param.restype = i32
     if path == LIB_PATH:
         _lib = L
     return L
@@ -203,6 +211,10 @@ class BwtSet:
     # -- the ABI
     def set_block_size(self, M: int) -> None:
         self._check(load().bwt_set_set_block_size(self._h, int(M)), "bwt_set_set_block_size")
+
+    def set_key_bits(self, bits: int) -> None:
+        self._check(load().bwt_set_set_param(self._h, BWT_PARAM_KEY_BITS, int(bits)),
+                    "bwt_set_set_param")
 
     def append(self, reads, offsets, stream=None) -> None:
         """Append m = len(offsets) - 1 reads (2-bit packed, see synth.py)."""

@@ -54,11 +54,12 @@ inline uint64_t superblocks_for(uint64_t n) { return (n >> SB_SHIFT) + 1; }
 // First sort key of p.  g[p] (ComputeRanks: old suffixes smaller than the
 // block suffix at p) is non-decreasing in suffix order, so it can lead the
 // key without changing the order, and g_sa comes out of the sort with it:
-//   key = g[p] << (64 - gbits) | sym << 5 | t,
-// gbits = bits needed for values up to n_ext (0 for an empty index),
-// K' = min(29, (59 - gbits) / 2) symbols, r = symbols of p's read before its
-// terminator, t = min(r, K'), sym = the first t symbols, 2 bits each, first
-// symbol most significant, zero-padded to K' symbols.  Equal keys with t < K'
+//   key = g[p] << gshift | sym << 5 | t,   gshift = key_bits - gbits,
+// gbits = bits needed for values up to n_ext (0 for an empty index: no g),
+// key_bits = width of the key (64 by default; fewer bits, fewer radix
+// passes), K' = min(29, (key_bits - 5 - gbits) / 2) symbols, r = symbols of
+// p's read before its terminator, t = min(r, K'), sym = the first t symbols,
+// 2 bits each, first symbol most significant, zero-padded to K' symbols.  Equal keys with t < K'
 // end in their terminators and are ordered by read index, i.e. by position,
 // which the stable sort keeps.  Later chunks of 29 symbols at depth d use the
 // same layout without g (chunk keys).
@@ -70,9 +71,10 @@ constexpr uint32_t POS_MASK = (1u << POS_BITS) - 1u;
 constexpr uint64_t MAX_BLOCK = (1ull << POS_BITS) - 1;  // suffixes per block
 constexpr uint64_t MAX_READ = MAX_BLOCK - 1;            // symbols per read
 
-__host__ __device__ inline int first_key_syms(int gbits) {
-    int k = (64 - KEY_LEN_BITS - gbits) / 2;
-    return k < KEY_K ? k : KEY_K;
+// symbols that fit a first key of key_bits bits after gbits bits of g
+__host__ __device__ inline int first_key_syms(int gbits, int key_bits) {
+    int k = (key_bits - KEY_LEN_BITS - gbits) / 2;
+    return k < 0 ? 0 : (k < KEY_K ? k : KEY_K);
 }
 
 // groups of tied suffixes up to this size are finished in LDS by comparing
@@ -101,22 +103,26 @@ __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a +
 // fails (a bounded wait timed out, an index would leave its buffer); the host
 // reads it after every append and treats a nonzero value as a failure.
 
-// radix sort pieces (k_radix.hip)
-hipError_t launch_radix_hist(const uint64_t *keys, uint64_t n, int npass, uint32_t *hist,
-                             hipStream_t s);
+// radix sort pieces (k_radix.hip).  hist: 8 x 256 digit counts, pass p at
+// p * 256; pass p reads its counts and adds the next pass's into hist_next.
+hipError_t launch_radix_hist1(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
+                              hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                             uint32_t *vout, uint64_t n, int shift, const uint32_t *dstart,
-                             uint64_t *status, uint32_t *counter, uint32_t epoch, uint32_t *err,
-                             hipStream_t s);
+                             uint32_t *vout, uint64_t n, int shift, const uint32_t *hist,
+                             uint32_t *hist_next, int shift_next, uint64_t *status,
+                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s);
 
 // block preparation, suffix sorting and refinement (k_sa.hip)
 hipError_t launch_block_soff(const uint64_t *off, uint32_t m_blk, uint32_t *soff, hipStream_t s);
 hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
                                    uint32_t *tile_first, hipStream_t s);
-// g may be null when gbits == 0
+// key = g[p] << gshift | (kfirst symbols) << 5 | count (g may be null: no
+// g); hist0 (zeroed by the caller) receives the counts of the low 8 bits
 hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                              const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
-                             int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s);
+                             int gshift, int kfirst, uint64_t *keys, uint32_t *vals,
+                             uint32_t *hist0, hipStream_t s);
 // Groups after a sort.  Round 0 (U == nullptr): element i is SA slot i, and a
 // key whose length field is below kshort is a singleton.  Doubling round:
 // element u is SA slot U[u] and its value is stored there.  rank == nullptr
@@ -144,9 +150,9 @@ hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const
                                 const uint64_t *meta, int big, uint64_t *g, hipStream_t s);
 
 // Insert and index bookkeeping (k_insert.hip).  The new symbols come in
-// suffix order as the sorted (key, value) pairs of ConstructSA: g_sa[i] is the
-// top gbits bits of gkeys[i] (0 when gbits == 0) and the symbol code (0..3
-// for A..T, 4 for '$') is vals[i] >> 29.
+// suffix order as the sorted (key, value) pairs of ConstructSA: g_sa[i] is
+// gkeys[i] >> gshift (0 for every i when gshift == 64) and the symbol code
+// (0..3 for A..T, 4 for '$') is vals[i] >> 29.
 hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream_t s);
 hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *bcnt, uint64_t *status,
                              uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s);
@@ -155,15 +161,15 @@ hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *bcnt, u
 hipError_t launch_check_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
                                    uint64_t n_ext, uint32_t *bad, hipStream_t s);
 hipError_t launch_pack_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
-                                  int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s);
-hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gbits, uint64_t n_new,
+                                  int gshift, uint64_t *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gshift, uint64_t n_new,
                                  uint64_t ntiles, uint64_t *first_new, hipStream_t s);
 hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
-                           const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                           const uint64_t *gkeys, int gshift, const uint32_t *vals,
                            const uint32_t *bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
                            hipStream_t s);
 hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
-                         const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                         const uint64_t *gkeys, int gshift, const uint32_t *vals,
                          const uint32_t *bcnt, uint64_t n_new, const uint64_t *first_new,
                          Rec *nrecs, const uint64_t *nsbc, uint32_t *err, hipStream_t s);
 

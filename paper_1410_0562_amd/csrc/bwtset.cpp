@@ -91,7 +91,14 @@ struct Timer {
     }
 };
 
-enum { SPAN_RANKS_K = 100, SPAN_INSERT_K = 101, SPAN_RADIX_PASS = 102 };
+enum {
+    SPAN_RANKS_K = 100,
+    SPAN_INSERT_K = 101,
+    SPAN_RADIX_PASS = 102,
+    SPAN_KEYS = 103,
+    SPAN_HEADS = 104,
+    SPAN_REFINE = 105
+};
 
 }  // namespace
 
@@ -103,6 +110,7 @@ struct bwt_set {
     int cur = 0;
     Workspace ws;
     uint64_t M = 1ull << 26;
+    int key_bits = 64;               // width of the first suffix-sort key
     uint64_t *first_new = nullptr;
     uint64_t first_new_cap = 0;
     // staging for host inputs / outputs
@@ -213,6 +221,12 @@ void timer_collect(bwt_set *h) {
             T.acc.sort_pass_ms += ms;
             T.acc.sort_pass_launches += 1;
             T.acc.sort_pass_keys += sp.units;
+        } else if (sp.stage == SPAN_KEYS) {
+            T.acc.keys_ms += ms;
+        } else if (sp.stage == SPAN_HEADS) {
+            T.acc.heads_ms += ms;
+        } else if (sp.stage == SPAN_REFINE) {
+            T.acc.refine_ms += ms;
         }
         T.pool.push_back(sp.a);
         T.pool.push_back(sp.b);
@@ -329,23 +343,29 @@ int bits_for(uint64_t v) {  // bits needed to hold values < v (at least 1)
 
 // ---- radix sort -------------------------------------------------------------
 // Sorts (kin, vin) by the low `bits` bits of the keys, ping-ponging with
-// (kalt, valt); returns via *ko / *vo where the sorted data ended up.
+// (kalt, valt); returns via *ko / *vo where the sorted data ended up.  When
+// counted0 is set, the producer of the keys already left the counts of their
+// low digit in the first 256 histogram words.
 int radix_sort(bwt_set *h, hipStream_t s, uint64_t *kin, uint32_t *vin, uint64_t *kalt,
-               uint32_t *valt, uint64_t n, int bits, uint64_t **ko, uint32_t **vo) {
+               uint32_t *valt, uint64_t n, int bits, bool counted0, uint64_t **ko,
+               uint32_t **vo) {
     Workspace &w = h->ws;
-    int npass = (bits + 7) / 8;
+    const int npass = bits < 1 ? 1 : (bits + 7) / 8;
     *ko = kin;
     *vo = vin;
     if (n <= 1) return BWT_OK;
-    HIPCHK(h, launch_radix_hist(kin, n, npass, w.misc + MISC_HIST, s));
+    uint32_t *hist = w.misc + MISC_HIST;
+    if (!counted0) HIPCHK(h, launch_radix_hist1(kin, n, 0, hist, s));
+    if (npass > 1) HIPCHK(h, launch_zero_u32(hist + 256, 256 * (npass - 1), s));
     uint64_t *ka = kin, *kb = kalt;
     uint32_t *va = vin, *vb = valt;
     for (int p = 0; p < npass; ++p) {
         {
             Scope sc(h, s, SPAN_RADIX_PASS, n);
-            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, 8 * p, w.misc + MISC_HIST + 256 * p,
-                                        w.status_radix, w.misc + MISC_CNT_RADIX, next_epoch(),
-                                        w.misc + MISC_ERR, s));
+            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, 8 * p, hist + 256 * p,
+                                        p + 1 < npass ? hist + 256 * (p + 1) : nullptr,
+                                        8 * (p + 1), w.status_radix, w.misc + MISC_CNT_RADIX,
+                                        next_epoch(), w.misc + MISC_ERR, s));
         }
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -394,45 +414,77 @@ int block_prep(bwt_set *h, hipStream_t s, const uint64_t *off, uint32_t m_blk, u
 }
 
 // Suffix array of one block (after block_prep).  reads/off: device; off
-// points at the block's first read (m_blk + 1 entries).  g (text order, may be
-// null when gbits == 0) leads the first sort key.  On return *sa_out holds the
-// suffix array (values carry the preceding symbol in bits 29..31) and
-// *gkeys_out keys whose top gbits bits are g_sa, both indexed by SA slot.
+// points at the block's first read (m_blk + 1 entries).  g (text order, may
+// be null when gbits == 0) leads the first sort key.  On return *sa_out holds
+// the suffix array (values carry the preceding symbol in bits 29..31) and
+// *gkeys_out / *gshift_out give g_sa per SA slot (g_sa = key >> gshift).
 int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *off,
                uint32_t m_blk, uint32_t n_blk, uint64_t maxlen, const uint64_t *g, int gbits,
-               uint32_t **sa_out, const uint64_t **gkeys_out) {
+               uint32_t **sa_out, const uint64_t **gkeys_out, int *gshift_out) {
     (void)m_blk;
     Workspace &w = h->ws;
     Scope sc(h, s, BWT_STAGE_SORT);
-    const int kfirst = first_key_syms(gbits);
-    HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, g, gbits, w.kA, w.v[0], s));
+    int key_bits = h->key_bits < gbits + 1 ? gbits + 1 : h->key_bits;
+    if (key_bits > 64) key_bits = 64;
+    int kfirst = first_key_syms(gbits, key_bits);
+    int gshift = gbits ? key_bits - gbits : 64;
+    int sort_bits = gbits ? key_bits : 2 * kfirst + KEY_LEN_BITS;
+    uint32_t *hist = w.misc + MISC_HIST;
+    HIPCHK(h, launch_zero_u32(hist, 256, s));
+    {
+        Scope sk(h, s, SPAN_KEYS);
+        HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
+                                    gshift, kfirst, w.kA, w.v[0], hist, s));
+    }
     uint64_t *ks;
     uint32_t *vs;
-    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, gbits ? 64 : 2 * kfirst + 5,
-                        &ks, &vs);
+    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, sort_bits, true, &ks, &vs);
     if (rc) return rc;
     uint32_t *sa = vs;
     *sa_out = sa;
     *gkeys_out = ks;
+    *gshift_out = gshift;
     HIPCHK(h, hipMemsetAsync(w.misc + MISC_LARGE, 0, 4, s));
-    HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, kfirst, sa, nullptr, w.U[0],
-                                 w.misc + MISC_NU, REFINE_LIMIT, w.misc + MISC_LARGE,
-                                 w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
-                                 w.misc + MISC_ERR, s));
+    {
+        Scope sk(h, s, SPAN_HEADS);
+        HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, kfirst, sa, nullptr, w.U[0],
+                                     w.misc + MISC_NU, REFINE_LIMIT, w.misc + MISC_LARGE,
+                                     w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
+                                     w.misc + MISC_ERR, s));
+    }
     HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     uint32_t nU = reinterpret_cast<uint32_t *>(h->pinned)[0];
     const bool large = reinterpret_cast<uint32_t *>(h->pinned)[1] != 0;
+    h->timer.acc.tied_suffixes += nU;
     if (nU == 0) return BWT_OK;
     if (!large) {
         // every tied group is small: finish them in LDS by chunk keys
         const uint32_t max_iter = (uint32_t)(maxlen / KEY_K + 2);
+        Scope sk(h, s, SPAN_REFINE);
         HIPCHK(h, launch_refine(reads, off, w.soff, w.tile_first, ks, w.U[0], nU, sa, kfirst,
                                 max_iter, w.misc + MISC_ERR, s));
         return BWT_OK;
     }
-    // A group too large for LDS: prefix doubling over all tied suffixes.
+    // A tied group too large for LDS: prefix doubling over all tied
+    // suffixes, from a first key with as many symbols as fit in 64 bits (a
+    // doubling round needs the tied suffixes to share at least one symbol).
     // The doubling sorts reuse both key buffers, so g_sa moves to w.g first.
+    h->timer.acc.fallback_blocks += 1;
+    if (key_bits < 64 || kfirst < 1) {
+        key_bits = 64;
+        kfirst = first_key_syms(gbits, key_bits);
+        gshift = gbits ? key_bits - gbits : 64;
+        if (kfirst < 1) return fail(h, BWT_EHIP);
+        HIPCHK(h, launch_zero_u32(hist, 256, s));
+        HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
+                                    gshift, kfirst, w.kA, w.v[0], hist, s));
+        rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, 64, true, &ks, &vs);
+        if (rc) return rc;
+        sa = vs;
+        *sa_out = sa;
+        *gshift_out = gshift;
+    }
     HIPCHK(h, hipMemcpyAsync(w.g, ks, (uint64_t)n_blk * 8, hipMemcpyDeviceToDevice, s));
     *gkeys_out = w.g;
     uint32_t *spare[2];
@@ -456,7 +508,7 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
         h->timer.acc.doubling_rounds += 1;
         HIPCHK(h, launch_doubling_keys(w.U[ui], nU, sa, w.rank, hlen, rbits, n_blk, w.kA,
                                        spare[0], w.misc + MISC_ERR, s));
-        rc = radix_sort(h, s, w.kA, spare[0], w.kB, spare[1], nU, 2 * rbits, &ks, &vs);
+        rc = radix_sort(h, s, w.kA, spare[0], w.kB, spare[1], nU, 2 * rbits, false, &ks, &vs);
         if (rc) return rc;
         HIPCHK(h, launch_group_heads(ks, vs, w.U[ui], nU, 0, sa, w.rank, w.U[ui ^ 1],
                                      w.misc + MISC_NU, 0xffffffffu, w.misc + MISC_LARGE,
@@ -473,7 +525,7 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
 // Merges the n_new sorted block symbols (gkeys/gbits give g_sa, vals the
 // symbol codes) into src, writing dst.
 int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, uint64_t n_ext,
-                 const uint64_t *gkeys, int gbits, const uint32_t *vals, uint64_t n_new) {
+                 const uint64_t *gkeys, int gshift, const uint32_t *vals, uint64_t n_new) {
     Workspace &w = h->ws;
     const uint64_t n_out = n_ext + n_new;
     const uint64_t ntiles = div_up(records_for(n_out), INS_TILE_RECS);
@@ -482,12 +534,12 @@ int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, 
     Scope sc(h, s, BWT_STAGE_INSERT);
     HIPCHK(h, launch_count_bint(vals, (uint32_t)n_new, w.bcnt, w.status_scan,
                                 w.misc + MISC_CNT_BINT, next_epoch(), w.misc + MISC_ERR, s));
-    HIPCHK(h, launch_ins_tile_first(gkeys, gbits, n_new, ntiles, h->first_new, s));
-    HIPCHK(h, launch_ins_meta(src.recs, src.sbc, src.meta, gkeys, gbits, vals, w.bcnt, n_new,
+    HIPCHK(h, launch_ins_tile_first(gkeys, gshift, n_new, ntiles, h->first_new, s));
+    HIPCHK(h, launch_ins_meta(src.recs, src.sbc, src.meta, gkeys, gshift, vals, w.bcnt, n_new,
                               dst.sbc, dst.meta, s));
     {
         Scope sk(h, s, SPAN_INSERT_K);
-        HIPCHK(h, launch_insert(src.recs, src.sbc, n_ext, gkeys, gbits, vals, w.bcnt, n_new,
+        HIPCHK(h, launch_insert(src.recs, src.sbc, n_ext, gkeys, gshift, vals, w.bcnt, n_new,
                                 h->first_new, dst.recs, dst.sbc, w.misc + MISC_ERR, s));
     }
     if (h->timer.on) {
@@ -740,10 +792,12 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
         }
         uint32_t *sa = nullptr;
         const uint64_t *gkeys = nullptr;
-        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, &sa, &gkeys)))
+        int gshift = 64;
+        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, &sa, &gkeys,
+                             &gshift)))
             return rc;
         const int dst = other[b & 1];
-        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gbits, sa, n_blk))) return rc;
+        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gshift, sa, n_blk))) return rc;
         n_cur += n_blk;
         h->timer.acc.blocks += 1;
         src = dst;
@@ -845,6 +899,18 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M) {
     return BWT_OK;
 }
 
+int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
+    if (!h) return BWT_EINVAL;
+    switch (param) {
+    case BWT_PARAM_KEY_BITS:
+        if (value < 16 || value > 64) return fail(h, BWT_EINVAL);
+        h->key_bits = (int)value;
+        return BWT_OK;
+    default:
+        return fail(h, BWT_EINVAL);
+    }
+}
+
 int bwt_set_last_error(bwt_set_t h) { return h ? h->last_error : g_create_error; }
 
 const char *bwt_set_strerror(int code) {
@@ -875,10 +941,11 @@ int bwt_set_block_sort(bwt_set_t h, const uint8_t *reads, const uint64_t *offset
     if ((rc = clear_err(h, s))) return rc;
     uint32_t *sa = nullptr;
     const uint64_t *gkeys = nullptr;
+    int gshift = 64;
     const uint32_t n_blk = (uint32_t)P.total_suffixes;
     if ((rc = block_prep(h, s, P.off, (uint32_t)m, n_blk))) return rc;
     if ((rc = block_sort(h, s, P.reads, P.off, (uint32_t)m, n_blk, P.maxlen, nullptr, 0, &sa,
-                         &gkeys)))
+                         &gkeys, &gshift)))
         return rc;
     HIPCHK(h, launch_vals_to_ascii(sa, n_blk, bint_out, s));
     HIPCHK(h, launch_sa_strip(sa, n_blk, sa_out, s));
@@ -933,8 +1000,9 @@ int bwt_set_insert(bwt_set_t h, const uint8_t *bint, const uint64_t *gsa, uint64
     if ((rc = read_u32(h, s, w.misc + MISC_BAD, &bad))) return rc;
     if (bad) return fail(h, BWT_EINVAL);
     const int gbits = bits_for_value(h->n);
-    HIPCHK(h, launch_pack_user_insert(bint, gsa, n_new, gbits, w.kA, w.v[0], s));
-    if ((rc = insert_block(h, s, h->buf[h->cur], h->buf[dst], h->n, w.kA, gbits, w.v[0], n_new)))
+    const int gshift = gbits ? 64 - gbits : 64;
+    HIPCHK(h, launch_pack_user_insert(bint, gsa, n_new, gshift, w.kA, w.v[0], s));
+    if ((rc = insert_block(h, s, h->buf[h->cur], h->buf[dst], h->n, w.kA, gshift, w.v[0], n_new)))
         return rc;
     // the number of terminators merged in comes from the new counts
     HIPCHK(h, hipMemcpyAsync(h->pinned, h->buf[dst].meta, META_WORDS * 8, hipMemcpyDeviceToHost, s));

@@ -37,9 +37,10 @@ __global__ void index_init_kernel(Rec *recs, uint64_t *sbc, uint64_t *meta) {
     if (t < META_WORDS) meta[t] = 0;
 }
 
-__device__ __forceinline__ uint64_t gsa_at(const uint64_t *__restrict__ gkeys, int gbits,
+// g_sa[i] sits in the key bits from gshift up (gshift = 64: no g, all zero)
+__device__ __forceinline__ uint64_t gsa_at(const uint64_t *__restrict__ gkeys, int gshift,
                                            uint64_t i) {
-    return gbits ? gkeys[i] >> (64 - gbits) : 0ull;
+    return gshift < 64 ? gkeys[i] >> gshift : 0ull;
 }
 
 __device__ __forceinline__ int code_at(const uint32_t *__restrict__ vals, uint64_t i) {
@@ -116,16 +117,16 @@ __global__ void check_user_insert_kernel(const uint8_t *__restrict__ bint,
 }
 
 __global__ void pack_user_insert_kernel(const uint8_t *__restrict__ bint,
-                                        const uint64_t *__restrict__ gsa, uint64_t n_new, int gbits,
+                                        const uint64_t *__restrict__ gsa, uint64_t n_new, int gshift,
                                         uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_new) return;
-    keys[i] = gbits ? gsa[i] << (64 - gbits) : 0ull;
+    keys[i] = gshift < 64 ? gsa[i] << gshift : 0ull;
     vals[i] = (uint32_t)code_of_ascii(bint[i]) << POS_BITS;
 }
 
 // first_new[t] = number of new symbols whose output row is below t * 2048
-__global__ void ins_tile_first_kernel(const uint64_t *__restrict__ gkeys, int gbits,
+__global__ void ins_tile_first_kernel(const uint64_t *__restrict__ gkeys, int gshift,
                                       uint64_t n_new, uint64_t ntiles,
                                       uint64_t *__restrict__ first_new) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,7 +135,7 @@ __global__ void ins_tile_first_kernel(const uint64_t *__restrict__ gkeys, int gb
     uint64_t lo = 0, hi = n_new;
     while (lo < hi) {  // first i with g_sa[i] + i >= Q
         uint64_t mid = (lo + hi) >> 1;
-        if (gsa_at(gkeys, gbits, mid) + mid >= Q) hi = mid;
+        if (gsa_at(gkeys, gshift, mid) + mid >= Q) hi = mid;
         else lo = mid + 1;
     }
     first_new[t] = lo;
@@ -151,7 +152,7 @@ __device__ uint64_t rank_bint(const uint32_t *__restrict__ vals, const uint32_t 
 // thread; the number of superblocks is n / 2^32 + 1).
 __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
                                 const uint64_t *__restrict__ ometa,
-                                const uint64_t *__restrict__ gkeys, int gbits,
+                                const uint64_t *__restrict__ gkeys, int gshift,
                                 const uint32_t *__restrict__ vals,
                                 const uint32_t *__restrict__ bcnt, uint64_t n_new,
                                 uint64_t *__restrict__ nsbc, uint64_t *__restrict__ nmeta) {
@@ -175,7 +176,7 @@ __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *_
         uint64_t lo = 0, hi = n_new;
         while (lo < hi) {
             uint64_t mid = (lo + hi) >> 1;
-            if (gsa_at(gkeys, gbits, mid) + mid >= Q) hi = mid;
+            if (gsa_at(gkeys, gshift, mid) + mid >= Q) hi = mid;
             else lo = mid + 1;
         }
         uint64_t o = Q - lo;
@@ -186,7 +187,7 @@ __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *_
 
 __global__ __launch_bounds__(256) void insert_kernel(
     const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
-    const uint64_t *__restrict__ gkeys, int gbits, const uint32_t *__restrict__ vals,
+    const uint64_t *__restrict__ gkeys, int gshift, const uint32_t *__restrict__ vals,
     const uint32_t *__restrict__ bcnt, const uint64_t *__restrict__ first_new,
     Rec *__restrict__ nrecs, const uint64_t *__restrict__ nsbc, uint64_t n_out, uint64_t nrec_out,
     uint64_t nrec_in, uint32_t *__restrict__ err) {
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(256) void insert_kernel(
     }
     __syncthreads();
     for (uint64_t i = a0 + tid; i < a1; i += 256) {
-        uint64_t pos = gsa_at(gkeys, gbits, i) + i - q0;
+        uint64_t pos = gsa_at(gkeys, gshift, i) + i - q0;
         if (pos < INS_TILE_SYMS) atomicOr(&s_bm[pos >> 5], 1u << (pos & 31));
         else atomicOr(err, 32u);
         s_new[i - a0] = (uint8_t)code_at(vals, i);
@@ -338,37 +339,37 @@ hipError_t launch_check_user_insert(const uint8_t *bint, const uint64_t *gsa, ui
 }
 
 hipError_t launch_pack_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
-                                  int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+                                  int gshift, uint64_t *keys, uint32_t *vals, hipStream_t s) {
     if (n_new == 0) return hipSuccess;
-    pack_user_insert_kernel<<<(unsigned)div_up(n_new, 256), 256, 0, s>>>(bint, gsa, n_new, gbits,
+    pack_user_insert_kernel<<<(unsigned)div_up(n_new, 256), 256, 0, s>>>(bint, gsa, n_new, gshift,
                                                                          keys, vals);
     return hipGetLastError();
 }
 
-hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gbits, uint64_t n_new,
+hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gshift, uint64_t n_new,
                                  uint64_t ntiles, uint64_t *first_new, hipStream_t s) {
-    ins_tile_first_kernel<<<(unsigned)div_up(ntiles + 1, 256), 256, 0, s>>>(gkeys, gbits, n_new,
+    ins_tile_first_kernel<<<(unsigned)div_up(ntiles + 1, 256), 256, 0, s>>>(gkeys, gshift, n_new,
                                                                            ntiles, first_new);
     return hipGetLastError();
 }
 
 hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
-                           const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                           const uint64_t *gkeys, int gshift, const uint32_t *vals,
                            const uint32_t *bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
                            hipStream_t s) {
-    ins_meta_kernel<<<1, 64, 0, s>>>(orecs, osbc, ometa, gkeys, gbits, vals, bcnt, n_new, nsbc,
+    ins_meta_kernel<<<1, 64, 0, s>>>(orecs, osbc, ometa, gkeys, gshift, vals, bcnt, n_new, nsbc,
                                      nmeta);
     return hipGetLastError();
 }
 
 hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
-                         const uint64_t *gkeys, int gbits, const uint32_t *vals,
+                         const uint64_t *gkeys, int gshift, const uint32_t *vals,
                          const uint32_t *bcnt, uint64_t n_new, const uint64_t *first_new,
                          Rec *nrecs, const uint64_t *nsbc, uint32_t *err, hipStream_t s) {
     const uint64_t n_out = n_ext + n_new;
     const uint64_t nrec_out = records_for(n_out);
     const uint64_t ntiles = div_up(nrec_out, INS_TILE_RECS);
-    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(orecs, osbc, gkeys, gbits, vals, bcnt, first_new,
+    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(orecs, osbc, gkeys, gshift, vals, bcnt, first_new,
                                                    nrecs, nsbc, n_out, nrec_out, records_for(n_ext),
                                                    err);
     return hipGetLastError();

@@ -41,24 +41,43 @@ __global__ void zero_words_kernel(uint64_t *p, int n) {
     if (i < n) p[i] = 0;
 }
 
-// res[0] |= 1 if offsets decrease somewhere; res[1] = longest read
-__global__ void check_offsets_kernel(const uint64_t *__restrict__ off, uint64_t m,
-                                     uint64_t *__restrict__ res) {
-    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// res[0] |= 1 if offsets decrease somewhere; res[1] = longest read.  A fixed
+// grid strides over the reads and each workgroup adds once, so the two
+// result words see one atomic per workgroup.
+__global__ __launch_bounds__(256) void check_offsets_kernel(const uint64_t *__restrict__ off,
+                                                            uint64_t m,
+                                                            uint64_t *__restrict__ res) {
+    __shared__ uint64_t s_len[4];
+    __shared__ uint32_t s_bad[4];
     uint64_t len = 0;
     bool bad = false;
-    if (j < m) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
+         j += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t a = off[j], b = off[j + 1];
-        bad = b < a;
-        len = bad ? 0 : b - a;
+        if (b < a) bad = true;
+        else len = (b - a) > len ? (b - a) : len;
     }
-    // one atomic per wave
-    if (__ballot(bad) != 0 && lane_id() == 0) atomicOr((unsigned long long *)&res[0], 1ull);
     for (int d = 32; d > 0; d >>= 1) {
         uint64_t o = __shfl_xor(len, d, 64);
         len = o > len ? o : len;
     }
-    if (lane_id() == 0 && len) atomicMax((unsigned long long *)&res[1], (unsigned long long)len);
+    const int w = threadIdx.x >> 6;
+    const bool anybad = __ballot(bad) != 0;
+    if (lane_id() == 0) {
+        s_len[w] = len;
+        s_bad[w] = anybad ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t L = 0;
+        uint32_t B = 0;
+        for (int k = 0; k < 4; ++k) {
+            L = s_len[k] > L ? s_len[k] : L;
+            B |= s_bad[k];
+        }
+        if (B) atomicOr((unsigned long long *)&res[0], 1ull);
+        if (L) atomicMax((unsigned long long *)&res[1], (unsigned long long)L);
+    }
 }
 
 // Greedy block split (Algorithm 1 blocks: whole reads, at most M suffixes,
@@ -110,8 +129,11 @@ hipError_t launch_export(const Rec *recs, uint64_t n, uint8_t *out, hipStream_t 
 // res: 4 words, cleared here
 hipError_t launch_check_offsets(const uint64_t *off, uint64_t m, uint64_t *res, hipStream_t s) {
     zero_words_kernel<<<1, 64, 0, s>>>(res, 4);
-    if (m > 0)
-        check_offsets_kernel<<<(unsigned)div_up(m, 256), 256, 0, s>>>(off, m, res);
+    if (m > 0) {
+        uint64_t want = div_up(m, 256 * 8);
+        unsigned grid = (unsigned)(want < 1024 ? (want > 0 ? want : 1) : 1024);
+        check_offsets_kernel<<<grid, 256, 0, s>>>(off, m, res);
+    }
     return hipGetLastError();
 }
 

@@ -8,8 +8,9 @@
 // with 8 wave ballots per key (stable: tile order is wave, item, lane), gets
 // the count of each digit in all earlier tiles by look-back, stages the tile
 // in LDS in sorted order and writes each digit run contiguously.  Keys are
-// read once and written once per pass; digit totals of every pass come from
-// one histogram kernel run before the first pass.
+// read once and written once per pass.  The digit totals a pass needs are
+// counted by the previous pass while it holds the keys in registers (the
+// first pass's by whoever built the keys), so no pass re-reads the keys.
 #include "dev_util.hpp"
 
 namespace bwt {
@@ -26,48 +27,29 @@ __global__ void radix_zero_kernel(uint32_t *hist, int n) {
     if (i < n) hist[i] = 0;
 }
 
-// Digit histograms of all passes in one read of the keys; the last workgroup
-// to finish turns them into exclusive digit starts (per pass).
-__global__ __launch_bounds__(256) void radix_hist_kernel(const uint64_t *__restrict__ keys,
-                                                         uint64_t n, int npass,
-                                                         uint32_t *__restrict__ hist,
-                                                         uint32_t *__restrict__ done) {
-    __shared__ uint32_t h[8][256];
-    __shared__ uint32_t s_last;
+// Counts of one digit of the keys (the first pass's digit for key producers
+// that do not count it themselves).  hist must be zero on entry.
+__global__ __launch_bounds__(256) void radix_hist1_kernel(const uint64_t *__restrict__ keys,
+                                                          uint64_t n, int shift,
+                                                          uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[256];
     int tid = threadIdx.x;
-    for (int p = 0; p < 8; ++p) h[p][tid] = 0;
+    h[tid] = 0;
     __syncthreads();
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + tid; i < n; i += (uint64_t)gridDim.x * 256) {
-        uint64_t k = keys[i];
-        for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255], 1u);
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + tid; i < n; i += (uint64_t)gridDim.x * 256)
+        atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
     __syncthreads();
-    for (int p = 0; p < npass; ++p)
-        if (h[p][tid]) atomicAdd(&hist[p * 256 + tid], h[p][tid]);
-    // the last workgroup converts counts to exclusive starts
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(done, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    __shared__ uint32_t tmp[4];
-    for (int p = 0; p < npass; ++p) {
-        uint32_t c = __hip_atomic_load(&hist[p * 256 + tid], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t tot;
-        uint32_t ex = block_excl_sum256(c, tmp, &tot);
-        hist[p * 256 + tid] = ex;
-    }
-    if (tid == 0) *done = 0;
+    if (h[tid]) atomicAdd(&hist[tid], h[tid]);
 }
 
 __global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ dstart,
-    uint64_t *__restrict__ status, uint32_t *__restrict__ counter, uint32_t ntiles, uint32_t epoch,
-    uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ hist,
+    uint32_t *__restrict__ hist_next, int shift_next, uint64_t *__restrict__ status,
+    uint32_t *__restrict__ counter, uint32_t ntiles, uint32_t epoch, uint32_t *__restrict__ err) {
     __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_dstart[256];        // global start of each digit
+    __shared__ uint32_t s_next[256];          // this tile's counts of the next pass's digit
     __shared__ uint32_t s_wh[RB_WAVES][256];  // per-wave digit counts, then wave offsets
     __shared__ uint32_t s_lstart[256];        // start of each digit inside the tile
     __shared__ int64_t s_gbase[256];          // global position minus tile position
@@ -77,6 +59,13 @@ __global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int d = lane; d < 256; d += WAVE) s_wh[wave][d] = 0;
+    s_next[tid] = 0;
+    {
+        // digit totals of this pass (counted by the previous pass or by the
+        // key builder) -> exclusive starts
+        uint32_t tot;
+        s_dstart[tid] = block_excl_sum256(hist[tid], s_tmp, &tot);
+    }
     const uint32_t tile = acquire_tile(counter, ntiles, &s_tile);
     if (tile >= ntiles) {  // only if the tile counter was not zero at launch
         if (tid == 0) atomicOr(err, 2u);
@@ -94,6 +83,14 @@ __global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
         bool ok = idx < n;
         k[e] = ok ? kin[idx] : 0;
         v[e] = ok ? vin[idx] : 0;
+    }
+    if (hist_next) {
+        // histogram of the next pass's digit while the keys are in registers
+#pragma unroll
+        for (int e = 0; e < RB_ITEMS; ++e) {
+            uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
+            if (idx < n) atomicAdd(&s_next[(uint32_t)(k[e] >> shift_next) & 255u], 1u);
+        }
     }
     const uint64_t ltm = lanemask_lt();
 #pragma unroll
@@ -127,7 +124,8 @@ __global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
     s_wh[3][d] = c0 + c1 + c2;
     s_lstart[d] = lstart;
     uint32_t excl = lookback(status + d, 256u, tile, epoch, total, OpSum(), 0u, err);
-    s_gbase[d] = (int64_t)dstart[d] + (int64_t)excl - (int64_t)lstart;
+    s_gbase[d] = (int64_t)s_dstart[d] + (int64_t)excl - (int64_t)lstart;
+    if (hist_next && s_next[d]) atomicAdd(&hist_next[d], s_next[d]);
     __syncthreads();
     // stage in LDS in sorted order
 #pragma unroll
@@ -161,26 +159,30 @@ __global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
 
 }  // namespace
 
-// hist: 8*256 words (pass p at p*256) followed by one completion counter;
-// all of it is cleared first, so nothing needs to be zero beforehand.
-hipError_t launch_radix_hist(const uint64_t *keys, uint64_t n, int npass, uint32_t *hist,
-                             hipStream_t s) {
-    int nz = 8 * 256 + 1;   // all pass histograms and the completion counter
-    radix_zero_kernel<<<(nz + 255) / 256, 256, 0, s>>>(hist, nz);
+// hist: counts of the digit at `shift`; zeroed here first
+hipError_t launch_radix_hist1(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
+                              hipStream_t s) {
+    radix_zero_kernel<<<1, 256, 0, s>>>(hist, 256);
     uint64_t want = div_up(n, 256 * 16);
     int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
-    radix_hist_kernel<<<grid, 256, 0, s>>>(keys, n, npass, hist, hist + 8 * 256);
+    radix_hist1_kernel<<<grid, 256, 0, s>>>(keys, n, shift, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s) {
+    radix_zero_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, (int)n);
     return hipGetLastError();
 }
 
 hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                             uint32_t *vout, uint64_t n, int shift, const uint32_t *dstart,
-                             uint64_t *status, uint32_t *counter, uint32_t epoch, uint32_t *err,
-                             hipStream_t s) {
+                             uint32_t *vout, uint64_t n, int shift, const uint32_t *hist,
+                             uint32_t *hist_next, int shift_next, uint64_t *status,
+                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s) {
     uint32_t ntiles = (uint32_t)div_up(n, RADIX_TILE);
     if (ntiles == 0) return hipSuccess;
-    radix_pass_kernel<<<ntiles, RB_THREADS, 0, s>>>(kin, vin, kout, vout, n, shift, dstart, status,
-                                                    counter, ntiles, epoch, err);
+    radix_pass_kernel<<<ntiles, RB_THREADS, 0, s>>>(kin, vin, kout, vout, n, shift, hist, hist_next,
+                                                    shift_next, status, counter, ntiles, epoch,
+                                                    err);
     return hipGetLastError();
 }
 

@@ -78,23 +78,41 @@ __device__ __forceinline__ uint64_t chunk_key(const uint8_t *__restrict__ reads,
     return (sym << KEY_LEN_BITS) | (uint64_t)take;
 }
 
+// One suffix per thread; a wave covers 64 consecutive positions, so lane 0
+// finds the read of the first one and every lane steps forward from there.
+// The counts of the key's low digit (the first radix pass) are gathered in
+// LDS and added to hist0 once per workgroup.
 __global__ __launch_bounds__(256) void block_keys_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first, uint32_t n_blk,
-    const uint64_t *__restrict__ g, int gbits, uint64_t *__restrict__ keys,
-    uint32_t *__restrict__ vals) {
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_blk) return;
-    const uint32_t j = find_read(soff, tile_first, p);
-    const uint32_t sj = soff[j];
-    const uint32_t t = p - sj;
-    const uint32_t r = soff[j + 1] - 1 - p;  // symbols before the terminator
-    const uint64_t s = off[j] + t;
-    uint64_t key = chunk_key(reads, s, r, first_key_syms(gbits));
-    if (gbits > 0) key |= g[p] << (64 - gbits);
-    keys[p] = key;
-    uint32_t prev = t == 0 ? 4u : (uint32_t)load_sym(reads, s - 1);
-    vals[p] = p | (prev << POS_BITS);
+    const uint64_t *__restrict__ g, int gshift, int kfirst, uint64_t *__restrict__ keys,
+    uint32_t *__restrict__ vals, uint32_t *__restrict__ hist0) {
+    __shared__ uint32_t s_h[256];
+    const int tid = threadIdx.x;
+    s_h[tid] = 0;
+    __syncthreads();
+    const uint32_t p0 = blockIdx.x * blockDim.x + (tid & ~63);
+    const uint32_t p = p0 + (tid & 63);
+    if (p0 < n_blk) {
+        uint32_t j = 0;
+        if ((tid & 63) == 0) j = find_read(soff, tile_first, p0);
+        j = __shfl(j, 0, 64);
+        if (p < n_blk) {
+            while (soff[j + 1] <= p) ++j;
+            const uint32_t sj = soff[j];
+            const uint32_t t = p - sj;
+            const uint32_t r = soff[j + 1] - 1 - p;  // symbols before the terminator
+            const uint64_t s = off[j] + t;
+            uint64_t key = kfirst > 0 ? chunk_key(reads, s, r, kfirst) : 0ull;
+            if (g) key |= g[p] << gshift;
+            keys[p] = key;
+            uint32_t prev = t == 0 ? 4u : (uint32_t)load_sym(reads, s - 1);
+            vals[p] = p | (prev << POS_BITS);
+            atomicAdd(&s_h[key & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    if (s_h[tid]) atomicAdd(&hist0[tid], s_h[tid]);
 }
 
 constexpr int GH_ITEMS = SCAN_TILE / 256;  // 16 rows of 64 elements per wave
@@ -135,12 +153,16 @@ __global__ __launch_bounds__(256) void group_heads_kernel(
         uint64_t x = wbase + (uint64_t)e * 64 + lane;
         bool ok = x < n;
         uint32_t hv = 0, uv = 0;
+        uint64_t key = ok ? keys[x] : 0ull;
+        // neighbours from the adjacent lanes; the row ends load their own
+        uint64_t kprev = __shfl_up(key, 1, 64), knext = __shfl_down(key, 1, 64);
+        if (ok && lane == 0 && x > 0) kprev = keys[x - 1];
+        if (ok && lane == 63 && x + 1 < n) knext = keys[x + 1];
         if (ok) {
-            uint64_t key = keys[x];
             bool is_short =
                 round0 && (key & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)kshort;
-            bool head = (x == 0) || keys[x - 1] != key || is_short;
-            bool nhead = (x + 1 == n) || keys[x + 1] != key || is_short;
+            bool head = (x == 0) || kprev != key || is_short;
+            bool nhead = (x + 1 == n) || knext != key || is_short;
             bool unres = !(head && nhead);
             hv = head ? (uint32_t)x : 0u;
             uv = unres ? 1u : 0u;
@@ -445,9 +467,10 @@ hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_
 
 hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                              const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
-                             int gbits, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+                             int gshift, int kfirst, uint64_t *keys, uint32_t *vals,
+                             uint32_t *hist0, hipStream_t s) {
     block_keys_kernel<<<grid_for(n_blk, 256), 256, 0, s>>>(reads, off, soff, tile_first, n_blk, g,
-                                                          gbits, keys, vals);
+                                                          gshift, kfirst, keys, vals, hist0);
     return hipGetLastError();
 }
 

@@ -356,3 +356,39 @@ def test_identical_long_reads(B, oracle_mod):
         with B.BwtSet(block_size=M) as idx:
             idx.append(packed, offs)
             assert idx.export() == want, M
+
+
+@pytest.mark.parametrize("key_bits", [16, 24, 40, 48, 56, 64])
+def test_key_width_does_not_change_the_result(B, oracle_mod, key_bits):
+    # the first sort key holds g and as many symbols as fit; narrower keys
+    # leave more ties to the LDS refinement (or, for huge groups, doubling)
+    packed, offs = synth.short_reads(m=30_000, length=100, ref_len=600_000, seed=46)
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    want = oracle_mod.bwt_of_codes(c1, o1)
+    with B.BwtSet(block_size=400_000) as idx:
+        idx.set_key_bits(key_bits)
+        idx.enable_timing(True)
+        idx.append(packed, offs)
+        assert idx.export() == want
+        st = idx.stats()
+    assert st["blocks"] >= 7
+
+
+def test_key_width_with_large_groups(B, oracle_mod):
+    # many identical reads force the doubling fallback, which widens the key
+    rng = np.random.default_rng(47)
+    base = rng.integers(0, 4, 60, dtype=np.uint8)
+    reads = [base] * 700 + [rng.integers(0, 4, 90, dtype=np.uint8) for _ in range(3000)]
+    codes = np.concatenate(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(r) for r in reads])
+    packed = synth.pack_codes(codes)
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    want = oracle_mod.bwt_of_codes(c1, o1)
+    for kb in (16, 40):
+        with B.BwtSet(block_size=60_000) as idx:
+            idx.set_key_bits(kb)
+            idx.enable_timing(True)
+            idx.append(packed, offs)
+            assert idx.export() == want, kb
+            assert idx.stats()["fallback_blocks"] >= 1
