@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--block", type=int, default=1 << 26)
     ap.add_argument("--key-bits", type=int, default=None,
                     help="width of the first suffix-sort key (library default if omitted)")
+    ap.add_argument("--radix-tile", type=int, default=None,
+                    help="radix pass tile shape (library default if omitted)")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -134,6 +136,8 @@ def main():
     idx = bwtset.BwtSet(block_size=args.block)
     if args.key_bits is not None:
         idx.set_key_bits(args.key_bits)
+    if args.radix_tile is not None:
+        idx.set_param(bwtset.BWT_PARAM_RADIX_TILE, args.radix_tile)
     for w in range(args.warmup):
         idx.reset()
         idx.append(dev_reads, dev_offs, stream)
@@ -194,7 +198,8 @@ def main():
         "config": {"workload": "short reads: %d x 100 bp from a random 50 Mbp reference, both "
                                "strands, 1%% substitutions; block M=%d suffixes" % (m, args.block),
                    "reads": m, "bases": bases, "block_suffixes": args.block,
-                   "blocks": st["blocks"] // args.steps, "key_bits": args.key_bits},
+                   "blocks": st["blocks"] // args.steps, "key_bits": args.key_bits,
+                   "radix_tile": args.radix_tile},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
         "stages_ms_per_step": {s: round(st["ms"][s] / args.steps, 3) for s in bwtset.STAGES},

@@ -101,7 +101,10 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     suffix-sort key, which holds g (the rank among the old suffixes, from
  *     ComputeRanks) above as many 2-bit symbols as fit.  Fewer bits mean fewer
  *     8-bit radix passes and more ties left to the LDS refinement. */
-enum { BWT_PARAM_KEY_BITS = 1 };
+/*   BWT_PARAM_RADIX_TILE: tile shape of the radix passes (threads x keys per
+ *     thread): 0 = 256x16, 1 = 512x8, 2 = 256x8, 3 = 512x12 (default),
+ *     4 = 1024x4, 5 = 512x16, 6 = 1024x8, 7 = 1024x12, 8 = 768x12. */
+enum { BWT_PARAM_KEY_BITS = 1, BWT_PARAM_RADIX_TILE = 2 };
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
 
 /* Last error code recorded on h (or, for h == NULL, by bwt_set_create). */

@@ -71,6 +71,7 @@ EXPORTED = [
     "bwt_set_enable_timing", "bwt_set_get_stats", "bwt_set_set_param",
 ]
 BWT_PARAM_KEY_BITS = 1
+BWT_PARAM_RADIX_TILE = 2
 
 _lib = None
 
@@ -213,8 +214,10 @@ class BwtSet:
         self._check(load().bwt_set_set_block_size(self._h, int(M)), "bwt_set_set_block_size")
 
     def set_key_bits(self, bits: int) -> None:
-        self._check(load().bwt_set_set_param(self._h, BWT_PARAM_KEY_BITS, int(bits)),
-                    "bwt_set_set_param")
+        self.set_param(BWT_PARAM_KEY_BITS, bits)
+
+    def set_param(self, param: int, value: int) -> None:
+        self._check(load().bwt_set_set_param(self._h, int(param), int(value)), "bwt_set_set_param")
 
     def append(self, reads, offsets, stream=None) -> None:
         """Append m = len(offsets) - 1 reads (2-bit packed, see synth.py)."""

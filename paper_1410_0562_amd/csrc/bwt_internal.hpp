@@ -84,7 +84,6 @@ constexpr int REFINE_WINDOW = 1024;
 
 constexpr int PREP_TILE_SHIFT = 12;  // positions per read-lookup tile
 constexpr int SCAN_TILE = 4096;      // elements per look-back scan tile
-constexpr int RADIX_TILE = 4096;     // keys per radix pass tile
 constexpr int INS_TILE_RECS = 16;    // output records per Insert tile
 constexpr uint64_t INS_TILE_SYMS = INS_TILE_RECS * REC_SYMS;
 constexpr int CHUNK_SHIFT = 6;       // B_int counts sampled every 64 symbols
@@ -103,22 +102,35 @@ __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a +
 // fails (a bounded wait timed out, an index would leave its buffer); the host
 // reads it after every append and treats a nonzero value as a failure.
 
-// radix sort pieces (k_radix.hip).  hist: 8 x 256 digit counts, pass p at
-// p * 256; pass p reads its counts and adds the next pass's into hist_next.
+// radix sort pieces (k_radix.hip).  Digit counts are spread over HIST_COPIES
+// copies so that many workgroups adding to the same hot digit do not queue on
+// one atomic word: hist[(pass * HIST_COPIES + copy) * 256 + digit].  Before
+// pass p, launch_radix_starts sums the copies into exclusive digit starts
+// (starts[p * 256 + digit]); pass p adds the next pass's counts.
+constexpr int HIST_COPIES = 32;
+constexpr uint32_t HIST_WORDS = 8 * HIST_COPIES * 256;
 hipError_t launch_radix_hist1(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
                               hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s);
+hipError_t launch_radix_starts(const uint32_t *hist_pass, uint32_t *starts_pass, hipStream_t s);
+// cfg selects the tile shape (see radix_tile_keys); the status array must
+// hold 256 words per tile of the smallest shape
+int radix_tile_keys(int cfg);
+constexpr int RADIX_CFGS = 9;
+constexpr int RADIX_MIN_TILE = 2048;
 hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                             uint32_t *vout, uint64_t n, int shift, const uint32_t *hist,
+                             uint32_t *vout, uint64_t n, int shift, const uint32_t *starts,
                              uint32_t *hist_next, int shift_next, uint64_t *status,
-                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s);
+                             uint32_t *counter, uint32_t epoch, uint32_t *err, int cfg,
+                             hipStream_t s);
 
 // block preparation, suffix sorting and refinement (k_sa.hip)
 hipError_t launch_block_soff(const uint64_t *off, uint32_t m_blk, uint32_t *soff, hipStream_t s);
 hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
                                    uint32_t *tile_first, hipStream_t s);
 // key = g[p] << gshift | (kfirst symbols) << 5 | count (g may be null: no
-// g); hist0 (zeroed by the caller) receives the counts of the low 8 bits
+// g); hist0 (the first pass's HIST_COPIES x 256 words, zeroed by the caller)
+// receives the counts of the low 8 bits
 hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                              const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
                              int gshift, int kfirst, uint64_t *keys, uint32_t *vals,

@@ -65,8 +65,9 @@ constexpr int MISC_NU = 4;       // followed by MISC_LARGE (read together)
 constexpr int MISC_LARGE = 5;
 constexpr int MISC_BAD = 6;
 constexpr int MISC_ERR = 7;
-constexpr int MISC_HIST = 64;                 // 8*256 + 1 words
-constexpr int MISC_WORDS = MISC_HIST + 8 * 256 + 64;
+constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
+constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
+constexpr int MISC_WORDS = MISC_HIST + HIST_WORDS + 64;
 
 struct Timer {
     bool on = false;
@@ -111,6 +112,7 @@ struct bwt_set {
     Workspace ws;
     uint64_t M = 1ull << 26;
     int key_bits = 64;               // width of the first suffix-sort key
+    int radix_cfg = 3;               // radix pass tile shape (512 threads x 12 keys)
     uint64_t *first_new = nullptr;
     uint64_t first_new_cap = 0;
     // staging for host inputs / outputs
@@ -291,7 +293,7 @@ int ensure_ws(bwt_set *h, uint64_t need) {
     cap = std::min<uint64_t>(std::max<uint64_t>(cap, 4096), MAX_BLOCK + 1);
     free_ws(w);
     bool ok = true;
-    uint64_t tiles = div_up(cap, 4096) + 1;
+    uint64_t tiles = div_up(cap, RADIX_MIN_TILE) + 1;
     ok &= dalloc(&w.kA, cap) == hipSuccess;
     ok &= dalloc(&w.kB, cap) == hipSuccess;
     for (auto &p : w.v) ok &= dalloc(&p, cap) == hipSuccess;
@@ -354,18 +356,20 @@ int radix_sort(bwt_set *h, hipStream_t s, uint64_t *kin, uint32_t *vin, uint64_t
     *ko = kin;
     *vo = vin;
     if (n <= 1) return BWT_OK;
-    uint32_t *hist = w.misc + MISC_HIST;
+    uint32_t *hist = w.misc + MISC_HIST, *starts = w.misc + MISC_STARTS;
+    const uint32_t per_pass = HIST_COPIES * 256;
     if (!counted0) HIPCHK(h, launch_radix_hist1(kin, n, 0, hist, s));
-    if (npass > 1) HIPCHK(h, launch_zero_u32(hist + 256, 256 * (npass - 1), s));
+    if (npass > 1) HIPCHK(h, launch_zero_u32(hist + per_pass, per_pass * (npass - 1), s));
     uint64_t *ka = kin, *kb = kalt;
     uint32_t *va = vin, *vb = valt;
     for (int p = 0; p < npass; ++p) {
+        HIPCHK(h, launch_radix_starts(hist + per_pass * p, starts + 256 * p, s));
         {
             Scope sc(h, s, SPAN_RADIX_PASS, n);
-            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, 8 * p, hist + 256 * p,
-                                        p + 1 < npass ? hist + 256 * (p + 1) : nullptr,
+            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, 8 * p, starts + 256 * p,
+                                        p + 1 < npass ? hist + per_pass * (p + 1) : nullptr,
                                         8 * (p + 1), w.status_radix, w.misc + MISC_CNT_RADIX,
-                                        next_epoch(), w.misc + MISC_ERR, s));
+                                        next_epoch(), w.misc + MISC_ERR, h->radix_cfg, s));
         }
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -430,7 +434,7 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     int gshift = gbits ? key_bits - gbits : 64;
     int sort_bits = gbits ? key_bits : 2 * kfirst + KEY_LEN_BITS;
     uint32_t *hist = w.misc + MISC_HIST;
-    HIPCHK(h, launch_zero_u32(hist, 256, s));
+    HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
     {
         Scope sk(h, s, SPAN_KEYS);
         HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
@@ -476,7 +480,7 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
         kfirst = first_key_syms(gbits, key_bits);
         gshift = gbits ? key_bits - gbits : 64;
         if (kfirst < 1) return fail(h, BWT_EHIP);
-        HIPCHK(h, launch_zero_u32(hist, 256, s));
+        HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
         HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
                                     gshift, kfirst, w.kA, w.v[0], hist, s));
         rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, 64, true, &ks, &vs);
@@ -905,6 +909,10 @@ int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
     case BWT_PARAM_KEY_BITS:
         if (value < 16 || value > 64) return fail(h, BWT_EINVAL);
         h->key_bits = (int)value;
+        return BWT_OK;
+    case BWT_PARAM_RADIX_TILE:
+        if (value < 0 || value >= RADIX_CFGS) return fail(h, BWT_EINVAL);
+        h->radix_cfg = (int)value;
         return BWT_OK;
     default:
         return fail(h, BWT_EINVAL);

@@ -17,10 +17,6 @@ namespace bwt {
 
 namespace {
 
-constexpr int RB_THREADS = 256;
-constexpr int RB_ITEMS = RADIX_TILE / RB_THREADS;  // 16
-constexpr int RB_WAVES = RB_THREADS / WAVE;          // 4
-constexpr int RB_WAVE_KEYS = RB_ITEMS * WAVE;        // 1024 keys per wave
 
 __global__ void radix_zero_kernel(uint32_t *hist, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -28,7 +24,8 @@ __global__ void radix_zero_kernel(uint32_t *hist, int n) {
 }
 
 // Counts of one digit of the keys (the first pass's digit for key producers
-// that do not count it themselves).  hist must be zero on entry.
+// that do not count it themselves), into the copies of one pass.  hist must be
+// zero on entry.
 __global__ __launch_bounds__(256) void radix_hist1_kernel(const uint64_t *__restrict__ keys,
                                                           uint64_t n, int shift,
                                                           uint32_t *__restrict__ hist) {
@@ -39,46 +36,77 @@ __global__ __launch_bounds__(256) void radix_hist1_kernel(const uint64_t *__rest
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + tid; i < n; i += (uint64_t)gridDim.x * 256)
         atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
     __syncthreads();
-    if (h[tid]) atomicAdd(&hist[tid], h[tid]);
+    if (h[tid]) atomicAdd(&hist[(blockIdx.x % HIST_COPIES) * 256 + tid], h[tid]);
 }
 
-__global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
+// Sums the copies of one pass's counts and turns them into exclusive starts.
+__global__ __launch_bounds__(256) void radix_starts_kernel(const uint32_t *__restrict__ hist,
+                                                           uint32_t *__restrict__ starts) {
+    __shared__ uint32_t tmp[4];
+    const int d = threadIdx.x;
+    uint32_t c = 0;
+    for (int k = 0; k < HIST_COPIES; ++k) c += hist[k * 256 + d];
+    uint32_t tot;
+    starts[d] = block_excl_sum256(c, tmp, &tot);
+}
+
+// Block-wide exclusive sum over THREADS threads (every thread calls it);
+// tmp holds THREADS/64 words.  Contains barriers.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp) {
+    constexpr int W = THREADS / WAVE;
+    const int tid = threadIdx.x, w = tid >> 6;
+    uint32_t inc = wave_incl_sum(v);
+    if ((tid & 63) == 63) tmp[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        if (k < w) before += tmp[k];
+    __syncthreads();
+    return before + inc - v;
+}
+
+// One digit pass over tiles of THREADS * ITEMS keys.  Wave w of a tile owns
+// the ITEMS * 64 consecutive keys starting at w * ITEMS * 64 and takes them
+// row by row, so tile order = (wave, row, lane) and the ranking is stable.
+// Keys and then values go through the same LDS buffer to keep the tile small
+// enough for several workgroups per CU.
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void radix_pass_kernel(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ hist,
+    uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ starts,
     uint32_t *__restrict__ hist_next, int shift_next, uint64_t *__restrict__ status,
     uint32_t *__restrict__ counter, uint32_t ntiles, uint32_t epoch, uint32_t *__restrict__ err) {
+    constexpr int WAVES = THREADS / WAVE;
+    constexpr int TILE = THREADS * ITEMS;
+    constexpr int WKEYS = ITEMS * WAVE;
+    static_assert(THREADS >= 256, "one thread per digit");
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_dstart[256];        // global start of each digit
-    __shared__ uint32_t s_next[256];          // this tile's counts of the next pass's digit
-    __shared__ uint32_t s_wh[RB_WAVES][256];  // per-wave digit counts, then wave offsets
-    __shared__ uint32_t s_lstart[256];        // start of each digit inside the tile
-    __shared__ int64_t s_gbase[256];          // global position minus tile position
-    __shared__ uint32_t s_tmp[4];
-    __shared__ uint64_t s_keys[RADIX_TILE];
-    __shared__ uint32_t s_vals[RADIX_TILE];
+    __shared__ uint32_t s_wh[WAVES][256];  // per-wave digit counts, then wave offsets
+    __shared__ uint32_t s_lstart[256];     // start of each digit inside the tile
+    __shared__ int32_t s_gbase[256];       // global position minus tile position
+    __shared__ uint32_t s_next[256];       // this tile's counts of the next pass's digit
+    __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint64_t s_buf[TILE];       // keys, then values
+    __shared__ uint8_t s_dig[TILE];        // digit of each staged key
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int d = lane; d < 256; d += WAVE) s_wh[wave][d] = 0;
-    s_next[tid] = 0;
-    {
-        // digit totals of this pass (counted by the previous pass or by the
-        // key builder) -> exclusive starts
-        uint32_t tot;
-        s_dstart[tid] = block_excl_sum256(hist[tid], s_tmp, &tot);
-    }
+    if (tid < 256) s_next[tid] = 0;
     const uint32_t tile = acquire_tile(counter, ntiles, &s_tile);
     if (tile >= ntiles) {  // only if the tile counter was not zero at launch
         if (tid == 0) atomicOr(err, 2u);
         return;
     }
-    const uint64_t base = (uint64_t)tile * RADIX_TILE;
-    const uint64_t wbase = base + (uint64_t)wave * RB_WAVE_KEYS;
+    const uint64_t base = (uint64_t)tile * TILE;
+    const uint64_t wbase = base + (uint64_t)wave * WKEYS;
 
-    uint64_t k[RB_ITEMS];
-    uint32_t v[RB_ITEMS];
-    uint32_t rk[RB_ITEMS];
+    uint64_t k[ITEMS];
+    uint32_t v[ITEMS];
+    uint32_t rk[ITEMS];
 #pragma unroll
-    for (int e = 0; e < RB_ITEMS; ++e) {
+    for (int e = 0; e < ITEMS; ++e) {
         uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
         bool ok = idx < n;
         k[e] = ok ? kin[idx] : 0;
@@ -87,14 +115,14 @@ __global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
     if (hist_next) {
         // histogram of the next pass's digit while the keys are in registers
 #pragma unroll
-        for (int e = 0; e < RB_ITEMS; ++e) {
+        for (int e = 0; e < ITEMS; ++e) {
             uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
             if (idx < n) atomicAdd(&s_next[(uint32_t)(k[e] >> shift_next) & 255u], 1u);
         }
     }
     const uint64_t ltm = lanemask_lt();
 #pragma unroll
-    for (int e = 0; e < RB_ITEMS; ++e) {
+    for (int e = 0; e < ITEMS; ++e) {
         uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
         bool ok = idx < n;
         uint32_t d = (uint32_t)(k[e] >> shift) & 255u;
@@ -113,59 +141,76 @@ __global__ __launch_bounds__(RB_THREADS) void radix_pass_kernel(
     }
     __syncthreads();
     // digit totals of the tile, wave offsets, tile-local digit starts
-    const int d = tid;
-    uint32_t c0 = s_wh[0][d], c1 = s_wh[1][d], c2 = s_wh[2][d], c3 = s_wh[3][d];
-    uint32_t total = c0 + c1 + c2 + c3;
-    uint32_t tile_total;
-    uint32_t lstart = block_excl_sum256(total, s_tmp, &tile_total);
-    s_wh[0][d] = 0;
-    s_wh[1][d] = c0;
-    s_wh[2][d] = c0 + c1;
-    s_wh[3][d] = c0 + c1 + c2;
-    s_lstart[d] = lstart;
-    uint32_t excl = lookback(status + d, 256u, tile, epoch, total, OpSum(), 0u, err);
-    s_gbase[d] = (int64_t)s_dstart[d] + (int64_t)excl - (int64_t)lstart;
-    if (hist_next && s_next[d]) atomicAdd(&hist_next[d], s_next[d]);
-    __syncthreads();
-    // stage in LDS in sorted order
+    uint32_t total = 0;
+    if (tid < 256) {
 #pragma unroll
-    for (int e = 0; e < RB_ITEMS; ++e) {
+        for (int w = 0; w < WAVES; ++w) {
+            uint32_t c = s_wh[w][tid];
+            s_wh[w][tid] = total;
+            total += c;
+        }
+    }
+    const uint32_t lstart = block_excl_sum<THREADS>(tid < 256 ? total : 0u, s_tmp);
+    if (tid < 256) {
+        s_lstart[tid] = lstart;
+        uint32_t excl = lookback(status + tid, 256u, tile, epoch, total, OpSum(), 0u, err);
+        s_gbase[tid] = (int32_t)(starts[tid] + excl) - (int32_t)lstart;
+        if (hist_next && s_next[tid])
+            atomicAdd(&hist_next[(tile % HIST_COPIES) * 256 + tid], s_next[tid]);
+    }
+    __syncthreads();
+    // keys: stage in LDS in sorted order, then write each digit run out
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) {
         uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
+        pos[e] = 0xffffffffu;
         if (idx < n) {
             uint32_t dd = (uint32_t)(k[e] >> shift) & 255u;
-            uint32_t pos = s_lstart[dd] + s_wh[wave][dd] + rk[e];
-            if (pos < RADIX_TILE) {
-                s_keys[pos] = k[e];
-                s_vals[pos] = v[e];
+            uint32_t q = s_lstart[dd] + s_wh[wave][dd] + rk[e];
+            if (q < (uint32_t)TILE) {
+                pos[e] = q;
+                s_buf[q] = k[e];
+                s_dig[q] = (uint8_t)dd;
             } else {
                 atomicOr(err, 4u);
             }
         }
     }
     __syncthreads();
-    uint32_t cnt_tile = (uint32_t)((n - base) < (uint64_t)RADIX_TILE ? (n - base) : RADIX_TILE);
-    for (uint32_t i = tid; i < cnt_tile; i += RB_THREADS) {
-        uint64_t key = s_keys[i];
-        uint32_t dd = (uint32_t)(key >> shift) & 255u;
-        uint64_t dst = (uint64_t)(s_gbase[dd] + (int64_t)i);
-        if (dst < n) {
-            kout[dst] = key;
-            vout[dst] = s_vals[i];
-        } else {
-            atomicOr(err, 4u);
-        }
+    const uint32_t cnt_tile = (uint32_t)((n - base) < (uint64_t)TILE ? (n - base) : TILE);
+    for (uint32_t i = tid; i < cnt_tile; i += THREADS) {
+        int64_t dst = (int64_t)s_gbase[s_dig[i]] + (int64_t)i;
+        if ((uint64_t)dst < n) kout[dst] = s_buf[i];
+        else atomicOr(err, 4u);
+    }
+    __syncthreads();
+    // values through the same buffer
+    uint32_t *s_val = reinterpret_cast<uint32_t *>(s_buf);
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e)
+        if (pos[e] != 0xffffffffu) s_val[pos[e]] = v[e];
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt_tile; i += THREADS) {
+        int64_t dst = (int64_t)s_gbase[s_dig[i]] + (int64_t)i;
+        if ((uint64_t)dst < n) vout[dst] = s_val[i];
     }
 }
 
 }  // namespace
 
-// hist: counts of the digit at `shift`; zeroed here first
+// hist: the copies of one pass (HIST_COPIES x 256 words); zeroed here first
 hipError_t launch_radix_hist1(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
                               hipStream_t s) {
-    radix_zero_kernel<<<1, 256, 0, s>>>(hist, 256);
+    radix_zero_kernel<<<HIST_COPIES, 256, 0, s>>>(hist, HIST_COPIES * 256);
     uint64_t want = div_up(n, 256 * 16);
     int grid = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
     radix_hist1_kernel<<<grid, 256, 0, s>>>(keys, n, shift, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_radix_starts(const uint32_t *hist_pass, uint32_t *starts_pass, hipStream_t s) {
+    radix_starts_kernel<<<1, 256, 0, s>>>(hist_pass, starts_pass);
     return hipGetLastError();
 }
 
@@ -174,15 +219,44 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Tile shapes (threads x keys per thread) the pass can run with.
+int radix_tile_keys(int cfg) {
+    switch (cfg) {
+    case 1: return 512 * 8;
+    case 2: return 256 * 8;
+    case 3: return 512 * 12;
+    case 4: return 1024 * 4;
+    case 5: return 512 * 16;
+    case 6: return 1024 * 8;
+    case 7: return 1024 * 12;
+    case 8: return 768 * 12;
+    default: return 256 * 16;
+    }
+}
+
 hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                             uint32_t *vout, uint64_t n, int shift, const uint32_t *hist,
+                             uint32_t *vout, uint64_t n, int shift, const uint32_t *starts,
                              uint32_t *hist_next, int shift_next, uint64_t *status,
-                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s) {
-    uint32_t ntiles = (uint32_t)div_up(n, RADIX_TILE);
+                             uint32_t *counter, uint32_t epoch, uint32_t *err, int cfg,
+                             hipStream_t s) {
+    const uint32_t ntiles = (uint32_t)div_up(n, (uint64_t)radix_tile_keys(cfg));
     if (ntiles == 0) return hipSuccess;
-    radix_pass_kernel<<<ntiles, RB_THREADS, 0, s>>>(kin, vin, kout, vout, n, shift, hist, hist_next,
-                                                    shift_next, status, counter, ntiles, epoch,
-                                                    err);
+#define BWT_PASS(T, I)                                                                      \
+    radix_pass_kernel<T, I><<<ntiles, T, 0, s>>>(kin, vin, kout, vout, n, shift, starts,    \
+                                                 hist_next, shift_next, status, counter,    \
+                                                 ntiles, epoch, err)
+    switch (cfg) {
+    case 1: BWT_PASS(512, 8); break;
+    case 2: BWT_PASS(256, 8); break;
+    case 3: BWT_PASS(512, 12); break;
+    case 4: BWT_PASS(1024, 4); break;
+    case 5: BWT_PASS(512, 16); break;
+    case 6: BWT_PASS(1024, 8); break;
+    case 7: BWT_PASS(1024, 12); break;
+    case 8: BWT_PASS(768, 12); break;
+    default: BWT_PASS(256, 16); break;
+    }
+#undef BWT_PASS
     return hipGetLastError();
 }
 

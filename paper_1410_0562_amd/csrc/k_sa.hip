@@ -78,10 +78,11 @@ __device__ __forceinline__ uint64_t chunk_key(const uint8_t *__restrict__ reads,
     return (sym << KEY_LEN_BITS) | (uint64_t)take;
 }
 
-// One suffix per thread; a wave covers 64 consecutive positions, so lane 0
-// finds the read of the first one and every lane steps forward from there.
-// The counts of the key's low digit (the first radix pass) are gathered in
-// LDS and added to hist0 once per workgroup.
+// A fixed grid strides over the block, one suffix per thread per step; a
+// wave covers 64 consecutive positions, so lane 0 finds the read of the
+// first one and every lane steps forward from there.  The counts of the key's
+// low digit (the first radix pass) are gathered in LDS and added once per
+// workgroup to one of the HIST_COPIES copies.
 __global__ __launch_bounds__(256) void block_keys_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first, uint32_t n_blk,
@@ -91,9 +92,11 @@ __global__ __launch_bounds__(256) void block_keys_kernel(
     const int tid = threadIdx.x;
     s_h[tid] = 0;
     __syncthreads();
-    const uint32_t p0 = blockIdx.x * blockDim.x + (tid & ~63);
-    const uint32_t p = p0 + (tid & 63);
-    if (p0 < n_blk) {
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n_blk;
+         base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t p0 = (uint32_t)base + (tid & ~63);
+        const uint32_t p = p0 + (tid & 63);
+        if (p0 >= n_blk) continue;
         uint32_t j = 0;
         if ((tid & 63) == 0) j = find_read(soff, tile_first, p0);
         j = __shfl(j, 0, 64);
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(256) void block_keys_kernel(
         }
     }
     __syncthreads();
-    if (s_h[tid]) atomicAdd(&hist0[tid], s_h[tid]);
+    if (s_h[tid]) atomicAdd(&hist0[(blockIdx.x % HIST_COPIES) * 256 + tid], s_h[tid]);
 }
 
 constexpr int GH_ITEMS = SCAN_TILE / 256;  // 16 rows of 64 elements per wave
@@ -469,8 +472,10 @@ hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const ui
                              const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
                              int gshift, int kfirst, uint64_t *keys, uint32_t *vals,
                              uint32_t *hist0, hipStream_t s) {
-    block_keys_kernel<<<grid_for(n_blk, 256), 256, 0, s>>>(reads, off, soff, tile_first, n_blk, g,
-                                                          gshift, kfirst, keys, vals, hist0);
+    uint64_t want = div_up(n_blk, 256 * 8);
+    unsigned grid = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    block_keys_kernel<<<grid, 256, 0, s>>>(reads, off, soff, tile_first, n_blk, g, gshift, kfirst,
+                                           keys, vals, hist0);
     return hipGetLastError();
 }
 

@@ -392,3 +392,21 @@ def test_key_width_with_large_groups(B, oracle_mod):
             idx.append(packed, offs)
             assert idx.export() == want, kb
             assert idx.stats()["fallback_blocks"] >= 1
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+def test_radix_tile_shapes(B, torch_dev, oracle_mod, cfg):
+    torch = torch_dev
+    packed, offs = synth.random_reads(48, 4000, 0, 160)
+    c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
+    sa_want, T = oracle_mod.construct_sa(c1, o1)
+    n = len(T)
+    sa = torch.empty(n, dtype=torch.int32, device="cuda")
+    bint = torch.empty(n, dtype=torch.uint8, device="cuda")
+    with B.BwtSet() as idx:
+        idx.set_param(B.BWT_PARAM_RADIX_TILE, cfg)
+        idx.block_sort(packed, offs, sa, bint)
+        assert np.array_equal(sa.cpu().numpy().astype(np.uint64), sa_want)
+        idx.set_block_size(50_000)
+        idx.append(packed, offs)
+        assert idx.export() == oracle_mod.bwt_of_codes(c1, o1)
