@@ -84,8 +84,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--reads", type=int, default=4_000_000)
-    ap.add_argument("--block", type=int, default=1 << 26)
+    ap.add_argument("--workload", choices=["short", "long", "uniform"], default="short",
+                    help="short: 4M x 100 bp (default, the headline); long: 250k lognormal "
+                         "reads, mean 5 kbp, M = 2^27; uniform: 10k x 100 bp, M = 2^18")
+    ap.add_argument("--reads", type=int, default=None)
+    ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--key-bits", type=int, default=None,
                     help="width of the first suffix-sort key (library default if omitted)")
     ap.add_argument("--radix-tile", type=int, default=None,
@@ -125,7 +128,21 @@ def main():
         return
 
     log("generating workload")
-    packed, offs = synth.short_reads(m=args.reads)
+    if args.workload == "short":
+        packed, offs = synth.short_reads(m=args.reads or 4_000_000)
+        block = args.block or (1 << 26)
+        wdesc = ("short reads: %d x 100 bp from a random 50 Mbp reference, both strands, 1%% "
+                 "substitutions; block M=%d suffixes")
+    elif args.workload == "long":
+        packed, offs = synth.long_reads(m=args.reads or 250_000, threads=16)
+        block = args.block or (1 << 27)
+        wdesc = ("long reads: %d reads, lognormal lengths (mean 5 kbp, 1-50 kbp) from a random "
+                 "100 Mbp reference, both strands, 10%% noise; block M=%d suffixes")
+    else:
+        packed, offs = synth.uniform_reads(m=args.reads or 10_000)
+        block = args.block or (1 << 18)
+        wdesc = "uniform reads: %d x 100 bp i.i.d.; block M=%d suffixes"
+    args.block = block
     bases = int(offs[-1]) - int(offs[0])
     m = len(offs) - 1
     dev_reads = torch.from_numpy(packed).cuda()
@@ -195,8 +212,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "short reads: %d x 100 bp from a random 50 Mbp reference, both "
-                               "strands, 1%% substitutions; block M=%d suffixes" % (m, args.block),
+        "config": {"workload": wdesc % (m, args.block),
                    "reads": m, "bases": bases, "block_suffixes": args.block,
                    "blocks": st["blocks"] // args.steps, "key_bits": args.key_bits,
                    "radix_tile": args.radix_tile},

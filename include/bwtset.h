@@ -104,7 +104,19 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
 /*   BWT_PARAM_RADIX_TILE: tile shape of the radix passes (threads x keys per
  *     thread): 0 = 256x16, 1 = 512x8, 2 = 256x8, 3 = 512x12 (default),
  *     4 = 1024x4, 5 = 512x16, 6 = 1024x8, 7 = 1024x12, 8 = 768x12. */
-enum { BWT_PARAM_KEY_BITS = 1, BWT_PARAM_RADIX_TILE = 2 };
+/*   BWT_PARAM_RANK_SEGMENT: ComputeRanks walks a read longer than this many
+ *     symbols in segments of this length, each one started by a backward
+ *     search (FM-index interval) BWT_PARAM_RANK_OVERLAP symbols past its end
+ *     and continued by Lemma 1 once the interval holds no old suffix; reads
+ *     with a longer repeat fall back to one whole walk.  0 = never (256 ..
+ *     2^24, default 1024).
+ *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 128). */
+enum {
+    BWT_PARAM_KEY_BITS = 1,
+    BWT_PARAM_RADIX_TILE = 2,
+    BWT_PARAM_RANK_SEGMENT = 3,
+    BWT_PARAM_RANK_OVERLAP = 4
+};
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
 
 /* Last error code recorded on h (or, for h == NULL, by bwt_set_create). */

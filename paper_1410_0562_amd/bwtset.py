@@ -72,6 +72,8 @@ EXPORTED = [
 ]
 BWT_PARAM_KEY_BITS = 1
 BWT_PARAM_RADIX_TILE = 2
+BWT_PARAM_RANK_SEGMENT = 3
+BWT_PARAM_RANK_OVERLAP = 4
 
 _lib = None
 

@@ -156,10 +156,23 @@ hipError_t launch_refine(const uint8_t *reads, const uint64_t *off, const uint32
 hipError_t launch_vals_to_ascii(const uint32_t *sa, uint32_t n, uint8_t *bint, hipStream_t s);
 hipError_t launch_sa_strip(const uint32_t *sa, uint32_t n, uint32_t *out, hipStream_t s);
 
-// ComputeRanks (k_ranks.hip)
+// ComputeRanks (k_ranks.hip).  Reads longer than seg_len symbols (0: never)
+// are walked in segments of seg_len symbols, each starting overlap symbols
+// past its end (see k_ranks.hip); seg_list holds seg_cap entries, fb_flag and
+// fb_list one word per read of the block, counters two words.
+struct RankSegments {
+    uint32_t seg_len = 0;
+    uint32_t overlap = 0;
+    uint64_t *seg_list = nullptr;
+    uint32_t seg_cap = 0;
+    uint32_t *fb_flag = nullptr;
+    uint32_t *fb_list = nullptr;
+    uint32_t *counters = nullptr;
+};
 hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
-                                uint32_t m_blk, const Rec *recs, const uint64_t *sbc,
-                                const uint64_t *meta, int big, uint64_t *g, hipStream_t s);
+                                uint32_t m_blk, uint32_t n_blk, const Rec *recs,
+                                const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
+                                const RankSegments &sg, uint32_t *err, hipStream_t s);
 
 // Insert and index bookkeeping (k_insert.hip).  The new symbols come in
 // suffix order as the sorted (key, value) pairs of ConstructSA: g_sa[i] is

@@ -55,6 +55,9 @@ struct Workspace {
     uint64_t *status_radix = nullptr;        // radix look-back words
     uint64_t *status_scan = nullptr;         // scan look-back words
     uint32_t *misc = nullptr;                // counters, histograms, flags
+    uint64_t *seg_list = nullptr;            // long-read segments of ComputeRanks
+    uint32_t seg_cap = 0;
+    uint32_t *fb_flag = nullptr, *fb_list = nullptr;
 };
 
 // layout of Workspace::misc (uint32 words)
@@ -65,6 +68,8 @@ constexpr int MISC_NU = 4;       // followed by MISC_LARGE (read together)
 constexpr int MISC_LARGE = 5;
 constexpr int MISC_BAD = 6;
 constexpr int MISC_ERR = 7;
+constexpr int MISC_SEG = 8;      // 2 words: queued segments, fallback reads
+constexpr uint32_t MIN_SEG_LEN = 256;
 constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
 constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
 constexpr int MISC_WORDS = MISC_HIST + HIST_WORDS + 64;
@@ -113,6 +118,8 @@ struct bwt_set {
     uint64_t M = 1ull << 26;
     int key_bits = 64;               // width of the first suffix-sort key
     int radix_cfg = 3;               // radix pass tile shape (512 threads x 12 keys)
+    uint32_t seg_len = 1024;         // ComputeRanks segment length for long reads
+    uint32_t seg_overlap = 128;      // symbols a segment walk starts past its end
     uint64_t *first_new = nullptr;
     uint64_t first_new_cap = 0;
     // staging for host inputs / outputs
@@ -283,6 +290,10 @@ void free_ws(Workspace &w) {
     dfree(w.status_radix);
     dfree(w.status_scan);
     dfree(w.misc);
+    dfree(w.seg_list);
+    dfree(w.fb_flag);
+    dfree(w.fb_list);
+    w.seg_cap = 0;
     w.cap = 0;
 }
 
@@ -308,6 +319,10 @@ int ensure_ws(bwt_set *h, uint64_t need) {
     ok &= dalloc(&w.status_radix, tiles * 256) == hipSuccess;
     ok &= dalloc(&w.status_scan, tiles * 8) == hipSuccess;
     ok &= dalloc(&w.misc, MISC_WORDS) == hipSuccess;
+    const uint64_t segs = 2 * div_up(cap, MIN_SEG_LEN) + 2;
+    ok &= dalloc(&w.seg_list, segs) == hipSuccess;
+    ok &= dalloc(&w.fb_flag, cap + 1) == hipSuccess;
+    ok &= dalloc(&w.fb_list, cap + 1) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         free_ws(w);
@@ -319,6 +334,7 @@ int ensure_ws(bwt_set *h, uint64_t need) {
     HIPCHK(h, hipMemsetAsync(w.status_radix, 0, tiles * 256 * 8, h->stream));
     HIPCHK(h, hipMemsetAsync(w.status_scan, 0, tiles * 8 * 8, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    w.seg_cap = (uint32_t)segs;
     w.cap = cap;
     return BWT_OK;
 }
@@ -406,6 +422,19 @@ int check_err(bwt_set *h, hipStream_t s) {
         return BWT_EHIP;
     }
     return BWT_OK;
+}
+
+RankSegments rank_segments(bwt_set *h) {
+    RankSegments sg;
+    Workspace &w = h->ws;
+    sg.seg_len = h->seg_len;
+    sg.overlap = h->seg_overlap;
+    sg.seg_list = w.seg_list;
+    sg.seg_cap = w.seg_cap;
+    sg.fb_flag = w.fb_flag;
+    sg.fb_list = w.fb_list;
+    sg.counters = w.misc + MISC_SEG;
+    return sg;
 }
 
 // ---- ConstructSA of one block --------------------------------------------
@@ -791,8 +820,9 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
         if (gbits > 0) {
             Scope sc(h, s, BWT_STAGE_RANKS);
             Scope sk(h, s, SPAN_RANKS_K, n_blk - m_blk);
-            HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, S.recs, S.sbc, S.meta,
-                                           n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, s));
+            HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
+                                           S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g,
+                                           rank_segments(h), w.misc + MISC_ERR, s));
         }
         uint32_t *sa = nullptr;
         const uint64_t *gkeys = nullptr;
@@ -914,6 +944,15 @@ int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
         if (value < 0 || value >= RADIX_CFGS) return fail(h, BWT_EINVAL);
         h->radix_cfg = (int)value;
         return BWT_OK;
+    case BWT_PARAM_RANK_SEGMENT:
+        if (value != 0 && (value < (int64_t)MIN_SEG_LEN || value > (1 << 24)))
+            return fail(h, BWT_EINVAL);
+        h->seg_len = (uint32_t)value;
+        return BWT_OK;
+    case BWT_PARAM_RANK_OVERLAP:
+        if (value < 0 || value > (1 << 24)) return fail(h, BWT_EINVAL);
+        h->seg_overlap = (uint32_t)value;
+        return BWT_OK;
     default:
         return fail(h, BWT_EINVAL);
     }
@@ -979,8 +1018,10 @@ int bwt_set_compute_ranks(bwt_set_t h, const uint8_t *reads, const uint64_t *off
     HIPCHK(h, launch_block_soff(P.off, (uint32_t)m, h->ws.soff, s));
     {
         Scope sk(h, s, SPAN_RANKS_K, P.total_suffixes - m);
-        HIPCHK(h, launch_compute_ranks(P.reads, P.off, h->ws.soff, (uint32_t)m, B.recs, B.sbc,
-                                       B.meta, h->n >= (1ull << SB_SHIFT) ? 1 : 0, g_out, s));
+        HIPCHK(h, launch_compute_ranks(P.reads, P.off, h->ws.soff, (uint32_t)m,
+                                       (uint32_t)P.total_suffixes, B.recs, B.sbc, B.meta,
+                                       h->n >= (1ull << SB_SHIFT) ? 1 : 0, g_out, rank_segments(h),
+                                       h->ws.misc + MISC_ERR, s));
     }
     HIPCHK(h, hipStreamSynchronize(s));
     if (h->timer.on) timer_collect(h);

@@ -1,14 +1,24 @@
 // k_ranks.hip -- ComputeRanks (Section 4, Lemma 1 and Algorithm 2).
 //
-// For each read P_j of the block, one lane walks the read from its end:
-// the terminator suffix $_j is larger than exactly the m_ext terminators
-// already in B_ext and smaller than every old suffix that starts with a base,
-// so it starts at i = m_ext; then for k = |P_j|-1 .. 0, with c = P_j[k],
-// i := C[c] + rank(c, i, B_ext) (Lemma 1), and g[off_j + k] = i, where off_j
-// is the exclusive prefix sum of |P_j| + 1 (the block text position of the
-// read's first symbol).  Each step is one random 64-byte record read from
-// the HBM-resident index; the reads of a block are independent, so a block
-// keeps hundreds of thousands of walks in flight.
+// For each read P_j of the block, a walk from the read's end gives the rank
+// of every suffix among the old ones: the terminator suffix $_j is larger than
+// exactly the m_ext terminators already in B_ext and smaller than every old
+// suffix that starts with a base, so the walk starts at i = m_ext; then for
+// k = |P_j|-1 .. 0, with c = P_j[k], i := C[c] + rank(c, i, B_ext) (Lemma 1),
+// and g[off_j + k] = i, where off_j is the exclusive prefix sum of |P_j| + 1
+// (the block text position of the read's first symbol).  Each step is one
+// random 64-byte record read from the HBM-resident index.
+//
+// A read of more than `seg` symbols is cut into segments of `seg` symbols so
+// that its walk does not serialize the block.  The walk of segment [a, b)
+// starts `ov` symbols past b as an FM-index backward search: it keeps the
+// interval [lo, hi) of old suffixes (rows) prefixed by the symbols read so
+// far, starting from all rows.  Once no old suffix has that prefix (lo ==
+// hi), lo is exactly the number of old suffixes smaller than the new suffix,
+// and the walk continues as Lemma 1's single rank.  A segment whose interval
+// has not closed by the time it reaches b (a repeat longer than ov) hands its
+// read to a last kernel that walks the whole read from its end, so the result
+// is exact in every case.
 #include "dev_util.hpp"
 
 namespace bwt {
@@ -19,7 +29,7 @@ namespace {
 // an 8-entry shift register and written as one aligned 64-byte chunk when the
 // register covers indices [8q, 8q + 8), so the writes are whole half-lines
 // instead of single words spread over the cache (partial chunks at both ends
-// of a read are written word by word).
+// of a walk are written word by word).
 struct GBuf {
     uint64_t r0, r1, r2, r3, r4, r5, r6, r7;  // r0 = lowest index held
     uint32_t cnt;
@@ -49,56 +59,204 @@ struct GBuf {
     }
 };
 
-__global__ __launch_bounds__(256) void compute_ranks_kernel(
-    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, uint32_t m_blk, const Rec *__restrict__ recs,
-    const uint64_t *__restrict__ sbc, const uint64_t *__restrict__ meta, int big,
-    uint64_t *__restrict__ g) {
-    // C[c]: symbols of B_ext smaller than c; every terminator is smaller than A
-    const uint64_t m_ext = meta[5], n_ext = meta[4];
-    const uint64_t C0 = m_ext, C1 = C0 + meta[0], C2 = C1 + meta[1], C3 = C2 + meta[2];
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m_blk) return;
-    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;  // uniform
-    const uint64_t s0 = off[j];
-    uint32_t k = (uint32_t)(off[j + 1] - s0);
-    const uint64_t gb = soff[j];
-    GBuf buf;
-    buf.cnt = 0;
-    uint64_t i = m_ext;
-    buf.push(i);
-    if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
-    // the 8-byte word of packed input holding the current symbol
-    uintptr_t wa = 0;
-    uint64_t word = 0;
-    const bool isbig = big != 0;
-    while (k > 0) {
-        --k;
-        uint64_t s = s0 + k;
-        uintptr_t addr = (uintptr_t)reads + (uintptr_t)(s >> 2);
+// The 8-byte word of packed input holding the current symbol, reloaded only
+// when the walk crosses into the previous word.
+struct SymReader {
+    const uint8_t *base;
+    uintptr_t wa;
+    uint64_t word;
+    __device__ int get(uint64_t s) {
+        uintptr_t addr = (uintptr_t)base + (uintptr_t)(s >> 2);
         uintptr_t a0 = addr & ~(uintptr_t)7;
         if (a0 != wa) {
             word = *reinterpret_cast<const uint64_t *>(a0);
             wa = a0;
         }
-        int c = (int)(word >> ((addr - a0) * 8 + 2 * (s & 3))) & 3;
+        return (int)(word >> ((addr - a0) * 8 + 2 * (s & 3))) & 3;
+    }
+};
+
+// C[c] and the size of B_ext, read from the index meta words
+struct LF {
+    uint64_t C0, C1, C2, C3, m_ext, n_ext;
+    bool big;
+    __device__ LF(const uint64_t *__restrict__ meta, int big_) {
+        m_ext = meta[5];
+        n_ext = meta[4];
+        C0 = m_ext;               // every terminator is smaller than A
+        C1 = C0 + meta[0];
+        C2 = C1 + meta[1];
+        C3 = C2 + meta[2];
+        big = big_ != 0;
+    }
+    // Lemma 1: C[c] + rank(c, i, B_ext); a consistent index never needs the clamp
+    __device__ uint64_t step(const Rec *__restrict__ recs, const uint64_t *__restrict__ sbc,
+                             uint64_t i, int c) const {
         uint64_t Cc = c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : C3;
-        i = Cc + rank_base(recs, sbc, i, c, isbig);
-        i = i < n_ext ? i : n_ext;  // a consistent index never needs the clamp
+        uint64_t r = Cc + rank_base(recs, sbc, i, c, big);
+        return r < n_ext ? r : n_ext;
+    }
+};
+
+// Whole-read walk from the terminator: writes g[gb + k] for k = len .. 0.
+__device__ void walk_read(const LF &lf, const Rec *__restrict__ recs,
+                          const uint64_t *__restrict__ sbc, SymReader &sym, uint64_t s0,
+                          uint32_t len, uint64_t gb, uint64_t *__restrict__ g, bool vec) {
+    GBuf buf;
+    buf.cnt = 0;
+    uint64_t i = lf.m_ext;
+    uint32_t k = len;
+    buf.push(i);
+    if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
+    while (k > 0) {
+        --k;
+        i = lf.step(recs, sbc, i, sym.get(s0 + k));
         buf.push(i);
         if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
     }
     buf.flush(g, gb, false);  // what is left below the last aligned index
 }
 
+// One lane per read.  Reads longer than `seg` symbols (seg > 0) are cut into
+// segments that are queued for rank_segments_kernel instead.
+__global__ __launch_bounds__(256) void compute_ranks_kernel(
+    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ soff, uint32_t m_blk, const Rec *__restrict__ recs,
+    const uint64_t *__restrict__ sbc, const uint64_t *__restrict__ meta, int big,
+    uint64_t *__restrict__ g, uint32_t seg, uint64_t *__restrict__ seg_list,
+    uint32_t *__restrict__ seg_count, uint32_t seg_cap, uint32_t *__restrict__ err) {
+    const LF lf(meta, big);
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m_blk) return;
+    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;  // uniform
+    const uint64_t s0 = off[j];
+    const uint32_t len = (uint32_t)(off[j + 1] - s0);
+    if (seg > 0 && len > seg) {
+        const uint32_t nseg = (len + seg - 1) / seg;
+        const uint32_t at = atomicAdd(seg_count, nseg);
+        if (at + nseg > seg_cap) {
+            atomicOr(err, 128u);
+            return;
+        }
+        for (uint32_t s = 0; s < nseg; ++s) seg_list[at + s] = ((uint64_t)j << 32) | s;
+        return;
+    }
+    SymReader sym{reads, 0, 0};
+    walk_read(lf, recs, sbc, sym, s0, len, soff[j], g, vec);
+}
+
+// One lane per queued segment (j, s) of a long read: symbols [a, b) with
+// a = s * seg, b = min(len, a + seg); the walk starts at e = min(len, b + ov).
+__global__ __launch_bounds__(256) void rank_segments_kernel(
+    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ soff, uint32_t m_blk, const Rec *__restrict__ recs,
+    const uint64_t *__restrict__ sbc, const uint64_t *__restrict__ meta, int big,
+    uint64_t *__restrict__ g, uint32_t seg, uint32_t ov, const uint64_t *__restrict__ seg_list,
+    const uint32_t *__restrict__ seg_count, uint32_t *__restrict__ fb_flag,
+    uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, uint32_t *__restrict__ err) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *seg_count) return;
+    const LF lf(meta, big);
+    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
+    const uint64_t e_js = seg_list[t];
+    const uint32_t j = (uint32_t)(e_js >> 32), s = (uint32_t)e_js;
+    if (j >= m_blk) {  // only if the queue overflowed (already flagged)
+        atomicOr(err, 128u);
+        return;
+    }
+    const uint64_t s0 = off[j];
+    const uint32_t len = (uint32_t)(off[j + 1] - s0);
+    const uint64_t gb = soff[j];
+    if ((uint64_t)s * seg >= len) {
+        atomicOr(err, 128u);
+        return;
+    }
+    const uint32_t a = s * seg;
+    const uint32_t b = a + seg < len ? a + seg : len;
+    const uint32_t e = b + ov < len ? b + ov : len;
+    SymReader sym{reads, 0, 0};
+    GBuf buf;
+    buf.cnt = 0;
+    uint64_t lo, hi;
+    if (e == len) {
+        lo = hi = lf.m_ext;  // exact start at the terminator suffix
+        if (b == len) {
+            buf.push(lo);
+            if (((gb + len) & 7) == 0) buf.flush(g, gb + len, vec);
+        }
+    } else {
+        lo = 0;             // the empty prefix: every row of B_ext
+        hi = lf.n_ext;
+    }
+    uint32_t k = e;
+    while (k > a) {
+        --k;
+        const int c = sym.get(s0 + k);
+        const uint64_t nlo = lf.step(recs, sbc, lo, c);
+        hi = (lo == hi) ? nlo : lf.step(recs, sbc, hi, c);
+        lo = nlo;
+        if (k < b) {
+            if (lo != hi) {
+                // a repeat longer than ov: the whole read is walked exactly
+                if (atomicExch(&fb_flag[j], 1u) == 0u) fb_list[atomicAdd(fb_count, 1u)] = j;
+                return;
+            }
+            buf.push(lo);
+            if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
+        }
+    }
+    buf.flush(g, gb + a, false);
+}
+
+// Whole-read walks for the reads whose segments could not close their
+// interval within the overlap.
+__global__ __launch_bounds__(256) void rank_fallback_kernel(
+    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ soff, const Rec *__restrict__ recs,
+    const uint64_t *__restrict__ sbc, const uint64_t *__restrict__ meta, int big,
+    uint64_t *__restrict__ g, const uint32_t *__restrict__ fb_list,
+    const uint32_t *__restrict__ fb_count) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *fb_count) return;
+    const LF lf(meta, big);
+    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
+    const uint32_t j = fb_list[t];
+    const uint64_t s0 = off[j];
+    SymReader sym{reads, 0, 0};
+    walk_read(lf, recs, sbc, sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], g, vec);
+}
+
+__global__ void zero_kernel(uint32_t *p, uint32_t n) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 }  // namespace
 
 hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
-                                uint32_t m_blk, const Rec *recs, const uint64_t *sbc,
-                                const uint64_t *meta, int big, uint64_t *g, hipStream_t s) {
+                                uint32_t m_blk, uint32_t n_blk, const Rec *recs,
+                                const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
+                                const RankSegments &sg, uint32_t *err, hipStream_t s) {
     if (m_blk == 0) return hipSuccess;
-    compute_ranks_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(reads, off, soff, m_blk, recs,
-                                                                      sbc, meta, big, g);
+    uint32_t seg = sg.seg_len;
+    uint32_t cap = 0;
+    if (seg > 0) {
+        cap = (uint32_t)(2 * div_up(n_blk, seg) + 2);
+        if (cap > sg.seg_cap) seg = 0;  // no room to queue segments: whole-read walks
+    }
+    if (seg > 0) {
+        zero_kernel<<<1, 64, 0, s>>>(sg.counters, 2);
+        zero_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(sg.fb_flag, m_blk);
+    }
+    compute_ranks_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
+        reads, off, soff, m_blk, recs, sbc, meta, big, g, seg, sg.seg_list, sg.counters, cap, err);
+    if (seg > 0) {
+        rank_segments_kernel<<<(unsigned)div_up(cap, 256), 256, 0, s>>>(
+            reads, off, soff, m_blk, recs, sbc, meta, big, g, seg, sg.overlap, sg.seg_list,
+            sg.counters, sg.fb_flag, sg.fb_list, sg.counters + 1, err);
+        rank_fallback_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
+            reads, off, soff, recs, sbc, meta, big, g, sg.fb_list, sg.counters + 1);
+    }
     return hipGetLastError();
 }
 

@@ -410,3 +410,39 @@ def test_radix_tile_shapes(B, torch_dev, oracle_mod, cfg):
         idx.set_block_size(50_000)
         idx.append(packed, offs)
         assert idx.export() == oracle_mod.bwt_of_codes(c1, o1)
+
+
+@pytest.mark.parametrize("seg,ov", [(0, 0), (256, 0), (256, 16), (256, 128), (1024, 64)])
+def test_segmented_compute_ranks(B, torch_dev, oracle_mod, seg, ov):
+    # long reads walked in segments that start with a backward search: exact
+    # whether the interval closes within the overlap or the read falls back
+    torch = torch_dev
+    rng = np.random.default_rng(49)
+    ref = rng.integers(0, 4, 40_000, dtype=np.uint8)
+    reads = []
+    for _ in range(60):
+        a = int(rng.integers(0, 30_000))
+        r = ref[a:a + int(rng.integers(300, 9000))].copy()
+        hit = rng.random(len(r)) < 0.05
+        r[hit] = (r[hit] + 1) & 3
+        reads.append(r)
+    reads += [rng.integers(0, 4, int(rng.integers(0, 400)), dtype=np.uint8) for _ in range(200)]
+    codes = np.concatenate(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(x) for x in reads])
+    packed = synth.pack_codes(codes)
+    (pa, oa), (pb, ob) = _split(packed, offs, 130)
+    ca, oa2 = _oracle_inputs(oracle_mod, pa, oa)
+    B_ext = oracle_mod.bwt_of_codes(ca, oa2)
+    cb, ob2 = _oracle_inputs(oracle_mod, pb, ob)
+    T, soff = oracle_mod.concat_text(cb, ob2)
+    want = oracle_mod.compute_ranks(B_ext, T, soff)
+    g = torch.empty(len(T), dtype=torch.int64, device="cuda")
+    with B.BwtSet() as idx:
+        idx.set_param(B.BWT_PARAM_RANK_SEGMENT, seg)
+        idx.set_param(B.BWT_PARAM_RANK_OVERLAP, ov)
+        idx.append(pa, oa)
+        idx.compute_ranks(pb, ob, g)
+        assert np.array_equal(g.cpu().numpy().astype(np.uint64), want)
+        idx.append(pb, ob)
+        assert idx.export() == oracle_mod.bwt_of_codes(*_oracle_inputs(oracle_mod, packed, offs))
