@@ -86,6 +86,22 @@ int bwt_set_rank_many(bwt_set_t h, const uint8_t *cs, const uint64_t *ks,
  * negative code. */
 int64_t bwt_set_export(bwt_set_t h, uint8_t *out);
 
+/* Replaces the index by the one whose BWT is B (n ASCII bytes over
+ * "ACGT$", host or device): the records and occurrence counters are rebuilt
+ * from B, so an exported index can be stored and loaded again (checkpoint,
+ * or FM-index queries on a BWT built elsewhere).  Every '$' counts as one
+ * string.  Returns BWT_EINVAL for another byte; on error the index is
+ * unchanged. */
+int bwt_set_import(bwt_set_t h, const uint8_t *B, uint64_t n, void *stream);
+
+/* Device memory held by the handle, in bytes (index buffers, workspace,
+ * staging). */
+int bwt_set_memory(bwt_set_t h, uint64_t *bytes);
+
+/* Frees everything but the current index (workspace, staging, spare index
+ * buffers); the next call that needs them allocates them again. */
+int bwt_set_trim(bwt_set_t h);
+
 /* Number of symbols n and strings m in the index. */
 int bwt_set_size(bwt_set_t h, uint64_t *n, uint64_t *m);
 

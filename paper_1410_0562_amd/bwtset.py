@@ -69,6 +69,7 @@ EXPORTED = [
     "bwt_set_set_block_size", "bwt_set_last_error", "bwt_set_strerror",
     "bwt_set_block_sort", "bwt_set_compute_ranks", "bwt_set_insert",
     "bwt_set_enable_timing", "bwt_set_get_stats", "bwt_set_set_param",
+    "bwt_set_import", "bwt_set_memory", "bwt_set_trim",
 ]
 BWT_PARAM_KEY_BITS = 1
 BWT_PARAM_RADIX_TILE = 2
@@ -122,6 +123,12 @@ def load(path: str = LIB_PATH):
     L.bwt_set_get_stats.restype = i32
     L.bwt_set_set_param.argtypes = [vp, i32, ctypes.c_int64]
     L.bwt_set_set_param.restype = i32
+    L.bwt_set_import.argtypes = [vp, vp, u64, vp]
+    L.bwt_set_import.restype = i32
+    L.bwt_set_memory.argtypes = [vp, ctypes.POINTER(u64)]
+    L.bwt_set_memory.restype = i32
+    L.bwt_set_trim.argtypes = [vp]
+    L.bwt_set_trim.restype = i32
     if path == LIB_PATH:
         _lib = L
     return L
@@ -263,6 +270,21 @@ class BwtSet:
 
     def reset(self) -> None:
         self._check(load().bwt_set_reset(self._h), "bwt_set_reset")
+
+    def import_bwt(self, B, stream=None) -> None:
+        """Load the index whose BWT is B (bytes, numpy uint8 array or device tensor)."""
+        if isinstance(B, (bytes, bytearray)):
+            B = np.frombuffer(bytes(B), dtype=np.uint8)
+        self._check(load().bwt_set_import(self._h, _ptr(B) if _len(B) else None, _len(B),
+                                          _stream(stream)), "bwt_set_import")
+
+    def memory(self) -> int:
+        b = ctypes.c_uint64()
+        self._check(load().bwt_set_memory(self._h, ctypes.byref(b)), "bwt_set_memory")
+        return int(b.value)
+
+    def trim(self) -> None:
+        self._check(load().bwt_set_trim(self._h), "bwt_set_trim")
 
     # -- single steps
     def block_sort(self, reads, offsets, sa_out, bint_out, stream=None) -> None:

@@ -179,6 +179,7 @@ hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const
 // gkeys[i] >> gshift (0 for every i when gshift == 64) and the symbol code
 // (0..3 for A..T, 4 for '$') is vals[i] >> 29.
 hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *bcnt, uint64_t *status,
                              uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s);
 // user-supplied B_int (ASCII) and g_sa: *bad |= 1 for a byte outside "ACGT$",

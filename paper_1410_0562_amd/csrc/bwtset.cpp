@@ -906,6 +906,106 @@ int64_t bwt_set_export(bwt_set_t h, uint8_t *out) {
     return (int64_t)h->n;
 }
 
+int bwt_set_import(bwt_set_t h, const uint8_t *B, uint64_t n, void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (!B && n) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    const bool dev = n ? is_device_ptr(B) : true;
+    // Built into the two buffers other than the current one, chunk by chunk,
+    // each chunk merged after every row so far (g_sa = current size); a bad
+    // byte stops the build before the current index is replaced.
+    int other[2], k = 0;
+    for (int b = 0; b < 3; ++b)
+        if (b != h->cur) other[k++] = b;
+    for (int b : other)
+        if ((rc = ensure_index(h, h->buf[b], n))) return rc;
+    const uint64_t CH = std::min<uint64_t>(std::max<uint64_t>(n, 1), 1ull << 26);
+    if ((rc = ensure_ws(h, CH))) return rc;
+    Workspace &w = h->ws;
+    if ((rc = clear_err(h, s))) return rc;
+    int src = other[0], dst = other[1];
+    HIPCHK(h, launch_index_init(h->buf[src].recs, h->buf[src].sbc, h->buf[src].meta, s));
+    uint64_t n_cur = 0;
+    for (uint64_t o = 0; o < n; o += CH) {
+        const uint64_t cnt = std::min(CH, n - o);
+        const uint8_t *chunk = B + o;
+        if (!dev) {
+            if ((rc = ensure_buf(h, h->stage_reads, h->stage_reads_cap, CH + 16))) return rc;
+            HIPCHK(h, hipMemcpyAsync(h->stage_reads, chunk, cnt, hipMemcpyHostToDevice, s));
+            chunk = h->stage_reads;
+        }
+        HIPCHK(h, hipMemsetAsync(w.misc + MISC_BAD, 0, 4, s));
+        HIPCHK(h, launch_fill_u64(w.kA, cnt, n_cur, s));
+        HIPCHK(h, launch_check_user_insert(chunk, w.kA, cnt, n_cur, w.misc + MISC_BAD, s));
+        uint32_t bad = 0;
+        if ((rc = read_u32(h, s, w.misc + MISC_BAD, &bad))) return rc;
+        if (bad) return fail(h, BWT_EINVAL);
+        HIPCHK(h, launch_pack_user_insert(chunk, w.kA, cnt, 0, w.kA, w.v[0], s));
+        if ((rc = insert_block(h, s, h->buf[src], h->buf[dst], n_cur, w.kA, 0, w.v[0], cnt)))
+            return rc;
+        if (!dev) HIPCHK(h, hipStreamSynchronize(s));  // the staging buffer is reused
+        n_cur += cnt;
+        std::swap(src, dst);
+    }
+    HIPCHK(h, hipMemcpyAsync(h->pinned, h->buf[src].meta, META_WORDS * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (h->timer.on) timer_collect(h);
+    const uint64_t new_m = h->pinned[5];
+    if ((rc = check_err(h, s))) return rc;
+    h->cur = src;
+    h->n = n;
+    h->m = new_m;
+    return BWT_OK;
+}
+
+int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
+    if (!h || !bytes) return BWT_EINVAL;
+    uint64_t b = 0;
+    for (auto &x : h->buf) {
+        if (x.recs) b += x.rec_cap * sizeof(Rec);
+        if (x.sbc) b += x.sbc_cap * 4 * 8;
+        if (x.meta) b += META_WORDS * 8;
+    }
+    const Workspace &w = h->ws;
+    if (w.cap) {
+        const uint64_t c = w.cap, tiles = div_up(c, RADIX_MIN_TILE) + 1;
+        b += c * (8 * 4 + 4 * 6 + 1 + 4 * 2) + div_up(c, 64) * 16 + div_up(c, 4096) * 4 +
+             tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4;
+    }
+    b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
+         h->stage_out_cap;
+    *bytes = b;
+    return BWT_OK;
+}
+
+int bwt_set_trim(bwt_set_t h) {
+    if (!h) return BWT_EINVAL;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (int b = 0; b < 3; ++b) {
+        if (b == h->cur) continue;
+        IndexBuf &x = h->buf[b];
+        dfree(x.recs);
+        dfree(x.sbc);
+        dfree(x.meta);
+        x.rec_cap = x.sbc_cap = 0;
+    }
+    free_ws(h->ws);
+    dfree(h->first_new);
+    h->first_new_cap = 0;
+    dfree(h->stage_reads);
+    h->stage_reads_cap = 0;
+    dfree(h->stage_off);
+    h->stage_off_cap = 0;
+    dfree(h->cuts);
+    h->cuts_cap = 0;
+    dfree(h->stage_out);
+    h->stage_out_cap = 0;
+    return BWT_OK;
+}
+
 int bwt_set_size(bwt_set_t h, uint64_t *n, uint64_t *m) {
     if (!h) return BWT_EINVAL;
     if (n) *n = h->n;

@@ -315,7 +315,18 @@ __global__ __launch_bounds__(256) void insert_kernel(
     }
 }
 
+__global__ void fill_u64_kernel(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    fill_u64_kernel<<<(unsigned)div_up(n, 256), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream_t s) {
     index_init_kernel<<<1, 64, 0, s>>>(recs, sbc, meta);

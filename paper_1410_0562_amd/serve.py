@@ -1,0 +1,262 @@
+"""Serving form: many tenant indices on one GPU, with continuous batching.
+
+Each tenant owns one incremental index (a ``BwtSet``).  Append requests
+arrive over time; a tenant's appends are applied in arrival order (the order
+fixes the terminator numbering, so it fixes the result), while appends of
+different tenants run concurrently: a pool of worker threads each drives one
+append at a time through the C ABI on the tenant handle's own HIP stream, so
+their kernels overlap on the device.  A request is admitted as soon as a
+worker is free, its tenant has nothing in flight, and the device memory
+budget allows it; to make room, idle tenants are first trimmed (workspace and
+spare buffers freed) and then spilled: the index is exported to pinned host
+memory and the device copy released; the next request of a spilled tenant
+restores it with ``import_bwt`` before appending.  Every step of the BWT work
+runs in the library's kernels; this module only schedules.
+
+Latency of a request = completion time - arrival time.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import bwtset
+
+
+@dataclass
+class Request:
+    tenant: int
+    reads: object          # packed reads (numpy or device tensor)
+    offsets: object        # offsets (numpy uint64 or device int64 tensor)
+    bases: int
+    arrival: float = 0.0
+    start: float = 0.0
+    finish: float = 0.0
+    error: Optional[BaseException] = None
+    reserved: int = 0
+    done: threading.Event = field(default_factory=threading.Event)
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+
+class _Tenant:
+    def __init__(self, tid: int):
+        self.tid = tid
+        self.index: Optional[bwtset.BwtSet] = None
+        self.spill = None            # pinned host copy of B while spilled
+        self.pending = collections.deque()
+        self.busy = False
+        self.last_used = 0.0
+        self.trimmed = True
+
+
+class BwtService:
+    """Continuous-batching append service over `tenants` indices.
+
+    budget_bytes: device memory the tenants' handles may hold together.
+    workers: appends in flight at once (one per tenant at most).
+    """
+
+    def __init__(self, tenants: int, budget_bytes: int, workers: int = 4,
+                 block_size: int = 1 << 26, per_append_bytes: Optional[int] = None):
+        import torch
+        self.torch = torch
+        self.tenants = [_Tenant(t) for t in range(tenants)]
+        self.budget = int(budget_bytes)
+        self.block_size = int(block_size)
+        # device bytes an append needs beyond the resident index: the block
+        # workspace (about 90 bytes per suffix of a block) plus staging
+        self.per_append = int(per_append_bytes or 96 * min(self.block_size, 1 << 26))
+        self.lock = threading.Condition()
+        self.queue = collections.deque()      # arrival order
+        self.reserved = 0                     # bytes promised to appends in flight
+        self.stats = collections.Counter()
+        self.completed = []
+        self._stop = False
+        self._workers = [threading.Thread(target=self._worker, daemon=True, name="bwt-serve-%d" % i)
+                         for i in range(workers)]
+        self._device = torch.cuda.current_device()
+        for w in self._workers:
+            w.start()
+
+    # ---------------------------------------------------------------- client
+    def submit(self, tenant: int, reads, offsets) -> Request:
+        offs = offsets
+        if isinstance(offs, np.ndarray):
+            bases = int(offs[-1]) - int(offs[0])
+        else:
+            bases = int(offs[-1].item()) - int(offs[0].item())
+        req = Request(tenant, reads, offsets, bases, arrival=time.perf_counter())
+        with self.lock:
+            self.queue.append(req)
+            self.stats["submitted"] += 1
+            self.lock.notify_all()
+        return req
+
+    def drain(self, timeout: Optional[float] = None) -> None:
+        """Wait until every submitted request has finished."""
+        t_end = None if timeout is None else time.perf_counter() + timeout
+        with self.lock:
+            while self.queue or any(t.busy for t in self.tenants):
+                left = None if t_end is None else t_end - time.perf_counter()
+                if left is not None and left <= 0:
+                    raise TimeoutError("requests still pending")
+                self.lock.wait(timeout=left if left is not None else 0.5)
+
+    def close(self) -> None:
+        with self.lock:
+            self._stop = True
+            self.lock.notify_all()
+        for w in self._workers:
+            w.join(timeout=60)
+        for t in self.tenants:
+            if t.index is not None:
+                t.index.close()
+                t.index = None
+
+    def export(self, tenant: int) -> bytes:
+        """The tenant's BWT (waits for its pending appends)."""
+        t = self.tenants[tenant]
+        with self.lock:
+            while t.busy or any(r.tenant == tenant for r in self.queue):
+                self.lock.wait(timeout=0.5)
+            if t.index is not None:
+                return t.index.export()
+            if t.spill is not None:
+                return bytes(t.spill.numpy().tobytes())
+            return b""
+
+    # ----------------------------------------------------------- scheduling
+    def _resident_bytes(self) -> int:
+        return self.reserved + sum(t.index.memory() for t in self.tenants
+                                   if t.index is not None and not t.busy)
+
+    def _make_room(self, need: int, keep: _Tenant) -> bool:
+        """Trim, then spill, idle tenants (least recently used first) until
+        `need` more bytes fit the budget.  Called with the lock held."""
+        if self._resident_bytes() + need <= self.budget:
+            return True
+        idle = sorted((t for t in self.tenants
+                       if t is not keep and not t.busy and t.index is not None),
+                      key=lambda t: t.last_used)
+        for t in idle:
+            if not t.trimmed:
+                t.index.trim()
+                t.trimmed = True
+                self.stats["trims"] += 1
+                if self._resident_bytes() + need <= self.budget:
+                    return True
+        for t in idle:
+            self._spill(t)
+            if self._resident_bytes() + need <= self.budget:
+                return True
+        return self._resident_bytes() + need <= self.budget
+
+    def _spill(self, t: _Tenant) -> None:
+        n, _ = t.index.size()
+        host = self.torch.empty(max(n, 1), dtype=self.torch.uint8, pin_memory=True)
+        if n:
+            t.index.export(host.numpy()[:n])
+        t.spill = host[:n]
+        t.index.close()
+        t.index = None
+        self.stats["spills"] += 1
+
+    def _restore(self, t: _Tenant) -> None:
+        t.index = bwtset.BwtSet(block_size=self.block_size)
+        if t.spill is not None:
+            if len(t.spill):
+                t.index.import_bwt(t.spill.numpy())
+            t.spill = None
+            self.stats["restores"] += 1
+        t.trimmed = False
+
+    def _next_admissible(self) -> Optional[Request]:
+        """First queued request (arrival order) whose tenant is idle and that
+        fits the budget.  Called with the lock held."""
+        seen = set()
+        for i, req in enumerate(self.queue):
+            t = self.tenants[req.tenant]
+            if req.tenant in seen or t.busy:
+                seen.add(req.tenant)       # keep per-tenant order
+                continue
+            seen.add(req.tenant)
+            grow = 2 * (req.bases + 2 * len(req.offsets))  # index growth, 3 buffers
+            resident = 0 if t.index is None else t.index.memory()
+            restore = 0 if t.index is not None else (
+                int(len(t.spill) * 1.6) if t.spill is not None else 0)
+            need = self.per_append + grow + restore
+            if t.index is not None and not t.trimmed:
+                need = max(0, need - resident)
+            fits = self._make_room(need, t)
+            if not fits and not any(x.busy for x in self.tenants):
+                # larger than the whole budget: run it alone rather than never
+                fits = True
+                self.stats["oversize"] += 1
+            if fits:
+                del self.queue[i]
+                req.reserved = need + (resident if t.index is not None else 0)
+                self.reserved += req.reserved
+                return req
+            self.stats["deferred"] += 1
+            return None
+        return None
+
+    def _worker(self) -> None:
+        torch = self.torch
+        torch.cuda.set_device(self._device)
+        while True:
+            with self.lock:
+                req = None
+                while not self._stop:
+                    req = self._next_admissible()
+                    if req is not None:
+                        break
+                    self.lock.wait(timeout=0.05)
+                if req is None:
+                    return
+                t = self.tenants[req.tenant]
+                t.busy = True
+            # restore and append outside the lock: other workers keep
+            # admitting and running other tenants meanwhile
+            req.start = time.perf_counter()
+            try:
+                if t.index is None:
+                    self._restore(t)
+                t.index.append(req.reads, req.offsets)
+                t.trimmed = False
+            except BaseException as e:  # noqa: BLE001
+                req.error = e
+            req.finish = time.perf_counter()
+            with self.lock:
+                self.reserved -= req.reserved
+                t.busy = False
+                t.last_used = req.finish
+                self.stats["completed"] += 1
+                self.completed.append(req)
+                self.lock.notify_all()
+            req.done.set()
+
+    # -------------------------------------------------------------- reports
+    def latency_summary(self) -> dict:
+        lat = np.array([r.latency for r in self.completed if r.error is None])
+        bases = sum(r.bases for r in self.completed if r.error is None)
+        if len(lat) == 0:
+            return {"requests": 0}
+        t0 = min(r.arrival for r in self.completed)
+        t1 = max(r.finish for r in self.completed)
+        return {"requests": int(len(lat)), "bases": int(bases),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3),
+                "bases_per_s": bases / (t1 - t0) if t1 > t0 else 0.0,
+                "spills": int(self.stats["spills"]), "restores": int(self.stats["restores"]),
+                "trims": int(self.stats["trims"]), "errors": sum(1 for r in self.completed
+                                                                 if r.error is not None)}
