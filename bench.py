@@ -79,6 +79,75 @@ def cpu_baseline(packed, offs, nreads):
                       "comparison sort of all suffixes (%.1f s)" % (nreads, bases, dt)}
 
 
+def run_served(args, torch, bwtset, synth):
+    """Served form: tenants' append requests arrive as a Poisson process at
+    `load` times the measured single-stream capacity; a continuous-batching
+    service (paper_1410_0562_amd.serve) runs them.  Prints one JSON line."""
+    import numpy as np
+    from paper_1410_0562_amd.serve import BwtService
+    tenants = 16
+    log("generating %d requests on the GPU" % args.requests)
+    tids, reqs = synth.served_requests_gpu(tenants=tenants, count=args.requests)
+    torch.cuda.synchronize()
+    mean_bases = float(np.mean([b for _, _, b in reqs]))
+    # single-stream capacity: one fresh index, requests appended back to back
+    log("measuring single-stream capacity")
+    cal = bwtset.BwtSet(block_size=1 << 26)
+    cal_reqs = sorted(reqs, key=lambda r: r[2])[len(reqs) // 2: len(reqs) // 2 + 4]
+    cal.append(cal_reqs[0][0], cal_reqs[0][1])  # warm the workspace
+    cal.reset()
+    t0 = time.perf_counter()
+    nb = 0
+    for p, o, b in cal_reqs:
+        cal.append(p, o)
+        nb += b
+    torch.cuda.synchronize()
+    capacity = nb / (time.perf_counter() - t0)
+    cal.close()
+    rate = args.load * capacity / mean_bases       # requests per second
+    rng = np.random.default_rng(14100562 + 55)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+    svc = BwtService(tenants, budget_bytes=int(args.budget_gb * (1 << 30)), workers=args.workers,
+                     block_size=1 << 26)
+    log("serving %d requests at %.1f req/s" % (len(reqs), rate))
+    t_start = time.perf_counter()
+    for k, ((p, o, b), t) in enumerate(zip(reqs, tids)):
+        delay = t_start + arrivals[k] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        svc.submit(int(t), p, o)
+        if k % 64 == 63:
+            log("submitted %d" % (k + 1))
+    svc.drain(timeout=600)
+    summ = svc.latency_summary()
+    svc.close()
+    out = {
+        "metric": METRIC,
+        "value": summ["bases_per_s"],
+        "unit": "bases/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": (max(r.finish for r in svc.completed) - t_start) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "served: %d tenants with random 100 Mbp references, %d append "
+                               "requests of 10k-1M reads (log-uniform) x 150 bp, 1%% "
+                               "substitutions, Poisson arrivals at %.0f%% of single-stream "
+                               "capacity; %g GB budget, %d workers" % (
+                                   tenants, len(reqs), args.load * 100, args.budget_gb,
+                                   args.workers)},
+        "served": {"p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
+                   "requests": summ["requests"], "errors": summ["errors"],
+                   "spills": summ["spills"], "restores": summ["restores"], "trims": summ["trims"],
+                   "single_stream_bases_per_s": capacity, "arrival_rate_per_s": rate},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +166,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
+    ap.add_argument("--served", action="store_true",
+                    help="served form: 16 tenants, Poisson append requests (p50/p99 latency)")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--budget-gb", type=float, default=100.0)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="offered load as a fraction of the single-stream capacity")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -126,6 +202,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 1 << 30, "launches": 3}))
         return
+
+    if args.served:
+        return run_served(args, torch, bwtset, synth)
 
     log("generating workload")
     if args.workload == "short":

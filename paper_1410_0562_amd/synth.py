@@ -183,3 +183,38 @@ def take_reads(packed: np.ndarray, offsets: np.ndarray, j0: int, j1: int):
         codes[q::4] = (sub >> (2 * q)) & 3
     codes = codes[s0 - 4 * b0:s0 - 4 * b0 + n]
     return pack_codes(codes), (offsets[j0:j1 + 1] - np.uint64(s0)).astype(np.uint64)
+
+
+def served_requests_gpu(tenants: int = 16, count: int = 512, ref_len: int = 100_000_000,
+                        min_reads: int = 10_000, max_reads: int = 1_000_000, length: int = 150,
+                        sub_rate: float = 0.01, seed: int = SEED_BASE + 5):
+    """Workload 5 drawn on the GPU with torch: per-tenant uniform random
+    references, `count` requests to uniformly drawn tenants with
+    log-uniform read counts, reads sampled at uniform positions (forward
+    strand) with i.i.d. substitutions.  Returns (tenant ids, list of
+    (packed device tensor, offsets device int64 tensor, bases))."""
+    import torch
+    rng = np.random.default_rng(seed)
+    tids = rng.integers(0, tenants, count)
+    ms = np.floor(np.exp(rng.uniform(np.log(min_reads), np.log(max_reads), count))).astype(np.int64)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    refs = [torch.randint(0, 4, (ref_len,), dtype=torch.uint8, device="cuda", generator=gen)
+            for _ in range(tenants)]
+    ar = torch.arange(length, device="cuda", dtype=torch.int64)
+    shifts = torch.tensor([0, 2, 4, 6], device="cuda", dtype=torch.uint8)
+    out = []
+    for t, m in zip(tids, ms):
+        starts = torch.randint(0, ref_len - length + 1, (int(m),), device="cuda", generator=gen)
+        codes = refs[int(t)][starts[:, None] + ar[None, :]].reshape(-1)
+        hit = torch.rand(codes.shape, device="cuda", generator=gen) < sub_rate
+        delta = torch.randint(1, 4, codes.shape, dtype=torch.uint8, device="cuda", generator=gen)
+        codes = torch.where(hit, (codes + delta) & 3, codes)
+        pad = (-codes.numel()) % 4
+        if pad:
+            codes = torch.cat([codes, torch.zeros(pad, dtype=torch.uint8, device="cuda")])
+        packed = (codes.view(-1, 4) << shifts).sum(dim=1, dtype=torch.uint8)
+        offs = torch.arange(int(m) + 1, device="cuda", dtype=torch.int64) * length
+        out.append((packed, offs, int(m) * length))
+    del refs
+    return tids, out

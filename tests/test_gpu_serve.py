@@ -117,3 +117,27 @@ def test_import_roundtrip(torch_dev, oracle_mod):
         a.trim()
         assert a.export() == before
         assert a.memory() > 0
+
+
+def test_served_generator_through_service(torch_dev, oracle_mod):
+    """The device-side request generator used by the served benchmark, at a
+    small size: every tenant's index equals the oracle BWT of its requests."""
+    tenants = 3
+    tids, reqs = synth.served_requests_gpu(tenants=tenants, count=9, ref_len=50_000,
+                                           min_reads=100, max_reads=2000, length=150)
+    host = [(int(t), p.cpu().numpy(), o.cpu().numpy().astype(np.uint64))
+            for t, (p, o, _) in zip(tids, reqs)]
+    for (_, p, o), (_, _, b) in zip(host, reqs):
+        assert int(o[-1]) == b and len(p) == (b + 3) // 4
+    from paper_1410_0562_amd.serve import BwtService
+    svc = BwtService(tenants, budget_bytes=64 << 30, workers=2, block_size=1 << 18)
+    try:
+        for t, (p, o, _) in zip(tids, reqs):
+            svc.submit(int(t), p, o)
+        svc.drain(timeout=120)
+        out = [svc.export(t) for t in range(tenants)]
+        assert svc.latency_summary()["errors"] == 0
+    finally:
+        svc.close()
+    for t in range(tenants):
+        assert out[t] == _oracle_of(oracle_mod, host, t), t
