@@ -71,6 +71,25 @@ void bwt_set_destroy(bwt_set_t h);
 int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
                    uint64_t m, void *stream);
 
+/* Batched form: appends reads[i]/offsets[i] (m[i] strings) to hs[i] for every
+ * i < count, with the same result on each handle as bwt_set_append.  The sets
+ * are cut into blocks as bwt_set_append cuts them (Algorithm 1), and blocks of
+ * different sets (units) share one device block: the block is suffix-sorted as
+ * one text whose keys lead with each suffix's rank among its own set's old
+ * suffixes plus a per-unit offset, so that the units sort apart; each unit is
+ * ranked against its own set's index (Lemma 1) and merged into it, all units
+ * of a block in one launch per step.  Many small sets then share the launches
+ * and synchronizations of a few blocks.
+ * hs: count distinct handles of one device, none unusable.  The batch runs on
+ * hs[0]'s workspace, block size and tuning parameters and on `stream` (NULL:
+ * hs[0]'s stream).  m[i] == 0 leaves hs[i] as it is.  reads[i]/offsets[i]:
+ * host or device, as for bwt_set_append, and valid until the call returns.
+ * Returns BWT_OK or a negative code (kept as hs[0]'s last error); on error
+ * every index is unchanged. */
+int bwt_set_append_many(bwt_set_t *hs, const uint8_t *const *reads,
+                        const uint64_t *const *offsets, const uint64_t *m,
+                        uint64_t count, void *stream);
+
 /* rank(c, k, B) = |{ i < k : B[i] = c }| (Eq. 2).  c: 'A','C','G','T' or '$';
  * 0 <= k <= n.  Returns the count, or UINT64_MAX on error. */
 uint64_t bwt_set_rank(bwt_set_t h, char c, uint64_t k);

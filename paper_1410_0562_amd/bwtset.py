@@ -69,7 +69,7 @@ EXPORTED = [
     "bwt_set_set_block_size", "bwt_set_last_error", "bwt_set_strerror",
     "bwt_set_block_sort", "bwt_set_compute_ranks", "bwt_set_insert",
     "bwt_set_enable_timing", "bwt_set_get_stats", "bwt_set_set_param",
-    "bwt_set_import", "bwt_set_memory", "bwt_set_trim",
+    "bwt_set_import", "bwt_set_memory", "bwt_set_trim", "bwt_set_append_many",
 ]
 BWT_PARAM_KEY_BITS = 1
 BWT_PARAM_RADIX_TILE = 2
@@ -129,6 +129,9 @@ def load(path: str = LIB_PATH):
     L.bwt_set_memory.restype = i32
     L.bwt_set_trim.argtypes = [vp]
     L.bwt_set_trim.restype = i32
+    L.bwt_set_append_many.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(u64), u64, vp]
+    L.bwt_set_append_many.restype = i32
     if path == LIB_PATH:
         _lib = L
     return L
@@ -314,3 +317,24 @@ class BwtSet:
         self._check(load().bwt_set_get_stats(self._h, ctypes.byref(st), 1 if reset else 0),
                     "bwt_set_get_stats")
         return st.as_dict()
+
+
+def append_many(sets, reads_list, offsets_list, stream=None) -> None:
+    """Batched form: sets[i].append(reads_list[i], offsets_list[i]) for every
+    i, run as one schedule on sets[0]'s workspace and parameters (see
+    bwt_set_append_many).  Same result on every set as one append each."""
+    n = len(sets)
+    if n != len(reads_list) or n != len(offsets_list):
+        raise ValueError("sets, reads and offsets must have the same length")
+    if n == 0:
+        return
+    reads_list = [_as_reads(r) for r in reads_list]
+    offsets_list = [_as_offsets(o) for o in offsets_list]
+    vp = ctypes.c_void_p
+    hs = (vp * n)(*[s._h for s in sets])
+    rp = (vp * n)(*[_ptr(r) for r in reads_list])
+    op = (vp * n)(*[_ptr(o) for o in offsets_list])
+    ms = (ctypes.c_uint64 * n)(*[max(_len(o) - 1, 0) for o in offsets_list])
+    rc = load().bwt_set_append_many(hs, rp, op, ms, n, _stream(stream))
+    if rc != 0:
+        raise BwtSetError(rc, "bwt_set_append_many")

@@ -40,8 +40,8 @@ constexpr uint64_t REC_SYMS = 1ull << REC_SHIFT;
 constexpr int SB_SHIFT = 32;
 constexpr int META_WORDS = 8;
 
-inline uint64_t records_for(uint64_t n) { return (n >> REC_SHIFT) + 1; }
-inline uint64_t superblocks_for(uint64_t n) { return (n >> SB_SHIFT) + 1; }
+__host__ __device__ inline uint64_t records_for(uint64_t n) { return (n >> REC_SHIFT) + 1; }
+__host__ __device__ inline uint64_t superblocks_for(uint64_t n) { return (n >> SB_SHIFT) + 1; }
 
 // ---------------------------------------------------------------------------
 // Block suffix sorting.
@@ -173,6 +173,83 @@ hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const
                                 uint32_t m_blk, uint32_t n_blk, const Rec *recs,
                                 const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
                                 const RankSegments &sg, uint32_t *err, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched form: one block holds reads of several independent sets (units).
+// Unit u of a block is a run of consecutive reads of one set; its reads are
+// ranked against that set's own index, and every rank is offset by
+//   goff[u] = sum over the earlier units u' of (n_ext[u'] + 1),
+// the number of values the earlier units' ranks can take, so that the ranks
+// of different units never meet.  Leading the suffix-sort key with the offset
+// rank sorts the block unit by unit, each unit in its own suffix order, so
+// the units' sorted suffixes are consecutive runs of the sorted block and
+// each run merges into its own set's index.
+// ---------------------------------------------------------------------------
+struct RankUnit {
+    const Rec *recs;
+    const uint64_t *sbc;
+    const uint64_t *meta;
+    uint64_t goff;
+    uint32_t read0;   // first read of the unit in the block (ascending over units)
+    uint32_t big;     // index of 2^32 symbols or more
+};
+hipError_t launch_compute_ranks_units(const uint8_t *reads, const uint64_t *off,
+                                      const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
+                                      const RankUnit *units, uint32_t nunits, uint64_t *g,
+                                      const RankSegments &sg, uint32_t *err, hipStream_t s);
+
+struct InsertUnit {
+    const Rec *orecs;
+    const uint64_t *osbc;
+    const uint64_t *ometa;
+    Rec *nrecs;
+    uint64_t *nsbc;
+    uint64_t *nmeta;
+    uint64_t n_ext, n_new;
+    uint64_t sa0;    // first slot of the unit among the block's sorted suffixes
+    uint64_t goff;   // subtracted from the key's g to give the unit's g_sa
+    uint64_t tile0;  // first Insert tile of the unit; its first_new entries
+                     // start at tile0 + (unit index)
+};
+// first_new for every unit; ntiles_all = sum of the units' tiles
+hipError_t launch_ins_tile_first_units(const InsertUnit *units, uint32_t nunits,
+                                       const uint64_t *gkeys, int gshift, uint64_t ntiles_all,
+                                       uint64_t *first_new, hipStream_t s);
+hipError_t launch_ins_meta_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
+                                 int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                                 hipStream_t s);
+hipError_t launch_insert_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
+                               int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                               const uint64_t *first_new, uint64_t ntiles_all, uint32_t *err,
+                               hipStream_t s);
+
+// Staging of a batch: the reads of every unit, in schedule order, copied
+// into one packed buffer with one offsets array, so that every block of the
+// batch is a contiguous run of reads.  Unit u takes the reads [j0, j1) of its
+// set and lands at staged read dst_read0 and staged symbol dst_sym0 (both
+// non-decreasing over units, with no gaps).
+struct GatherUnit {
+    const uint8_t *reads;   // the set's packed reads (device), from symbol sym_base
+    const uint64_t *off;    // the set's offsets (device)
+    uint64_t j0, j1;
+    uint64_t dst_read0, dst_sym0;
+    uint64_t sym_base;      // multiple of 4: symbol p is at reads[(p - sym_base) / 4]
+};
+hipError_t launch_gather_offsets(const GatherUnit *units, uint32_t nunits, uint64_t total_reads,
+                                 uint64_t total_syms, uint64_t *dst_off, hipStream_t s);
+hipError_t launch_gather_reads(const GatherUnit *units, uint32_t nunits, uint64_t total_syms,
+                               uint8_t *dst, hipStream_t s);
+// Per set of a batch (device offsets, m reads): res[4s..4s+3] = {1 if the
+// offsets decrease, longest read, suffixes, number of blocks of at most M
+// suffixes}; with cuts (cut_base[s] words into it), the block cuts as
+// launch_plan_blocks writes them.
+struct PlanSet {
+    const uint64_t *off;
+    uint64_t m;
+    uint64_t cut_base;
+};
+hipError_t launch_plan_sets(const PlanSet *sets, uint32_t nsets, uint64_t M, uint64_t *res,
+                            uint64_t *cuts, hipStream_t s);
 
 // Insert and index bookkeeping (k_insert.hip).  The new symbols come in
 // suffix order as the sorted (key, value) pairs of ConstructSA: g_sa[i] is

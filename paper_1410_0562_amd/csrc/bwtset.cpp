@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -131,6 +132,12 @@ struct bwt_set {
     uint64_t cuts_cap = 0;
     uint8_t *stage_out = nullptr;
     uint64_t stage_out_cap = 0;
+    // batched form (when this handle drives a batch): device tables, staged
+    // host inputs
+    uint8_t *btab = nullptr;
+    uint64_t btab_cap = 0;
+    uint8_t *bstage = nullptr;
+    uint64_t bstage_cap = 0;
     uint64_t *res = nullptr;       // 4 words of device results
     uint64_t *pinned = nullptr;    // small pinned host area (512 words)
     int last_error = BWT_OK;
@@ -695,6 +702,345 @@ int set_device(bwt_set *h) {
     return BWT_OK;
 }
 
+// ---- batched form ---------------------------------------------------------------
+// One unit = one block of one set (Algorithm 1 blocks, cut per set).  Units
+// are scheduled level by level (every set's first block, then every set's
+// second block, ...) and packed greedily into device blocks of at most M
+// suffixes; a new device block starts with each level, so a set's block k
+// always runs after its block k-1 has been merged.
+struct HostUnit {
+    uint32_t set;        // position in the batch
+    uint32_t level;      // block index within the set
+    uint64_t j0, j1;     // reads of the set
+    uint64_t nsuf, nsym;
+    uint64_t dst_read0, dst_sym0;
+    uint64_t n_ext;      // the set's index size before this unit
+    int src, dst;        // index buffers of the set read and written
+};
+
+struct DevBlock {
+    uint32_t u0, u1;     // units [u0, u1)
+    uint64_t read0, m_blk, n_blk;
+    uint64_t gtotal;     // sum of (n_ext + 1) over the units
+    uint64_t ntiles;     // Insert tiles over all units
+    size_t rank_off, ins_off;  // byte offsets of the unit tables in btab
+};
+
+template <class T>
+size_t put_table(std::vector<uint8_t> &tab, const std::vector<T> &v) {
+    size_t at = (tab.size() + 255) & ~(size_t)255;
+    tab.resize(at + v.size() * sizeof(T));
+    if (!v.empty()) memcpy(tab.data() + at, v.data(), v.size() * sizeof(T));
+    return at;
+}
+
+int append_many(bwt_set *d, bwt_set **hs, const uint8_t *const *reads,
+                const uint64_t *const *offsets, const uint64_t *m, uint64_t count, hipStream_t s) {
+    std::vector<uint32_t> act;
+    for (uint64_t i = 0; i < count; ++i) {
+        if (m[i] == 0) continue;
+        if (!reads[i] || !offsets[i]) return fail(d, BWT_EINVAL);
+        act.push_back((uint32_t)i);
+    }
+    if (act.empty()) return BWT_OK;
+    const uint32_t na = (uint32_t)act.size();
+
+    // 1. device copies of host inputs.  Host offsets are checked for order
+    // here (their byte range depends on it); device offsets on the device.
+    std::vector<const uint8_t *> dreads(na);
+    std::vector<const uint64_t *> doff(na);
+    std::vector<uint64_t> sym_base(na, 0);
+    std::vector<uint64_t> stage_need(na, 0);
+    std::vector<uint64_t> first_last(2 * na, 0);
+    std::vector<bool> rdev(na), odev(na);
+    uint64_t stage_total = 0;
+    bool need_ends = false;
+    for (uint32_t a = 0; a < na; ++a) {
+        const uint32_t i = act[a];
+        rdev[a] = is_device_ptr(reads[i]);
+        odev[a] = is_device_ptr(offsets[i]);
+        if (!odev[a]) {
+            for (uint64_t j = 0; j < m[i]; ++j)
+                if (offsets[i][j + 1] < offsets[i][j]) return fail(d, BWT_EINVAL);
+            first_last[2 * a] = offsets[i][0];
+            first_last[2 * a + 1] = offsets[i][m[i]];
+            stage_total += ((m[i] + 1) * 8 + 255) & ~255ull;
+        } else if (!rdev[a]) {
+            need_ends = true;
+        }
+    }
+    if (need_ends) {
+        // host reads with device offsets: the byte range comes from the device
+        for (uint32_t a = 0; a < na; ++a) {
+            if (rdev[a] || !odev[a]) continue;
+            const uint32_t i = act[a];
+            HIPCHK(d, hipMemcpyAsync(&first_last[2 * a], offsets[i], 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(d, hipMemcpyAsync(&first_last[2 * a + 1], offsets[i] + m[i], 8,
+                                     hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(d, hipStreamSynchronize(s));
+    }
+    for (uint32_t a = 0; a < na; ++a) {
+        if (rdev[a]) continue;
+        if (first_last[2 * a + 1] < first_last[2 * a]) return fail(d, BWT_EINVAL);
+        const uint64_t b0 = first_last[2 * a] / 4, b1 = (first_last[2 * a + 1] + 3) / 4;
+        stage_need[a] = b1 - b0;
+        stage_total += ((b1 - b0) + 255) & ~255ull;
+    }
+    int rc;
+    if (stage_total) {
+        if ((rc = ensure_buf(d, d->bstage, d->bstage_cap, stage_total))) return rc;
+        uint64_t at = 0;
+        for (uint32_t a = 0; a < na; ++a) {
+            const uint32_t i = act[a];
+            if (!odev[a]) {
+                HIPCHK(d, hipMemcpyAsync(d->bstage + at, offsets[i], (m[i] + 1) * 8,
+                                         hipMemcpyHostToDevice, s));
+                doff[a] = reinterpret_cast<const uint64_t *>(d->bstage + at);
+                at += ((m[i] + 1) * 8 + 255) & ~255ull;
+            } else {
+                doff[a] = offsets[i];
+            }
+            if (!rdev[a]) {
+                const uint64_t b0 = first_last[2 * a] / 4;
+                if (stage_need[a])
+                    HIPCHK(d, hipMemcpyAsync(d->bstage + at, reads[i] + b0, stage_need[a],
+                                             hipMemcpyHostToDevice, s));
+                dreads[a] = d->bstage + at;
+                sym_base[a] = 4 * b0;
+                at += (stage_need[a] + 255) & ~255ull;
+            } else {
+                dreads[a] = reads[i];
+            }
+        }
+    } else {
+        for (uint32_t a = 0; a < na; ++a) {
+            dreads[a] = reads[act[a]];
+            doff[a] = offsets[act[a]];
+        }
+    }
+
+    // 2. plan: offsets check, suffix and block counts per set; cuts of the
+    // sets with more than one block
+    const uint64_t M = d->M;
+    std::vector<PlanSet> ps(na);
+    for (uint32_t a = 0; a < na; ++a) ps[a] = PlanSet{doff[a], m[act[a]], 0};
+    std::vector<uint8_t> tab;
+    size_t ps_at = put_table(tab, ps);
+    size_t res_at = (tab.size() + 255) & ~(size_t)255;
+    const uint64_t plan_bytes = res_at + (uint64_t)na * 32;
+    if ((rc = ensure_buf(d, d->btab, d->btab_cap, plan_bytes))) return rc;
+    HIPCHK(d, hipMemcpyAsync(d->btab + ps_at, tab.data() + ps_at, na * sizeof(PlanSet),
+                             hipMemcpyHostToDevice, s));
+    uint64_t *res_dev = reinterpret_cast<uint64_t *>(d->btab + res_at);
+    HIPCHK(d, launch_plan_sets(reinterpret_cast<const PlanSet *>(d->btab + ps_at), na, M, res_dev,
+                               nullptr, s));
+    std::vector<uint64_t> res(4 * (size_t)na);
+    HIPCHK(d, hipMemcpyAsync(res.data(), res_dev, res.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(d, hipStreamSynchronize(s));
+    uint64_t maxlen = 0, cut_words = 0;
+    bool multi = false;
+    for (uint32_t a = 0; a < na; ++a) {
+        if (res[4 * a] || res[4 * a + 1] > MAX_READ || res[4 * a + 3] == 0)
+            return fail(d, BWT_EINVAL);
+        maxlen = std::max(maxlen, res[4 * a + 1]);
+        ps[a].cut_base = cut_words;
+        cut_words += 2 * (res[4 * a + 3] + 1);
+        multi |= res[4 * a + 3] > 1;
+    }
+    std::vector<uint64_t> cuts(cut_words);
+    if (multi) {
+        if ((rc = ensure_buf(d, d->cuts, d->cuts_cap, cut_words))) return rc;
+        HIPCHK(d, hipMemcpyAsync(d->btab + ps_at, ps.data(), na * sizeof(PlanSet),
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(d, launch_plan_sets(reinterpret_cast<const PlanSet *>(d->btab + ps_at), na, M,
+                                   res_dev, d->cuts, s));
+        HIPCHK(d, hipMemcpyAsync(cuts.data(), d->cuts, cut_words * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(d, hipStreamSynchronize(s));
+    } else {
+        for (uint32_t a = 0; a < na; ++a) {
+            uint64_t *c = cuts.data() + ps[a].cut_base;
+            c[0] = 0;
+            c[1] = 0;
+            c[2] = m[act[a]];
+            c[3] = res[4 * a + 2];
+        }
+    }
+
+    // 3. units, level by level, and device blocks
+    std::vector<HostUnit> units;
+    std::vector<uint64_t> n_run(na);
+    std::vector<std::array<int, 2>> other(na);
+    uint64_t maxK = 0;
+    for (uint32_t a = 0; a < na; ++a) {
+        bwt_set *h = hs[act[a]];
+        n_run[a] = h->n;
+        int k = 0;
+        for (int b = 0; b < 3; ++b)
+            if (b != h->cur) other[a][k++] = b;
+        maxK = std::max(maxK, res[4 * a + 3]);
+    }
+    std::vector<DevBlock> blocks;
+    uint64_t dst_read = 0, dst_sym = 0;
+    for (uint64_t lv = 0; lv < maxK; ++lv) {
+        bool open_block = false;
+        for (uint32_t a = 0; a < na; ++a) {
+            if (lv >= res[4 * a + 3]) continue;
+            const uint64_t *c = cuts.data() + ps[a].cut_base;
+            HostUnit u;
+            u.set = a;
+            u.level = (uint32_t)lv;
+            u.j0 = c[2 * lv];
+            u.j1 = c[2 * lv + 2];
+            u.nsuf = c[2 * lv + 3] - c[2 * lv + 1];
+            u.nsym = u.nsuf - (u.j1 - u.j0);
+            u.dst_read0 = dst_read;
+            u.dst_sym0 = dst_sym;
+            u.n_ext = n_run[a];
+            u.src = lv == 0 ? hs[act[a]]->cur : other[a][(lv - 1) & 1];
+            u.dst = other[a][lv & 1];
+            dst_read += u.j1 - u.j0;
+            dst_sym += u.nsym;
+            n_run[a] += u.nsuf;
+            if (!open_block || blocks.back().n_blk + u.nsuf > M) {
+                DevBlock B{};
+                B.u0 = B.u1 = (uint32_t)units.size();
+                B.read0 = u.dst_read0;
+                blocks.push_back(B);
+                open_block = true;
+            }
+            DevBlock &B = blocks.back();
+            B.u1 += 1;
+            B.m_blk += u.j1 - u.j0;
+            B.n_blk += u.nsuf;
+            B.gtotal += u.n_ext + 1;
+            B.ntiles += div_up(records_for(u.n_ext + u.nsuf), INS_TILE_RECS);
+            units.push_back(u);
+        }
+    }
+    const uint64_t total_reads = dst_read, total_syms = dst_sym;
+    uint64_t max_nblk = 0, max_fn = 0;
+    for (auto &B : blocks) {
+        if (B.n_blk > MAX_BLOCK) return fail(d, BWT_EINVAL);
+        max_nblk = std::max(max_nblk, B.n_blk);
+        max_fn = std::max(max_fn, B.ntiles + (B.u1 - B.u0));
+    }
+
+    // 4. memory: the sets' spare index buffers, the shared workspace, staging
+    for (uint32_t a = 0; a < na; ++a) {
+        bwt_set *h = hs[act[a]];
+        for (int b : other[a])
+            if ((rc = ensure_index(h, h->buf[b], n_run[a]))) return fail(d, rc);
+    }
+    if ((rc = ensure_ws(d, max_nblk))) return rc;
+    if ((rc = ensure_buf(d, d->stage_reads, d->stage_reads_cap, div_up(total_syms, 16) * 4 + 16)))
+        return rc;
+    if ((rc = ensure_buf(d, d->stage_off, d->stage_off_cap, total_reads + 1))) return rc;
+    if ((rc = ensure_buf(d, d->first_new, d->first_new_cap, max_fn + 2))) return rc;
+
+    // 5. unit tables (one upload)
+    tab.clear();
+    std::vector<GatherUnit> gu(units.size());
+    for (size_t k = 0; k < units.size(); ++k) {
+        const HostUnit &u = units[k];
+        // the staged copy of host reads starts at symbol sym_base of the set
+        gu[k] = GatherUnit{dreads[u.set], doff[u.set], u.j0, u.j1, u.dst_read0, u.dst_sym0,
+                           sym_base[u.set]};
+    }
+    const size_t gu_at = put_table(tab, gu);
+    for (auto &B : blocks) {
+        std::vector<RankUnit> ru;
+        std::vector<InsertUnit> iu;
+        uint64_t goff = 0, sa0 = 0, tile0 = 0;
+        for (uint32_t k = B.u0; k < B.u1; ++k) {
+            const HostUnit &u = units[k];
+            bwt_set *h = hs[act[u.set]];
+            const IndexBuf &S = h->buf[u.src];
+            IndexBuf &D = h->buf[u.dst];
+            ru.push_back(RankUnit{S.recs, S.sbc, S.meta, goff, (uint32_t)(u.dst_read0 - B.read0),
+                                  u.n_ext >= (1ull << SB_SHIFT) ? 1u : 0u});
+            iu.push_back(InsertUnit{S.recs, S.sbc, S.meta, D.recs, D.sbc, D.meta, u.n_ext, u.nsuf,
+                                    sa0, goff, tile0});
+            goff += u.n_ext + 1;
+            sa0 += u.nsuf;
+            tile0 += div_up(records_for(u.n_ext + u.nsuf), INS_TILE_RECS);
+        }
+        B.rank_off = put_table(tab, ru);
+        B.ins_off = put_table(tab, iu);
+    }
+    if ((rc = ensure_buf(d, d->btab, d->btab_cap, tab.size()))) return rc;
+    HIPCHK(d, hipMemcpyAsync(d->btab, tab.data(), tab.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(d, hipStreamSynchronize(s));  // tab is pageable host memory
+
+    // 6. staging: every unit's reads, in schedule order, into one input
+    {
+        Scope sc(d, s, BWT_STAGE_PLAN);
+        const GatherUnit *gdev = reinterpret_cast<const GatherUnit *>(d->btab + gu_at);
+        HIPCHK(d, launch_gather_offsets(gdev, (uint32_t)units.size(), total_reads, total_syms,
+                                        d->stage_off, s));
+        HIPCHK(d, launch_gather_reads(gdev, (uint32_t)units.size(), total_syms, d->stage_reads, s));
+    }
+
+    // 7. the device blocks
+    Workspace &w = d->ws;
+    if ((rc = clear_err(d, s))) return rc;
+    for (auto &B : blocks) {
+        const uint32_t nu = B.u1 - B.u0;
+        const uint32_t m_blk = (uint32_t)B.m_blk, n_blk = (uint32_t)B.n_blk;
+        const uint64_t *off = d->stage_off + B.read0;
+        const RankUnit *rdev = reinterpret_cast<const RankUnit *>(d->btab + B.rank_off);
+        const InsertUnit *idev = reinterpret_cast<const InsertUnit *>(d->btab + B.ins_off);
+        if ((rc = block_prep(d, s, off, m_blk, n_blk))) return rc;
+        // one empty unit alone needs no ranks (all 0); otherwise the ranks
+        // carry the unit offsets
+        const int gbits = bits_for_value(B.gtotal - 1);
+        if (gbits > 0) {
+            Scope sc(d, s, BWT_STAGE_RANKS);
+            Scope sk(d, s, SPAN_RANKS_K, n_blk - m_blk);
+            HIPCHK(d, launch_compute_ranks_units(d->stage_reads, off, w.soff, m_blk, n_blk, rdev, nu,
+                                                 w.g, rank_segments(d), w.misc + MISC_ERR, s));
+        }
+        uint32_t *sa = nullptr;
+        const uint64_t *gkeys = nullptr;
+        int gshift = 64;
+        if ((rc = block_sort(d, s, d->stage_reads, off, m_blk, n_blk, maxlen, w.g, gbits, &sa,
+                             &gkeys, &gshift)))
+            return rc;
+        {
+            Scope sc(d, s, BWT_STAGE_INSERT);
+            HIPCHK(d, launch_count_bint(sa, n_blk, w.bcnt, w.status_scan, w.misc + MISC_CNT_BINT,
+                                        next_epoch(), w.misc + MISC_ERR, s));
+            HIPCHK(d, launch_ins_tile_first_units(idev, nu, gkeys, gshift, B.ntiles, d->first_new,
+                                                  s));
+            HIPCHK(d, launch_ins_meta_units(idev, nu, gkeys, gshift, sa, w.bcnt, s));
+            Scope sk(d, s, SPAN_INSERT_K);
+            HIPCHK(d, launch_insert_units(idev, nu, gkeys, gshift, sa, w.bcnt, d->first_new,
+                                          B.ntiles, w.misc + MISC_ERR, s));
+        }
+        if (d->timer.on) {
+            for (uint32_t k = B.u0; k < B.u1; ++k) {
+                d->timer.acc.insert_records_out += records_for(units[k].n_ext + units[k].nsuf);
+                d->timer.acc.insert_records_in += records_for(units[k].n_ext);
+            }
+            d->timer.acc.insert_new_symbols += n_blk;
+        }
+        d->timer.acc.blocks += 1;
+    }
+    HIPCHK(d, hipStreamSynchronize(s));
+    if (d->timer.on) timer_collect(d);
+    if ((rc = check_err(d, s))) return rc;
+
+    // 8. commit every set
+    for (uint32_t a = 0; a < na; ++a) {
+        bwt_set *h = hs[act[a]];
+        const uint64_t K = res[4 * a + 3];
+        h->cur = other[a][(K - 1) & 1];
+        h->n = n_run[a];
+        h->m += m[act[a]];
+    }
+    return BWT_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -759,6 +1105,8 @@ void bwt_set_destroy(bwt_set_t h) {
     dfree(h->stage_off);
     dfree(h->cuts);
     dfree(h->stage_out);
+    dfree(h->btab);
+    dfree(h->bstage);
     dfree(h->res);
     if (h->pinned) (void)hipHostFree(h->pinned);
     for (auto e : h->timer.pool) (void)hipEventDestroy(e);
@@ -843,6 +1191,32 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
     h->n = n_final;
     h->m += m;
     return BWT_OK;
+}
+
+int bwt_set_append_many(bwt_set_t *hs, const uint8_t *const *reads,
+                        const uint64_t *const *offsets, const uint64_t *m, uint64_t count,
+                        void *stream) {
+    if (!hs || count == 0) return count == 0 ? BWT_OK : BWT_EINVAL;
+    bwt_set *d = hs[0];
+    if (!d) return BWT_EINVAL;
+    if (!reads || !offsets || !m) return fail(d, BWT_EINVAL);
+    std::vector<bwt_set *> seen;
+    for (uint64_t i = 0; i < count; ++i) {
+        if (!hs[i] || hs[i]->device != d->device) return fail(d, BWT_EINVAL);
+        if (hs[i]->broken) return fail(d, BWT_ESTATE);
+        seen.push_back(hs[i]);
+    }
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return fail(d, BWT_EINVAL);
+    int rc = set_device(d);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : d->stream;
+    rc = append_many(d, hs, reads, offsets, m, count, s);
+    if (rc && d->timer.on) {
+        (void)hipStreamSynchronize(s);
+        timer_collect(d);
+    }
+    return rc;
 }
 
 uint64_t bwt_set_rank(bwt_set_t h, char c, uint64_t k) {
@@ -976,7 +1350,7 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
              tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4;
     }
     b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
-         h->stage_out_cap;
+         h->stage_out_cap + h->btab_cap + h->bstage_cap;
     *bytes = b;
     return BWT_OK;
 }
@@ -1003,6 +1377,10 @@ int bwt_set_trim(bwt_set_t h) {
     h->cuts_cap = 0;
     dfree(h->stage_out);
     h->stage_out_cap = 0;
+    dfree(h->btab);
+    h->btab_cap = 0;
+    dfree(h->bstage);
+    h->bstage_cap = 0;
     return BWT_OK;
 }
 

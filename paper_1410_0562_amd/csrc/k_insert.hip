@@ -37,14 +37,50 @@ __global__ void index_init_kernel(Rec *recs, uint64_t *sbc, uint64_t *meta) {
     if (t < META_WORDS) meta[t] = 0;
 }
 
-// g_sa[i] sits in the key bits from gshift up (gshift = 64: no g, all zero)
+// g_sa[i] sits in the key bits from gshift up (gshift = 64: no g, all zero);
+// in a block of several units the key holds g_sa + goff (unit offset)
 __device__ __forceinline__ uint64_t gsa_at(const uint64_t *__restrict__ gkeys, int gshift,
-                                           uint64_t i) {
-    return gshift < 64 ? gkeys[i] >> gshift : 0ull;
+                                           uint64_t i, uint64_t goff = 0) {
+    return gshift < 64 ? (gkeys[i] >> gshift) - goff : 0ull;
 }
 
 __device__ __forceinline__ int code_at(const uint32_t *__restrict__ vals, uint64_t i) {
     return (int)(vals[i] >> POS_BITS);
+}
+
+// occurrences of base c among the first a sorted symbols of the block
+__device__ uint64_t rank_bint(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ bcnt,
+                              uint64_t a, int c) {
+    uint64_t r = bcnt[(a >> CHUNK_SHIFT) * 4 + c];
+    for (uint64_t x = a & ~63ull; x < a; ++x) r += (code_at(vals, x) == c);
+    return r;
+}
+
+// One unit's share of an Insert: its n_new symbols are the sorted slots
+// [sa0, sa0 + n_new) of the block (vals, bcnt and gkeys cover the block).
+struct InsJob {
+    const Rec *orecs;
+    const uint64_t *osbc;
+    Rec *nrecs;
+    const uint64_t *nsbc;
+    const uint64_t *gkeys;
+    const uint32_t *vals;
+    const uint32_t *bcnt;
+    const uint64_t *first_new;   // the unit's tiles' entries
+    uint64_t n_ext, n_new, sa0, goff;
+    int gshift;
+};
+
+// first i in [0, n_new) of the unit with g_sa[i] + i >= Q (n_new if none)
+__device__ uint64_t first_at_or_after(const uint64_t *__restrict__ gkeys, int gshift,
+                                      uint64_t sa0, uint64_t goff, uint64_t n_new, uint64_t Q) {
+    uint64_t lo = 0, hi = n_new;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (gsa_at(gkeys, gshift, sa0 + mid, goff) + mid >= Q) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 // bcnt[k*4 + c] = occurrences of base c among the first 64k new symbols, for
@@ -131,36 +167,42 @@ __global__ void ins_tile_first_kernel(const uint64_t *__restrict__ gkeys, int gs
                                       uint64_t *__restrict__ first_new) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > ntiles) return;
-    uint64_t Q = t * INS_TILE_SYMS;
-    uint64_t lo = 0, hi = n_new;
-    while (lo < hi) {  // first i with g_sa[i] + i >= Q
-        uint64_t mid = (lo + hi) >> 1;
-        if (gsa_at(gkeys, gshift, mid) + mid >= Q) hi = mid;
-        else lo = mid + 1;
+    first_new[t] = first_at_or_after(gkeys, gshift, 0, 0, n_new, t * INS_TILE_SYMS);
+}
+
+// first_new of every unit of a block: entry e belongs to the last unit u with
+// tile0[u] + u <= e, and is that unit's entry e - tile0[u] - u
+__global__ void ins_tile_first_units_kernel(const InsertUnit *__restrict__ units,
+                                            uint32_t nunits, const uint64_t *__restrict__ gkeys,
+                                            int gshift, uint64_t nentries,
+                                            uint64_t *__restrict__ first_new) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nentries) return;
+    uint32_t lo = 0, hi = nunits - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (units[mid].tile0 + mid <= e) lo = mid;
+        else hi = mid - 1;
     }
-    first_new[t] = lo;
+    const InsertUnit &u = units[lo];
+    const uint64_t t = e - u.tile0 - lo;
+    first_new[e] = first_at_or_after(gkeys, gshift, u.sa0, u.goff, u.n_new, t * INS_TILE_SYMS);
 }
 
-__device__ uint64_t rank_bint(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ bcnt,
-                              uint64_t a, int c) {
-    uint64_t r = bcnt[(a >> CHUNK_SHIFT) * 4 + c];
-    for (uint64_t x = a & ~63ull; x < a; ++x) r += (code_at(vals, x) == c);
-    return r;
-}
 
-// New totals, n, m and superblock base counts of the merged index (one
+// New totals, n, m and superblock base counts of one merged index (one
 // thread; the number of superblocks is n / 2^32 + 1).
-__global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
-                                const uint64_t *__restrict__ ometa,
-                                const uint64_t *__restrict__ gkeys, int gshift,
-                                const uint32_t *__restrict__ vals,
-                                const uint32_t *__restrict__ bcnt, uint64_t n_new,
-                                uint64_t *__restrict__ nsbc, uint64_t *__restrict__ nmeta) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint64_t nch = div_up(n_new, 64);
+__device__ void ins_meta_one(const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
+                             const uint64_t *__restrict__ ometa, const uint64_t *__restrict__ gkeys,
+                             int gshift, const uint32_t *__restrict__ vals,
+                             const uint32_t *__restrict__ bcnt, uint64_t sa0, uint64_t goff,
+                             uint64_t n_new, uint64_t *__restrict__ nsbc,
+                             uint64_t *__restrict__ nmeta) {
+    uint64_t base[4];
+    for (int c = 0; c < 4; ++c) base[c] = rank_bint(vals, bcnt, sa0, c);
     uint64_t add = 0;
     for (int c = 0; c < 4; ++c) {
-        uint64_t t = bcnt[nch * 4 + c];
+        uint64_t t = rank_bint(vals, bcnt, sa0 + n_new, c) - base[c];
         nmeta[c] = ometa[c] + t;
         add += t;
     }
@@ -172,25 +214,51 @@ __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *_
     const uint64_t nsb = (n_out >> SB_SHIFT) + 1;
     for (int c = 0; c < 4; ++c) nsbc[c] = 0;
     for (uint64_t sb = 1; sb < nsb; ++sb) {
-        uint64_t Q = sb << SB_SHIFT;
-        uint64_t lo = 0, hi = n_new;
-        while (lo < hi) {
-            uint64_t mid = (lo + hi) >> 1;
-            if (gsa_at(gkeys, gshift, mid) + mid >= Q) hi = mid;
-            else lo = mid + 1;
-        }
-        uint64_t o = Q - lo;
+        const uint64_t Q = sb << SB_SHIFT;
+        const uint64_t lo = first_at_or_after(gkeys, gshift, sa0, goff, n_new, Q);
+        const uint64_t o = Q - lo;
         for (int c = 0; c < 4; ++c)
-            nsbc[sb * 4 + c] = rank_base(orecs, osbc, o, c, true) + rank_bint(vals, bcnt, lo, c);
+            nsbc[sb * 4 + c] = rank_base(orecs, osbc, o, c, true) +
+                               (rank_bint(vals, bcnt, sa0 + lo, c) - base[c]);
     }
 }
 
-__global__ __launch_bounds__(256) void insert_kernel(
-    const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
-    const uint64_t *__restrict__ gkeys, int gshift, const uint32_t *__restrict__ vals,
-    const uint32_t *__restrict__ bcnt, const uint64_t *__restrict__ first_new,
-    Rec *__restrict__ nrecs, const uint64_t *__restrict__ nsbc, uint64_t n_out, uint64_t nrec_out,
-    uint64_t nrec_in, uint32_t *__restrict__ err) {
+__global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
+                                const uint64_t *__restrict__ ometa,
+                                const uint64_t *__restrict__ gkeys, int gshift,
+                                const uint32_t *__restrict__ vals,
+                                const uint32_t *__restrict__ bcnt, uint64_t n_new,
+                                uint64_t *__restrict__ nsbc, uint64_t *__restrict__ nmeta) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    ins_meta_one(orecs, osbc, ometa, gkeys, gshift, vals, bcnt, 0, 0, n_new, nsbc, nmeta);
+}
+
+// one thread per unit
+__global__ void ins_meta_units_kernel(const InsertUnit *__restrict__ units, uint32_t nunits,
+                                      const uint64_t *__restrict__ gkeys, int gshift,
+                                      const uint32_t *__restrict__ vals,
+                                      const uint32_t *__restrict__ bcnt) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nunits) return;
+    const InsertUnit &u = units[k];
+    ins_meta_one(u.orecs, u.osbc, u.ometa, gkeys, gshift, vals, bcnt, u.sa0, u.goff, u.n_new,
+                 u.nsbc, u.nmeta);
+}
+
+// Output tile t of one unit (256 threads).
+__device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, uint32_t *__restrict__ err) {
+    const Rec *__restrict__ orecs = J.orecs;
+    const uint64_t *__restrict__ osbc = J.osbc;
+    const uint64_t *__restrict__ gkeys = J.gkeys;
+    const uint32_t *__restrict__ vals = J.vals;
+    const uint32_t *__restrict__ bcnt = J.bcnt;
+    const int gshift = J.gshift;
+    const uint64_t sa0 = J.sa0, goff = J.goff;
+    Rec *__restrict__ nrecs = J.nrecs;
+    const uint64_t *__restrict__ nsbc = J.nsbc;
+    const uint64_t n_out = J.n_ext + J.n_new;
+    const uint64_t nrec_out = records_for(n_out);
+    const uint64_t nrec_in = records_for(J.n_ext);
     __shared__ uint32_t s_bm[INS_TILE_SYMS / 32];
     __shared__ uint8_t s_new[INS_TILE_SYMS];
     __shared__ uint64_t s_old[(INS_TILE_RECS + 1) * 6];
@@ -202,12 +270,11 @@ __global__ __launch_bounds__(256) void insert_kernel(
     __shared__ uint32_t s_tmp[4];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const uint64_t t = blockIdx.x;
     const uint64_t R0 = t * INS_TILE_RECS;
     const uint64_t nrec = (nrec_out - R0) < (uint64_t)INS_TILE_RECS ? (nrec_out - R0) : INS_TILE_RECS;
     const uint64_t q0 = R0 * REC_SYMS;
     const uint64_t q1 = (q0 + INS_TILE_SYMS) < n_out ? (q0 + INS_TILE_SYMS) : n_out;
-    const uint64_t a0 = first_new[t], a1 = first_new[t + 1];
+    const uint64_t a0 = J.first_new[t], a1 = J.first_new[t + 1];
     const uint64_t o0 = q0 - a0;                     // old rows before the tile
     const uint64_t nold = (q1 - q0) - (a1 - a0);     // old rows inside it
     const uint64_t r_lo = o0 >> REC_SHIFT;
@@ -226,21 +293,29 @@ __global__ __launch_bounds__(256) void insert_kernel(
     }
     __syncthreads();
     for (uint64_t i = a0 + tid; i < a1; i += 256) {
-        uint64_t pos = gsa_at(gkeys, gshift, i) + i - q0;
+        uint64_t pos = gsa_at(gkeys, gshift, sa0 + i, goff) + i - q0;
         if (pos < INS_TILE_SYMS) atomicOr(&s_bm[pos >> 5], 1u << (pos & 31));
         else atomicOr(err, 32u);
-        s_new[i - a0] = (uint8_t)code_at(vals, i);
+        s_new[i - a0] = (uint8_t)code_at(vals, sa0 + i);
     }
     if (wave == 1) {
         // counts at the tile start: old part by a rank on B_ext, new part from
         // the sampled B_int counts plus the < 64 symbols since the sample
-        uint64_t x = (a0 & ~63ull) + lane;
-        int c = x < a0 ? code_at(vals, x) : 6;
+        // (taken at the unit's first slot too, and subtracted)
+        const uint64_t A = sa0 + a0;
+        uint64_t x = (A & ~63ull) + lane;
+        int c = x < A ? code_at(vals, x) : 6;
         uint32_t cA = __popcll(__ballot(c == 0)), cC = __popcll(__ballot(c == 1));
         uint32_t cG = __popcll(__ballot(c == 2)), cT = __popcll(__ballot(c == 3));
+        uint64_t y = (sa0 & ~63ull) + lane;
+        int d = y < sa0 ? code_at(vals, y) : 6;
+        uint32_t dA = __popcll(__ballot(d == 0)), dC = __popcll(__ballot(d == 1));
+        uint32_t dG = __popcll(__ballot(d == 2)), dT = __popcll(__ballot(d == 3));
         if (lane < 4) {
             uint32_t part = lane == 0 ? cA : lane == 1 ? cC : lane == 2 ? cG : cT;
-            s_base[lane] = (uint64_t)bcnt[(a0 >> CHUNK_SHIFT) * 4 + lane] + part +
+            uint32_t part0 = lane == 0 ? dA : lane == 1 ? dC : lane == 2 ? dG : dT;
+            s_base[lane] = ((uint64_t)bcnt[(A >> CHUNK_SHIFT) * 4 + lane] + part) -
+                           ((uint64_t)bcnt[(sa0 >> CHUNK_SHIFT) * 4 + lane] + part0) +
                            rank_base(orecs, osbc, o0, lane, true);
         }
     }
@@ -315,6 +390,41 @@ __global__ __launch_bounds__(256) void insert_kernel(
     }
 }
 
+__global__ __launch_bounds__(256) void insert_kernel(InsJob J, uint32_t *__restrict__ err) {
+    insert_tile(J, blockIdx.x, err);
+}
+
+// one workgroup per tile of every unit: tile T belongs to the last unit with
+// tile0 <= T
+__global__ __launch_bounds__(256) void insert_units_kernel(
+    const InsertUnit *__restrict__ units, uint32_t nunits, const uint64_t *__restrict__ gkeys,
+    int gshift, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ bcnt,
+    const uint64_t *__restrict__ first_new, uint32_t *__restrict__ err) {
+    const uint64_t T = blockIdx.x;
+    uint32_t lo = 0, hi = nunits - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (units[mid].tile0 <= T) lo = mid;
+        else hi = mid - 1;
+    }
+    const InsertUnit &u = units[lo];
+    InsJob J;
+    J.orecs = u.orecs;
+    J.osbc = u.osbc;
+    J.nrecs = u.nrecs;
+    J.nsbc = u.nsbc;
+    J.gkeys = gkeys;
+    J.vals = vals;
+    J.bcnt = bcnt;
+    J.first_new = first_new + u.tile0 + lo;
+    J.n_ext = u.n_ext;
+    J.n_new = u.n_new;
+    J.sa0 = u.sa0;
+    J.goff = u.goff;
+    J.gshift = gshift;
+    insert_tile(J, T - u.tile0, err);
+}
+
 __global__ void fill_u64_kernel(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -377,12 +487,51 @@ hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
                          const uint64_t *gkeys, int gshift, const uint32_t *vals,
                          const uint32_t *bcnt, uint64_t n_new, const uint64_t *first_new,
                          Rec *nrecs, const uint64_t *nsbc, uint32_t *err, hipStream_t s) {
-    const uint64_t n_out = n_ext + n_new;
-    const uint64_t nrec_out = records_for(n_out);
-    const uint64_t ntiles = div_up(nrec_out, INS_TILE_RECS);
-    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(orecs, osbc, gkeys, gshift, vals, bcnt, first_new,
-                                                   nrecs, nsbc, n_out, nrec_out, records_for(n_ext),
-                                                   err);
+    const uint64_t ntiles = div_up(records_for(n_ext + n_new), INS_TILE_RECS);
+    InsJob J;
+    J.orecs = orecs;
+    J.osbc = osbc;
+    J.nrecs = nrecs;
+    J.nsbc = nsbc;
+    J.gkeys = gkeys;
+    J.vals = vals;
+    J.bcnt = bcnt;
+    J.first_new = first_new;
+    J.n_ext = n_ext;
+    J.n_new = n_new;
+    J.sa0 = 0;
+    J.goff = 0;
+    J.gshift = gshift;
+    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(J, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ins_tile_first_units(const InsertUnit *units, uint32_t nunits,
+                                       const uint64_t *gkeys, int gshift, uint64_t ntiles_all,
+                                       uint64_t *first_new, hipStream_t s) {
+    if (nunits == 0) return hipSuccess;
+    const uint64_t ne = ntiles_all + nunits;
+    ins_tile_first_units_kernel<<<(unsigned)div_up(ne, 256), 256, 0, s>>>(units, nunits, gkeys,
+                                                                          gshift, ne, first_new);
+    return hipGetLastError();
+}
+
+hipError_t launch_ins_meta_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
+                                 int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                                 hipStream_t s) {
+    if (nunits == 0) return hipSuccess;
+    ins_meta_units_kernel<<<(unsigned)div_up(nunits, 64), 64, 0, s>>>(units, nunits, gkeys,
+                                                                      gshift, vals, bcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_insert_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
+                               int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                               const uint64_t *first_new, uint64_t ntiles_all, uint32_t *err,
+                               hipStream_t s) {
+    if (nunits == 0 || ntiles_all == 0) return hipSuccess;
+    insert_units_kernel<<<(unsigned)ntiles_all, 256, 0, s>>>(units, nunits, gkeys, gshift, vals,
+                                                             bcnt, first_new, err);
     return hipGetLastError();
 }
 

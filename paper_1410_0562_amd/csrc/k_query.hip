@@ -1,5 +1,6 @@
-// k_query.hip -- rank queries (Eq. 2), export of B, and the device-side
-// checks and block split of an append whose offsets live in device memory.
+// k_query.hip -- rank queries (Eq. 2), export of B, the device-side checks
+// and block split of an append whose offsets live in device memory, and the
+// staging of a batch of sets into one packed input.
 #include "dev_util.hpp"
 
 namespace bwt {
@@ -82,15 +83,16 @@ __global__ __launch_bounds__(256) void check_offsets_kernel(const uint64_t *__re
 
 // Greedy block split (Algorithm 1 blocks: whole reads, at most M suffixes,
 // a read with more than M suffixes alone).  S(j) = off[j] - off[0] + j is the
-// block-text position of read j.  Writes cuts[2k] = first read of block k,
-// cuts[2k+1] = S(first read); res[2] = number of blocks.  One thread.
-__global__ void plan_blocks_kernel(const uint64_t *__restrict__ off, uint64_t m, uint64_t M,
-                                   uint64_t *__restrict__ cuts, uint64_t *__restrict__ res) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// block-text position of read j.  With cuts, writes cuts[2k] = first read of
+// block k, cuts[2k+1] = S(first read).  Returns the number of blocks.
+__device__ uint64_t greedy_cuts(const uint64_t *__restrict__ off, uint64_t m, uint64_t M,
+                                uint64_t *__restrict__ cuts) {
     const uint64_t o0 = off[0];
     uint64_t j = 0, K = 0;
-    cuts[0] = 0;
-    cuts[1] = 0;
+    if (cuts) {
+        cuts[0] = 0;
+        cuts[1] = 0;
+    }
     while (j < m) {
         const uint64_t Sj = off[j] - o0 + j;
         // largest k in [j+1, m] with S(k) - S(j) <= M, at least j+1
@@ -103,10 +105,119 @@ __global__ void plan_blocks_kernel(const uint64_t *__restrict__ off, uint64_t m,
         }
         j = lo;
         ++K;
-        cuts[2 * K] = j;
-        cuts[2 * K + 1] = off[j] - o0 + j;
+        if (cuts) {
+            cuts[2 * K] = j;
+            cuts[2 * K + 1] = off[j] - o0 + j;
+        }
     }
-    res[2] = K;
+    return K;
+}
+
+// res[2] = number of blocks.  One thread.
+__global__ void plan_blocks_kernel(const uint64_t *__restrict__ off, uint64_t m, uint64_t M,
+                                   uint64_t *__restrict__ cuts, uint64_t *__restrict__ res) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    res[2] = greedy_cuts(off, m, M, cuts);
+}
+
+// One workgroup per set of a batch: the offsets check, the suffix count and
+// the block count, and the cuts when a cut area is given.
+__global__ __launch_bounds__(256) void plan_sets_kernel(const PlanSet *__restrict__ sets,
+                                                        uint64_t M, uint64_t *__restrict__ res,
+                                                        uint64_t *__restrict__ cuts) {
+    __shared__ uint64_t s_len[4];
+    __shared__ uint32_t s_bad[4];
+    const PlanSet ps = sets[blockIdx.x];
+    uint64_t len = 0;
+    bool bad = false;
+    for (uint64_t j = threadIdx.x; j < ps.m; j += blockDim.x) {
+        uint64_t a = ps.off[j], b = ps.off[j + 1];
+        if (b < a) bad = true;
+        else len = (b - a) > len ? (b - a) : len;
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        uint64_t o = __shfl_xor(len, d, 64);
+        len = o > len ? o : len;
+    }
+    const int w = threadIdx.x >> 6;
+    const bool anybad = __ballot(bad) != 0;
+    if (lane_id() == 0) {
+        s_len[w] = len;
+        s_bad[w] = anybad ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t L = 0;
+        uint32_t B = 0;
+        for (int k = 0; k < 4; ++k) {
+            L = s_len[k] > L ? s_len[k] : L;
+            B |= s_bad[k];
+        }
+        uint64_t *r = res + 4ull * blockIdx.x;
+        r[0] = B;
+        r[1] = L;
+        // a decreasing offsets array has no meaningful split
+        r[2] = B ? 0 : ps.off[ps.m] - ps.off[0] + ps.m;
+        r[3] = B ? 0 : greedy_cuts(ps.off, ps.m, M, cuts ? cuts + ps.cut_base : nullptr);
+    }
+}
+
+// last unit with key(unit) <= x, for keys non-decreasing over units
+template <class Key>
+__device__ uint32_t last_unit_at_or_below(const GatherUnit *__restrict__ units, uint32_t n,
+                                          uint64_t x, Key key) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (key(units[mid]) <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// staged offsets: entry r of unit u = dst_sym0 + off[j0 + r - dst_read0] - off[j0];
+// the last entry is the total symbol count
+__global__ void gather_offsets_kernel(const GatherUnit *__restrict__ units, uint32_t nunits,
+                                      uint64_t total_reads, uint64_t total_syms,
+                                      uint64_t *__restrict__ dst_off) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > total_reads) return;
+    if (r == total_reads) {
+        dst_off[r] = total_syms;
+        return;
+    }
+    const uint32_t u = last_unit_at_or_below(units, nunits, r,
+                                             [](const GatherUnit &g) { return g.dst_read0; });
+    const GatherUnit &g = units[u];
+    dst_off[r] = g.dst_sym0 + (g.off[g.j0 + (r - g.dst_read0)] - g.off[g.j0]);
+}
+
+// staged reads: one thread per 16 symbols (one 32-bit word) of the output
+__global__ void gather_reads_kernel(const GatherUnit *__restrict__ units, uint32_t nunits,
+                                    uint64_t total_syms, uint32_t *__restrict__ dst) {
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t q0 = w * 16;
+    if (q0 >= total_syms) return;
+    uint32_t u = last_unit_at_or_below(units, nunits, q0,
+                                       [](const GatherUnit &g) { return g.dst_sym0; });
+    uint64_t d0 = units[u].dst_sym0, s0 = units[u].off[units[u].j0] - units[u].sym_base;
+    const uint8_t *src = units[u].reads;
+    uint64_t next = u + 1 < nunits ? units[u + 1].dst_sym0 : ~0ull;
+    uint32_t word = 0;
+    for (int k = 0; k < 16; ++k) {
+        const uint64_t q = q0 + k;
+        if (q >= total_syms) break;
+        while (q >= next) {  // later units (skipping units without symbols)
+            ++u;
+            d0 = units[u].dst_sym0;
+            s0 = units[u].off[units[u].j0] - units[u].sym_base;
+            src = units[u].reads;
+            next = u + 1 < nunits ? units[u + 1].dst_sym0 : ~0ull;
+        }
+        const uint64_t p = s0 + (q - d0);
+        word |= (uint32_t)((src[p >> 2] >> (2 * (p & 3))) & 3u) << (2 * k);
+    }
+    dst[w] = word;
 }
 
 }  // namespace
@@ -140,6 +251,31 @@ hipError_t launch_check_offsets(const uint64_t *off, uint64_t m, uint64_t *res, 
 hipError_t launch_plan_blocks(const uint64_t *off, uint64_t m, uint64_t M, uint64_t *cuts,
                               uint64_t *res, hipStream_t s) {
     plan_blocks_kernel<<<1, 64, 0, s>>>(off, m, M, cuts, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_sets(const PlanSet *sets, uint32_t nsets, uint64_t M, uint64_t *res,
+                            uint64_t *cuts, hipStream_t s) {
+    if (nsets == 0) return hipSuccess;
+    plan_sets_kernel<<<nsets, 256, 0, s>>>(sets, M, res, cuts);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_offsets(const GatherUnit *units, uint32_t nunits, uint64_t total_reads,
+                                 uint64_t total_syms, uint64_t *dst_off, hipStream_t s) {
+    if (nunits == 0) return hipSuccess;
+    gather_offsets_kernel<<<(unsigned)div_up(total_reads + 1, 256), 256, 0, s>>>(
+        units, nunits, total_reads, total_syms, dst_off);
+    return hipGetLastError();
+}
+
+// dst must hold ceil(total_syms / 16) 32-bit words
+hipError_t launch_gather_reads(const GatherUnit *units, uint32_t nunits, uint64_t total_syms,
+                               uint8_t *dst, hipStream_t s) {
+    if (nunits == 0 || total_syms == 0) return hipSuccess;
+    const uint64_t words = div_up(total_syms, 16);
+    gather_reads_kernel<<<(unsigned)div_up(words, 256), 256, 0, s>>>(
+        units, nunits, total_syms, reinterpret_cast<uint32_t *>(dst));
     return hipGetLastError();
 }
 

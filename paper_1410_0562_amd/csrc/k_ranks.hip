@@ -89,29 +89,63 @@ struct LF {
         C3 = C2 + meta[2];
         big = big_ != 0;
     }
-    // Lemma 1: C[c] + rank(c, i, B_ext); a consistent index never needs the clamp
+    // Lemma 1: C[c] + rank(c, i, B_ext); a consistent index never needs the
+    // clamp.  Against an empty index every rank is 0 (no record is read).
     __device__ uint64_t step(const Rec *__restrict__ recs, const uint64_t *__restrict__ sbc,
                              uint64_t i, int c) const {
+        if (n_ext == 0) return 0;
         uint64_t Cc = c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : C3;
         uint64_t r = Cc + rank_base(recs, sbc, i, c, big);
         return r < n_ext ? r : n_ext;
     }
 };
 
+// The index a read is ranked against, and the offset added to its ranks.
+struct Walker {
+    const Rec *recs;
+    const uint64_t *sbc;
+    LF lf;
+    uint64_t goff;
+};
+
+// Every read of the block against one index.
+struct OneIndex {
+    const Rec *recs;
+    const uint64_t *sbc;
+    const uint64_t *meta;
+    int big;
+    __device__ Walker at(uint32_t) const { return Walker{recs, sbc, LF(meta, big), 0}; }
+};
+
+// Read j against the index of its unit (the last unit with read0 <= j).
+struct UnitIndex {
+    const RankUnit *units;
+    uint32_t n;
+    __device__ Walker at(uint32_t j) const {
+        uint32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (units[mid].read0 <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const RankUnit &u = units[lo];
+        return Walker{u.recs, u.sbc, LF(u.meta, (int)u.big), u.goff};
+    }
+};
+
 // Whole-read walk from the terminator: writes g[gb + k] for k = len .. 0.
-__device__ void walk_read(const LF &lf, const Rec *__restrict__ recs,
-                          const uint64_t *__restrict__ sbc, SymReader &sym, uint64_t s0,
-                          uint32_t len, uint64_t gb, uint64_t *__restrict__ g, bool vec) {
+__device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t len, uint64_t gb,
+                          uint64_t *__restrict__ g, bool vec) {
     GBuf buf;
     buf.cnt = 0;
-    uint64_t i = lf.m_ext;
+    uint64_t i = W.lf.m_ext;
     uint32_t k = len;
-    buf.push(i);
+    buf.push(i + W.goff);
     if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
     while (k > 0) {
         --k;
-        i = lf.step(recs, sbc, i, sym.get(s0 + k));
-        buf.push(i);
+        i = W.lf.step(W.recs, W.sbc, i, sym.get(s0 + k));
+        buf.push(i + W.goff);
         if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
     }
     buf.flush(g, gb, false);  // what is left below the last aligned index
@@ -119,13 +153,12 @@ __device__ void walk_read(const LF &lf, const Rec *__restrict__ recs,
 
 // One lane per read.  Reads longer than `seg` symbols (seg > 0) are cut into
 // segments that are queued for rank_segments_kernel instead.
+template <class Src>
 __global__ __launch_bounds__(256) void compute_ranks_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, uint32_t m_blk, const Rec *__restrict__ recs,
-    const uint64_t *__restrict__ sbc, const uint64_t *__restrict__ meta, int big,
-    uint64_t *__restrict__ g, uint32_t seg, uint64_t *__restrict__ seg_list,
-    uint32_t *__restrict__ seg_count, uint32_t seg_cap, uint32_t *__restrict__ err) {
-    const LF lf(meta, big);
+    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, uint64_t *__restrict__ g,
+    uint32_t seg, uint64_t *__restrict__ seg_list, uint32_t *__restrict__ seg_count,
+    uint32_t seg_cap, uint32_t *__restrict__ err) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m_blk) return;
     const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;  // uniform
@@ -142,21 +175,20 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
         return;
     }
     SymReader sym{reads, 0, 0};
-    walk_read(lf, recs, sbc, sym, s0, len, soff[j], g, vec);
+    walk_read(src.at(j), sym, s0, len, soff[j], g, vec);
 }
 
 // One lane per queued segment (j, s) of a long read: symbols [a, b) with
 // a = s * seg, b = min(len, a + seg); the walk starts at e = min(len, b + ov).
+template <class Src>
 __global__ __launch_bounds__(256) void rank_segments_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, uint32_t m_blk, const Rec *__restrict__ recs,
-    const uint64_t *__restrict__ sbc, const uint64_t *__restrict__ meta, int big,
-    uint64_t *__restrict__ g, uint32_t seg, uint32_t ov, const uint64_t *__restrict__ seg_list,
+    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, uint64_t *__restrict__ g,
+    uint32_t seg, uint32_t ov, const uint64_t *__restrict__ seg_list,
     const uint32_t *__restrict__ seg_count, uint32_t *__restrict__ fb_flag,
     uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, uint32_t *__restrict__ err) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *seg_count) return;
-    const LF lf(meta, big);
     const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
     const uint64_t e_js = seg_list[t];
     const uint32_t j = (uint32_t)(e_js >> 32), s = (uint32_t)e_js;
@@ -171,6 +203,8 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
         atomicOr(err, 128u);
         return;
     }
+    const Walker W = src.at(j);
+    const LF &lf = W.lf;
     const uint32_t a = s * seg;
     const uint32_t b = a + seg < len ? a + seg : len;
     const uint32_t e = b + ov < len ? b + ov : len;
@@ -181,7 +215,7 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
     if (e == len) {
         lo = hi = lf.m_ext;  // exact start at the terminator suffix
         if (b == len) {
-            buf.push(lo);
+            buf.push(lo + W.goff);
             if (((gb + len) & 7) == 0) buf.flush(g, gb + len, vec);
         }
     } else {
@@ -192,8 +226,8 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
     while (k > a) {
         --k;
         const int c = sym.get(s0 + k);
-        const uint64_t nlo = lf.step(recs, sbc, lo, c);
-        hi = (lo == hi) ? nlo : lf.step(recs, sbc, hi, c);
+        const uint64_t nlo = lf.step(W.recs, W.sbc, lo, c);
+        hi = (lo == hi) ? nlo : lf.step(W.recs, W.sbc, hi, c);
         lo = nlo;
         if (k < b) {
             if (lo != hi) {
@@ -201,7 +235,7 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
                 if (atomicExch(&fb_flag[j], 1u) == 0u) fb_list[atomicAdd(fb_count, 1u)] = j;
                 return;
             }
-            buf.push(lo);
+            buf.push(lo + W.goff);
             if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
         }
     }
@@ -210,20 +244,18 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
 
 // Whole-read walks for the reads whose segments could not close their
 // interval within the overlap.
+template <class Src>
 __global__ __launch_bounds__(256) void rank_fallback_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, const Rec *__restrict__ recs,
-    const uint64_t *__restrict__ sbc, const uint64_t *__restrict__ meta, int big,
-    uint64_t *__restrict__ g, const uint32_t *__restrict__ fb_list,
-    const uint32_t *__restrict__ fb_count) {
+    const uint32_t *__restrict__ soff, Src src, uint64_t *__restrict__ g,
+    const uint32_t *__restrict__ fb_list, const uint32_t *__restrict__ fb_count) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *fb_count) return;
-    const LF lf(meta, big);
     const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
     const uint32_t j = fb_list[t];
     const uint64_t s0 = off[j];
     SymReader sym{reads, 0, 0};
-    walk_read(lf, recs, sbc, sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], g, vec);
+    walk_read(src.at(j), sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], g, vec);
 }
 
 __global__ void zero_kernel(uint32_t *p, uint32_t n) {
@@ -231,12 +263,10 @@ __global__ void zero_kernel(uint32_t *p, uint32_t n) {
     if (i < n) p[i] = 0;
 }
 
-}  // namespace
-
-hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
-                                uint32_t m_blk, uint32_t n_blk, const Rec *recs,
-                                const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
-                                const RankSegments &sg, uint32_t *err, hipStream_t s) {
+template <class Src>
+hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                         uint32_t m_blk, uint32_t n_blk, Src src, uint64_t *g,
+                         const RankSegments &sg, uint32_t *err, hipStream_t s) {
     if (m_blk == 0) return hipSuccess;
     uint32_t seg = sg.seg_len;
     uint32_t cap = 0;
@@ -248,16 +278,34 @@ hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const
         zero_kernel<<<1, 64, 0, s>>>(sg.counters, 2);
         zero_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(sg.fb_flag, m_blk);
     }
-    compute_ranks_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
-        reads, off, soff, m_blk, recs, sbc, meta, big, g, seg, sg.seg_list, sg.counters, cap, err);
+    compute_ranks_kernel<Src><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
+        reads, off, soff, m_blk, src, g, seg, sg.seg_list, sg.counters, cap, err);
     if (seg > 0) {
-        rank_segments_kernel<<<(unsigned)div_up(cap, 256), 256, 0, s>>>(
-            reads, off, soff, m_blk, recs, sbc, meta, big, g, seg, sg.overlap, sg.seg_list,
-            sg.counters, sg.fb_flag, sg.fb_list, sg.counters + 1, err);
-        rank_fallback_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
-            reads, off, soff, recs, sbc, meta, big, g, sg.fb_list, sg.counters + 1);
+        rank_segments_kernel<Src><<<(unsigned)div_up(cap, 256), 256, 0, s>>>(
+            reads, off, soff, m_blk, src, g, seg, sg.overlap, sg.seg_list, sg.counters,
+            sg.fb_flag, sg.fb_list, sg.counters + 1, err);
+        rank_fallback_kernel<Src><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
+            reads, off, soff, src, g, sg.fb_list, sg.counters + 1);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                                uint32_t m_blk, uint32_t n_blk, const Rec *recs,
+                                const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
+                                const RankSegments &sg, uint32_t *err, hipStream_t s) {
+    return compute_ranks(reads, off, soff, m_blk, n_blk, OneIndex{recs, sbc, meta, big}, g, sg,
+                         err, s);
+}
+
+hipError_t launch_compute_ranks_units(const uint8_t *reads, const uint64_t *off,
+                                      const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
+                                      const RankUnit *units, uint32_t nunits, uint64_t *g,
+                                      const RankSegments &sg, uint32_t *err, hipStream_t s) {
+    if (nunits == 0) return hipSuccess;
+    return compute_ranks(reads, off, soff, m_blk, n_blk, UnitIndex{units, nunits}, g, sg, err, s);
 }
 
 }  // namespace bwt

@@ -22,6 +22,12 @@ Workloads (seed = 14100562 + workload number):
    log 0.5, clipped to [1,000, 50,000]) from a uniform 100 Mbp reference, either
    strand, 10% noise per base split 6% substitution / 2% insertion / 2%
    deletion.  Stands in for a long-read (Sanger-like) set.
+4. ``batch_sets_gpu``: 64 independent sets, each from its own uniform 10 Mbp
+   reference, floor(exp(U(ln 1e3, ln 2e6))) reads per set of uniform length
+   in [36, 250], either strand, 1% substitutions (drawn on the GPU).
+5. ``served_requests_gpu``: 16 tenants with their own uniform 100 Mbp
+   references; 512 append requests of floor(exp(U(ln 1e4, ln 1e6))) reads x
+   150 bp, forward strand, 1% substitutions (drawn on the GPU).
 """
 from __future__ import annotations
 
@@ -218,3 +224,51 @@ def served_requests_gpu(tenants: int = 16, count: int = 512, ref_len: int = 100_
         out.append((packed, offs, int(m) * length))
     del refs
     return tids, out
+
+
+def batch_sets_gpu(count: int = 64, ref_len: int = 10_000_000, min_reads: int = 1_000,
+                   max_reads: int = 2_000_000, min_len: int = 36, max_len: int = 250,
+                   sub_rate: float = 0.01, seed: int = SEED_BASE + 4):
+    """Workload 4 drawn on the GPU with torch: `count` independent sets, each
+    with its own uniform random reference of ref_len bases and
+    floor(exp(U(ln min_reads, ln max_reads))) reads of uniform integer
+    length in [min_len, max_len], sampled at uniform positions on a random
+    strand (reverse complement for the minus strand) with i.i.d.
+    substitutions to one of the other three bases.  Returns a list of
+    (packed device tensor, offsets device int64 tensor, bases)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    ms = np.floor(np.exp(rng.uniform(np.log(min_reads), np.log(max_reads), count))).astype(np.int64)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    shifts = torch.tensor([0, 2, 4, 6], device="cuda", dtype=torch.uint8)
+    out = []
+    for m in ms:
+        m = int(m)
+        ref = torch.randint(0, 4, (ref_len,), dtype=torch.uint8, device="cuda", generator=gen)
+        lens = torch.randint(min_len, max_len + 1, (m,), device="cuda", generator=gen)
+        offs = torch.zeros(m + 1, dtype=torch.int64, device="cuda")
+        torch.cumsum(lens, 0, out=offs[1:])
+        total = int(offs[-1].item())
+        starts = (torch.rand(m, device="cuda", generator=gen, dtype=torch.float64) *
+                  (ref_len - lens + 1).to(torch.float64)).to(torch.int64)
+        minus = torch.rand(m, device="cuda", generator=gen) < 0.5
+        rid = torch.repeat_interleave(torch.arange(m, device="cuda"), lens)
+        within = torch.arange(total, device="cuda", dtype=torch.int64) - offs[:-1][rid]
+        fwd = starts[rid] + within
+        rev = starts[rid] + lens[rid] - 1 - within
+        mr = minus[rid]
+        codes = ref[torch.where(mr, rev, fwd)]
+        codes = torch.where(mr, 3 - codes, codes)
+        del rid, within, fwd, rev, mr
+        hit = torch.rand(total, device="cuda", generator=gen) < sub_rate
+        delta = torch.randint(1, 4, (total,), dtype=torch.uint8, device="cuda", generator=gen)
+        codes = torch.where(hit, (codes + delta) & 3, codes)
+        del hit, delta
+        pad = (-total) % 4
+        if pad:
+            codes = torch.cat([codes, torch.zeros(pad, dtype=torch.uint8, device="cuda")])
+        packed = (codes.view(-1, 4) << shifts).sum(dim=1, dtype=torch.uint8)
+        out.append((packed, offs, total))
+        del ref, codes
+    return out
