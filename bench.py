@@ -79,6 +79,98 @@ def cpu_baseline(packed, offs, nreads):
                       "comparison sort of all suffixes (%.1f s)" % (nreads, bases, dt)}
 
 
+def run_batched(args, torch, bwtset, synth):
+    """Batched form: `sets` independent read sets appended to fresh indices,
+    one bwt_set_append_many call per step, timed beside the plain loop of one
+    bwt_set_append per set on the same GPU.  Both build the same indices (the
+    exports are compared on the device).  Prints one JSON line."""
+    block = args.block or (1 << 26)
+    log("generating %d sets on the GPU" % args.sets)
+    lo_r, hi_r = (1000, 2_000_000)
+    if args.set_reads:
+        lo_r, hi_r = (int(x) for x in args.set_reads.split(","))
+    sets = synth.batch_sets_gpu(count=args.sets, min_reads=lo_r, max_reads=hi_r)
+    torch.cuda.synchronize()
+    bases = sum(b for _, _, b in sets)
+    reads = sum(int(o.numel()) - 1 for _, o, _ in sets)
+    reads_l = [p for p, _, _ in sets]
+    offs_l = [o for _, o, _ in sets]
+    hb = [bwtset.BwtSet(block_size=block) for _ in sets]
+    hl = [bwtset.BwtSet(block_size=block) for _ in sets]
+    if args.lanes is not None:
+        hb[0].set_param(bwtset.BWT_PARAM_BATCH_LANES, args.lanes)
+    for h in hb + hl:
+        if args.key_bits is not None:
+            h.set_key_bits(args.key_bits)
+        if args.radix_tile is not None:
+            h.set_param(bwtset.BWT_PARAM_RADIX_TILE, args.radix_tile)
+
+    def timed(run, hs):
+        total = 0.0
+        for k in range(args.warmup + args.steps):
+            for h in hs:
+                h.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                total += time.perf_counter() - t0
+        return total
+
+    def batched():
+        bwtset.append_many(hb, reads_l, offs_l)
+
+    def loop():
+        for h, p, o in zip(hl, reads_l, offs_l):
+            h.append(p, o)
+
+    t_batch = timed(batched, hb)
+    log("batched: %.3f s for %d steps" % (t_batch, args.steps))
+    t_loop = timed(loop, hl)
+    log("per-set loop: %.3f s for %d steps" % (t_loop, args.steps))
+    same = 0
+    for a, b in zip(hb, hl):
+        n = a.size()[0]
+        assert n == b.size()[0]
+        ea = torch.empty(n, dtype=torch.uint8, device="cuda")
+        eb = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a.export(ea)
+        b.export(eb)
+        same += bool(torch.equal(ea, eb))
+        del ea, eb
+    assert same == len(sets), "batched and per-set indices differ"
+    for h in hb + hl:
+        h.close()
+    v_batch = bases * args.steps / t_batch
+    v_loop = bases * args.steps / t_loop
+    out = {
+        "metric": METRIC,
+        "value": v_batch,
+        "unit": "bases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "batched: %d independent sets, each from its own random 10 Mbp "
+                               "reference, %d-%d reads per set (log-uniform), 36-250 bp, both "
+                               "strands, 1%% substitutions; block M=%d suffixes" % (
+                                   len(sets), lo_r, hi_r, block),
+                   "sets": len(sets), "reads": reads, "bases": bases, "block_suffixes": block,
+                   "lanes": args.lanes},
+        "batched": {"per_set_loop_bases_per_s": v_loop,
+                    "per_set_loop_ms_per_step": t_loop / args.steps * 1e3,
+                    "speedup_vs_per_set_loop": v_batch / v_loop,
+                    "identical_indices": same},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_served(args, torch, bwtset, synth):
     """Served form: tenants' append requests arrive as a Poisson process at
     `load` times the measured single-stream capacity; a continuous-batching
@@ -173,6 +265,14 @@ def main():
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--load", type=float, default=0.7,
                     help="offered load as a fraction of the single-stream capacity")
+    ap.add_argument("--batched", action="store_true",
+                    help="batched form: 64 independent sets in one call, against one append "
+                         "per set")
+    ap.add_argument("--sets", type=int, default=64)
+    ap.add_argument("--lanes", type=int, default=None,
+                    help="batched form: blocks run side by side (library default if omitted)")
+    ap.add_argument("--set-reads", type=str, default=None,
+                    help="batched form: MIN,MAX reads per set (default 1000,2000000)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -205,6 +305,8 @@ def main():
 
     if args.served:
         return run_served(args, torch, bwtset, synth)
+    if args.batched:
+        return run_batched(args, torch, bwtset, synth)
 
     log("generating workload")
     if args.workload == "short":

@@ -145,12 +145,16 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     and continued by Lemma 1 once the interval holds no old suffix; reads
  *     with a longer repeat fall back to one whole walk.  0 = never (256 ..
  *     2^24, default 1024).
- *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 128). */
+ *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 128).
+ *   BWT_PARAM_BATCH_LANES: blocks of one level of a batch (bwt_set_append_many
+ *     on this handle as hs[0]) that run side by side, each on its own stream
+ *     and workspace (1 .. 4, default 2). */
 enum {
     BWT_PARAM_KEY_BITS = 1,
     BWT_PARAM_RADIX_TILE = 2,
     BWT_PARAM_RANK_SEGMENT = 3,
-    BWT_PARAM_RANK_OVERLAP = 4
+    BWT_PARAM_RANK_OVERLAP = 4,
+    BWT_PARAM_BATCH_LANES = 5
 };
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
 

@@ -75,6 +75,7 @@ BWT_PARAM_KEY_BITS = 1
 BWT_PARAM_RADIX_TILE = 2
 BWT_PARAM_RANK_SEGMENT = 3
 BWT_PARAM_RANK_OVERLAP = 4
+BWT_PARAM_BATCH_LANES = 5
 
 _lib = None
 

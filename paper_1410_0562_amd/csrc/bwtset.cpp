@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <array>
+#include <thread>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -71,6 +72,7 @@ constexpr int MISC_BAD = 6;
 constexpr int MISC_ERR = 7;
 constexpr int MISC_SEG = 8;      // 2 words: queued segments, fallback reads
 constexpr uint32_t MIN_SEG_LEN = 256;
+constexpr int MAX_LANES = 4;
 constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
 constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
 constexpr int MISC_WORDS = MISC_HIST + HIST_WORDS + 64;
@@ -138,6 +140,10 @@ struct bwt_set {
     uint64_t btab_cap = 0;
     uint8_t *bstage = nullptr;
     uint64_t bstage_cap = 0;
+    // extra lanes of a batch: internal handles used only for their stream and
+    // workspace, so that independent blocks of a batch run side by side
+    int batch_lanes = 2;
+    std::vector<bwt_set *> lanes;
     uint64_t *res = nullptr;       // 4 words of device results
     uint64_t *pinned = nullptr;    // small pinned host area (512 words)
     int last_error = BWT_OK;
@@ -726,6 +732,86 @@ struct DevBlock {
     size_t rank_off, ins_off;  // byte offsets of the unit tables in btab
 };
 
+// Read-only inputs shared by the blocks of a batch.
+struct BatchInput {
+    const uint8_t *reads;      // staged packed reads
+    const uint64_t *off;       // staged offsets
+    const uint8_t *tab;        // device unit tables
+    uint64_t maxlen;
+};
+
+// One device block of a batch on lane L (its workspace) and stream s.
+int run_block(bwt_set *L, hipStream_t s, const DevBlock &B, const std::vector<HostUnit> &units,
+              const BatchInput &in) {
+    Workspace &w = L->ws;
+    const uint32_t nu = B.u1 - B.u0;
+    const uint32_t m_blk = (uint32_t)B.m_blk, n_blk = (uint32_t)B.n_blk;
+    const uint64_t *off = in.off + B.read0;
+    const RankUnit *rdev = reinterpret_cast<const RankUnit *>(in.tab + B.rank_off);
+    const InsertUnit *idev = reinterpret_cast<const InsertUnit *>(in.tab + B.ins_off);
+    int rc;
+    if ((rc = block_prep(L, s, off, m_blk, n_blk))) return rc;
+    // one empty unit alone needs no ranks (all 0); otherwise the ranks
+    // carry the unit offsets
+    const int gbits = bits_for_value(B.gtotal - 1);
+    if (gbits > 0) {
+        Scope sc(L, s, BWT_STAGE_RANKS);
+        Scope sk(L, s, SPAN_RANKS_K, n_blk - m_blk);
+        HIPCHK(L, launch_compute_ranks_units(in.reads, off, w.soff, m_blk, n_blk, rdev, nu, w.g,
+                                             rank_segments(L), w.misc + MISC_ERR, s));
+    }
+    uint32_t *sa = nullptr;
+    const uint64_t *gkeys = nullptr;
+    int gshift = 64;
+    if ((rc = block_sort(L, s, in.reads, off, m_blk, n_blk, in.maxlen, w.g, gbits, &sa, &gkeys,
+                         &gshift)))
+        return rc;
+    {
+        Scope sc(L, s, BWT_STAGE_INSERT);
+        HIPCHK(L, launch_count_bint(sa, n_blk, w.bcnt, w.status_scan, w.misc + MISC_CNT_BINT,
+                                    next_epoch(), w.misc + MISC_ERR, s));
+        HIPCHK(L, launch_ins_tile_first_units(idev, nu, gkeys, gshift, B.ntiles, L->first_new, s));
+        HIPCHK(L, launch_ins_meta_units(idev, nu, gkeys, gshift, sa, w.bcnt, s));
+        Scope sk(L, s, SPAN_INSERT_K);
+        HIPCHK(L, launch_insert_units(idev, nu, gkeys, gshift, sa, w.bcnt, L->first_new, B.ntiles,
+                                      w.misc + MISC_ERR, s));
+    }
+    if (L->timer.on) {
+        for (uint32_t k = B.u0; k < B.u1; ++k) {
+            L->timer.acc.insert_records_out += records_for(units[k].n_ext + units[k].nsuf);
+            L->timer.acc.insert_records_in += records_for(units[k].n_ext);
+        }
+        L->timer.acc.insert_new_symbols += n_blk;
+    }
+    L->timer.acc.blocks += 1;
+    return BWT_OK;
+}
+
+void stats_add(bwt_stats_t &a, const bwt_stats_t &b) {
+    for (int k = 0; k < BWT_NSTAGES; ++k) {
+        a.ms[k] += b.ms[k];
+        a.launches[k] += b.launches[k];
+    }
+    a.ranks_kernel_ms += b.ranks_kernel_ms;
+    a.ranks_launches += b.ranks_launches;
+    a.ranks_steps += b.ranks_steps;
+    a.insert_kernel_ms += b.insert_kernel_ms;
+    a.insert_launches += b.insert_launches;
+    a.insert_records_out += b.insert_records_out;
+    a.insert_records_in += b.insert_records_in;
+    a.insert_new_symbols += b.insert_new_symbols;
+    a.sort_pass_ms += b.sort_pass_ms;
+    a.sort_pass_launches += b.sort_pass_launches;
+    a.sort_pass_keys += b.sort_pass_keys;
+    a.blocks += b.blocks;
+    a.doubling_rounds += b.doubling_rounds;
+    a.keys_ms += b.keys_ms;
+    a.heads_ms += b.heads_ms;
+    a.refine_ms += b.refine_ms;
+    a.tied_suffixes += b.tied_suffixes;
+    a.fallback_blocks += b.fallback_blocks;
+}
+
 template <class T>
 size_t put_table(std::vector<uint8_t> &tab, const std::vector<T> &v) {
     size_t at = (tab.size() + 255) & ~(size_t)255;
@@ -981,54 +1067,100 @@ int append_many(bwt_set *d, bwt_set **hs, const uint8_t *const *reads,
         HIPCHK(d, launch_gather_reads(gdev, (uint32_t)units.size(), total_syms, d->stage_reads, s));
     }
 
-    // 7. the device blocks
-    Workspace &w = d->ws;
-    if ((rc = clear_err(d, s))) return rc;
-    for (auto &B : blocks) {
-        const uint32_t nu = B.u1 - B.u0;
-        const uint32_t m_blk = (uint32_t)B.m_blk, n_blk = (uint32_t)B.n_blk;
-        const uint64_t *off = d->stage_off + B.read0;
-        const RankUnit *rdev = reinterpret_cast<const RankUnit *>(d->btab + B.rank_off);
-        const InsertUnit *idev = reinterpret_cast<const InsertUnit *>(d->btab + B.ins_off);
-        if ((rc = block_prep(d, s, off, m_blk, n_blk))) return rc;
-        // one empty unit alone needs no ranks (all 0); otherwise the ranks
-        // carry the unit offsets
-        const int gbits = bits_for_value(B.gtotal - 1);
-        if (gbits > 0) {
-            Scope sc(d, s, BWT_STAGE_RANKS);
-            Scope sk(d, s, SPAN_RANKS_K, n_blk - m_blk);
-            HIPCHK(d, launch_compute_ranks_units(d->stage_reads, off, w.soff, m_blk, n_blk, rdev, nu,
-                                                 w.g, rank_segments(d), w.misc + MISC_ERR, s));
-        }
-        uint32_t *sa = nullptr;
-        const uint64_t *gkeys = nullptr;
-        int gshift = 64;
-        if ((rc = block_sort(d, s, d->stage_reads, off, m_blk, n_blk, maxlen, w.g, gbits, &sa,
-                             &gkeys, &gshift)))
-            return rc;
-        {
-            Scope sc(d, s, BWT_STAGE_INSERT);
-            HIPCHK(d, launch_count_bint(sa, n_blk, w.bcnt, w.status_scan, w.misc + MISC_CNT_BINT,
-                                        next_epoch(), w.misc + MISC_ERR, s));
-            HIPCHK(d, launch_ins_tile_first_units(idev, nu, gkeys, gshift, B.ntiles, d->first_new,
-                                                  s));
-            HIPCHK(d, launch_ins_meta_units(idev, nu, gkeys, gshift, sa, w.bcnt, s));
-            Scope sk(d, s, SPAN_INSERT_K);
-            HIPCHK(d, launch_insert_units(idev, nu, gkeys, gshift, sa, w.bcnt, d->first_new,
-                                          B.ntiles, w.misc + MISC_ERR, s));
-        }
-        if (d->timer.on) {
-            for (uint32_t k = B.u0; k < B.u1; ++k) {
-                d->timer.acc.insert_records_out += records_for(units[k].n_ext + units[k].nsuf);
-                d->timer.acc.insert_records_in += records_for(units[k].n_ext);
-            }
-            d->timer.acc.insert_new_symbols += n_blk;
-        }
-        d->timer.acc.blocks += 1;
-    }
+    // 7. the device blocks, level by level.  Blocks of one level touch
+    // disjoint sets, so they are spread over lanes (streams with their own
+    // workspace) that run side by side; the next level starts when all are done.
     HIPCHK(d, hipStreamSynchronize(s));
-    if (d->timer.on) timer_collect(d);
-    if ((rc = check_err(d, s))) return rc;
+    const int nl = std::max(1, std::min<int>(d->batch_lanes, MAX_LANES));
+    std::vector<bwt_set *> lane{d};
+    for (int k = 1; k < nl; ++k) {
+        if ((int)d->lanes.size() < k) {
+            bwt_set *l = bwt_set_create("ACGT");
+            if (!l) return fail(d, BWT_ENOMEM);
+            d->lanes.push_back(l);
+        }
+        bwt_set *l = d->lanes[k - 1];
+        l->key_bits = d->key_bits;
+        l->radix_cfg = d->radix_cfg;
+        l->seg_len = d->seg_len;
+        l->seg_overlap = d->seg_overlap;
+        l->timer.on = d->timer.on;
+        lane.push_back(l);
+    }
+    for (int k = 1; k < nl; ++k) {
+        if ((rc = ensure_ws(lane[k], max_nblk))) return fail(d, rc);
+        if ((rc = ensure_buf(lane[k], lane[k]->first_new, lane[k]->first_new_cap, max_fn + 2)))
+            return fail(d, rc);
+    }
+    std::vector<hipStream_t> ls{s};
+    for (int k = 1; k < nl; ++k) ls.push_back(lane[k]->stream);
+    for (int k = 0; k < nl; ++k)
+        if ((rc = clear_err(lane[k], ls[k]))) return fail(d, rc);
+    const BatchInput in{d->stage_reads, d->stage_off, d->btab, maxlen};
+    size_t b0 = 0;
+    while (b0 < blocks.size()) {
+        size_t b1 = b0;
+        while (b1 < blocks.size() && units[blocks[b1].u0].level == units[blocks[b0].u0].level) ++b1;
+        const int used = (int)std::min<size_t>(nl, b1 - b0);
+        // largest block first onto the least loaded lane
+        std::vector<std::vector<size_t>> mine(used);
+        {
+            std::vector<size_t> ord;
+            for (size_t b = b0; b < b1; ++b) ord.push_back(b);
+            std::sort(ord.begin(), ord.end(),
+                      [&](size_t x, size_t y) { return blocks[x].n_blk > blocks[y].n_blk; });
+            std::vector<uint64_t> load(used, 0);
+            for (size_t b : ord) {
+                int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                mine[k].push_back(b);
+                load[k] += blocks[b].n_blk;
+            }
+        }
+        std::vector<int> lrc(used, BWT_OK);
+        auto work = [&](int k) {
+            if (k > 0 && hipSetDevice(d->device) != hipSuccess) {
+                (void)hipGetLastError();
+                lrc[k] = BWT_EHIP;
+                return;
+            }
+            for (size_t b : mine[k]) {
+                lrc[k] = run_block(lane[k], ls[k], blocks[b], units, in);
+                if (lrc[k]) return;
+            }
+            if (hipStreamSynchronize(ls[k]) != hipSuccess) {
+                (void)hipGetLastError();
+                lrc[k] = BWT_EHIP;
+            }
+        };
+        if (used == 1) {
+            work(0);
+        } else {
+            std::vector<std::thread> th;
+            for (int k = 1; k < used; ++k) th.emplace_back(work, k);
+            work(0);
+            for (auto &t : th) t.join();
+        }
+        for (int k = 0; k < used; ++k)
+            if (lrc[k]) {
+                for (int j = 0; j < nl; ++j) (void)hipStreamSynchronize(ls[j]);
+                if (lrc[k] == BWT_EHIP) d->broken = true;
+                return fail(d, lrc[k]);
+            }
+        b0 = b1;
+    }
+    for (int k = 0; k < nl; ++k) HIPCHK(d, hipStreamSynchronize(ls[k]));
+    for (int k = 0; k < nl; ++k) {
+        if (lane[k]->timer.on) timer_collect(lane[k]);
+        if (k > 0) {
+            stats_add(d->timer.acc, lane[k]->timer.acc);
+            memset(&lane[k]->timer.acc, 0, sizeof lane[k]->timer.acc);
+        }
+    }
+    for (int k = 0; k < nl; ++k)
+        if ((rc = check_err(lane[k], ls[k]))) {
+            if (k > 0) d->broken = lane[k]->broken;
+            return fail(d, rc);
+        }
 
     // 8. commit every set
     for (uint32_t a = 0; a < na; ++a) {
@@ -1107,6 +1239,8 @@ void bwt_set_destroy(bwt_set_t h) {
     dfree(h->stage_out);
     dfree(h->btab);
     dfree(h->bstage);
+    for (auto *l : h->lanes) bwt_set_destroy(l);
+    h->lanes.clear();
     dfree(h->res);
     if (h->pinned) (void)hipHostFree(h->pinned);
     for (auto e : h->timer.pool) (void)hipEventDestroy(e);
@@ -1351,6 +1485,10 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
     }
     b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
          h->stage_out_cap + h->btab_cap + h->bstage_cap;
+    for (auto *l : h->lanes) {
+        uint64_t lb = 0;
+        if (bwt_set_memory(l, &lb) == BWT_OK) b += lb;
+    }
     *bytes = b;
     return BWT_OK;
 }
@@ -1381,6 +1519,8 @@ int bwt_set_trim(bwt_set_t h) {
     h->btab_cap = 0;
     dfree(h->bstage);
     h->bstage_cap = 0;
+    for (auto *l : h->lanes) bwt_set_destroy(l);
+    h->lanes.clear();
     return BWT_OK;
 }
 
@@ -1430,6 +1570,10 @@ int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
     case BWT_PARAM_RANK_OVERLAP:
         if (value < 0 || value > (1 << 24)) return fail(h, BWT_EINVAL);
         h->seg_overlap = (uint32_t)value;
+        return BWT_OK;
+    case BWT_PARAM_BATCH_LANES:
+        if (value < 1 || value > MAX_LANES) return fail(h, BWT_EINVAL);
+        h->batch_lanes = (int)value;
         return BWT_OK;
     default:
         return fail(h, BWT_EINVAL);

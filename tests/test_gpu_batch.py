@@ -153,3 +153,28 @@ def test_batch_workload_generator_small(torch_dev, oracle_mod):
     finally:
         for h in hs:
             h.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_batch_lanes_do_not_change_the_result(torch_dev, oracle_mod, lanes):
+    """Blocks of one level run side by side on `lanes` streams; several
+    levels (small M, a few large sets) and many blocks per level."""
+    from paper_1410_0562_amd import bwtset
+    sizes = [900, 30, 2500, 7, 1200, 400, 0, 1800]
+    data = [_set(600 + k, m) for k, m in enumerate(sizes)]
+    hs = [bwtset.BwtSet(block_size=1 << 15) for _ in sizes]
+    try:
+        hs[0].set_param(bwtset.BWT_PARAM_BATCH_LANES, lanes)
+        hs[0].enable_timing(True)
+        bwtset.append_many(hs, [p for p, _ in data], [o for _, o in data])
+        st = hs[0].stats()
+        assert st["blocks"] > 4 and st["insert_new_symbols"] == sum(
+            int(o[-1]) + len(o) - 1 for _, o in data)
+        for k, (p, o) in enumerate(data):
+            want = _oracle(oracle_mod, [(p, o)]) if sizes[k] else b""
+            assert hs[k].export() == want, k
+        with pytest.raises(bwtset.BwtSetError):
+            hs[0].set_param(bwtset.BWT_PARAM_BATCH_LANES, 5)
+    finally:
+        for h in hs:
+            h.close()
