@@ -404,6 +404,7 @@ def main():
             "keys": round(st["keys_ms"] / args.steps, 3),
             "radix_passes": round(st["sort_pass_ms"] / args.steps, 3),
             "tie_detection": round(st["heads_ms"] / args.steps, 3),
+            "bucket_finish": round(st["bucket_ms"] / args.steps, 3),
             "refine": round(st["refine_ms"] / args.steps, 3)},
         "tied_fraction": st["tied_suffixes"] / float(args.steps * (bases + m)),
         "fallback_blocks_per_step": st["fallback_blocks"] / args.steps,

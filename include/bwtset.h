@@ -148,13 +148,18 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 128).
  *   BWT_PARAM_BATCH_LANES: blocks of one level of a batch (bwt_set_append_many
  *     on this handle as hs[0]) that run side by side, each on its own stream
- *     and workspace (1 .. 4, default 2). */
+ *     and workspace (1 .. 4, default 2).
+ *   BWT_PARAM_SORT_BUCKETS: 1 (default) = the first suffix sort runs radix
+ *     passes on the top 8-24 bits of the key only (about 64 suffixes per
+ *     bucket of equal top bits) and one wavefront finishes each bucket in
+ *     registers; 0 = radix passes over the whole key. */
 enum {
     BWT_PARAM_KEY_BITS = 1,
     BWT_PARAM_RADIX_TILE = 2,
     BWT_PARAM_RANK_SEGMENT = 3,
     BWT_PARAM_RANK_OVERLAP = 4,
-    BWT_PARAM_BATCH_LANES = 5
+    BWT_PARAM_BATCH_LANES = 5,
+    BWT_PARAM_SORT_BUCKETS = 6
 };
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
 
@@ -223,6 +228,7 @@ typedef struct {
     double refine_ms;               /* LDS refinement of tied groups */
     uint64_t tied_suffixes;         /* suffixes left tied by the first sort */
     uint64_t fallback_blocks;       /* blocks sorted by prefix doubling */
+    double bucket_ms;               /* LDS bucket finish of the first sort */
 } bwt_stats_t;
 
 /* Turns per-stage HIP-event timing on (1) or off (0).  Timing adds event

@@ -50,6 +50,7 @@ class Stats(ctypes.Structure):
         ("refine_ms", ctypes.c_double),
         ("tied_suffixes", ctypes.c_uint64),
         ("fallback_blocks", ctypes.c_uint64),
+        ("bucket_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -76,6 +77,7 @@ BWT_PARAM_RADIX_TILE = 2
 BWT_PARAM_RANK_SEGMENT = 3
 BWT_PARAM_RANK_OVERLAP = 4
 BWT_PARAM_BATCH_LANES = 5
+BWT_PARAM_SORT_BUCKETS = 6
 
 _lib = None
 

@@ -130,11 +130,50 @@ hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_
                                    uint32_t *tile_first, hipStream_t s);
 // key = g[p] << gshift | (kfirst symbols) << 5 | count (g may be null: no
 // g); hist0 (the first pass's HIST_COPIES x 256 words, zeroed by the caller)
-// receives the counts of the low 8 bits
+// receives the counts of the 8-bit digit at bit hshift
 hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                              const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
-                             int gshift, int kfirst, uint64_t *keys, uint32_t *vals,
+                             int gshift, int kfirst, int hshift, uint64_t *keys, uint32_t *vals,
                              uint32_t *hist0, hipStream_t s);
+
+// Bucket finish of the first sort (k_bucket.hip).  After radix passes on the
+// top digits, keys sit in nb = 2^B buckets of equal bits above bshift, each
+// a contiguous run.  bucket_bounds: bstart/bend of every bucket that occurs
+// (bstart = ABSENT otherwise).  bucket_sort: every bucket of 2 .. BUCKET_CAP
+// suffixes sorted in place by one wave (*large set for a tied group above
+// limit); then per bucket tcnt = tied suffixes before it (exclusive prefix)
+// and osz = its size if above BUCKET_CAP; the oversized buckets in bucket
+// order in olist, their starts in the gathered array in ooff (ooff[count] =
+// total); res = {tied suffixes, oversized buckets, oversized suffixes}; part
+// holds 3 words per 4096 bucket ids.  bucket_emit lists the tied suffixes of
+// the sorted buckets in U (slot order).  oversize_gather copies the oversized
+// buckets to ck/cv; once sorted there on the whole key, oversize_scatter puts
+// them back and oversize_ties_map appends their tied suffixes (gathered
+// indices U2[0 .. *nU2)) to U after the first `base`, setting *nU.
+constexpr uint32_t BUCKET_CAP = 256;
+constexpr int BUCKET_MAX_BITS = 24;
+hipError_t launch_bucket_bounds(const uint64_t *keys, uint32_t n, int bshift, uint32_t nb,
+                                uint32_t *bstart, uint32_t *bend, uint32_t *err, hipStream_t s);
+hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, const uint32_t *bstart,
+                              const uint32_t *bend, uint32_t nb, int kshort, uint32_t limit,
+                              uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint32_t *part,
+                              uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *err,
+                              hipStream_t s);
+hipError_t launch_bucket_emit(const uint64_t *keys, const uint32_t *bstart, const uint32_t *bend,
+                              const uint32_t *tpre, uint32_t nb, int kshort, uint32_t *U,
+                              uint32_t ucap, uint32_t *err, hipStream_t s);
+hipError_t launch_oversize_gather(const uint64_t *keys, const uint32_t *vals,
+                                  const uint32_t *bstart, const uint32_t *olist,
+                                  const uint32_t *ooff, uint32_t nob, uint32_t no, uint32_t n,
+                                  uint64_t *ck, uint32_t *cv, uint32_t *err, hipStream_t s);
+hipError_t launch_oversize_scatter(const uint64_t *ck, const uint32_t *cv, uint32_t no,
+                                   const uint32_t *bstart, const uint32_t *olist,
+                                   const uint32_t *ooff, uint32_t nob, uint32_t n, uint64_t *keys,
+                                   uint32_t *vals, uint32_t *err, hipStream_t s);
+hipError_t launch_oversize_ties_map(const uint32_t *U2, const uint32_t *nU2, const uint32_t *bstart,
+                                    const uint32_t *olist, const uint32_t *ooff, uint32_t nob,
+                                    uint32_t no, uint32_t base, uint32_t ucap, uint32_t *U,
+                                    uint32_t *nU, uint32_t *err, hipStream_t s);
 // Groups after a sort.  Round 0 (U == nullptr): element i is SA slot i, and a
 // key whose length field is below kshort is a singleton.  Doubling round:
 // element u is SA slot U[u] and its value is stored there.  rank == nullptr

@@ -49,7 +49,8 @@ struct Workspace {
     uint32_t *v[3] = {nullptr, nullptr, nullptr};  // sort values / suffix array
     uint32_t *U[2] = {nullptr, nullptr};     // unresolved SA slots
     uint32_t *rank = nullptr;                // group rank per block position
-    uint64_t *g = nullptr, *gsa = nullptr;   // ranks in text order / in SA order
+    uint64_t *g = nullptr;                   // ranks in text order
+    uint64_t *gsa = nullptr;                 // second spare key buffer of the bucket finish
     uint8_t *bint = nullptr;
     uint32_t *bcnt = nullptr;                // B_int counts per 64 symbols
     uint32_t *soff = nullptr;                // block position of each read
@@ -60,6 +61,8 @@ struct Workspace {
     uint64_t *seg_list = nullptr;            // long-read segments of ComputeRanks
     uint32_t seg_cap = 0;
     uint32_t *fb_flag = nullptr, *fb_list = nullptr;
+    uint32_t *bk = nullptr;                  // BK_TABLES bucket tables of bk_words each
+    uint32_t bk_words = 0;
 };
 
 // layout of Workspace::misc (uint32 words)
@@ -71,8 +74,13 @@ constexpr int MISC_LARGE = 5;
 constexpr int MISC_BAD = 6;
 constexpr int MISC_ERR = 7;
 constexpr int MISC_SEG = 8;      // 2 words: queued segments, fallback reads
+constexpr int MISC_BK = 10;      // 3 words: tied suffixes, oversized buckets, their suffixes
+constexpr int MISC_NU2 = 13;     // tied suffixes among the oversized buckets
+constexpr int BK_TABLES = 6;     // bucket starts, ends, tie counts, sizes; oversized list, offsets
+constexpr uint32_t BK_PART = 3 * 4096 + 16;  // tile partials of the bucket scans
 constexpr uint32_t MIN_SEG_LEN = 256;
 constexpr int MAX_LANES = 4;
+constexpr uint32_t BUCKET_TARGET = 64;  // suffixes per bucket the bucket count aims at
 constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
 constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
 constexpr int MISC_WORDS = MISC_HIST + HIST_WORDS + 64;
@@ -106,7 +114,8 @@ enum {
     SPAN_RADIX_PASS = 102,
     SPAN_KEYS = 103,
     SPAN_HEADS = 104,
-    SPAN_REFINE = 105
+    SPAN_REFINE = 105,
+    SPAN_BUCKET = 106
 };
 
 }  // namespace
@@ -123,6 +132,7 @@ struct bwt_set {
     int radix_cfg = 3;               // radix pass tile shape (512 threads x 12 keys)
     uint32_t seg_len = 1024;         // ComputeRanks segment length for long reads
     uint32_t seg_overlap = 128;      // symbols a segment walk starts past its end
+    bool sort_buckets = true;        // first sort: top digits + LDS bucket finish
     uint64_t *first_new = nullptr;
     uint64_t first_new_cap = 0;
     // staging for host inputs / outputs
@@ -249,6 +259,8 @@ void timer_collect(bwt_set *h) {
             T.acc.heads_ms += ms;
         } else if (sp.stage == SPAN_REFINE) {
             T.acc.refine_ms += ms;
+        } else if (sp.stage == SPAN_BUCKET) {
+            T.acc.bucket_ms += ms;
         }
         T.pool.push_back(sp.a);
         T.pool.push_back(sp.b);
@@ -306,6 +318,7 @@ void free_ws(Workspace &w) {
     dfree(w.seg_list);
     dfree(w.fb_flag);
     dfree(w.fb_list);
+    dfree(w.bk);
     w.seg_cap = 0;
     w.cap = 0;
 }
@@ -336,6 +349,12 @@ int ensure_ws(bwt_set *h, uint64_t need) {
     ok &= dalloc(&w.seg_list, segs) == hipSuccess;
     ok &= dalloc(&w.fb_flag, cap + 1) == hipSuccess;
     ok &= dalloc(&w.fb_list, cap + 1) == hipSuccess;
+    {
+        uint32_t nb = 256;
+        while ((uint64_t)nb * BUCKET_TARGET < cap && nb < (1u << BUCKET_MAX_BITS)) nb <<= 1;
+        w.bk_words = nb + 16;
+    }
+    ok &= dalloc(&w.bk, (uint64_t)BK_TABLES * w.bk_words + BK_PART) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         free_ws(w);
@@ -373,21 +392,21 @@ int bits_for(uint64_t v) {  // bits needed to hold values < v (at least 1)
 }
 
 // ---- radix sort -------------------------------------------------------------
-// Sorts (kin, vin) by the low `bits` bits of the keys, ping-ponging with
+// Sorts (kin, vin) by bits shift0 .. bits-1 of the keys, ping-ponging with
 // (kalt, valt); returns via *ko / *vo where the sorted data ended up.  When
 // counted0 is set, the producer of the keys already left the counts of their
 // low digit in the first 256 histogram words.
 int radix_sort(bwt_set *h, hipStream_t s, uint64_t *kin, uint32_t *vin, uint64_t *kalt,
                uint32_t *valt, uint64_t n, int bits, bool counted0, uint64_t **ko,
-               uint32_t **vo) {
+               uint32_t **vo, int shift0 = 0) {
     Workspace &w = h->ws;
-    const int npass = bits < 1 ? 1 : (bits + 7) / 8;
+    const int npass = bits - shift0 < 1 ? 1 : (bits - shift0 + 7) / 8;
     *ko = kin;
     *vo = vin;
     if (n <= 1) return BWT_OK;
     uint32_t *hist = w.misc + MISC_HIST, *starts = w.misc + MISC_STARTS;
     const uint32_t per_pass = HIST_COPIES * 256;
-    if (!counted0) HIPCHK(h, launch_radix_hist1(kin, n, 0, hist, s));
+    if (!counted0) HIPCHK(h, launch_radix_hist1(kin, n, shift0, hist, s));
     if (npass > 1) HIPCHK(h, launch_zero_u32(hist + per_pass, per_pass * (npass - 1), s));
     uint64_t *ka = kin, *kb = kalt;
     uint32_t *va = vin, *vb = valt;
@@ -395,9 +414,9 @@ int radix_sort(bwt_set *h, hipStream_t s, uint64_t *kin, uint32_t *vin, uint64_t
         HIPCHK(h, launch_radix_starts(hist + per_pass * p, starts + 256 * p, s));
         {
             Scope sc(h, s, SPAN_RADIX_PASS, n);
-            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, 8 * p, starts + 256 * p,
+            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, shift0 + 8 * p, starts + 256 * p,
                                         p + 1 < npass ? hist + per_pass * (p + 1) : nullptr,
-                                        8 * (p + 1), w.status_radix, w.misc + MISC_CNT_RADIX,
+                                        shift0 + 8 * (p + 1), w.status_radix, w.misc + MISC_CNT_RADIX,
                                         next_epoch(), w.misc + MISC_ERR, h->radix_cfg, s));
         }
         std::swap(ka, kb);
@@ -459,6 +478,71 @@ int block_prep(bwt_set *h, hipStream_t s, const uint64_t *off, uint32_t m_blk, u
     return BWT_OK;
 }
 
+// Finishes a first sort whose radix passes covered only the top digits:
+// buckets of up to BUCKET_CAP suffixes are sorted by one wave each, larger
+// ones are gathered, radix-sorted on the whole key and put back; the tied
+// suffixes of both end up in U[0] (count in *nU, *large for a group above
+// REFINE_LIMIT).
+int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *ks, uint32_t *vs, uint32_t n, int sort_bits,
+                  int B, int kfirst, uint32_t *nU, bool *large) {
+    Workspace &w = h->ws;
+    const uint32_t nb = 1u << B;
+    const int bshift = sort_bits - B;
+    const uint32_t W = w.bk_words;
+    uint32_t *bstart = w.bk, *bend = w.bk + W, *tcnt = w.bk + 2 * W, *osz = w.bk + 3 * W,
+             *olist = w.bk + 4 * W, *ooff = w.bk + 5 * W, *part = w.bk + 6 * W;
+    uint32_t *err = w.misc + MISC_ERR, *res = w.misc + MISC_BK;
+    HIPCHK(h, launch_zero_u32(w.misc + MISC_NU, 2, s));  // tied count, large flag
+    {
+        Scope sk(h, s, SPAN_BUCKET);
+        HIPCHK(h, launch_bucket_bounds(ks, n, bshift, nb, bstart, bend, err, s));
+        HIPCHK(h, launch_bucket_sort(ks, vs, bstart, bend, nb, kfirst, REFINE_LIMIT,
+                                     w.misc + MISC_LARGE, tcnt, osz, part, res, olist, ooff, err,
+                                     s));
+        HIPCHK(h, launch_bucket_emit(ks, bstart, bend, tcnt, nb, kfirst, w.U[0], n, err, s));
+    }
+    const uint32_t *pw = reinterpret_cast<const uint32_t *>(h->pinned);
+    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, (MISC_BK + 3 - MISC_NU) * 4,
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    const uint32_t tied = pw[MISC_BK - MISC_NU], nob = pw[MISC_BK + 1 - MISC_NU],
+                   no = pw[MISC_BK + 2 - MISC_NU];
+    *nU = tied;
+    *large = pw[MISC_LARGE - MISC_NU] != 0;
+    if (no == 0) return BWT_OK;
+    if (no > n || nob == 0 || nob > nb || tied > n) return fail(h, BWT_EHIP);
+    // two key and two value buffers that hold neither the sorted block nor g
+    // (the doubling fallback may build the keys from g again)
+    uint64_t *kf[2];
+    uint32_t *vf[2];
+    {
+        int a = 0, b = 0;
+        for (uint64_t *p : {w.kA, w.kB, w.gsa})
+            if (p != ks && a < 2) kf[a++] = p;
+        for (uint32_t *p : w.v)
+            if (p != vs && b < 2) vf[b++] = p;
+    }
+    HIPCHK(h, launch_oversize_gather(ks, vs, bstart, olist, ooff, nob, no, n, kf[0], vf[0], err, s));
+    uint64_t *ck;
+    uint32_t *cv;
+    int rc = radix_sort(h, s, kf[0], vf[0], kf[1], vf[1], no, sort_bits, false, &ck, &cv);
+    if (rc) return rc;
+    {
+        Scope sk(h, s, SPAN_BUCKET);
+        HIPCHK(h, launch_oversize_scatter(ck, cv, no, bstart, olist, ooff, nob, n, ks, vs, err, s));
+        HIPCHK(h, launch_group_heads(ck, cv, nullptr, no, kfirst, cv, nullptr, w.U[1],
+                                     w.misc + MISC_NU2, REFINE_LIMIT, w.misc + MISC_LARGE,
+                                     w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(), err, s));
+        HIPCHK(h, launch_oversize_ties_map(w.U[1], w.misc + MISC_NU2, bstart, olist, ooff, nob, no,
+                                           tied, n, w.U[0], w.misc + MISC_NU, err, s));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    *nU = pw[0];
+    *large = pw[1] != 0;
+    return BWT_OK;
+}
+
 // Suffix array of one block (after block_prep).  reads/off: device; off
 // points at the block's first read (m_blk + 1 entries).  g (text order, may
 // be null when gbits == 0) leads the first sort key.  On return *sa_out holds
@@ -476,32 +560,51 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     int gshift = gbits ? key_bits - gbits : 64;
     int sort_bits = gbits ? key_bits : 2 * kfirst + KEY_LEN_BITS;
     uint32_t *hist = w.misc + MISC_HIST;
+    // With the bucket finish the radix passes cover only the top digits: B
+    // bucket bits, enough for about BUCKET_TARGET suffixes per bucket.
+    const bool buckets = h->sort_buckets && n_blk > 1;
+    int B = 0, shift0 = 0;
+    if (buckets) {
+        B = 1;
+        while (B < BUCKET_MAX_BITS && ((uint64_t)BUCKET_TARGET << B) < n_blk &&
+               (2ull << B) + 16 <= w.bk_words)
+            ++B;
+        if (B > sort_bits) B = sort_bits;
+        shift0 = sort_bits - 8 * ((B + 7) / 8);
+        if (shift0 < 0) shift0 = 0;
+    }
     HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
     {
         Scope sk(h, s, SPAN_KEYS);
         HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
-                                    gshift, kfirst, w.kA, w.v[0], hist, s));
+                                    gshift, kfirst, shift0, w.kA, w.v[0], hist, s));
     }
     uint64_t *ks;
     uint32_t *vs;
-    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, sort_bits, true, &ks, &vs);
+    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, sort_bits, true, &ks, &vs, shift0);
     if (rc) return rc;
     uint32_t *sa = vs;
     *sa_out = sa;
     *gkeys_out = ks;
     *gshift_out = gshift;
-    HIPCHK(h, hipMemsetAsync(w.misc + MISC_LARGE, 0, 4, s));
-    {
-        Scope sk(h, s, SPAN_HEADS);
-        HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, kfirst, sa, nullptr, w.U[0],
-                                     w.misc + MISC_NU, REFINE_LIMIT, w.misc + MISC_LARGE,
-                                     w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
-                                     w.misc + MISC_ERR, s));
+    uint32_t nU = 0;
+    bool large = false;
+    if (buckets) {
+        if ((rc = bucket_finish(h, s, ks, vs, n_blk, sort_bits, B, kfirst, &nU, &large))) return rc;
+    } else {
+        HIPCHK(h, launch_zero_u32(w.misc + MISC_LARGE, 1, s));
+        {
+            Scope sk(h, s, SPAN_HEADS);
+            HIPCHK(h, launch_group_heads(ks, vs, nullptr, n_blk, kfirst, sa, nullptr, w.U[0],
+                                         w.misc + MISC_NU, REFINE_LIMIT, w.misc + MISC_LARGE,
+                                         w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
+                                         w.misc + MISC_ERR, s));
+        }
+        HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        nU = reinterpret_cast<uint32_t *>(h->pinned)[0];
+        large = reinterpret_cast<uint32_t *>(h->pinned)[1] != 0;
     }
-    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    uint32_t nU = reinterpret_cast<uint32_t *>(h->pinned)[0];
-    const bool large = reinterpret_cast<uint32_t *>(h->pinned)[1] != 0;
     h->timer.acc.tied_suffixes += nU;
     if (nU == 0) return BWT_OK;
     if (!large) {
@@ -524,7 +627,7 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
         if (kfirst < 1) return fail(h, BWT_EHIP);
         HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
         HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
-                                    gshift, kfirst, w.kA, w.v[0], hist, s));
+                                    gshift, kfirst, 0, w.kA, w.v[0], hist, s));
         rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, 64, true, &ks, &vs);
         if (rc) return rc;
         sa = vs;
@@ -808,6 +911,7 @@ void stats_add(bwt_stats_t &a, const bwt_stats_t &b) {
     a.keys_ms += b.keys_ms;
     a.heads_ms += b.heads_ms;
     a.refine_ms += b.refine_ms;
+    a.bucket_ms += b.bucket_ms;
     a.tied_suffixes += b.tied_suffixes;
     a.fallback_blocks += b.fallback_blocks;
 }
@@ -1084,6 +1188,7 @@ int append_many(bwt_set *d, bwt_set **hs, const uint8_t *const *reads,
         l->radix_cfg = d->radix_cfg;
         l->seg_len = d->seg_len;
         l->seg_overlap = d->seg_overlap;
+        l->sort_buckets = d->sort_buckets;
         l->timer.on = d->timer.on;
         lane.push_back(l);
     }
@@ -1481,7 +1586,8 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
     if (w.cap) {
         const uint64_t c = w.cap, tiles = div_up(c, RADIX_MIN_TILE) + 1;
         b += c * (8 * 4 + 4 * 6 + 1 + 4 * 2) + div_up(c, 64) * 16 + div_up(c, 4096) * 4 +
-             tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4;
+             tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4 +
+             4ull * (BK_TABLES * w.bk_words + BK_PART);
     }
     b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
          h->stage_out_cap + h->btab_cap + h->bstage_cap;
@@ -1570,6 +1676,10 @@ int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
     case BWT_PARAM_RANK_OVERLAP:
         if (value < 0 || value > (1 << 24)) return fail(h, BWT_EINVAL);
         h->seg_overlap = (uint32_t)value;
+        return BWT_OK;
+    case BWT_PARAM_SORT_BUCKETS:
+        if (value != 0 && value != 1) return fail(h, BWT_EINVAL);
+        h->sort_buckets = value != 0;
         return BWT_OK;
     case BWT_PARAM_BATCH_LANES:
         if (value < 1 || value > MAX_LANES) return fail(h, BWT_EINVAL);

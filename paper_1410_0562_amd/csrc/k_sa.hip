@@ -80,14 +80,15 @@ __device__ __forceinline__ uint64_t chunk_key(const uint8_t *__restrict__ reads,
 
 // A fixed grid strides over the block, one suffix per thread per step; a
 // wave covers 64 consecutive positions, so lane 0 finds the read of the
-// first one and every lane steps forward from there.  The counts of the key's
-// low digit (the first radix pass) are gathered in LDS and added once per
-// workgroup to one of the HIST_COPIES copies.
+// first one and every lane steps forward from there.  The counts of the
+// first radix pass's digit (bits hshift .. hshift + 7 of the key) are
+// gathered in LDS and added once per workgroup to one of the HIST_COPIES
+// copies.
 __global__ __launch_bounds__(256) void block_keys_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first, uint32_t n_blk,
-    const uint64_t *__restrict__ g, int gshift, int kfirst, uint64_t *__restrict__ keys,
-    uint32_t *__restrict__ vals, uint32_t *__restrict__ hist0) {
+    const uint64_t *__restrict__ g, int gshift, int kfirst, int hshift,
+    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t *__restrict__ hist0) {
     __shared__ uint32_t s_h[256];
     const int tid = threadIdx.x;
     s_h[tid] = 0;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void block_keys_kernel(
             keys[p] = key;
             uint32_t prev = t == 0 ? 4u : (uint32_t)load_sym(reads, s - 1);
             vals[p] = p | (prev << POS_BITS);
-            atomicAdd(&s_h[key & 255u], 1u);
+            atomicAdd(&s_h[(uint32_t)(key >> hshift) & 255u], 1u);
         }
     }
     __syncthreads();
@@ -470,12 +471,12 @@ hipError_t launch_block_tile_first(const uint32_t *soff, uint32_t m_blk, uint32_
 
 hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                              const uint32_t *tile_first, uint32_t n_blk, const uint64_t *g,
-                             int gshift, int kfirst, uint64_t *keys, uint32_t *vals,
+                             int gshift, int kfirst, int hshift, uint64_t *keys, uint32_t *vals,
                              uint32_t *hist0, hipStream_t s) {
     uint64_t want = div_up(n_blk, 256 * 8);
     unsigned grid = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
     block_keys_kernel<<<grid, 256, 0, s>>>(reads, off, soff, tile_first, n_blk, g, gshift, kfirst,
-                                           keys, vals, hist0);
+                                           hshift, keys, vals, hist0);
     return hipGetLastError();
 }
 

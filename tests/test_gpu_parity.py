@@ -446,3 +446,35 @@ def test_segmented_compute_ranks(B, torch_dev, oracle_mod, seg, ov):
         assert np.array_equal(g.cpu().numpy().astype(np.uint64), want)
         idx.append(pb, ob)
         assert idx.export() == oracle_mod.bwt_of_codes(*_oracle_inputs(oracle_mod, packed, offs))
+
+
+@pytest.mark.parametrize("buckets", [0, 1])
+def test_sort_modes_agree(B, torch_dev, oracle_mod, buckets):
+    """The first sort either runs radix passes over the whole key, or only
+    over its top digits and finishes each bucket in LDS (piles of identical
+    short suffixes, larger than a bucket can hold, take the gathered radix
+    path).  Both give the oracle's suffix array and BWT, on one block and
+    through appends that rank against a growing index."""
+    torch = torch_dev
+    cases = [
+        synth.short_reads(m=30_000, length=100, ref_len=300_000, seed=51),   # 10x, $-pile of 30k
+        synth.random_reads(52, 6000, 0, 200),                                # ragged, empty reads
+        synth.random_reads(53, 3000, 0, 50, alphabet=2),                     # few distinct keys
+        synth.random_reads(54, 40, 0, 6),                                    # tiny block
+    ]
+    for k, (packed, offs) in enumerate(cases):
+        codes, o = _oracle_inputs(oracle_mod, packed, offs)
+        sa_want, T = oracle_mod.construct_sa(codes, o)
+        n = len(T)
+        sa = torch.empty(n, dtype=torch.int32, device="cuda")
+        bint = torch.empty(n, dtype=torch.uint8, device="cuda")
+        with B.BwtSet() as idx:
+            idx.set_param(B.BWT_PARAM_SORT_BUCKETS, buckets)
+            idx.enable_timing(True)
+            idx.block_sort(packed, offs, sa, bint)
+            assert np.array_equal(sa.cpu().numpy().astype(np.uint64), sa_want), k
+            assert (idx.stats()["bucket_ms"] > 0) == bool(buckets and n > 1), k
+        with B.BwtSet(block_size=max(64, n // 5)) as idx:
+            idx.set_param(B.BWT_PARAM_SORT_BUCKETS, buckets)
+            idx.append(packed, offs)
+            assert idx.export() == oracle_mod.bwt_of_codes(codes, o), k
