@@ -150,7 +150,7 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     on this handle as hs[0]) that run side by side, each on its own stream
  *     and workspace (1 .. 4, default 2).
  *   BWT_PARAM_SORT_BUCKETS: 1 (default) = the first suffix sort runs radix
- *     passes on the top 8-24 bits of the key only (about 64 suffixes per
+ *     passes on the top 8-24 bits of the key only (about 32 suffixes per
  *     bucket of equal top bits) and one wavefront finishes each bucket in
  *     registers; 0 = radix passes over the whole key. */
 enum {

@@ -80,7 +80,7 @@ constexpr int BK_TABLES = 6;     // bucket starts, ends, tie counts, sizes; over
 constexpr uint32_t BK_PART = 3 * 4096 + 16;  // tile partials of the bucket scans
 constexpr uint32_t MIN_SEG_LEN = 256;
 constexpr int MAX_LANES = 4;
-constexpr uint32_t BUCKET_TARGET = 64;  // suffixes per bucket the bucket count aims at
+constexpr uint32_t BUCKET_TARGET = 32;  // suffixes per bucket the bucket count aims at
 constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
 constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
 constexpr int MISC_WORDS = MISC_HIST + HIST_WORDS + 64;
@@ -354,7 +354,9 @@ int ensure_ws(bwt_set *h, uint64_t need) {
         while ((uint64_t)nb * BUCKET_TARGET < cap && nb < (1u << BUCKET_MAX_BITS)) nb <<= 1;
         w.bk_words = nb + 16;
     }
-    ok &= dalloc(&w.bk, (uint64_t)BK_TABLES * w.bk_words + BK_PART) == hipSuccess;
+    // bucket tables, scan partials, and two words per 2048-position tile
+    ok &= dalloc(&w.bk, (uint64_t)BK_TABLES * w.bk_words + BK_PART + 2 * (cap / 2048 + 2)) ==
+          hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         free_ws(w);
@@ -490,16 +492,19 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *ks, uint32_t *vs, uint32_
     const int bshift = sort_bits - B;
     const uint32_t W = w.bk_words;
     uint32_t *bstart = w.bk, *bend = w.bk + W, *tcnt = w.bk + 2 * W, *osz = w.bk + 3 * W,
-             *olist = w.bk + 4 * W, *ooff = w.bk + 5 * W, *part = w.bk + 6 * W;
+             *olist = w.bk + 4 * W, *ooff = w.bk + 5 * W, *part = w.bk + 6 * W,
+             *trange = part + BK_PART;
     uint32_t *err = w.misc + MISC_ERR, *res = w.misc + MISC_BK;
     HIPCHK(h, launch_zero_u32(w.misc + MISC_NU, 2, s));  // tied count, large flag
     {
         Scope sk(h, s, SPAN_BUCKET);
         HIPCHK(h, launch_bucket_bounds(ks, n, bshift, nb, bstart, bend, err, s));
-        HIPCHK(h, launch_bucket_sort(ks, vs, bstart, bend, nb, kfirst, REFINE_LIMIT,
+        HIPCHK(h, launch_bucket_sort(ks, vs, n, bstart, bend, trange, nb, bshift, kfirst,
+                                     REFINE_LIMIT,
                                      w.misc + MISC_LARGE, tcnt, osz, part, res, olist, ooff, err,
                                      s));
-        HIPCHK(h, launch_bucket_emit(ks, bstart, bend, tcnt, nb, kfirst, w.U[0], n, err, s));
+        HIPCHK(h, launch_bucket_emit(ks, n, bshift, bstart, bend, trange, tcnt, nb, kfirst, w.U[0],
+                                     n, err, s));
     }
     const uint32_t *pw = reinterpret_cast<const uint32_t *>(h->pinned);
     HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, (MISC_BK + 3 - MISC_NU) * 4,
@@ -1587,7 +1592,7 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
         const uint64_t c = w.cap, tiles = div_up(c, RADIX_MIN_TILE) + 1;
         b += c * (8 * 4 + 4 * 6 + 1 + 4 * 2) + div_up(c, 64) * 16 + div_up(c, 4096) * 4 +
              tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4 +
-             4ull * (BK_TABLES * w.bk_words + BK_PART);
+             4ull * (BK_TABLES * w.bk_words + BK_PART + 2 * (c / 2048 + 2));
     }
     b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
          h->stage_out_cap + h->btab_cap + h->bstage_cap;

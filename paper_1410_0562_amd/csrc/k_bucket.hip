@@ -2,9 +2,10 @@
 //
 // Radix passes on the top digits of the first key (see bwt_internal.hpp)
 // leave the suffixes in buckets of equal top B bits, each bucket a contiguous
-// run in position order (the passes are stable); B is chosen for about 64
+// run in position order (the passes are stable); B is chosen for about 32
 // suffixes per bucket.  One wavefront finishes a bucket of at most
-// BUCKET_CAP = 256 suffixes in registers: a bitonic network over
+// BUCKET_CAP = 256 suffixes in registers (four buckets of at most 64 at
+// once, one per register row, so that their shuffles overlap): a bitonic network over
 // (key, index in the bucket) -- the index keeps equal keys in position order,
 // which is terminator order -- with 64 x E elements per wave (element
 // r * 64 + lane in register r of that lane), so the compare-exchanges at
@@ -23,6 +24,11 @@ namespace bwt {
 namespace {
 
 constexpr uint32_t ABSENT = 0xffffffffu;
+
+__global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t n, uint32_t v) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 __global__ void bucket_fill_kernel(uint32_t *__restrict__ bstart, uint32_t nb) {
     uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,6 +109,60 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&x)[E],
     }
 }
 
+// Value of lane (lane ^ J) of the wave.  Distances 1 and 2 stay inside a
+// quad (DPP quad_perm), 4 and 8 inside a row of 16 (DPP row shifts, one per
+// direction); 16 and 32 go through the LDS crossbar.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (J == 4 || J == 8) {
+        // row_shl:J reads lane + J, row_shr:J reads lane - J (inside the row)
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + J, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + J, 0xF, 0xF, false);
+        return (lane & J) ? dn : up;
+    } else {
+        return (uint32_t)__shfl_xor((int)v, J, 64);
+    }
+}
+
+// One compare-exchange stage (block size KK, distance J) on R independent
+// rows of composite words cut into segments of S lanes (each segment is
+// sorted ascending as a whole at KK = S), then the stages of the same block
+// at J / 2, J / 4, ...
+template <int KK, int J, int R, int S>
+__device__ __forceinline__ void row_stage(uint64_t (&c)[R], int lane) {
+    const bool lower = (lane & J) == 0;
+    const bool up = KK == S || (lane & KK) == 0;
+    const bool keep_min = lower == up;
+    uint64_t p[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t lo = lane_xor<J>((uint32_t)c[r], lane);
+        const uint32_t hi = lane_xor<J>((uint32_t)(c[r] >> 32), lane);
+        p[r] = (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (keep_min == (c[r] > p[r])) c[r] = p[r];
+    if constexpr (J > 1) row_stage<KK, J / 2, R, S>(c, lane);
+}
+
+template <int KK, int R, int S>
+__device__ __forceinline__ void row_levels(uint64_t (&c)[R], int lane) {
+    row_stage<KK, KK / 2, R, S>(c, lane);
+    if constexpr (KK < S) row_levels<KK * 2, R, S>(c, lane);
+}
+
+// Sorts each segment of S lanes of each of R rows of distinct 64-bit words
+// ascending (S = 64: whole rows; S = 32: two segments per row).
+template <int R, int S>
+__device__ __forceinline__ void wave_sort_rows(uint64_t (&c)[R], int lane) {
+    row_levels<2, R, S>(c, lane);
+}
+
 // a key whose length field is below kshort ends at its terminator: never tied
 __device__ __forceinline__ bool short_key(uint64_t k, int kshort) {
     return (k & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)kshort;
@@ -145,6 +205,34 @@ __device__ __forceinline__ uint32_t wave_ties(const uint64_t (&k)[E], uint32_t z
     return rows;
 }
 
+// Tied elements of R sorted buckets held one per row (z[r] <= 64 keys,
+// element = lane): bit r of the result is this lane's element of row r;
+// cnt[r] = tied elements of row r (wave-uniform).
+template <int R>
+__device__ __forceinline__ uint32_t rows_ties(const uint64_t (&k)[R], const uint32_t (&z)[R],
+                                              int kshort, uint32_t limit,
+                                              uint32_t *__restrict__ large, uint32_t (&cnt)[R]) {
+    const int lane = lane_id();
+    uint32_t rows = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)lane;
+        const bool ok = i < z[r];
+        const uint64_t kp = __shfl_up(k[r], 1, 64);
+        const uint64_t kn = __shfl_down(k[r], 1, 64);
+        const bool eq_prev = ok && i > 0 && kp == k[r];
+        const bool eq_next = ok && i + 1 < z[r] && kn == k[r];
+        const bool t = ok && !short_key(k[r], kshort) && (eq_prev || eq_next);
+        cnt[r] = (uint32_t)__popcll(__ballot(t));
+        rows |= (t ? 1u : 0u) << r;
+        if (limit < 64) {
+            const uint32_t hm = wave_incl_max((ok && !eq_prev) ? i : 0u);
+            if (t && !eq_next && i - hm + 1 > limit) atomicOr(large, 1u);
+        }
+    }
+    return rows;
+}
+
 // One bucket of z (2 .. 64 * E) suffixes at s0, sorted by one wave and
 // written back; returns its number of tied suffixes.
 template <int E>
@@ -179,42 +267,6 @@ __device__ uint32_t wave_bucket(uint64_t *__restrict__ keys, uint32_t *__restric
     uint32_t cnt;
     (void)wave_ties<E>(k, z, kshort, limit, large, &cnt);
     return cnt;
-}
-
-// Four waves per workgroup, one bucket id per wave.  Every bucket id gets
-// tcnt[b] (its tied suffixes) and osz[b] (its size if above BUCKET_CAP, else
-// 0); buckets of 2 .. BUCKET_CAP suffixes are sorted here.
-__global__ __launch_bounds__(256) void bucket_sort_kernel(
-    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, const uint32_t *__restrict__ bstart,
-    const uint32_t *__restrict__ bend, uint32_t nb, int kshort, uint32_t limit,
-    uint32_t *__restrict__ large, uint32_t *__restrict__ tcnt, uint32_t *__restrict__ osz,
-    uint32_t *__restrict__ err) {
-    __shared__ uint32_t s_v[4][BUCKET_CAP];
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t b = blockIdx.x * 4 + wave;
-    if (b >= nb) return;
-    const uint32_t s0 = bstart[b];
-    uint32_t z = 0;
-    if (s0 != ABSENT) {
-        const uint32_t e = bend[b];
-        if (e <= s0) {
-            if (lane == 0) atomicOr(err, 256u);
-        } else {
-            z = e - s0;
-        }
-    }
-    uint32_t ties = 0;
-    if (z >= 2 && z <= BUCKET_CAP) {
-        uint32_t *sv = s_v[wave];
-        if (z <= 64) ties = wave_bucket<1>(keys, vals, s0, z, kshort, sv, limit, large);
-        else if (z <= 128) ties = wave_bucket<2>(keys, vals, s0, z, kshort, sv, limit, large);
-        else ties = wave_bucket<4>(keys, vals, s0, z, kshort, sv, limit, large);
-    }
-    static_assert(BUCKET_CAP == 256, "the size classes above cover 2 .. 256");
-    if (lane == 0) {
-        tcnt[b] = ties;
-        osz[b] = z > BUCKET_CAP ? z : 0u;
-    }
 }
 
 // ---- exclusive scans over the bucket table, three columns at once:
@@ -346,23 +398,298 @@ __device__ void wave_emit(const uint64_t *__restrict__ keys, uint32_t s0, uint32
     }
 }
 
-__global__ __launch_bounds__(256) void bucket_emit_kernel(
-    const uint64_t *__restrict__ keys, const uint32_t *__restrict__ bstart,
-    const uint32_t *__restrict__ bend, const uint32_t *__restrict__ tpre, uint32_t nb,
-    int kshort, uint32_t *__restrict__ U, uint32_t ucap, uint32_t *__restrict__ err) {
-    const int wave = threadIdx.x >> 6;
-    const uint32_t b = blockIdx.x * 4 + wave;
-    if (b >= nb) return;
-    const uint32_t at = tpre[b];
-    const uint32_t next = b + 1 < nb ? tpre[b + 1] : ucap;
-    if (next == at) return;  // no tied suffix in this bucket
-    const uint32_t s0 = bstart[b];
-    if (s0 == ABSENT) return;
-    const uint32_t z = bend[b] - s0;
-    if (z < 2 || z > BUCKET_CAP) return;
-    if (z <= 64) wave_emit<1>(keys, s0, z, kshort, at, U, ucap, err);
-    else if (z <= 128) wave_emit<2>(keys, s0, z, kshort, at, U, ucap, err);
-    else wave_emit<4>(keys, s0, z, kshort, at, U, ucap, err);
+// ---- tile-wise finish: a workgroup owns the buckets that start in its tile
+// of BT_T positions; they end at most BUCKET_CAP past it unless oversized.
+constexpr uint32_t BT_T = 2048;
+constexpr uint32_t BT_WIN = BT_T + BUCKET_CAP;
+
+// The owned range [a, b) of tile t: a = first bucket start at or after t * BT_T,
+// b = first bucket start at or after (t + 1) * BT_T (or n).
+__device__ __forceinline__ void tile_range(const uint64_t *__restrict__ keys, uint32_t n,
+                                           int bshift, uint32_t nb,
+                                           const uint32_t *__restrict__ bstart,
+                                           const uint32_t *__restrict__ bend, uint32_t t,
+                                           uint32_t *a, uint32_t *b) {
+    const uint32_t t0 = t * BT_T;
+    uint32_t x = t0 < n ? t0 : n, y = t0 + BT_T < n ? t0 + BT_T : n;
+    if (x < n) {
+        const uint64_t bb = keys[x] >> bshift;
+        if (bb >= nb) x = n;  // out of range keys were flagged by the bounds pass
+        else if (bstart[bb] != x) x = bend[bb];
+    }
+    if (y < n) {
+        const uint64_t bb = keys[y] >> bshift;
+        if (bb >= nb) y = n;
+        else if (bstart[bb] != y) y = bend[bb];
+    }
+    *a = x;
+    *b = y < n ? y : n;
+}
+
+// trange[2t], trange[2t + 1] = owned range of tile t, for every tile.
+__global__ void tile_ranges_kernel(const uint64_t *__restrict__ keys, uint32_t n, int bshift,
+                                   uint32_t nb, const uint32_t *__restrict__ bstart,
+                                   const uint32_t *__restrict__ bend, uint32_t ntiles,
+                                   uint32_t *__restrict__ trange) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    uint32_t a, b;
+    tile_range(keys, n, bshift, nb, bstart, bend, t, &a, &b);
+    trange[2 * t] = a;
+    trange[2 * t + 1] = b;
+}
+
+// Loads keys [a, a + w) of the owned range into s_k and lists the bucket
+// starts (window offsets) in s_bs, ending with w; returns the bucket count.
+// Contains barriers.
+__device__ uint32_t tile_buckets(const uint64_t *__restrict__ keys, uint32_t a, uint32_t w,
+                                 int bshift, uint64_t *__restrict__ s_k,
+                                 uint16_t *__restrict__ s_bs, uint32_t *__restrict__ s_tmp) {
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < w; i += 256) s_k[i] = keys[a + i];
+    __syncthreads();
+    // each thread a contiguous run of the window, so the list keeps order
+    constexpr uint32_t PER = (BT_WIN + 255) / 256;
+    const uint32_t i0 = tid * PER;
+    uint32_t flags = 0, cnt = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t i = i0 + q;
+        if (i < w && (i == 0 || (s_k[i] >> bshift) != (s_k[i - 1] >> bshift))) {
+            flags |= 1u << q;
+            ++cnt;
+        }
+    }
+    uint32_t tot;
+    uint32_t at = block_excl_sum256(cnt, s_tmp, &tot);
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q)
+        if ((flags >> q) & 1u) s_bs[at++] = (uint16_t)(i0 + q);
+    if (tid == 0) s_bs[tot] = (uint16_t)w;
+    __syncthreads();
+    return tot;
+}
+
+// Sorts the owned buckets of each tile: groups of four buckets of at most 64
+// suffixes in registers (one per row) straight from LDS, larger ones up to
+// BUCKET_CAP one at a time from global memory; records tcnt / osz for every
+// owned bucket (both tables zeroed beforehand).
+__global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
+    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t n, int bshift, uint32_t nb,
+    const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bend,
+    const uint32_t *__restrict__ trange, int kshort,
+    uint32_t limit, uint32_t *__restrict__ large, uint32_t *__restrict__ tcnt,
+    uint32_t *__restrict__ osz, uint32_t *__restrict__ err) {
+    __shared__ uint64_t s_k[BT_WIN];
+    __shared__ uint32_t s_v[BT_WIN];
+    __shared__ uint16_t s_bs[BT_WIN + 1];
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_big[4][BUCKET_CAP];
+    const uint32_t tid = threadIdx.x;
+    const int wave = (int)(tid >> 6), lane = lane_id();
+    const uint32_t a = trange[2 * blockIdx.x], b = trange[2 * blockIdx.x + 1];
+    if (a >= b) return;
+    const uint32_t w = b - a < BT_WIN ? b - a : BT_WIN;
+    for (uint32_t i = tid; i < w; i += 256) s_v[i] = vals[a + i];
+    const uint32_t nbk = tile_buckets(keys, a, w, bshift, s_k, s_bs, s_tmp);
+    const bool composite = bshift <= 58;
+    // chunks of eight consecutive buckets per wave: two per row (32 lanes
+    // each) when all eight have at most 32 suffixes, else four per row pass
+    for (uint32_t g = (uint32_t)wave * 8; g < nbk; g += 32) {
+        uint32_t st[8], z[8], id[8];
+        bool halves = composite;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t j = g + q;
+            st[q] = 0;
+            z[q] = 0;
+            id[q] = 0;
+            if (j < nbk) {
+                st[q] = s_bs[j];
+                const uint32_t e = s_bs[j + 1];
+                id[q] = (uint32_t)(s_k[st[q]] >> bshift);
+                // true size (the last bucket of the window may be cut off)
+                z[q] = j + 1 < nbk || a + e == b ? e - st[q] : bend[id[q]] - bstart[id[q]];
+            }
+            halves = halves && z[q] <= 32;
+        }
+        uint32_t ties[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (halves) {
+            const bool hi = lane >= 32;
+            const uint32_t hl = (uint32_t)lane & 31u;
+            uint32_t sth[4], zh[4], idh[4];
+            uint64_t c[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sth[r] = hi ? st[2 * r + 1] : st[2 * r];
+                zh[r] = hi ? z[2 * r + 1] : z[2 * r];
+                idh[r] = hi ? id[2 * r + 1] : id[2 * r];
+                const uint64_t base = (uint64_t)idh[r] << bshift;
+                c[r] = hl < zh[r] ? ((s_k[sth[r] + hl] - base) << 6) | (uint64_t)hl : ~0ull;
+            }
+            wave_sort_rows<4, 32>(c, lane);
+            uint64_t k[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool ok = hl < zh[r];
+                k[r] = ok ? ((uint64_t)idh[r] << bshift) + (c[r] >> 6) : ~0ull;
+                if (ok) {
+                    keys[a + sth[r] + hl] = k[r];
+                    vals[a + sth[r] + hl] = s_v[sth[r] + (uint32_t)(c[r] & 63u)];
+                }
+            }
+            // ties inside each 32-lane segment (groups are at most 32 long,
+            // below any limit)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool ok = hl < zh[r];
+                const uint64_t kp = __shfl_up(k[r], 1, 64);
+                const uint64_t kn = __shfl_down(k[r], 1, 64);
+                const bool eq_prev = ok && hl > 0 && kp == k[r];
+                const bool eq_next = ok && hl + 1 < zh[r] && kn == k[r];
+                const bool t = ok && !short_key(k[r], kshort) && (eq_prev || eq_next);
+                const uint64_t tb = __ballot(t);
+                ties[2 * r] = (uint32_t)__popcll(tb & 0xffffffffull);
+                ties[2 * r + 1] = (uint32_t)__popcll(tb >> 32);
+            }
+            (void)limit;
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint32_t st4[4], z4[4], id4[4];
+                bool small = composite;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    st4[r] = st[4 * h + r];
+                    z4[r] = z[4 * h + r];
+                    id4[r] = id[4 * h + r];
+                    small = small && z4[r] <= 64;
+                }
+                uint32_t t4[4] = {0, 0, 0, 0};
+                if (small) {
+                    uint64_t c[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const uint64_t base = (uint64_t)id4[r] << bshift;
+                        c[r] = (uint32_t)lane < z4[r]
+                                   ? ((s_k[st4[r] + lane] - base) << 6) | (uint64_t)lane
+                                   : ~0ull;  // a real key never has all length bits set
+                    }
+                    wave_sort_rows<4, 64>(c, lane);
+                    uint64_t k[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bool ok = (uint32_t)lane < z4[r];
+                        k[r] = ok ? ((uint64_t)id4[r] << bshift) + (c[r] >> 6) : ~0ull;
+                        if (ok) {
+                            keys[a + st4[r] + lane] = k[r];
+                            vals[a + st4[r] + lane] = s_v[st4[r] + (uint32_t)(c[r] & 63u)];
+                        }
+                    }
+                    (void)rows_ties<4>(k, z4, kshort, limit, large, t4);
+                } else {
+#pragma unroll 1
+                    for (int r = 0; r < 4; ++r) {
+                        const uint32_t zz = z4[r];
+                        if (zz >= 2 && zz <= BUCKET_CAP) {
+                            uint32_t *sv = s_big[wave];
+                            const uint32_t s0 = a + st4[r];
+                            if (zz <= 64) t4[r] = wave_bucket<1>(keys, vals, s0, zz, kshort, sv, limit, large);
+                            else if (zz <= 128) t4[r] = wave_bucket<2>(keys, vals, s0, zz, kshort, sv, limit, large);
+                            else t4[r] = wave_bucket<4>(keys, vals, s0, zz, kshort, sv, limit, large);
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ties[4 * h + r] = t4[r];
+            }
+        }
+        // lane q < 8 records bucket g + q
+        uint32_t tr = 0, zr = 0, ir = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (lane == q) {
+                tr = ties[q];
+                zr = z[q];
+                ir = id[q];
+            }
+        if (lane < 8 && g + lane < nbk) {
+            tcnt[ir] = tr;
+            if (zr > BUCKET_CAP) osz[ir] = zr;
+        }
+    }
+}
+
+// Lists the tied suffixes of the owned buckets of each tile from U[tpre[b]]
+// (slot order), reading the sorted keys once more.
+__global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
+    const uint64_t *__restrict__ keys, uint32_t n, int bshift,
+    const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bend,
+    const uint32_t *__restrict__ trange, const uint32_t *__restrict__ tpre, uint32_t nb,
+    int kshort, uint32_t *__restrict__ U,
+    uint32_t ucap, uint32_t *__restrict__ err) {
+    __shared__ uint64_t s_k[BT_WIN];
+    __shared__ uint16_t s_bs[BT_WIN + 1];
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t tid = threadIdx.x;
+    const int wave = (int)(tid >> 6), lane = lane_id();
+    const uint32_t a = trange[2 * blockIdx.x], b = trange[2 * blockIdx.x + 1];
+    if (a >= b) return;
+    const uint32_t w = b - a < BT_WIN ? b - a : BT_WIN;
+    const uint32_t nbk = tile_buckets(keys, a, w, bshift, s_k, s_bs, s_tmp);
+    for (uint32_t g = (uint32_t)wave * 4; g < nbk; g += 16) {
+        uint32_t st[4], z[4], at[4];
+        bool small = true, any = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t j = g + r;
+            st[r] = 0;
+            z[r] = 0;
+            at[r] = 0;
+            if (j < nbk) {
+                st[r] = s_bs[j];
+                const uint32_t e = s_bs[j + 1];
+                const uint32_t id = (uint32_t)(s_k[st[r]] >> bshift);
+                const uint32_t zz = j + 1 < nbk || a + e == b ? e - st[r] : bend[id] - bstart[id];
+                at[r] = tpre[id];
+                const uint32_t next = id + 1 < nb ? tpre[id + 1] : ucap;
+                if (next != at[r] && zz >= 2 && zz <= BUCKET_CAP) z[r] = zz;
+            }
+            small = small && z[r] <= 64;
+            any = any || z[r] > 0;
+        }
+        if (!any) continue;
+        if (small) {
+            uint64_t k[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) k[r] = (uint32_t)lane < z[r] ? s_k[st[r] + lane] : ~0ull;
+            uint32_t cnt[4];
+            uint32_t dummy = 0;
+            const uint32_t rows = rows_ties<4>(k, z, kshort, 0xffffffffu, &dummy, cnt);
+            const uint64_t ltm = lanemask_lt();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (at[r] + cnt[r] > ucap) {
+                    if (lane == 0) atomicOr(err, 512u);
+                    continue;
+                }
+                const bool t = (rows >> r) & 1u;
+                const uint64_t tb = __ballot(t);
+                if (t) U[at[r] + (uint32_t)__popcll(tb & ltm)] = a + st[r] + (uint32_t)lane;
+            }
+        } else {
+#pragma unroll 1
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t zz = z[r];
+                if (zz == 0) continue;
+                if (zz <= 64) wave_emit<1>(keys, a + st[r], zz, kshort, at[r], U, ucap, err);
+                else if (zz <= 128) wave_emit<2>(keys, a + st[r], zz, kshort, at[r], U, ucap, err);
+                else wave_emit<4>(keys, a + st[r], zz, kshort, at[r], U, ucap, err);
+            }
+        }
+    }
 }
 
 // Gathered index j lies in the oversized bucket olist[q] with
@@ -458,27 +785,37 @@ hipError_t launch_bucket_bounds(const uint64_t *keys, uint32_t n, int bshift, ui
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, const uint32_t *bstart,
-                              const uint32_t *bend, uint32_t nb, int kshort, uint32_t limit,
+hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, uint32_t n, const uint32_t *bstart,
+                              const uint32_t *bend, uint32_t *trange, uint32_t nb, int bshift,
+                              int kshort, uint32_t limit,
                               uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint32_t *part,
                               uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *err,
                               hipStream_t s) {
     const uint32_t ntiles = (uint32_t)div_up(nb, BT_TILE);
     if (ntiles > 4 * 1024) return hipErrorInvalidValue;
-    bucket_sort_kernel<<<(unsigned)div_up(nb, 4), 256, 0, s>>>(keys, vals, bstart, bend, nb,
-                                                               kshort, limit, large, tcnt, osz,
-                                                               err);
+    fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(tcnt, nb, 0u);
+    fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(osz, nb, 0u);
+    const uint32_t nt = (uint32_t)div_up(n, BT_T);
+    if (nt > 0) {
+        tile_ranges_kernel<<<(unsigned)div_up(nt, 256), 256, 0, s>>>(keys, n, bshift, nb, bstart,
+                                                                     bend, nt, trange);
+        bucket_tile_sort_kernel<<<nt, 256, 0, s>>>(keys, vals, n, bshift, nb, bstart, bend, trange,
+                                                   kshort, limit, large, tcnt, osz, err);
+    }
     bucket_scan_up_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part);
     bucket_scan_top_kernel<<<1, 1024, 0, s>>>(part, ntiles, res);
     bucket_scan_down_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part, res, olist, ooff);
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_emit(const uint64_t *keys, const uint32_t *bstart, const uint32_t *bend,
-                              const uint32_t *tpre, uint32_t nb, int kshort, uint32_t *U,
-                              uint32_t ucap, uint32_t *err, hipStream_t s) {
-    bucket_emit_kernel<<<(unsigned)div_up(nb, 4), 256, 0, s>>>(keys, bstart, bend, tpre, nb,
-                                                               kshort, U, ucap, err);
+hipError_t launch_bucket_emit(const uint64_t *keys, uint32_t n, int bshift,
+                              const uint32_t *bstart, const uint32_t *bend,
+                              const uint32_t *trange, const uint32_t *tpre,
+                              uint32_t nb, int kshort, uint32_t *U, uint32_t ucap, uint32_t *err,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    bucket_tile_emit_kernel<<<(unsigned)div_up(n, BT_T), 256, 0, s>>>(
+        keys, n, bshift, bstart, bend, trange, tpre, nb, kshort, U, ucap, err);
     return hipGetLastError();
 }
 
