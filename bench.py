@@ -22,7 +22,7 @@ if ROOT not in sys.path:
 
 METRIC = "input bases indexed/sec (incremental BWT) + HBM GB/s fraction; p99 append latency"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-RANKS_BYTES_PER_STEP = 64 + 8 + 0.25   # one index record, one g write, one 2-bit symbol
+RANKS_BYTES_PER_STEP = 64 + 8 + 4 + 0.25   # one index record, key and value writes, one 2-bit symbol
 RADIX_BYTES_PER_KEY = 24               # read and write a 64-bit key and a 32-bit value
 INSERT_BYTES_PER_RECORD = 64           # each index record read (old) or written (new)
 INSERT_BYTES_PER_NEW = 9               # one B_int byte and one 64-bit g_sa per new symbol

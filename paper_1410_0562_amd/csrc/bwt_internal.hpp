@@ -196,6 +196,9 @@ hipError_t launch_refine(const uint8_t *reads, const uint64_t *off, const uint32
                          hipStream_t s);
 // B_int as ASCII from sorted values, and the plain suffix array
 hipError_t launch_vals_to_ascii(const uint32_t *sa, uint32_t n, uint8_t *bint, hipStream_t s);
+// g in text order back from sorted first keys: g[vals[i] & POS_MASK] = keys[i] >> gshift
+hipError_t launch_scatter_g(const uint64_t *keys, const uint32_t *vals, uint32_t n, int gshift,
+                            uint64_t *g, hipStream_t s);
 hipError_t launch_sa_strip(const uint32_t *sa, uint32_t n, uint32_t *out, hipStream_t s);
 
 // ComputeRanks (k_ranks.hip).  Reads longer than seg_len symbols (0: never)
@@ -211,10 +214,20 @@ struct RankSegments {
     uint32_t *fb_list = nullptr;
     uint32_t *counters = nullptr;
 };
+// Key mode (kk != null): instead of g, the walks write the first sort key of
+// every block position, g << gshift | its next kfirst symbols << 5 | their
+// count (what launch_block_keys builds), and its sort value (see below).
+struct RankKeys {
+    uint64_t *keys;
+    uint32_t *vals;
+    int gshift;
+    int kfirst;
+};
 hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                                 uint32_t m_blk, uint32_t n_blk, const Rec *recs,
                                 const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
-                                const RankSegments &sg, uint32_t *err, hipStream_t s);
+                                const RankKeys *kk, const RankSegments &sg, uint32_t *err,
+                                hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched form: one block holds reads of several independent sets (units).
@@ -238,7 +251,8 @@ struct RankUnit {
 hipError_t launch_compute_ranks_units(const uint8_t *reads, const uint64_t *off,
                                       const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
                                       const RankUnit *units, uint32_t nunits, uint64_t *g,
-                                      const RankSegments &sg, uint32_t *err, hipStream_t s);
+                                      const RankKeys *kk, const RankSegments &sg, uint32_t *err,
+                                      hipStream_t s);
 
 struct InsertUnit {
     const Rec *orecs;

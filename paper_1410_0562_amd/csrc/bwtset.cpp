@@ -548,22 +548,37 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *ks, uint32_t *vs, uint32_
     return BWT_OK;
 }
 
+// Layout of a block's first sort key for gbits bits of g (see bwt_internal.hpp).
+struct KeyLayout {
+    int key_bits, kfirst, gshift, sort_bits;
+};
+
+KeyLayout key_layout(const bwt_set *h, int gbits) {
+    KeyLayout L;
+    L.key_bits = h->key_bits < gbits + 1 ? gbits + 1 : h->key_bits;
+    if (L.key_bits > 64) L.key_bits = 64;
+    L.kfirst = first_key_syms(gbits, L.key_bits);
+    L.gshift = gbits ? L.key_bits - gbits : 64;
+    L.sort_bits = gbits ? L.key_bits : 2 * L.kfirst + KEY_LEN_BITS;
+    return L;
+}
+
 // Suffix array of one block (after block_prep).  reads/off: device; off
 // points at the block's first read (m_blk + 1 entries).  g (text order, may
 // be null when gbits == 0) leads the first sort key.  On return *sa_out holds
 // the suffix array (values carry the preceding symbol in bits 29..31) and
 // *gkeys_out / *gshift_out give g_sa per SA slot (g_sa = key >> gshift).
 int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *off,
-               uint32_t m_blk, uint32_t n_blk, uint64_t maxlen, const uint64_t *g, int gbits,
-               uint32_t **sa_out, const uint64_t **gkeys_out, int *gshift_out) {
+               uint32_t m_blk, uint32_t n_blk, uint64_t maxlen, uint64_t *g, int gbits,
+               bool keys_ready, uint32_t **sa_out, const uint64_t **gkeys_out, int *gshift_out) {
     (void)m_blk;
     Workspace &w = h->ws;
     Scope sc(h, s, BWT_STAGE_SORT);
-    int key_bits = h->key_bits < gbits + 1 ? gbits + 1 : h->key_bits;
-    if (key_bits > 64) key_bits = 64;
-    int kfirst = first_key_syms(gbits, key_bits);
-    int gshift = gbits ? key_bits - gbits : 64;
-    int sort_bits = gbits ? key_bits : 2 * kfirst + KEY_LEN_BITS;
+    const KeyLayout KL = key_layout(h, gbits);
+    int key_bits = KL.key_bits;
+    int kfirst = KL.kfirst;
+    int gshift = KL.gshift;
+    const int sort_bits = KL.sort_bits;
     uint32_t *hist = w.misc + MISC_HIST;
     // With the bucket finish the radix passes cover only the top digits: B
     // bucket bits, enough for about BUCKET_TARGET suffixes per bucket.
@@ -578,15 +593,16 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
         shift0 = sort_bits - 8 * ((B + 7) / 8);
         if (shift0 < 0) shift0 = 0;
     }
-    HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
-    {
+    if (!keys_ready) {
+        HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
         Scope sk(h, s, SPAN_KEYS);
         HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
                                     gshift, kfirst, shift0, w.kA, w.v[0], hist, s));
     }
     uint64_t *ks;
     uint32_t *vs;
-    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, sort_bits, true, &ks, &vs, shift0);
+    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, sort_bits, !keys_ready, &ks, &vs,
+                        shift0);
     if (rc) return rc;
     uint32_t *sa = vs;
     *sa_out = sa;
@@ -625,11 +641,14 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     // doubling round needs the tied suffixes to share at least one symbol).
     // The doubling sorts reuse both key buffers, so g_sa moves to w.g first.
     h->timer.acc.fallback_blocks += 1;
+    const int gshift_first = gshift;
     if (key_bits < 64 || kfirst < 1) {
         key_bits = 64;
         kfirst = first_key_syms(gbits, key_bits);
         gshift = gbits ? key_bits - gbits : 64;
         if (kfirst < 1) return fail(h, BWT_EHIP);
+        // keys built by ComputeRanks left no g array: take g back from the keys
+        if (keys_ready && gbits) HIPCHK(h, launch_scatter_g(ks, vs, n_blk, gshift_first, g, s));
         HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
         HIPCHK(h, launch_block_keys(reads, off, w.soff, w.tile_first, n_blk, gbits ? g : nullptr,
                                     gshift, kfirst, 0, w.kA, w.v[0], hist, s));
@@ -865,13 +884,16 @@ int run_block(bwt_set *L, hipStream_t s, const DevBlock &B, const std::vector<Ho
     if (gbits > 0) {
         Scope sc(L, s, BWT_STAGE_RANKS);
         Scope sk(L, s, SPAN_RANKS_K, n_blk - m_blk);
+        const KeyLayout KL = key_layout(L, gbits);
+        const RankKeys kk{w.kA, w.v[0], KL.gshift, KL.kfirst};
         HIPCHK(L, launch_compute_ranks_units(in.reads, off, w.soff, m_blk, n_blk, rdev, nu, w.g,
-                                             rank_segments(L), w.misc + MISC_ERR, s));
+                                             &kk, rank_segments(L), w.misc + MISC_ERR, s));
     }
     uint32_t *sa = nullptr;
     const uint64_t *gkeys = nullptr;
     int gshift = 64;
-    if ((rc = block_sort(L, s, in.reads, off, m_blk, n_blk, in.maxlen, w.g, gbits, &sa, &gkeys,
+    if ((rc = block_sort(L, s, in.reads, off, m_blk, n_blk, in.maxlen, w.g, gbits, gbits > 0, &sa,
+                         &gkeys,
                          &gshift)))
         return rc;
     {
@@ -1412,14 +1434,17 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
         if (gbits > 0) {
             Scope sc(h, s, BWT_STAGE_RANKS);
             Scope sk(h, s, SPAN_RANKS_K, n_blk - m_blk);
+            const KeyLayout KL = key_layout(h, gbits);
+            const RankKeys kk{w.kA, w.v[0], KL.gshift, KL.kfirst};
             HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
-                                           S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g,
+                                           S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
                                            rank_segments(h), w.misc + MISC_ERR, s));
         }
         uint32_t *sa = nullptr;
         const uint64_t *gkeys = nullptr;
         int gshift = 64;
-        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, &sa, &gkeys,
+        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, gbits > 0, &sa,
+                             &gkeys,
                              &gshift)))
             return rc;
         const int dst = other[b & 1];
@@ -1728,7 +1753,7 @@ int bwt_set_block_sort(bwt_set_t h, const uint8_t *reads, const uint64_t *offset
     int gshift = 64;
     const uint32_t n_blk = (uint32_t)P.total_suffixes;
     if ((rc = block_prep(h, s, P.off, (uint32_t)m, n_blk))) return rc;
-    if ((rc = block_sort(h, s, P.reads, P.off, (uint32_t)m, n_blk, P.maxlen, nullptr, 0, &sa,
+    if ((rc = block_sort(h, s, P.reads, P.off, (uint32_t)m, n_blk, P.maxlen, nullptr, 0, false, &sa,
                          &gkeys, &gshift)))
         return rc;
     HIPCHK(h, launch_vals_to_ascii(sa, n_blk, bint_out, s));
@@ -1757,8 +1782,8 @@ int bwt_set_compute_ranks(bwt_set_t h, const uint8_t *reads, const uint64_t *off
         Scope sk(h, s, SPAN_RANKS_K, P.total_suffixes - m);
         HIPCHK(h, launch_compute_ranks(P.reads, P.off, h->ws.soff, (uint32_t)m,
                                        (uint32_t)P.total_suffixes, B.recs, B.sbc, B.meta,
-                                       h->n >= (1ull << SB_SHIFT) ? 1 : 0, g_out, rank_segments(h),
-                                       h->ws.misc + MISC_ERR, s));
+                                       h->n >= (1ull << SB_SHIFT) ? 1 : 0, g_out, nullptr,
+                                       rank_segments(h), h->ws.misc + MISC_ERR, s));
     }
     HIPCHK(h, hipStreamSynchronize(s));
     if (h->timer.on) timer_collect(h);

@@ -59,6 +59,44 @@ struct GBuf {
     }
 };
 
+// The same for 4-byte values: 16 of them make one aligned 64-byte chunk.
+struct VBuf {
+    uint32_t r[16];  // r[0] = lowest index held
+    uint32_t cnt;
+    __device__ void push(uint32_t v) {
+#pragma unroll
+        for (int q = 15; q > 0; --q) r[q] = r[q - 1];
+        r[0] = v;
+        cnt = cnt < 16 ? cnt + 1 : 16;
+    }
+    __device__ void flush(uint32_t *__restrict__ p, uint64_t idx, bool vec) {
+        if (cnt == 16 && vec) {
+            uint4 *q = reinterpret_cast<uint4 *>(p + idx);
+            q[0] = make_uint4(r[0], r[1], r[2], r[3]);
+            q[1] = make_uint4(r[4], r[5], r[6], r[7]);
+            q[2] = make_uint4(r[8], r[9], r[10], r[11]);
+            q[3] = make_uint4(r[12], r[13], r[14], r[15]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if ((uint32_t)q < cnt) p[idx + q] = r[q];
+        }
+        cnt = 0;
+    }
+};
+
+// Where the walks write.  g mode (keys == nullptr): g[p] for every block
+// position p.  Key mode: the first sort key of p, g << gshift | the next
+// kfirst symbols << 5 | their count (the key launch_block_keys builds), and
+// its sort value p | (previous symbol, 4 at a read start) << 29.
+struct Out {
+    uint64_t *g;
+    uint64_t *keys;
+    uint32_t *vals;
+    int gshift, kfirst;
+    bool vec, vvec;  // 64-byte aligned arrays: whole chunks may be written
+};
+
 // The 8-byte word of packed input holding the current symbol, reloaded only
 // when the walk crosses into the previous word.
 struct SymReader {
@@ -133,35 +171,57 @@ struct UnitIndex {
     }
 };
 
-// Whole-read walk from the terminator: writes g[gb + k] for k = len .. 0.
+// Whole-read walk from the terminator: writes the results of positions
+// gb + len .. gb (terminator first).  In key mode the walk keeps the kfirst
+// symbols after the current position in `win` (first symbol most
+// significant), and writes each position's value one step late, once the
+// symbol before it has been read.
+template <bool KEYS>
 __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t len, uint64_t gb,
-                          uint64_t *__restrict__ g, bool vec) {
+                          const Out &o) {
     GBuf buf;
     buf.cnt = 0;
+    VBuf vb;
+    vb.cnt = 0;
+    uint64_t *dst = KEYS ? o.keys : o.g;
+    uint64_t win = 0;
+    const int top = 2 * (o.kfirst - 1);
     uint64_t i = W.lf.m_ext;
     uint32_t k = len;
-    buf.push(i + W.goff);
-    if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
+    buf.push(KEYS ? (i + W.goff) << o.gshift : i + W.goff);  // terminator: no symbols
+    if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
     while (k > 0) {
         --k;
-        i = W.lf.step(W.recs, W.sbc, i, sym.get(s0 + k));
-        buf.push(i + W.goff);
-        if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
+        const int c = sym.get(s0 + k);
+        i = W.lf.step(W.recs, W.sbc, i, c);
+        if constexpr (KEYS) {
+            vb.push((uint32_t)(gb + k + 1) | ((uint32_t)c << POS_BITS));
+            if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
+            if (o.kfirst > 0) win = (win >> 2) | ((uint64_t)c << top);
+            const uint32_t t = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
+            buf.push(((i + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | t);
+        } else {
+            buf.push(i + W.goff);
+        }
+        if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
     }
-    buf.flush(g, gb, false);  // what is left below the last aligned index
+    buf.flush(dst, gb, false);  // what is left below the last aligned index
+    if constexpr (KEYS) {
+        vb.push((uint32_t)gb | (4u << POS_BITS));  // the read's first position
+        vb.flush(o.vals, gb, false);
+    }
 }
 
 // One lane per read.  Reads longer than `seg` symbols (seg > 0) are cut into
 // segments that are queued for rank_segments_kernel instead.
-template <class Src>
+template <class Src, bool KEYS>
 __global__ __launch_bounds__(256) void compute_ranks_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, uint64_t *__restrict__ g,
-    uint32_t seg, uint64_t *__restrict__ seg_list, uint32_t *__restrict__ seg_count,
-    uint32_t seg_cap, uint32_t *__restrict__ err) {
+    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, Out o, uint32_t seg,
+    uint64_t *__restrict__ seg_list, uint32_t *__restrict__ seg_count, uint32_t seg_cap,
+    uint32_t *__restrict__ err) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m_blk) return;
-    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;  // uniform
     const uint64_t s0 = off[j];
     const uint32_t len = (uint32_t)(off[j + 1] - s0);
     if (seg > 0 && len > seg) {
@@ -175,21 +235,20 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
         return;
     }
     SymReader sym{reads, 0, 0};
-    walk_read(src.at(j), sym, s0, len, soff[j], g, vec);
+    walk_read<KEYS>(src.at(j), sym, s0, len, soff[j], o);
 }
 
 // One lane per queued segment (j, s) of a long read: symbols [a, b) with
 // a = s * seg, b = min(len, a + seg); the walk starts at e = min(len, b + ov).
-template <class Src>
+template <class Src, bool KEYS>
 __global__ __launch_bounds__(256) void rank_segments_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, uint64_t *__restrict__ g,
-    uint32_t seg, uint32_t ov, const uint64_t *__restrict__ seg_list,
-    const uint32_t *__restrict__ seg_count, uint32_t *__restrict__ fb_flag,
-    uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, uint32_t *__restrict__ err) {
+    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, Out o, uint32_t seg, uint32_t ov,
+    const uint64_t *__restrict__ seg_list, const uint32_t *__restrict__ seg_count,
+    uint32_t *__restrict__ fb_flag, uint32_t *__restrict__ fb_list,
+    uint32_t *__restrict__ fb_count, uint32_t *__restrict__ err) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *seg_count) return;
-    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
     const uint64_t e_js = seg_list[t];
     const uint32_t j = (uint32_t)(e_js >> 32), s = (uint32_t)e_js;
     if (j >= m_blk) {  // only if the queue overflowed (already flagged)
@@ -208,15 +267,28 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
     const uint32_t a = s * seg;
     const uint32_t b = a + seg < len ? a + seg : len;
     const uint32_t e = b + ov < len ? b + ov : len;
+    uint64_t *dst = KEYS ? o.keys : o.g;
     SymReader sym{reads, 0, 0};
     GBuf buf;
     buf.cnt = 0;
+    VBuf vb;
+    vb.cnt = 0;
+    uint64_t win = 0;
+    const int top = 2 * (o.kfirst - 1);
+    if (KEYS && o.kfirst > 0) {
+        // the symbols a key of [a, b) needs beyond the walk's start
+        const uint32_t need = b + (uint32_t)o.kfirst < len ? b + (uint32_t)o.kfirst : len;
+        for (uint32_t q = need; q > e;) {
+            --q;
+            win = (win >> 2) | ((uint64_t)sym.get(s0 + q) << top);
+        }
+    }
     uint64_t lo, hi;
     if (e == len) {
         lo = hi = lf.m_ext;  // exact start at the terminator suffix
         if (b == len) {
-            buf.push(lo + W.goff);
-            if (((gb + len) & 7) == 0) buf.flush(g, gb + len, vec);
+            buf.push(KEYS ? (lo + W.goff) << o.gshift : lo + W.goff);
+            if (((gb + len) & 7) == 0) buf.flush(dst, gb + len, o.vec);
         }
     } else {
         lo = 0;             // the empty prefix: every row of B_ext
@@ -229,33 +301,47 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
         const uint64_t nlo = lf.step(W.recs, W.sbc, lo, c);
         hi = (lo == hi) ? nlo : lf.step(W.recs, W.sbc, hi, c);
         lo = nlo;
+        if (KEYS && o.kfirst > 0) win = (win >> 2) | ((uint64_t)c << top);
         if (k < b) {
             if (lo != hi) {
                 // a repeat longer than ov: the whole read is walked exactly
                 if (atomicExch(&fb_flag[j], 1u) == 0u) fb_list[atomicAdd(fb_count, 1u)] = j;
                 return;
             }
-            buf.push(lo + W.goff);
-            if (((gb + k) & 7) == 0) buf.flush(g, gb + k, vec);
+            if constexpr (KEYS) {
+                if (k + 1 < b || k + 1 == len) {
+                    vb.push((uint32_t)(gb + k + 1) | ((uint32_t)c << POS_BITS));
+                    if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
+                }
+                const uint32_t tt = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
+                buf.push(((lo + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | tt);
+            } else {
+                buf.push(lo + W.goff);
+            }
+            if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
         }
     }
-    buf.flush(g, gb + a, false);
+    buf.flush(dst, gb + a, false);
+    if constexpr (KEYS) {
+        const uint32_t prev = a > 0 ? (uint32_t)sym.get(s0 + a - 1) : 4u;
+        vb.push((uint32_t)(gb + a) | (prev << POS_BITS));
+        vb.flush(o.vals, gb + a, false);
+    }
 }
 
 // Whole-read walks for the reads whose segments could not close their
 // interval within the overlap.
-template <class Src>
+template <class Src, bool KEYS>
 __global__ __launch_bounds__(256) void rank_fallback_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, Src src, uint64_t *__restrict__ g,
-    const uint32_t *__restrict__ fb_list, const uint32_t *__restrict__ fb_count) {
+    const uint32_t *__restrict__ soff, Src src, Out o, const uint32_t *__restrict__ fb_list,
+    const uint32_t *__restrict__ fb_count) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *fb_count) return;
-    const bool vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
     const uint32_t j = fb_list[t];
     const uint64_t s0 = off[j];
     SymReader sym{reads, 0, 0};
-    walk_read(src.at(j), sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], g, vec);
+    walk_read<KEYS>(src.at(j), sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], o);
 }
 
 __global__ void zero_kernel(uint32_t *p, uint32_t n) {
@@ -263,11 +349,10 @@ __global__ void zero_kernel(uint32_t *p, uint32_t n) {
     if (i < n) p[i] = 0;
 }
 
-template <class Src>
+template <class Src, bool KEYS>
 hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
-                         uint32_t m_blk, uint32_t n_blk, Src src, uint64_t *g,
+                         uint32_t m_blk, uint32_t n_blk, Src src, const Out &o,
                          const RankSegments &sg, uint32_t *err, hipStream_t s) {
-    if (m_blk == 0) return hipSuccess;
     uint32_t seg = sg.seg_len;
     uint32_t cap = 0;
     if (seg > 0) {
@@ -278,16 +363,37 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
         zero_kernel<<<1, 64, 0, s>>>(sg.counters, 2);
         zero_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(sg.fb_flag, m_blk);
     }
-    compute_ranks_kernel<Src><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
-        reads, off, soff, m_blk, src, g, seg, sg.seg_list, sg.counters, cap, err);
+    compute_ranks_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
+        reads, off, soff, m_blk, src, o, seg, sg.seg_list, sg.counters, cap, err);
     if (seg > 0) {
-        rank_segments_kernel<Src><<<(unsigned)div_up(cap, 256), 256, 0, s>>>(
-            reads, off, soff, m_blk, src, g, seg, sg.overlap, sg.seg_list, sg.counters,
-            sg.fb_flag, sg.fb_list, sg.counters + 1, err);
-        rank_fallback_kernel<Src><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
-            reads, off, soff, src, g, sg.fb_list, sg.counters + 1);
+        rank_segments_kernel<Src, KEYS><<<(unsigned)div_up(cap, 256), 256, 0, s>>>(
+            reads, off, soff, m_blk, src, o, seg, sg.overlap, sg.seg_list, sg.counters, sg.fb_flag,
+            sg.fb_list, sg.counters + 1, err);
+        rank_fallback_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
+            reads, off, soff, src, o, sg.fb_list, sg.counters + 1);
     }
     return hipGetLastError();
+}
+
+template <class Src>
+hipError_t compute_ranks_any(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                             uint32_t m_blk, uint32_t n_blk, Src src, uint64_t *g,
+                             const RankKeys *kk, const RankSegments &sg, uint32_t *err,
+                             hipStream_t s) {
+    if (m_blk == 0) return hipSuccess;
+    Out o{};
+    if (kk) {
+        o.keys = kk->keys;
+        o.vals = kk->vals;
+        o.gshift = kk->gshift;
+        o.kfirst = kk->kfirst;
+        o.vec = (reinterpret_cast<uintptr_t>(o.keys) & 63) == 0;
+        o.vvec = (reinterpret_cast<uintptr_t>(o.vals) & 63) == 0;
+        return compute_ranks<Src, true>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s);
+    }
+    o.g = g;
+    o.vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
+    return compute_ranks<Src, false>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s);
 }
 
 }  // namespace
@@ -295,17 +401,20 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
 hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                                 uint32_t m_blk, uint32_t n_blk, const Rec *recs,
                                 const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
-                                const RankSegments &sg, uint32_t *err, hipStream_t s) {
-    return compute_ranks(reads, off, soff, m_blk, n_blk, OneIndex{recs, sbc, meta, big}, g, sg,
-                         err, s);
+                                const RankKeys *kk, const RankSegments &sg, uint32_t *err,
+                                hipStream_t s) {
+    return compute_ranks_any(reads, off, soff, m_blk, n_blk, OneIndex{recs, sbc, meta, big}, g, kk,
+                             sg, err, s);
 }
 
 hipError_t launch_compute_ranks_units(const uint8_t *reads, const uint64_t *off,
                                       const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
                                       const RankUnit *units, uint32_t nunits, uint64_t *g,
-                                      const RankSegments &sg, uint32_t *err, hipStream_t s) {
+                                      const RankKeys *kk, const RankSegments &sg, uint32_t *err,
+                                      hipStream_t s) {
     if (nunits == 0) return hipSuccess;
-    return compute_ranks(reads, off, soff, m_blk, n_blk, UnitIndex{units, nunits}, g, sg, err, s);
+    return compute_ranks_any(reads, off, soff, m_blk, n_blk, UnitIndex{units, nunits}, g, kk, sg,
+                             err, s);
 }
 
 }  // namespace bwt

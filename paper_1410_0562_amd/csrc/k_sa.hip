@@ -446,6 +446,13 @@ __global__ void vals_to_ascii_kernel(const uint32_t *__restrict__ sa, uint32_t n
     bint[i] = (uint8_t)ascii[sa[i] >> POS_BITS];
 }
 
+__global__ void scatter_g_kernel(const uint64_t *__restrict__ keys,
+                                 const uint32_t *__restrict__ vals, uint32_t n, int gshift,
+                                 uint64_t *__restrict__ g) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) g[vals[i] & POS_MASK] = keys[i] >> gshift;
+}
+
 __global__ void sa_strip_kernel(const uint32_t *__restrict__ sa, uint32_t n,
                                 uint32_t *__restrict__ out) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -512,6 +519,13 @@ hipError_t launch_refine(const uint8_t *reads, const uint64_t *off, const uint32
 
 hipError_t launch_vals_to_ascii(const uint32_t *sa, uint32_t n, uint8_t *bint, hipStream_t s) {
     vals_to_ascii_kernel<<<grid_for(n, 256), 256, 0, s>>>(sa, n, bint);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_g(const uint64_t *keys, const uint32_t *vals, uint32_t n, int gshift,
+                            uint64_t *g, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    scatter_g_kernel<<<grid_for(n, 256), 256, 0, s>>>(keys, vals, n, gshift, g);
     return hipGetLastError();
 }
 
