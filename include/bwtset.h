@@ -152,7 +152,8 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *   BWT_PARAM_SORT_BUCKETS: 1 (default) = the first suffix sort runs radix
  *     passes on the top 8-24 bits of the key only (about 32 suffixes per
  *     bucket of equal top bits) and one wavefront finishes each bucket in
- *     registers; 0 = radix passes over the whole key. */
+ *     registers (blocks of 2^20 suffixes or more); 0 = radix passes over the
+ *     whole key. */
 enum {
     BWT_PARAM_KEY_BITS = 1,
     BWT_PARAM_RADIX_TILE = 2,

@@ -81,6 +81,7 @@ constexpr uint32_t BK_PART = 3 * 4096 + 16;  // tile partials of the bucket scan
 constexpr uint32_t MIN_SEG_LEN = 256;
 constexpr int MAX_LANES = 4;
 constexpr uint32_t BUCKET_TARGET = 32;  // suffixes per bucket the bucket count aims at
+constexpr uint32_t BUCKET_MIN_BLOCK = 1u << 20;  // smallest block that takes the bucket finish
 constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
 constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
 constexpr int MISC_WORDS = MISC_HIST + HIST_WORDS + 64;
@@ -582,7 +583,8 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     uint32_t *hist = w.misc + MISC_HIST;
     // With the bucket finish the radix passes cover only the top digits: B
     // bucket bits, enough for about BUCKET_TARGET suffixes per bucket.
-    const bool buckets = h->sort_buckets && n_blk > 1;
+    // (small blocks are latency-bound: fewer launches and host reads win there)
+    const bool buckets = h->sort_buckets && n_blk >= BUCKET_MIN_BLOCK;
     int B = 0, shift0 = 0;
     if (buckets) {
         B = 1;

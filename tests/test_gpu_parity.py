@@ -359,19 +359,22 @@ def test_identical_long_reads(B, oracle_mod):
 
 
 @pytest.mark.parametrize("key_bits", [16, 24, 40, 48, 56, 64])
-def test_key_width_does_not_change_the_result(B, oracle_mod, key_bits):
+@pytest.mark.parametrize("block", [400_000, 1_100_000])
+def test_key_width_does_not_change_the_result(B, oracle_mod, key_bits, block):
     # the first sort key holds g and as many symbols as fit; narrower keys
-    # leave more ties to the LDS refinement (or, for huge groups, doubling)
+    # leave more ties to the LDS refinement (or, for huge groups, doubling);
+    # blocks of 2^20 suffixes and more take the bucket finish
     packed, offs = synth.short_reads(m=30_000, length=100, ref_len=600_000, seed=46)
     c1, o1 = _oracle_inputs(oracle_mod, packed, offs)
     want = oracle_mod.bwt_of_codes(c1, o1)
-    with B.BwtSet(block_size=400_000) as idx:
+    with B.BwtSet(block_size=block) as idx:
         idx.set_key_bits(key_bits)
         idx.enable_timing(True)
         idx.append(packed, offs)
         assert idx.export() == want
         st = idx.stats()
-    assert st["blocks"] >= 7
+    assert st["blocks"] >= 3
+    assert (st["bucket_ms"] > 0) == (block >= (1 << 20))
 
 
 def test_key_width_with_large_groups(B, oracle_mod):
@@ -458,8 +461,8 @@ def test_sort_modes_agree(B, torch_dev, oracle_mod, buckets):
     torch = torch_dev
     cases = [
         synth.short_reads(m=30_000, length=100, ref_len=300_000, seed=51),   # 10x, $-pile of 30k
-        synth.random_reads(52, 6000, 0, 200),                                # ragged, empty reads
-        synth.random_reads(53, 3000, 0, 50, alphabet=2),                     # few distinct keys
+        synth.random_reads(52, 12_000, 0, 200),                              # ragged, empty reads
+        synth.random_reads(53, 60_000, 0, 50, alphabet=2),                   # few distinct keys
         synth.random_reads(54, 40, 0, 6),                                    # tiny block
     ]
     for k, (packed, offs) in enumerate(cases):
@@ -473,7 +476,7 @@ def test_sort_modes_agree(B, torch_dev, oracle_mod, buckets):
             idx.enable_timing(True)
             idx.block_sort(packed, offs, sa, bint)
             assert np.array_equal(sa.cpu().numpy().astype(np.uint64), sa_want), k
-            assert (idx.stats()["bucket_ms"] > 0) == bool(buckets and n > 1), k
+            assert (idx.stats()["bucket_ms"] > 0) == bool(buckets and n >= (1 << 20)), k
         with B.BwtSet(block_size=max(64, n // 5)) as idx:
             idx.set_param(B.BWT_PARAM_SORT_BUCKETS, buckets)
             idx.append(packed, offs)
