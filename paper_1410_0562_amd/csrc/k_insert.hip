@@ -245,8 +245,19 @@ __global__ void ins_meta_units_kernel(const InsertUnit *__restrict__ units, uint
                  u.nsbc, u.nmeta);
 }
 
-// Output tile t of one unit (256 threads).
-__device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, uint32_t *__restrict__ err) {
+// LDS of one wave's tile.
+struct InsLds {
+    uint32_t bm[INS_TILE_SYMS / 32];           // bit per output row: a new symbol goes there
+    uint8_t nsym[INS_TILE_SYMS];                // codes of the tile's new symbols, in order
+    uint64_t old[(INS_TILE_RECS + 1) * 6];      // planes of the old records the tile reads
+    uint64_t base[4];                           // counts of A, C, G, T before the tile
+};
+
+// Output tile t of one unit, by one wave: lane l builds rows 32l .. 32l + 31
+// of the tile's 16 records (one 32-bit word of each bit plane) and writes
+// 4 of the 256 words.
+__device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds &L,
+                                            uint32_t *__restrict__ err) {
     const Rec *__restrict__ orecs = J.orecs;
     const uint64_t *__restrict__ osbc = J.osbc;
     const uint64_t *__restrict__ gkeys = J.gkeys;
@@ -259,17 +270,8 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, uint32_
     const uint64_t n_out = J.n_ext + J.n_new;
     const uint64_t nrec_out = records_for(n_out);
     const uint64_t nrec_in = records_for(J.n_ext);
-    __shared__ uint32_t s_bm[INS_TILE_SYMS / 32];
-    __shared__ uint8_t s_new[INS_TILE_SYMS];
-    __shared__ uint64_t s_old[(INS_TILE_RECS + 1) * 6];
-    __shared__ alignas(16) uint8_t s_lo[256];
-    __shared__ alignas(16) uint8_t s_hi[256];
-    __shared__ alignas(16) uint8_t s_dl[256];
-    __shared__ uint32_t s_rc[INS_TILE_RECS][4];
-    __shared__ uint64_t s_base[4];
-    __shared__ uint32_t s_tmp[4];
+    const int lane = lane_id();
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint64_t R0 = t * INS_TILE_RECS;
     const uint64_t nrec = (nrec_out - R0) < (uint64_t)INS_TILE_RECS ? (nrec_out - R0) : INS_TILE_RECS;
     const uint64_t q0 = R0 * REC_SYMS;
@@ -278,129 +280,123 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, uint32_
     const uint64_t o0 = q0 - a0;                     // old rows before the tile
     const uint64_t nold = (q1 - q0) - (a1 - a0);     // old rows inside it
     const uint64_t r_lo = o0 >> REC_SHIFT;
-    uint32_t nr_old = nold ? (uint32_t)(((o0 + nold - 1) >> REC_SHIFT) - r_lo + 1) : 0u;
+    const uint32_t nr_old = nold ? (uint32_t)(((o0 + nold - 1) >> REC_SHIFT) - r_lo + 1) : 0u;
     // a consistent split never trips these; they keep a broken one in bounds
     if (a1 < a0 || a1 - a0 > INS_TILE_SYMS || nr_old > INS_TILE_RECS + 1 ||
         (nr_old && r_lo + nr_old > nrec_in)) {
-        if (tid == 0) atomicOr(err, 32u);
+        if (lane == 0) atomicOr(err, 32u);
         return;
     }
-
-    if (tid < (int)(INS_TILE_SYMS / 32)) s_bm[tid] = 0;
-    if (tid < (int)nr_old * 6) {
-        const uint64_t *rw = reinterpret_cast<const uint64_t *>(orecs + r_lo + tid / 6);
-        s_old[tid] = rw[2 + tid % 6];
+    L.bm[lane] = 0;
+    for (uint32_t k = (uint32_t)lane; k < nr_old * 6; k += 64) {
+        const uint64_t *rw = reinterpret_cast<const uint64_t *>(orecs + r_lo + k / 6);
+        L.old[k] = rw[2 + k % 6];
     }
-    __syncthreads();
-    for (uint64_t i = a0 + tid; i < a1; i += 256) {
-        uint64_t pos = gsa_at(gkeys, gshift, sa0 + i, goff) + i - q0;
-        if (pos < INS_TILE_SYMS) atomicOr(&s_bm[pos >> 5], 1u << (pos & 31));
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint64_t i = a0 + lane; i < a1; i += 64) {
+        const uint64_t pos = gsa_at(gkeys, gshift, sa0 + i, goff) + i - q0;
+        if (pos < INS_TILE_SYMS) atomicOr(&L.bm[pos >> 5], 1u << (pos & 31));
         else atomicOr(err, 32u);
-        s_new[i - a0] = (uint8_t)code_at(vals, sa0 + i);
+        L.nsym[i - a0] = (uint8_t)code_at(vals, sa0 + i);
     }
-    if (wave == 1) {
+    {
         // counts at the tile start: old part by a rank on B_ext, new part from
         // the sampled B_int counts plus the < 64 symbols since the sample
         // (taken at the unit's first slot too, and subtracted)
         const uint64_t A = sa0 + a0;
-        uint64_t x = (A & ~63ull) + lane;
-        int c = x < A ? code_at(vals, x) : 6;
-        uint32_t cA = __popcll(__ballot(c == 0)), cC = __popcll(__ballot(c == 1));
-        uint32_t cG = __popcll(__ballot(c == 2)), cT = __popcll(__ballot(c == 3));
-        uint64_t y = (sa0 & ~63ull) + lane;
-        int d = y < sa0 ? code_at(vals, y) : 6;
-        uint32_t dA = __popcll(__ballot(d == 0)), dC = __popcll(__ballot(d == 1));
-        uint32_t dG = __popcll(__ballot(d == 2)), dT = __popcll(__ballot(d == 3));
+        const uint64_t x = (A & ~63ull) + lane;
+        const int c = x < A ? code_at(vals, x) : 6;
+        const uint32_t cA = __popcll(__ballot(c == 0)), cC = __popcll(__ballot(c == 1));
+        const uint32_t cG = __popcll(__ballot(c == 2)), cT = __popcll(__ballot(c == 3));
+        const uint64_t y = (sa0 & ~63ull) + lane;
+        const int d = y < sa0 ? code_at(vals, y) : 6;
+        const uint32_t dA = __popcll(__ballot(d == 0)), dC = __popcll(__ballot(d == 1));
+        const uint32_t dG = __popcll(__ballot(d == 2)), dT = __popcll(__ballot(d == 3));
         if (lane < 4) {
-            uint32_t part = lane == 0 ? cA : lane == 1 ? cC : lane == 2 ? cG : cT;
-            uint32_t part0 = lane == 0 ? dA : lane == 1 ? dC : lane == 2 ? dG : dT;
-            s_base[lane] = ((uint64_t)bcnt[(A >> CHUNK_SHIFT) * 4 + lane] + part) -
+            const uint32_t part = lane == 0 ? cA : lane == 1 ? cC : lane == 2 ? cG : cT;
+            const uint32_t part0 = lane == 0 ? dA : lane == 1 ? dC : lane == 2 ? dG : dT;
+            L.base[lane] = ((uint64_t)bcnt[(A >> CHUNK_SHIFT) * 4 + lane] + part) -
                            ((uint64_t)bcnt[(sa0 >> CHUNK_SHIFT) * 4 + lane] + part0) +
                            rank_base(orecs, osbc, o0, lane, true);
         }
     }
-    __syncthreads();
-    // this thread's 8 output rows: q0 + 8*tid .. +7
-    const uint32_t byte = (s_bm[tid >> 2] >> (8 * (tid & 3))) & 255u;
-    uint32_t tot;
-    uint32_t nb = block_excl_sum256((uint32_t)__popc(byte), s_tmp, &tot);
-    uint64_t ob = o0 + 8ull * tid - nb - r_lo * REC_SYMS;  // old row, relative to record r_lo
-    uint32_t lo_b = 0, hi_b = 0, dl_b = 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        uint64_t q = q0 + 8ull * tid + u;
-        if (q < q1) {
-            int sym;
-            if ((byte >> u) & 1u) {
-                sym = s_new[nb < INS_TILE_SYMS ? nb : INS_TILE_SYMS - 1];
-                ++nb;
-            } else {
-                uint32_t rr = (uint32_t)(ob >> REC_SHIFT), bit = (uint32_t)(ob & 127), w = bit >> 6,
-                         b = bit & 63;
-                ++ob;
-                if (rr > INS_TILE_RECS) rr = INS_TILE_RECS;
-                const uint64_t *R = s_old + rr * 6;
-                sym = ((R[4 + w] >> b) & 1) ? 4 : (int)(((R[w] >> b) & 1) | (((R[2 + w] >> b) & 1) << 1));
-            }
-            if (sym == 4) dl_b |= 1u << u;
-            else {
-                lo_b |= (uint32_t)(sym & 1) << u;
-                hi_b |= (uint32_t)(sym >> 1) << u;
-            }
-        }
-    }
-    s_lo[tid] = (uint8_t)lo_b;
-    s_hi[tid] = (uint8_t)hi_b;
-    s_dl[tid] = (uint8_t)dl_b;
-    __syncthreads();
-    if (tid < INS_TILE_RECS * 4) {
-        int r = tid >> 2, c = tid & 3;
-        uint64_t rq = q0 + (uint64_t)r * REC_SYMS;
-        uint64_t valid = rq < q1 ? (q1 - rq < REC_SYMS ? q1 - rq : REC_SYMS) : 0;
-        const uint64_t *L = reinterpret_cast<const uint64_t *>(s_lo + 16 * r);
-        const uint64_t *H = reinterpret_cast<const uint64_t *>(s_hi + 16 * r);
-        const uint64_t *D = reinterpret_cast<const uint64_t *>(s_dl + 16 * r);
-        uint64_t v0 = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
-        uint64_t v1 = valid > 64 ? (valid >= 128 ? ~0ull : ((1ull << (valid - 64)) - 1ull)) : 0ull;
-        s_rc[r][c] = (uint32_t)(__popcll(match_bits(L[0], H[0], D[0], c) & v0) +
-                                __popcll(match_bits(L[1], H[1], D[1], c) & v1));
-    }
-    __syncthreads();
-    if (tid < 4) {
-        uint32_t run = 0;
-        for (int r = 0; r < INS_TILE_RECS; ++r) {
-            uint32_t x = s_rc[r][tid];
-            s_rc[r][tid] = run;
-            run += x;
-        }
-    }
-    __syncthreads();
-    const int r = tid >> 4, w = tid & 15;
-    if ((uint64_t)r < nrec) {
-        const uint64_t R = R0 + r;
-        uint32_t val;
-        if (w < 4) {
-            uint64_t abs = s_base[w] + s_rc[r][w];
-            val = (uint32_t)(abs - nsbc[((R * REC_SYMS) >> SB_SHIFT) * 4 + w]);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // this lane's 32 output rows: q0 + 32 * lane .. + 31
+    const uint32_t word = L.bm[lane];
+    const uint32_t nnew = (uint32_t)__popc(word);
+    uint32_t nb = wave_incl_sum(nnew) - nnew;              // new symbols before this lane
+    uint64_t ob = o0 + 32ull * lane - nb - r_lo * REC_SYMS;  // old row, relative to record r_lo
+    const uint64_t ql = q0 + 32ull * lane;
+    const uint32_t nvalid = ql < q1 ? (q1 - ql < 32 ? (uint32_t)(q1 - ql) : 32u) : 0u;
+    uint32_t lo_w = 0, hi_w = 0, dl_w = 0;
+    for (uint32_t u = 0; u < nvalid; ++u) {
+        int sym;
+        if ((word >> u) & 1u) {
+            sym = L.nsym[nb < INS_TILE_SYMS ? nb : INS_TILE_SYMS - 1];
+            ++nb;
         } else {
-            const uint8_t *plane = (w < 8) ? s_lo : (w < 12) ? s_hi : s_dl;
-            val = *reinterpret_cast<const uint32_t *>(plane + 16 * r + 4 * ((w - 4) & 3));
+            uint32_t rr = (uint32_t)(ob >> REC_SHIFT);
+            const uint32_t bit = (uint32_t)(ob & 127), w = bit >> 6, b = bit & 63;
+            ++ob;
+            if (rr > INS_TILE_RECS) rr = INS_TILE_RECS;
+            const uint64_t *R = L.old + rr * 6;
+            sym = ((R[4 + w] >> b) & 1) ? 4 : (int)(((R[w] >> b) & 1) | (((R[2 + w] >> b) & 1) << 1));
         }
-        reinterpret_cast<uint32_t *>(nrecs)[R * 16 + w] = val;
+        if (sym == 4) dl_w |= 1u << u;
+        else {
+            lo_w |= (uint32_t)(sym & 1) << u;
+            hi_w |= (uint32_t)(sym >> 1) << u;
+        }
+    }
+    const uint32_t vmask = nvalid >= 32 ? 0xffffffffu : ((1u << nvalid) - 1u);
+    // counts of each base before this lane's rows, then at each record start
+    // (the record of lane l is l / 4; its first lane is l & ~3)
+    uint64_t before[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t a = (c & 1) ? lo_w : ~lo_w, b = (c & 2) ? hi_w : ~hi_w;
+        const uint32_t m = (uint32_t)__popc(a & b & ~dl_w & vmask);
+        before[c] = L.base[c] + (wave_incl_sum(m) - m);
+    }
+    const int first = lane & ~3, k = lane & 3;
+    uint64_t rec_before[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        rec_before[c] = (uint64_t)__shfl((long long)before[c], first, 64);
+    const uint64_t r = (uint64_t)(lane >> 2);
+    if (r < nrec) {
+        const uint64_t R = R0 + r;
+        const uint64_t cabs = k == 0 ? rec_before[0] : k == 1 ? rec_before[1] : k == 2 ? rec_before[2] : rec_before[3];
+        uint32_t *out = reinterpret_cast<uint32_t *>(nrecs) + R * 16;
+        out[k] = (uint32_t)(cabs - nsbc[((R * REC_SYMS) >> SB_SHIFT) * 4 + k]);
+        out[4 + k] = lo_w;
+        out[8 + k] = hi_w;
+        out[12 + k] = dl_w;
     }
 }
 
-__global__ __launch_bounds__(256) void insert_kernel(InsJob J, uint32_t *__restrict__ err) {
-    insert_tile(J, blockIdx.x, err);
+// four tiles per workgroup, one per wave
+__global__ __launch_bounds__(256) void insert_kernel(InsJob J, uint64_t ntiles,
+                                                     uint32_t *__restrict__ err) {
+    __shared__ InsLds s_l[4];
+    const int wave = threadIdx.x >> 6;
+    const uint64_t t = (uint64_t)blockIdx.x * 4 + wave;
+    if (t >= ntiles) return;
+    insert_tile(J, t, s_l[wave], err);
 }
 
-// one workgroup per tile of every unit: tile T belongs to the last unit with
+// tiles of every unit, one per wave: tile T belongs to the last unit with
 // tile0 <= T
 __global__ __launch_bounds__(256) void insert_units_kernel(
     const InsertUnit *__restrict__ units, uint32_t nunits, const uint64_t *__restrict__ gkeys,
     int gshift, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ bcnt,
-    const uint64_t *__restrict__ first_new, uint32_t *__restrict__ err) {
-    const uint64_t T = blockIdx.x;
+    const uint64_t *__restrict__ first_new, uint64_t ntiles_all, uint32_t *__restrict__ err) {
+    __shared__ InsLds s_l[4];
+    const int wave = threadIdx.x >> 6;
+    const uint64_t T = (uint64_t)blockIdx.x * 4 + wave;
+    if (T >= ntiles_all) return;
     uint32_t lo = 0, hi = nunits - 1;
     while (lo < hi) {
         uint32_t mid = (lo + hi + 1) >> 1;
@@ -422,7 +418,7 @@ __global__ __launch_bounds__(256) void insert_units_kernel(
     J.sa0 = u.sa0;
     J.goff = u.goff;
     J.gshift = gshift;
-    insert_tile(J, T - u.tile0, err);
+    insert_tile(J, T - u.tile0, s_l[wave], err);
 }
 
 __global__ void fill_u64_kernel(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
@@ -502,7 +498,7 @@ hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
     J.sa0 = 0;
     J.goff = 0;
     J.gshift = gshift;
-    insert_kernel<<<(unsigned)ntiles, 256, 0, s>>>(J, err);
+    insert_kernel<<<(unsigned)div_up(ntiles, 4), 256, 0, s>>>(J, ntiles, err);
     return hipGetLastError();
 }
 
@@ -530,8 +526,8 @@ hipError_t launch_insert_units(const InsertUnit *units, uint32_t nunits, const u
                                const uint64_t *first_new, uint64_t ntiles_all, uint32_t *err,
                                hipStream_t s) {
     if (nunits == 0 || ntiles_all == 0) return hipSuccess;
-    insert_units_kernel<<<(unsigned)ntiles_all, 256, 0, s>>>(units, nunits, gkeys, gshift, vals,
-                                                             bcnt, first_new, err);
+    insert_units_kernel<<<(unsigned)div_up(ntiles_all, 4), 256, 0, s>>>(
+        units, nunits, gkeys, gshift, vals, bcnt, first_new, ntiles_all, err);
     return hipGetLastError();
 }
 
