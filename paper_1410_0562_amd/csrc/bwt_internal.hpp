@@ -88,6 +88,17 @@ constexpr int INS_TILE_RECS = 16;    // output records per Insert tile
 constexpr uint64_t INS_TILE_SYMS = INS_TILE_RECS * REC_SYMS;
 constexpr int CHUNK_SHIFT = 6;       // B_int counts sampled every 64 symbols
 
+// B_int counts sampled every 64 sorted symbols: the count of base c among the
+// first 64k symbols is chunk[k*4 + c] + seg[(k >> BINT_SEG_SHIFT)*4 + c]
+// (the count inside a segment of 1024 chunks, plus the count before the
+// segment), for k = 0 .. ceil(n / 64).  chunk holds ceil(n/64) + 1 entries of
+// 4 words, seg ceil(n / 65536) + 1.
+constexpr int BINT_SEG_SHIFT = 10;
+struct BintCounts {
+    const uint32_t *chunk;
+    const uint32_t *seg;
+};
+
 __host__ __device__ inline int bits_for_value(uint64_t v) {  // bits to hold 0..v
     int b = 0;
     while (b < 64 && (v >> b) != 0) ++b;
@@ -272,10 +283,10 @@ hipError_t launch_ins_tile_first_units(const InsertUnit *units, uint32_t nunits,
                                        const uint64_t *gkeys, int gshift, uint64_t ntiles_all,
                                        uint64_t *first_new, hipStream_t s);
 hipError_t launch_ins_meta_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
-                                 int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                                 int gshift, const uint32_t *vals, BintCounts bcnt,
                                  hipStream_t s);
 hipError_t launch_insert_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
-                               int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                               int gshift, const uint32_t *vals, BintCounts bcnt,
                                const uint64_t *first_new, uint64_t ntiles_all, uint32_t *err,
                                hipStream_t s);
 
@@ -313,8 +324,8 @@ hipError_t launch_plan_sets(const PlanSet *sets, uint32_t nsets, uint64_t M, uin
 // (0..3 for A..T, 4 for '$') is vals[i] >> 29.
 hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *bcnt, uint64_t *status,
-                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s);
+hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *chunk, uint32_t *seg,
+                             hipStream_t s);
 // user-supplied B_int (ASCII) and g_sa: *bad |= 1 for a byte outside "ACGT$",
 // 2 for a g_sa that decreases or exceeds n_ext; then packed as keys/values
 hipError_t launch_check_user_insert(const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
@@ -325,11 +336,11 @@ hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gshift, uint64_t n_n
                                  uint64_t ntiles, uint64_t *first_new, hipStream_t s);
 hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
                            const uint64_t *gkeys, int gshift, const uint32_t *vals,
-                           const uint32_t *bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
+                           BintCounts bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
                            hipStream_t s);
 hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
                          const uint64_t *gkeys, int gshift, const uint32_t *vals,
-                         const uint32_t *bcnt, uint64_t n_new, const uint64_t *first_new,
+                         BintCounts bcnt, uint64_t n_new, const uint64_t *first_new,
                          Rec *nrecs, const uint64_t *nsbc, uint32_t *err, hipStream_t s);
 
 // queries and input checks (k_query.hip)

@@ -52,7 +52,8 @@ struct Workspace {
     uint64_t *g = nullptr;                   // ranks in text order
     uint64_t *gsa = nullptr;                 // second spare key buffer of the bucket finish
     uint8_t *bint = nullptr;
-    uint32_t *bcnt = nullptr;                // B_int counts per 64 symbols
+    uint32_t *bcnt = nullptr;                // B_int counts per 64 symbols, inside segments
+    uint32_t *bseg = nullptr;                // counts before each segment, segment totals
     uint32_t *soff = nullptr;                // block position of each read
     uint32_t *tile_first = nullptr;
     uint64_t *status_radix = nullptr;        // radix look-back words
@@ -311,6 +312,7 @@ void free_ws(Workspace &w) {
     dfree(w.gsa);
     dfree(w.bint);
     dfree(w.bcnt);
+    dfree(w.bseg);
     dfree(w.soff);
     dfree(w.tile_first);
     dfree(w.status_radix);
@@ -341,6 +343,7 @@ int ensure_ws(bwt_set *h, uint64_t need) {
     ok &= dalloc(&w.gsa, cap) == hipSuccess;
     ok &= dalloc(&w.bint, cap + 64) == hipSuccess;
     ok &= dalloc(&w.bcnt, (div_up(cap, 64) + 2) * 4) == hipSuccess;
+    ok &= dalloc(&w.bseg, (2 * (div_up(cap, 64 << BINT_SEG_SHIFT) + 2) + 1) * 4) == hipSuccess;
     ok &= dalloc(&w.soff, cap + 2) == hipSuccess;
     ok &= dalloc(&w.tile_first, div_up(cap, 1u << PREP_TILE_SHIFT) + 2) == hipSuccess;
     ok &= dalloc(&w.status_radix, tiles * 256) == hipSuccess;
@@ -707,14 +710,14 @@ int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, 
     int rc = ensure_buf(h, h->first_new, h->first_new_cap, ntiles + 2);
     if (rc) return rc;
     Scope sc(h, s, BWT_STAGE_INSERT);
-    HIPCHK(h, launch_count_bint(vals, (uint32_t)n_new, w.bcnt, w.status_scan,
-                                w.misc + MISC_CNT_BINT, next_epoch(), w.misc + MISC_ERR, s));
+    const BintCounts bc{w.bcnt, w.bseg};
+    HIPCHK(h, launch_count_bint(vals, (uint32_t)n_new, w.bcnt, w.bseg, s));
     HIPCHK(h, launch_ins_tile_first(gkeys, gshift, n_new, ntiles, h->first_new, s));
-    HIPCHK(h, launch_ins_meta(src.recs, src.sbc, src.meta, gkeys, gshift, vals, w.bcnt, n_new,
+    HIPCHK(h, launch_ins_meta(src.recs, src.sbc, src.meta, gkeys, gshift, vals, bc, n_new,
                               dst.sbc, dst.meta, s));
     {
         Scope sk(h, s, SPAN_INSERT_K);
-        HIPCHK(h, launch_insert(src.recs, src.sbc, n_ext, gkeys, gshift, vals, w.bcnt, n_new,
+        HIPCHK(h, launch_insert(src.recs, src.sbc, n_ext, gkeys, gshift, vals, bc, n_new,
                                 h->first_new, dst.recs, dst.sbc, w.misc + MISC_ERR, s));
     }
     if (h->timer.on) {
@@ -900,12 +903,12 @@ int run_block(bwt_set *L, hipStream_t s, const DevBlock &B, const std::vector<Ho
         return rc;
     {
         Scope sc(L, s, BWT_STAGE_INSERT);
-        HIPCHK(L, launch_count_bint(sa, n_blk, w.bcnt, w.status_scan, w.misc + MISC_CNT_BINT,
-                                    next_epoch(), w.misc + MISC_ERR, s));
+        const BintCounts bc{w.bcnt, w.bseg};
+        HIPCHK(L, launch_count_bint(sa, n_blk, w.bcnt, w.bseg, s));
         HIPCHK(L, launch_ins_tile_first_units(idev, nu, gkeys, gshift, B.ntiles, L->first_new, s));
-        HIPCHK(L, launch_ins_meta_units(idev, nu, gkeys, gshift, sa, w.bcnt, s));
+        HIPCHK(L, launch_ins_meta_units(idev, nu, gkeys, gshift, sa, bc, s));
         Scope sk(L, s, SPAN_INSERT_K);
-        HIPCHK(L, launch_insert_units(idev, nu, gkeys, gshift, sa, w.bcnt, L->first_new, B.ntiles,
+        HIPCHK(L, launch_insert_units(idev, nu, gkeys, gshift, sa, bc, L->first_new, B.ntiles,
                                       w.misc + MISC_ERR, s));
     }
     if (L->timer.on) {
@@ -1617,7 +1620,8 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
     const Workspace &w = h->ws;
     if (w.cap) {
         const uint64_t c = w.cap, tiles = div_up(c, RADIX_MIN_TILE) + 1;
-        b += c * (8 * 4 + 4 * 6 + 1 + 4 * 2) + div_up(c, 64) * 16 + div_up(c, 4096) * 4 +
+        b += c * (8 * 4 + 4 * 6 + 1 + 4 * 2) + div_up(c, 64) * 16 +
+             (2 * (div_up(c, 64 << BINT_SEG_SHIFT) + 2) + 1) * 16 + div_up(c, 4096) * 4 +
              tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4 +
              4ull * (BK_TABLES * w.bk_words + BK_PART + 2 * (c / 2048 + 2));
     }

@@ -48,10 +48,15 @@ __device__ __forceinline__ int code_at(const uint32_t *__restrict__ vals, uint64
     return (int)(vals[i] >> POS_BITS);
 }
 
+// count of base c among the first 64k sorted symbols of the block
+__device__ __forceinline__ uint64_t bint_sample(const BintCounts &bc, uint64_t k, int c) {
+    return (uint64_t)bc.chunk[k * 4 + c] + bc.seg[(k >> BINT_SEG_SHIFT) * 4 + c];
+}
+
 // occurrences of base c among the first a sorted symbols of the block
-__device__ uint64_t rank_bint(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ bcnt,
+__device__ uint64_t rank_bint(const uint32_t *__restrict__ vals, const BintCounts &bcnt,
                               uint64_t a, int c) {
-    uint64_t r = bcnt[(a >> CHUNK_SHIFT) * 4 + c];
+    uint64_t r = bint_sample(bcnt, a >> CHUNK_SHIFT, c);
     for (uint64_t x = a & ~63ull; x < a; ++x) r += (code_at(vals, x) == c);
     return r;
 }
@@ -65,7 +70,7 @@ struct InsJob {
     const uint64_t *nsbc;
     const uint64_t *gkeys;
     const uint32_t *vals;
-    const uint32_t *bcnt;
+    BintCounts bcnt;
     const uint64_t *first_new;   // the unit's tiles' entries
     uint64_t n_ext, n_new, sa0, goff;
     int gshift;
@@ -83,60 +88,79 @@ __device__ uint64_t first_at_or_after(const uint64_t *__restrict__ gkeys, int gs
     return lo;
 }
 
-// bcnt[k*4 + c] = occurrences of base c among the first 64k new symbols, for
-// k = 0 .. ceil(n/64) (the last entry holds the totals).  Tile of 4096
-// symbols = 64 chunks, one look-back chain per base.
+// Counts of each base per chunk of 64 sorted symbols, one workgroup per
+// segment of 1024 chunks (65,536 symbols): chunk[k] = counts in the segment
+// before chunk k, and stot[seg] = the segment's totals.  Wave w counts the
+// chunks w*256 .. w*256 + 255 of the segment, 16 rows of 64 symbols at a
+// time.  The chunk after the last (k = ceil(n/64)) is written by the segment
+// it falls in.
 __global__ __launch_bounds__(256) void count_bint_kernel(const uint32_t *__restrict__ vals,
-                                                         uint32_t n, uint32_t *__restrict__ bcnt,
-                                                         uint64_t *__restrict__ status,
-                                                         uint32_t *__restrict__ counter,
-                                                         uint32_t ntiles, uint32_t epoch,
-                                                         uint32_t *__restrict__ err) {
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_wtot[4][4];
-    __shared__ uint32_t s_pre[4];
+                                                         uint32_t n, uint32_t nch,
+                                                         uint32_t *__restrict__ chunk,
+                                                         uint32_t *__restrict__ stot) {
+    __shared__ uint32_t s_pre[1024][4];
+    __shared__ uint32_t s_wt[4][4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const uint32_t tile = acquire_tile(counter, ntiles, &s_tile);
-    if (tile >= ntiles) {
-        if (tid == 0) atomicOr(err, 2u);
-        return;
-    }
-    const uint64_t wbase = (uint64_t)tile * SCAN_TILE + (uint64_t)wave * 1024;
+    const uint32_t seg = blockIdx.x;
+    const uint32_t k0 = seg << BINT_SEG_SHIFT;
     uint32_t run[4] = {0, 0, 0, 0};
-    uint32_t loc[16][4];
+    for (uint32_t r0 = 0; r0 < 256; r0 += 16) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        uint64_t x = wbase + (uint64_t)e * 64 + lane;
-        int c = x < n ? code_at(vals, x) : 6;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            loc[e][b] = run[b];
-            run[b] += (uint32_t)__popcll(__ballot(c == b));
-        }
-    }
-    // the counts are uniform across the wave; lane b < 4 keeps base b
-    auto pick = [lane](const uint32_t *v) {
-        return lane == 0 ? v[0] : lane == 1 ? v[1] : lane == 2 ? v[2] : v[3];
-    };
-    if (lane < 4) s_wtot[wave][lane] = pick(run);
-    __syncthreads();
-    if (wave == 0 && lane < 4) {
-        uint32_t tot = s_wtot[0][lane] + s_wtot[1][lane] + s_wtot[2][lane] + s_wtot[3][lane];
-        uint32_t p = lookback(status + lane, 4u, tile, epoch, tot, OpSum(), 0u, err);
-        s_pre[lane] = p;
-        if (tile == ntiles - 1) {
-            uint64_t nch = div_up(n, 64);
-            bcnt[nch * 4 + lane] = p + tot;
-        }
-    }
-    __syncthreads();
-    if (lane < 4) {
-        uint32_t wpre = s_pre[lane];
-        for (int w = 0; w < wave; ++w) wpre += s_wtot[w][lane];
         for (int e = 0; e < 16; ++e) {
-            uint64_t x0 = wbase + (uint64_t)e * 64;
-            if (x0 < n) bcnt[(x0 >> 6) * 4 + lane] = wpre + pick(loc[e]);
+            const uint32_t kl = (uint32_t)wave * 256 + r0 + e;  // chunk inside the segment
+            const uint64_t x = (uint64_t)(k0 + kl) * 64 + lane;
+            const int c = x < n ? code_at(vals, x) : 6;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (lane == q) s_pre[kl][q] = run[q];
+                run[q] += (uint32_t)__popcll(__ballot(c == q));
+            }
         }
+    }
+    if (lane < 4) s_wt[wave][lane] = lane == 0 ? run[0] : lane == 1 ? run[1] : lane == 2 ? run[2] : run[3];
+    __syncthreads();
+    // 1024 chunks x 4 bases = 4096 words, 16 per thread; a chunk of wave w
+    // adds the counts of the waves before it
+    for (uint32_t i = tid; i < 4096; i += 256) {
+        const uint32_t kl = i >> 2, b = i & 3, w = kl >> 8;
+        uint32_t off = 0;
+        for (uint32_t v = 0; v < w; ++v) off += s_wt[v][b];
+        const uint32_t k = k0 + kl;
+        if (k <= nch) chunk[(uint64_t)k * 4 + b] = off + s_pre[kl][b];
+    }
+    if (tid < 4) stot[seg * 4 + tid] = s_wt[0][tid] + s_wt[1][tid] + s_wt[2][tid] + s_wt[3][tid];
+}
+
+// Exclusive scan of the segment totals (one workgroup of 1024 threads, at
+// most 8 segments each): seg[s] = counts before segment s, seg[nseg] = all.
+__global__ __launch_bounds__(1024) void bint_seg_scan_kernel(const uint32_t *__restrict__ stot,
+                                                             uint32_t nseg,
+                                                             uint32_t *__restrict__ seg) {
+    __shared__ uint32_t s_w[16][4];
+    const uint32_t tid = threadIdx.x, w = tid >> 6;
+    const uint32_t per = (nseg + 1023) / 1024;
+    for (int b = 0; b < 4; ++b) {
+        uint32_t sum = 0;
+        for (uint32_t q = 0; q < per; ++q) {
+            const uint32_t s_ = tid * per + q;
+            if (s_ < nseg) sum += stot[s_ * 4 + b];
+        }
+        const uint32_t inc = wave_incl_sum(sum);
+        if ((tid & 63) == 63) s_w[w][b] = inc;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (uint32_t k = 0; k < 16; ++k) {
+            before += k < w ? s_w[k][b] : 0u;
+            all += s_w[k][b];
+        }
+        uint32_t run = before + inc - sum;
+        for (uint32_t q = 0; q < per; ++q) {
+            const uint32_t s_ = tid * per + q;
+            if (s_ < nseg) seg[s_ * 4 + b] = run;
+            if (s_ < nseg) run += stot[s_ * 4 + b];
+        }
+        if (tid == 0) seg[nseg * 4 + b] = all;
+        __syncthreads();
     }
 }
 
@@ -195,7 +219,7 @@ __global__ void ins_tile_first_units_kernel(const InsertUnit *__restrict__ units
 __device__ void ins_meta_one(const Rec *__restrict__ orecs, const uint64_t *__restrict__ osbc,
                              const uint64_t *__restrict__ ometa, const uint64_t *__restrict__ gkeys,
                              int gshift, const uint32_t *__restrict__ vals,
-                             const uint32_t *__restrict__ bcnt, uint64_t sa0, uint64_t goff,
+                             const BintCounts bcnt, uint64_t sa0, uint64_t goff,
                              uint64_t n_new, uint64_t *__restrict__ nsbc,
                              uint64_t *__restrict__ nmeta) {
     uint64_t base[4];
@@ -227,7 +251,7 @@ __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *_
                                 const uint64_t *__restrict__ ometa,
                                 const uint64_t *__restrict__ gkeys, int gshift,
                                 const uint32_t *__restrict__ vals,
-                                const uint32_t *__restrict__ bcnt, uint64_t n_new,
+                                const BintCounts bcnt, uint64_t n_new,
                                 uint64_t *__restrict__ nsbc, uint64_t *__restrict__ nmeta) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     ins_meta_one(orecs, osbc, ometa, gkeys, gshift, vals, bcnt, 0, 0, n_new, nsbc, nmeta);
@@ -237,7 +261,7 @@ __global__ void ins_meta_kernel(const Rec *__restrict__ orecs, const uint64_t *_
 __global__ void ins_meta_units_kernel(const InsertUnit *__restrict__ units, uint32_t nunits,
                                       const uint64_t *__restrict__ gkeys, int gshift,
                                       const uint32_t *__restrict__ vals,
-                                      const uint32_t *__restrict__ bcnt) {
+                                      const BintCounts bcnt) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nunits) return;
     const InsertUnit &u = units[k];
@@ -262,7 +286,7 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
     const uint64_t *__restrict__ osbc = J.osbc;
     const uint64_t *__restrict__ gkeys = J.gkeys;
     const uint32_t *__restrict__ vals = J.vals;
-    const uint32_t *__restrict__ bcnt = J.bcnt;
+    const BintCounts bcnt = J.bcnt;
     const int gshift = J.gshift;
     const uint64_t sa0 = J.sa0, goff = J.goff;
     Rec *__restrict__ nrecs = J.nrecs;
@@ -316,8 +340,8 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
         if (lane < 4) {
             const uint32_t part = lane == 0 ? cA : lane == 1 ? cC : lane == 2 ? cG : cT;
             const uint32_t part0 = lane == 0 ? dA : lane == 1 ? dC : lane == 2 ? dG : dT;
-            L.base[lane] = ((uint64_t)bcnt[(A >> CHUNK_SHIFT) * 4 + lane] + part) -
-                           ((uint64_t)bcnt[(sa0 >> CHUNK_SHIFT) * 4 + lane] + part0) +
+            L.base[lane] = (bint_sample(bcnt, A >> CHUNK_SHIFT, lane) + part) -
+                           (bint_sample(bcnt, sa0 >> CHUNK_SHIFT, lane) + part0) +
                            rank_base(orecs, osbc, o0, lane, true);
         }
     }
@@ -391,7 +415,7 @@ __global__ __launch_bounds__(256) void insert_kernel(InsJob J, uint64_t ntiles,
 // tile0 <= T
 __global__ __launch_bounds__(256) void insert_units_kernel(
     const InsertUnit *__restrict__ units, uint32_t nunits, const uint64_t *__restrict__ gkeys,
-    int gshift, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ bcnt,
+    int gshift, const uint32_t *__restrict__ vals, const BintCounts bcnt,
     const uint64_t *__restrict__ first_new, uint64_t ntiles_all, uint32_t *__restrict__ err) {
     __shared__ InsLds s_l[4];
     const int wave = threadIdx.x >> 6;
@@ -439,11 +463,14 @@ hipError_t launch_index_init(Rec *recs, uint64_t *sbc, uint64_t *meta, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *bcnt, uint64_t *status,
-                             uint32_t *counter, uint32_t epoch, uint32_t *err, hipStream_t s) {
-    uint32_t ntiles = (uint32_t)div_up(n, SCAN_TILE);
-    if (ntiles == 0) return hipSuccess;
-    count_bint_kernel<<<ntiles, 256, 0, s>>>(vals, n, bcnt, status, counter, ntiles, epoch, err);
+hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *chunk, uint32_t *seg,
+                             hipStream_t s) {
+    const uint32_t nch = (uint32_t)div_up(n, 64);
+    const uint32_t nseg = (nch >> BINT_SEG_SHIFT) + 1;  // the end chunk included
+    // segment totals go after the scanned bases (nseg + 1 entries)
+    uint32_t *stot = seg + 4 * (uint64_t)(nseg + 1);
+    count_bint_kernel<<<nseg, 256, 0, s>>>(vals, n, nch, chunk, stot);
+    bint_seg_scan_kernel<<<1, 1024, 0, s>>>(stot, nseg, seg);
     return hipGetLastError();
 }
 
@@ -472,7 +499,7 @@ hipError_t launch_ins_tile_first(const uint64_t *gkeys, int gshift, uint64_t n_n
 
 hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_t *ometa,
                            const uint64_t *gkeys, int gshift, const uint32_t *vals,
-                           const uint32_t *bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
+                           BintCounts bcnt, uint64_t n_new, uint64_t *nsbc, uint64_t *nmeta,
                            hipStream_t s) {
     ins_meta_kernel<<<1, 64, 0, s>>>(orecs, osbc, ometa, gkeys, gshift, vals, bcnt, n_new, nsbc,
                                      nmeta);
@@ -481,7 +508,7 @@ hipError_t launch_ins_meta(const Rec *orecs, const uint64_t *osbc, const uint64_
 
 hipError_t launch_insert(const Rec *orecs, const uint64_t *osbc, uint64_t n_ext,
                          const uint64_t *gkeys, int gshift, const uint32_t *vals,
-                         const uint32_t *bcnt, uint64_t n_new, const uint64_t *first_new,
+                         BintCounts bcnt, uint64_t n_new, const uint64_t *first_new,
                          Rec *nrecs, const uint64_t *nsbc, uint32_t *err, hipStream_t s) {
     const uint64_t ntiles = div_up(records_for(n_ext + n_new), INS_TILE_RECS);
     InsJob J;
@@ -513,7 +540,7 @@ hipError_t launch_ins_tile_first_units(const InsertUnit *units, uint32_t nunits,
 }
 
 hipError_t launch_ins_meta_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
-                                 int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                                 int gshift, const uint32_t *vals, BintCounts bcnt,
                                  hipStream_t s) {
     if (nunits == 0) return hipSuccess;
     ins_meta_units_kernel<<<(unsigned)div_up(nunits, 64), 64, 0, s>>>(units, nunits, gkeys,
@@ -522,7 +549,7 @@ hipError_t launch_ins_meta_units(const InsertUnit *units, uint32_t nunits, const
 }
 
 hipError_t launch_insert_units(const InsertUnit *units, uint32_t nunits, const uint64_t *gkeys,
-                               int gshift, const uint32_t *vals, const uint32_t *bcnt,
+                               int gshift, const uint32_t *vals, BintCounts bcnt,
                                const uint64_t *first_new, uint64_t ntiles_all, uint32_t *err,
                                hipStream_t s) {
     if (nunits == 0 || ntiles_all == 0) return hipSuccess;
