@@ -69,7 +69,6 @@ struct Workspace {
 // layout of Workspace::misc (uint32 words)
 constexpr int MISC_CNT_RADIX = 0;
 constexpr int MISC_CNT_HEADS = 1;
-constexpr int MISC_CNT_BINT = 2;
 constexpr int MISC_NU = 4;       // followed by MISC_LARGE (read together)
 constexpr int MISC_LARGE = 5;
 constexpr int MISC_BAD = 6;

@@ -88,47 +88,60 @@ __device__ uint64_t first_at_or_after(const uint64_t *__restrict__ gkeys, int gs
     return lo;
 }
 
-// Counts of each base per chunk of 64 sorted symbols, one workgroup per
-// segment of 1024 chunks (65,536 symbols): chunk[k] = counts in the segment
-// before chunk k, and stot[seg] = the segment's totals.  Wave w counts the
-// chunks w*256 .. w*256 + 255 of the segment, 16 rows of 64 symbols at a
-// time.  The chunk after the last (k = ceil(n/64)) is written by the segment
-// it falls in.
-__global__ __launch_bounds__(256) void count_bint_kernel(const uint32_t *__restrict__ vals,
-                                                         uint32_t n, uint32_t nch,
-                                                         uint32_t *__restrict__ chunk,
-                                                         uint32_t *__restrict__ stot) {
-    __shared__ uint32_t s_pre[1024][4];
-    __shared__ uint32_t s_wt[4][4];
+// Counts of each base per chunk of 64 sorted symbols, one workgroup of 16
+// waves per segment of 1024 chunks (65,536 symbols): chunk[k] = counts in the
+// segment before chunk k, and stot[seg] = the segment's totals.  Wave w counts
+// the chunks w*64 .. w*64 + 63 of the segment, 16 rows of 64 symbols at a
+// time, so every wave has 16 loads in flight and a short serial part.  The
+// chunk after the last (k = ceil(n/64)) is written by the segment it falls in.
+constexpr int BINT_WAVES = 16;
+constexpr int BINT_WCH = (1 << BINT_SEG_SHIFT) / BINT_WAVES;  // chunks per wave
+
+__global__ __launch_bounds__(BINT_WAVES * 64) void count_bint_kernel(
+    const uint32_t *__restrict__ vals, uint32_t n, uint32_t nch, uint32_t *__restrict__ chunk,
+    uint32_t *__restrict__ stot) {
+    __shared__ uint32_t s_pre[1 << BINT_SEG_SHIFT][4];
+    __shared__ uint32_t s_wt[BINT_WAVES][4];
+    __shared__ uint32_t s_wb[BINT_WAVES][4];  // counts of the waves before
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t seg = blockIdx.x;
     const uint32_t k0 = seg << BINT_SEG_SHIFT;
     uint32_t run[4] = {0, 0, 0, 0};
-    for (uint32_t r0 = 0; r0 < 256; r0 += 16) {
+    for (uint32_t r0 = 0; r0 < (uint32_t)BINT_WCH; r0 += 16) {
+        int c[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const uint32_t kl = (uint32_t)wave * 256 + r0 + e;  // chunk inside the segment
+            const uint32_t kl = (uint32_t)wave * BINT_WCH + r0 + e;  // chunk inside the segment
             const uint64_t x = (uint64_t)(k0 + kl) * 64 + lane;
-            const int c = x < n ? code_at(vals, x) : 6;
+            c[e] = x < n ? code_at(vals, x) : 6;
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t kl = (uint32_t)wave * BINT_WCH + r0 + e;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (lane == q) s_pre[kl][q] = run[q];
-                run[q] += (uint32_t)__popcll(__ballot(c == q));
+                run[q] += (uint32_t)__popcll(__ballot(c[e] == q));
             }
         }
     }
     if (lane < 4) s_wt[wave][lane] = lane == 0 ? run[0] : lane == 1 ? run[1] : lane == 2 ? run[2] : run[3];
     __syncthreads();
-    // 1024 chunks x 4 bases = 4096 words, 16 per thread; a chunk of wave w
-    // adds the counts of the waves before it
-    for (uint32_t i = tid; i < 4096; i += 256) {
-        const uint32_t kl = i >> 2, b = i & 3, w = kl >> 8;
+    if (tid < 4 * BINT_WAVES) {
+        const uint32_t w = tid >> 2, b = tid & 3;
         uint32_t off = 0;
         for (uint32_t v = 0; v < w; ++v) off += s_wt[v][b];
-        const uint32_t k = k0 + kl;
-        if (k <= nch) chunk[(uint64_t)k * 4 + b] = off + s_pre[kl][b];
+        s_wb[w][b] = off;
+        if (w == BINT_WAVES - 1) stot[seg * 4 + b] = off + s_wt[w][b];
     }
-    if (tid < 4) stot[seg * 4 + tid] = s_wt[0][tid] + s_wt[1][tid] + s_wt[2][tid] + s_wt[3][tid];
+    __syncthreads();
+    // 1024 chunks x 4 bases = 4096 words, 4 per thread; a chunk adds the
+    // counts of the waves before its own
+    for (uint32_t i = tid; i < 4u << BINT_SEG_SHIFT; i += BINT_WAVES * 64) {
+        const uint32_t kl = i >> 2, b = i & 3, w = kl / BINT_WCH;
+        const uint32_t k = k0 + kl;
+        if (k <= nch) chunk[(uint64_t)k * 4 + b] = s_wb[w][b] + s_pre[kl][b];
+    }
 }
 
 // Exclusive scan of the segment totals (one workgroup of 1024 threads, at
@@ -469,7 +482,7 @@ hipError_t launch_count_bint(const uint32_t *vals, uint32_t n, uint32_t *chunk, 
     const uint32_t nseg = (nch >> BINT_SEG_SHIFT) + 1;  // the end chunk included
     // segment totals go after the scanned bases (nseg + 1 entries)
     uint32_t *stot = seg + 4 * (uint64_t)(nseg + 1);
-    count_bint_kernel<<<nseg, 256, 0, s>>>(vals, n, nch, chunk, stot);
+    count_bint_kernel<<<nseg, BINT_WAVES * 64, 0, s>>>(vals, n, nch, chunk, stot);
     bint_seg_scan_kernel<<<1, 1024, 0, s>>>(stot, nseg, seg);
     return hipGetLastError();
 }

@@ -308,17 +308,73 @@ __global__ __launch_bounds__(256) void refine_kernel(
         if (tid == 0) atomicOr(err, 64u);
         return;
     }
-    // load the members
-    for (int t = 0; t < RF_PER_THREAD; ++t) {
-        uint32_t x = tid + 256 * t;
-        if (x < W) {
-            uint32_t v = sa[U[a + x]];
-            uint32_t p = v & POS_MASK;
-            uint32_t j = find_read(soff, tile_first, p);
-            s_val[x] = v;
-            s_pos[x] = off[j] + (p - soff[j]);
-            s_rem[x] = soff[j + 1] - 1 - p;
-            s_gs[x] = group_start(U, keys, a + x) ? 1 : 0;  // head flag for now
+    // load the members.  Each step issues the loads of all of a thread's
+    // members before it uses any of them (a member past W works on a copy of
+    // element a, so every address stays valid), which keeps the dependent
+    // chain -- slot, value, read lookup, read start -- at one latency per step.
+    uint32_t v_m[RF_PER_THREAD], p_m[RF_PER_THREAD], lo[RF_PER_THREAD], hi[RF_PER_THREAD];
+    bool head_m[RF_PER_THREAD];
+    {
+        uint32_t u_m[RF_PER_THREAD], up_m[RF_PER_THREAD];
+#pragma unroll
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            uint32_t ix = x < W ? a + x : a;
+            u_m[t] = U[ix];
+            up_m[t] = U[ix > 0 ? ix - 1 : 0];
+        }
+#pragma unroll
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            uint32_t ix = x < W ? a + x : a;
+            v_m[t] = sa[u_m[t]];
+            uint64_t ku = keys[u_m[t]], kp = keys[up_m[t]];
+            head_m[t] = ix == 0 || up_m[t] + 1 != u_m[t] || kp != ku;
+        }
+#pragma unroll
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            p_m[t] = v_m[t] & POS_MASK;
+            uint32_t T = p_m[t] >> PREP_TILE_SHIFT;
+            lo[t] = tile_first[T];
+            hi[t] = tile_first[T + 1];
+        }
+    }
+    // read of each member: largest j in [lo, hi] with soff[j] <= p, all of a
+    // thread's searches stepping together
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int t = 0; t < RF_PER_THREAD; ++t) more |= lo[t] < hi[t];
+        if (!more) break;
+#pragma unroll
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            const bool open = lo[t] < hi[t];
+            const uint32_t mid = open ? (lo[t] + hi[t] + 1) >> 1 : lo[t];
+            const uint32_t sm = soff[mid];
+            if (open) {
+                if (sm <= p_m[t]) lo[t] = mid;
+                else hi[t] = mid - 1;
+            }
+        }
+    }
+    {
+        uint64_t o_m[RF_PER_THREAD];
+        uint32_t s0[RF_PER_THREAD], s1[RF_PER_THREAD];
+#pragma unroll
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            o_m[t] = off[lo[t]];
+            s0[t] = soff[lo[t]];
+            s1[t] = soff[lo[t] + 1];
+        }
+#pragma unroll
+        for (int t = 0; t < RF_PER_THREAD; ++t) {
+            uint32_t x = tid + 256 * t;
+            if (x < W) {
+                s_val[x] = v_m[t];
+                s_pos[x] = o_m[t] + (p_m[t] - s0[t]);
+                s_rem[x] = s1[t] - 1 - p_m[t];
+                s_gs[x] = head_m[t] ? 1 : 0;  // head flag for now
+            }
         }
     }
     __syncthreads();
@@ -346,14 +402,48 @@ __global__ __launch_bounds__(256) void refine_kernel(
 
     uint64_t d = (uint64_t)kfirst;
     for (uint32_t iter = 0;; ++iter) {
+        // chunk keys of the members of still-tied subgroups; the loads of all
+        // of a thread's members go out before any is used (an inactive member
+        // loads the word holding the first symbol of the reads, which exists)
         int any = 0;
-        for (int t = 0; t < RF_PER_THREAD; ++t) {
-            uint32_t x = tid + 256 * t;
-            if (x < W && s_ge[x] - s_gs[x] >= 2) {
-                uint32_t rem = s_rem[x];
-                uint32_t rd = rem >= d ? (uint32_t)(rem - d) : 0u;
-                s_key[x] = chunk_key(reads, s_pos[x] + d, rd, KEY_K);
-                any = 1;
+        {
+            bool act[RF_PER_THREAD];
+            uint32_t take[RF_PER_THREAD], bit[RF_PER_THREAD];
+            uint64_t w0[RF_PER_THREAD], w1[RF_PER_THREAD];
+#pragma unroll
+            for (int t = 0; t < RF_PER_THREAD; ++t) {
+                uint32_t x = tid + 256 * t;
+                act[t] = x < W && s_ge[x] - s_gs[x] >= 2;
+                uint64_t sp = 0;
+                take[t] = 0;
+                if (act[t]) {
+                    uint32_t rem = s_rem[x];
+                    uint32_t rd = rem >= d ? (uint32_t)(rem - d) : 0u;
+                    take[t] = rd < (uint32_t)KEY_K ? rd : (uint32_t)KEY_K;
+                    sp = take[t] ? s_pos[x] + d : 0;
+                }
+                uintptr_t addr = (uintptr_t)reads + (uintptr_t)(sp >> 2);
+                uintptr_t a0 = addr & ~(uintptr_t)7;
+                bit[t] = (uint32_t)((addr - a0) * 8 + 2 * (sp & 3));
+                const bool two = bit[t] + 2 * take[t] > 64;
+                w0[t] = *reinterpret_cast<const uint64_t *>(a0);
+                w1[t] = *reinterpret_cast<const uint64_t *>(two ? a0 + 8 : a0);
+                if (!two) w1[t] = 0;
+            }
+#pragma unroll
+            for (int t = 0; t < RF_PER_THREAD; ++t) {
+                uint32_t x = tid + 256 * t;
+                if (act[t]) {
+                    uint64_t sym = 0;
+                    if (take[t]) {
+                        uint64_t v = w0[t] >> bit[t];
+                        if (bit[t]) v |= w1[t] << (64 - bit[t]);
+                        v &= (1ull << (2 * take[t])) - 1ull;
+                        sym = reverse_pairs(v) >> (64 - 2 * KEY_K);
+                    }
+                    s_key[x] = (sym << KEY_LEN_BITS) | (uint64_t)take[t];
+                    any = 1;
+                }
             }
         }
         any = __syncthreads_or(any);
