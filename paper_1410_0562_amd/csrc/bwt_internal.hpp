@@ -82,7 +82,7 @@ __host__ __device__ inline int first_key_syms(int gbits, int key_bits) {
 constexpr int REFINE_LIMIT = 256;
 constexpr int REFINE_WINDOW = 1024;
 
-constexpr int PREP_TILE_SHIFT = 12;  // positions per read-lookup tile
+constexpr int PREP_TILE_SHIFT = 8;   // positions per read-lookup tile
 constexpr int SCAN_TILE = 4096;      // elements per look-back scan tile
 constexpr int INS_TILE_RECS = 16;    // output records per Insert tile
 constexpr uint64_t INS_TILE_SYMS = INS_TILE_RECS * REC_SYMS;

@@ -258,6 +258,9 @@ __global__ void doubling_keys_kernel(const uint32_t *__restrict__ U, uint32_t nU
 // ---------------------------------------------------------------- refinement
 constexpr int RF_CAP = REFINE_WINDOW + REFINE_LIMIT;
 constexpr int RF_PER_THREAD = (RF_CAP + 255) / 256;
+constexpr int RF_K = 2 * KEY_K;   // symbols compared per pass
+constexpr int RF_LEN_BITS = 6;    // holds a count up to RF_K
+static_assert(RF_K < (1 << RF_LEN_BITS), "count field");
 
 // U[x] starts a tied group: groups are runs of consecutive slots with equal
 // round-0 keys
@@ -271,12 +274,16 @@ __device__ __forceinline__ bool group_start(const uint32_t *__restrict__ U,
 // One workgroup per window of REFINE_WINDOW unresolved elements, extended to
 // whole groups.  Every member of a group shares g and the first kfirst
 // symbols.  Each pass takes, for every member of a still-tied subgroup, the
-// chunk key of its suffix at depth d, reorders the subgroup by (chunk key,
-// current order) -- stable, so members equal up to their terminators stay in
-// position order, which is terminator order -- and splits it where the key
-// changes.  A subgroup is settled when it has one member or its key reaches
-// the terminator.  d grows by 29 per pass, so a group settles within
-// (longest read / 29) + 1 passes.
+// chunk key of its suffix at depth d -- RF_K = 58 symbols as two words (the
+// first 29 symbols; the next 29 symbols and the count of symbols before the
+// terminator, at most RF_K), each zero-padded, first symbol most significant,
+// so comparing (high word, low word) orders the chunks with the terminator
+// below every base -- reorders the subgroup by (chunk key, current order) --
+// stable, so members equal up to their terminators stay in position order,
+// which is terminator order -- and splits it where the key changes.  A
+// subgroup is settled when it has one member or its key reaches the
+// terminator.  d grows by RF_K per pass, so a group settles within
+// (longest read / RF_K) + 1 passes.
 __global__ __launch_bounds__(256) void refine_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first,
@@ -285,7 +292,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
     __shared__ uint32_t s_val[RF_CAP];
     __shared__ uint64_t s_pos[RF_CAP];   // global symbol index of the suffix start
     __shared__ uint32_t s_rem[RF_CAP];   // symbols before its terminator
-    __shared__ uint64_t s_key[RF_CAP];
+    __shared__ uint64_t s_kh[RF_CAP], s_kl[RF_CAP];  // chunk key: symbols, then symbols + count
     __shared__ uint16_t s_gs[RF_CAP], s_ge[RF_CAP];  // subgroup [start, end)
     __shared__ uint32_t s_win[2];
     const int tid = threadIdx.x;
@@ -358,20 +365,18 @@ __global__ __launch_bounds__(256) void refine_kernel(
         }
     }
     {
-        uint64_t o_m[RF_PER_THREAD];
-        uint32_t s0[RF_PER_THREAD], s1[RF_PER_THREAD];
+        // soff[j] = off[j] - off[0] + j, so the suffix at block position p of
+        // read j starts at global symbol off[j] + p - soff[j] = off[0] + p - j
+        const uint64_t off0 = off[0];
+        uint32_t s1[RF_PER_THREAD];
 #pragma unroll
-        for (int t = 0; t < RF_PER_THREAD; ++t) {
-            o_m[t] = off[lo[t]];
-            s0[t] = soff[lo[t]];
-            s1[t] = soff[lo[t] + 1];
-        }
+        for (int t = 0; t < RF_PER_THREAD; ++t) s1[t] = soff[lo[t] + 1];
 #pragma unroll
         for (int t = 0; t < RF_PER_THREAD; ++t) {
             uint32_t x = tid + 256 * t;
             if (x < W) {
                 s_val[x] = v_m[t];
-                s_pos[x] = o_m[t] + (p_m[t] - s0[t]);
+                s_pos[x] = off0 + p_m[t] - lo[t];
                 s_rem[x] = s1[t] - 1 - p_m[t];
                 s_gs[x] = head_m[t] ? 1 : 0;  // head flag for now
             }
@@ -409,7 +414,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
         {
             bool act[RF_PER_THREAD];
             uint32_t take[RF_PER_THREAD], bit[RF_PER_THREAD];
-            uint64_t w0[RF_PER_THREAD], w1[RF_PER_THREAD];
+            uint64_t w0[RF_PER_THREAD], w1[RF_PER_THREAD], w2[RF_PER_THREAD];
 #pragma unroll
             for (int t = 0; t < RF_PER_THREAD; ++t) {
                 uint32_t x = tid + 256 * t;
@@ -419,29 +424,37 @@ __global__ __launch_bounds__(256) void refine_kernel(
                 if (act[t]) {
                     uint32_t rem = s_rem[x];
                     uint32_t rd = rem >= d ? (uint32_t)(rem - d) : 0u;
-                    take[t] = rd < (uint32_t)KEY_K ? rd : (uint32_t)KEY_K;
+                    take[t] = rd < (uint32_t)RF_K ? rd : (uint32_t)RF_K;
                     sp = take[t] ? s_pos[x] + d : 0;
                 }
                 uintptr_t addr = (uintptr_t)reads + (uintptr_t)(sp >> 2);
                 uintptr_t a0 = addr & ~(uintptr_t)7;
                 bit[t] = (uint32_t)((addr - a0) * 8 + 2 * (sp & 3));
-                const bool two = bit[t] + 2 * take[t] > 64;
+                const uint32_t end = bit[t] + 2 * take[t];  // bits used from a0 on
                 w0[t] = *reinterpret_cast<const uint64_t *>(a0);
-                w1[t] = *reinterpret_cast<const uint64_t *>(two ? a0 + 8 : a0);
-                if (!two) w1[t] = 0;
+                w1[t] = *reinterpret_cast<const uint64_t *>(end > 64 ? a0 + 8 : a0);
+                w2[t] = *reinterpret_cast<const uint64_t *>(end > 128 ? a0 + 16 : a0);
+                if (end <= 64) w1[t] = 0;
+                if (end <= 128) w2[t] = 0;
             }
 #pragma unroll
             for (int t = 0; t < RF_PER_THREAD; ++t) {
                 uint32_t x = tid + 256 * t;
                 if (act[t]) {
-                    uint64_t sym = 0;
-                    if (take[t]) {
-                        uint64_t v = w0[t] >> bit[t];
-                        if (bit[t]) v |= w1[t] << (64 - bit[t]);
-                        v &= (1ull << (2 * take[t])) - 1ull;
-                        sym = reverse_pairs(v) >> (64 - 2 * KEY_K);
+                    const uint32_t tk = take[t], sh = bit[t];
+                    // symbols 0..31 and 32..63 of the window, first in the low bits
+                    uint64_t lo64 = w0[t] >> sh, hi64 = w1[t] >> sh;
+                    if (sh) {
+                        lo64 |= w1[t] << (64 - sh);
+                        hi64 |= w2[t] << (64 - sh);
                     }
-                    s_key[x] = (sym << KEY_LEN_BITS) | (uint64_t)take[t];
+                    const uint32_t ta = tk < (uint32_t)KEY_K ? tk : (uint32_t)KEY_K;
+                    const uint32_t tb = tk - ta;
+                    uint64_t sa_ = ta ? lo64 & ((1ull << (2 * ta)) - 1ull) : 0ull;
+                    uint64_t sb_ = ((lo64 >> (2 * KEY_K)) | (hi64 << (64 - 2 * KEY_K)));
+                    sb_ = tb ? sb_ & ((1ull << (2 * tb)) - 1ull) : 0ull;
+                    s_kh[x] = reverse_pairs(sa_) >> (64 - 2 * KEY_K);
+                    s_kl[x] = ((reverse_pairs(sb_) >> (64 - 2 * KEY_K)) << RF_LEN_BITS) | tk;
                     any = 1;
                 }
             }
@@ -454,25 +467,26 @@ __global__ __launch_bounds__(256) void refine_kernel(
         }
         // new place of every member inside its subgroup
         uint32_t np[RF_PER_THREAD], v_r[RF_PER_THREAD], rem_r[RF_PER_THREAD];
-        uint64_t pos_r[RF_PER_THREAD], key_r[RF_PER_THREAD];
+        uint64_t pos_r[RF_PER_THREAD], kh_r[RF_PER_THREAD], kl_r[RF_PER_THREAD];
         for (int t = 0; t < RF_PER_THREAD; ++t) {
             uint32_t x = tid + 256 * t;
             np[t] = x;
             if (x < W) {
                 uint32_t gs = s_gs[x], ge = s_ge[x];
                 if (ge - gs >= 2) {
-                    uint64_t kx = s_key[x];
+                    const uint64_t hx = s_kh[x], lx = s_kl[x];
                     uint32_t c = 0;
                     for (uint32_t y = gs; y < ge; ++y) {
-                        uint64_t ky = s_key[y];
-                        c += (ky < kx) || (ky == kx && y < x);
+                        const uint64_t hy = s_kh[y], ly = s_kl[y];
+                        c += hy < hx || (hy == hx && (ly < lx || (ly == lx && y < x)));
                     }
                     np[t] = gs + c;
                 }
                 v_r[t] = s_val[x];
                 pos_r[t] = s_pos[x];
                 rem_r[t] = s_rem[x];
-                key_r[t] = s_key[x];
+                kh_r[t] = s_kh[x];
+                kl_r[t] = s_kl[x];
             }
         }
         __syncthreads();
@@ -483,7 +497,8 @@ __global__ __launch_bounds__(256) void refine_kernel(
                 s_val[q] = v_r[t];
                 s_pos[q] = pos_r[t];
                 s_rem[q] = rem_r[t];
-                s_key[q] = key_r[t];
+                s_kh[q] = kh_r[t];
+                s_kl[q] = kl_r[t];
             }
         }
         __syncthreads();
@@ -496,15 +511,15 @@ __global__ __launch_bounds__(256) void refine_kernel(
                 gs_r[t] = (uint16_t)gs;
                 ge_r[t] = (uint16_t)ge;
                 if (ge - gs >= 2) {
-                    uint64_t k = s_key[x];
-                    if ((k & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)KEY_K) {
+                    const uint64_t kh = s_kh[x], kl = s_kl[x];
+                    if ((kl & ((1u << RF_LEN_BITS) - 1)) < (uint64_t)RF_K) {
                         gs_r[t] = (uint16_t)x;
                         ge_r[t] = (uint16_t)(x + 1);
                     } else {
                         uint32_t y = x;
-                        while (y > gs && s_key[y - 1] == k) --y;
+                        while (y > gs && s_kh[y - 1] == kh && s_kl[y - 1] == kl) --y;
                         uint32_t z = x + 1;
-                        while (z < ge && s_key[z] == k) ++z;
+                        while (z < ge && s_kh[z] == kh && s_kl[z] == kl) ++z;
                         gs_r[t] = (uint16_t)y;
                         ge_r[t] = (uint16_t)z;
                     }
@@ -520,7 +535,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
             }
         }
         __syncthreads();
-        d += KEY_K;
+        d += RF_K;
     }
     for (int t = 0; t < RF_PER_THREAD; ++t) {
         uint32_t x = tid + 256 * t;
