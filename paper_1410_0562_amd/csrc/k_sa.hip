@@ -296,16 +296,24 @@ __global__ __launch_bounds__(256) void refine_kernel(
     __shared__ uint16_t s_gs[RF_CAP], s_ge[RF_CAP];  // subgroup [start, end)
     __shared__ uint32_t s_win[2];
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        uint64_t a = (uint64_t)blockIdx.x * REFINE_WINDOW, b = a + REFINE_WINDOW;
-        a = a < nU ? a : nU;
-        b = b < nU ? b : nU;
-        int guard = 0;
-        while (a < nU && !group_start(U, keys, (uint32_t)a) && guard++ < REFINE_LIMIT) ++a;
-        guard = 0;
-        while (b < nU && !group_start(U, keys, (uint32_t)b) && guard++ < REFINE_LIMIT) ++b;
-        s_win[0] = (uint32_t)a;
-        s_win[1] = (uint32_t)b;
+    if (tid < 128) {
+        // wave 0 moves the window start, wave 1 its end, to the next group
+        // start (at most REFINE_LIMIT places on, or the end of U), 64 places
+        // per step
+        const int wv = tid >> 6, ln = tid & 63;
+        uint64_t x0 = (uint64_t)blockIdx.x * REFINE_WINDOW + (wv ? REFINE_WINDOW : 0);
+        x0 = x0 < nU ? x0 : nU;
+        uint64_t r = x0 + REFINE_LIMIT < nU ? x0 + REFINE_LIMIT : nU;
+        for (uint64_t y0 = x0; y0 < r; y0 += 64) {
+            const uint64_t y = y0 + ln;
+            const bool st = y >= r || group_start(U, keys, (uint32_t)y);
+            const uint64_t m = __ballot(st);
+            if (m) {
+                r = y0 + __builtin_ctzll(m);
+                break;
+            }
+        }
+        if (ln == 0) s_win[wv] = (uint32_t)r;
     }
     __syncthreads();
     const uint32_t a = s_win[0], b = s_win[1];
