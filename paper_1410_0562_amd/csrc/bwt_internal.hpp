@@ -156,8 +156,9 @@ hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const ui
 // and osz = its size if above BUCKET_CAP; the oversized buckets in bucket
 // order in olist, their starts in the gathered array in ooff (ooff[count] =
 // total); res = {tied suffixes, oversized buckets, oversized suffixes}; part
-// holds 3 words per 4096 bucket ids; trange 2 words per 2048 positions.  bucket_emit lists the tied suffixes of
-// the sorted buckets in U (slot order).  oversize_gather copies the oversized
+// holds 3 words per 4096 bucket ids; trange 2 words per 2048 positions;
+// tflag one byte per position of a tile's window (1 = tied).  bucket_emit
+// lists the tied suffixes of the sorted buckets in U (slot order) from tflag.  oversize_gather copies the oversized
 // buckets to ck/cv; once sorted there on the whole key, oversize_scatter puts
 // them back and oversize_ties_map appends their tied suffixes (gathered
 // indices U2[0 .. *nU2)) to U after the first `base`, setting *nU.
@@ -168,14 +169,12 @@ hipError_t launch_bucket_bounds(const uint64_t *keys, uint32_t n, int bshift, ui
 hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, uint32_t n, const uint32_t *bstart,
                               const uint32_t *bend, uint32_t *trange, uint32_t nb, int bshift,
                               int kshort, uint32_t limit,
-                              uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint32_t *part,
-                              uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *err,
-                              hipStream_t s);
-hipError_t launch_bucket_emit(const uint64_t *keys, uint32_t n, int bshift,
-                              const uint32_t *bstart, const uint32_t *bend,
-                              const uint32_t *trange, const uint32_t *tpre,
-                              uint32_t nb, int kshort, uint32_t *U, uint32_t ucap, uint32_t *err,
-                              hipStream_t s);
+                              uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint8_t *tflag,
+                              uint32_t *part, uint32_t *res, uint32_t *olist, uint32_t *ooff,
+                              uint32_t *err, hipStream_t s);
+hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32_t n, int bshift,
+                              const uint32_t *trange, const uint32_t *tpre, uint32_t nb,
+                              uint32_t *U, uint32_t ucap, uint32_t *err, hipStream_t s);
 hipError_t launch_oversize_gather(const uint64_t *keys, const uint32_t *vals,
                                   const uint32_t *bstart, const uint32_t *olist,
                                   const uint32_t *ooff, uint32_t nob, uint32_t no, uint32_t n,

@@ -51,7 +51,7 @@ struct Workspace {
     uint32_t *rank = nullptr;                // group rank per block position
     uint64_t *g = nullptr;                   // ranks in text order
     uint64_t *gsa = nullptr;                 // second spare key buffer of the bucket finish
-    uint8_t *bint = nullptr;
+    uint8_t *tflag = nullptr;                // tie flag per position (bucket finish)
     uint32_t *bcnt = nullptr;                // B_int counts per 64 symbols, inside segments
     uint32_t *bseg = nullptr;                // counts before each segment, segment totals
     uint32_t *soff = nullptr;                // block position of each read
@@ -309,7 +309,7 @@ void free_ws(Workspace &w) {
     dfree(w.rank);
     dfree(w.g);
     dfree(w.gsa);
-    dfree(w.bint);
+    dfree(w.tflag);
     dfree(w.bcnt);
     dfree(w.bseg);
     dfree(w.soff);
@@ -340,7 +340,7 @@ int ensure_ws(bwt_set *h, uint64_t need) {
     ok &= dalloc(&w.rank, cap) == hipSuccess;
     ok &= dalloc(&w.g, cap) == hipSuccess;
     ok &= dalloc(&w.gsa, cap) == hipSuccess;
-    ok &= dalloc(&w.bint, cap + 64) == hipSuccess;
+    ok &= dalloc(&w.tflag, cap) == hipSuccess;
     ok &= dalloc(&w.bcnt, (div_up(cap, 64) + 2) * 4) == hipSuccess;
     ok &= dalloc(&w.bseg, (2 * (div_up(cap, 64 << BINT_SEG_SHIFT) + 2) + 1) * 4) == hipSuccess;
     ok &= dalloc(&w.soff, cap + 2) == hipSuccess;
@@ -503,11 +503,9 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *ks, uint32_t *vs, uint32_
         Scope sk(h, s, SPAN_BUCKET);
         HIPCHK(h, launch_bucket_bounds(ks, n, bshift, nb, bstart, bend, err, s));
         HIPCHK(h, launch_bucket_sort(ks, vs, n, bstart, bend, trange, nb, bshift, kfirst,
-                                     REFINE_LIMIT,
-                                     w.misc + MISC_LARGE, tcnt, osz, part, res, olist, ooff, err,
-                                     s));
-        HIPCHK(h, launch_bucket_emit(ks, n, bshift, bstart, bend, trange, tcnt, nb, kfirst, w.U[0],
-                                     n, err, s));
+                                     REFINE_LIMIT, w.misc + MISC_LARGE, tcnt, osz, w.tflag, part,
+                                     res, olist, ooff, err, s));
+        HIPCHK(h, launch_bucket_emit(ks, w.tflag, n, bshift, trange, tcnt, nb, w.U[0], n, err, s));
     }
     const uint32_t *pw = reinterpret_cast<const uint32_t *>(h->pinned);
     HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, (MISC_BK + 3 - MISC_NU) * 4,

@@ -238,7 +238,8 @@ __device__ __forceinline__ uint32_t rows_ties(const uint64_t (&k)[R], const uint
 template <int E>
 __device__ uint32_t wave_bucket(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                 uint32_t s0, uint32_t z, int kshort, uint32_t *__restrict__ s_v,
-                                uint32_t limit, uint32_t *__restrict__ large) {
+                                uint32_t limit, uint32_t *__restrict__ large,
+                                uint8_t *__restrict__ s_f) {
     const int lane = lane_id();
     uint64_t k[E];
     uint32_t x[E];
@@ -265,7 +266,10 @@ __device__ uint32_t wave_bucket(uint64_t *__restrict__ keys, uint32_t *__restric
         }
     }
     uint32_t cnt;
-    (void)wave_ties<E>(k, z, kshort, limit, large, &cnt);
+    const uint32_t rows = wave_ties<E>(k, z, kshort, limit, large, &cnt);
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+        if ((rows >> r) & 1u) s_f[r * 64 + lane] = 1;
     return cnt;
 }
 
@@ -368,36 +372,6 @@ __global__ __launch_bounds__(256) void bucket_scan_down_kernel(
     if (t == 0 && tid == 0) ooff[res[1]] = res[2];
 }
 
-// Tied suffixes of the buckets sorted in registers, listed from U[tpre[b]]
-// in slot order (the keys are read again, sorted).
-template <int E>
-__device__ void wave_emit(const uint64_t *__restrict__ keys, uint32_t s0, uint32_t z, int kshort,
-                          uint32_t at, uint32_t *__restrict__ U, uint32_t ucap,
-                          uint32_t *__restrict__ err) {
-    const int lane = lane_id();
-    uint64_t k[E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const uint32_t i = (uint32_t)(r * 64 + lane);
-        k[r] = i < z ? keys[s0 + i] : ~0ull;
-    }
-    uint32_t cnt, dummy = 0;
-    const uint32_t rows = wave_ties<E>(k, z, kshort, 0xffffffffu, &dummy, &cnt);
-    if (at + cnt > ucap) {
-        if (lane == 0) atomicOr(err, 512u);
-        return;
-    }
-    const uint64_t ltm = lanemask_lt();
-    uint32_t before = 0;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const bool t = (rows >> r) & 1u;
-        const uint64_t tb = __ballot(t);
-        if (t) U[at + before + (uint32_t)__popcll(tb & ltm)] = s0 + (uint32_t)(r * 64 + lane);
-        before += (uint32_t)__popcll(tb);
-    }
-}
-
 // ---- tile-wise finish: a workgroup owns the buckets that start in its tile
 // of BT_T positions; they end at most BUCKET_CAP past it unless oversized.
 constexpr uint32_t BT_T = 2048;
@@ -473,24 +447,29 @@ __device__ uint32_t tile_buckets(const uint64_t *__restrict__ keys, uint32_t a, 
 // Sorts the owned buckets of each tile: groups of four buckets of at most 64
 // suffixes in registers (one per row) straight from LDS, larger ones up to
 // BUCKET_CAP one at a time from global memory; records tcnt / osz for every
-// owned bucket (both tables zeroed beforehand).
+// owned bucket (both tables zeroed beforehand) and one flag byte per position
+// of the tile's window (1 = tied, 0 = settled or in an oversized bucket).
 __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t n, int bshift, uint32_t nb,
     const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bend,
     const uint32_t *__restrict__ trange, int kshort,
     uint32_t limit, uint32_t *__restrict__ large, uint32_t *__restrict__ tcnt,
-    uint32_t *__restrict__ osz, uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ osz, uint8_t *__restrict__ tflag, uint32_t *__restrict__ err) {
     __shared__ uint64_t s_k[BT_WIN];
     __shared__ uint32_t s_v[BT_WIN];
     __shared__ uint16_t s_bs[BT_WIN + 1];
     __shared__ uint32_t s_tmp[4];
     __shared__ uint32_t s_big[4][BUCKET_CAP];
+    __shared__ uint8_t s_f[BT_WIN];
     const uint32_t tid = threadIdx.x;
     const int wave = (int)(tid >> 6), lane = lane_id();
     const uint32_t a = trange[2 * blockIdx.x], b = trange[2 * blockIdx.x + 1];
     if (a >= b) return;
     const uint32_t w = b - a < BT_WIN ? b - a : BT_WIN;
-    for (uint32_t i = tid; i < w; i += 256) s_v[i] = vals[a + i];
+    for (uint32_t i = tid; i < w; i += 256) {
+        s_v[i] = vals[a + i];
+        s_f[i] = 0;
+    }
     const uint32_t nbk = tile_buckets(keys, a, w, bshift, s_k, s_bs, s_tmp);
     const bool composite = bshift <= 58;
     // chunks of eight consecutive buckets per wave: two per row (32 lanes
@@ -551,6 +530,7 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                 const uint64_t tb = __ballot(t);
                 ties[2 * r] = (uint32_t)__popcll(tb & 0xffffffffull);
                 ties[2 * r + 1] = (uint32_t)__popcll(tb >> 32);
+                if (t) s_f[sth[r] + hl] = 1;
             }
             (void)limit;
         } else {
@@ -586,7 +566,10 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                             vals[a + st4[r] + lane] = s_v[st4[r] + (uint32_t)(c[r] & 63u)];
                         }
                     }
-                    (void)rows_ties<4>(k, z4, kshort, limit, large, t4);
+                    const uint32_t rows = rows_ties<4>(k, z4, kshort, limit, large, t4);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if ((rows >> r) & 1u) s_f[st4[r] + lane] = 1;
                 } else {
 #pragma unroll 1
                     for (int r = 0; r < 4; ++r) {
@@ -594,9 +577,10 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                         if (zz >= 2 && zz <= BUCKET_CAP) {
                             uint32_t *sv = s_big[wave];
                             const uint32_t s0 = a + st4[r];
-                            if (zz <= 64) t4[r] = wave_bucket<1>(keys, vals, s0, zz, kshort, sv, limit, large);
-                            else if (zz <= 128) t4[r] = wave_bucket<2>(keys, vals, s0, zz, kshort, sv, limit, large);
-                            else t4[r] = wave_bucket<4>(keys, vals, s0, zz, kshort, sv, limit, large);
+                            uint8_t *sf = s_f + st4[r];
+                            if (zz <= 64) t4[r] = wave_bucket<1>(keys, vals, s0, zz, kshort, sv, limit, large, sf);
+                            else if (zz <= 128) t4[r] = wave_bucket<2>(keys, vals, s0, zz, kshort, sv, limit, large, sf);
+                            else t4[r] = wave_bucket<4>(keys, vals, s0, zz, kshort, sv, limit, large, sf);
                             __builtin_amdgcn_wave_barrier();
                             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                         }
@@ -620,76 +604,53 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
             if (zr > BUCKET_CAP) osz[ir] = zr;
         }
     }
+    __syncthreads();
+    for (uint32_t i = tid; i < w; i += 256) tflag[a + i] = s_f[i];
 }
 
-// Lists the tied suffixes of the owned buckets of each tile from U[tpre[b]]
-// (slot order), reading the sorted keys once more.
+// Lists the tied suffixes of the owned buckets of each tile in slot order,
+// from U[tpre[b]] for the tile's first bucket b, using the flags the tile sort
+// left for the tile's window.
 __global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
-    const uint64_t *__restrict__ keys, uint32_t n, int bshift,
-    const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bend,
+    const uint64_t *__restrict__ keys, const uint8_t *__restrict__ tflag, int bshift,
     const uint32_t *__restrict__ trange, const uint32_t *__restrict__ tpre, uint32_t nb,
-    int kshort, uint32_t *__restrict__ U,
-    uint32_t ucap, uint32_t *__restrict__ err) {
-    __shared__ uint64_t s_k[BT_WIN];
-    __shared__ uint16_t s_bs[BT_WIN + 1];
+    uint32_t *__restrict__ U, uint32_t ucap, uint32_t *__restrict__ err) {
+    __shared__ uint8_t s_f[BT_WIN];
     __shared__ uint32_t s_tmp[4];
     const uint32_t tid = threadIdx.x;
-    const int wave = (int)(tid >> 6), lane = lane_id();
     const uint32_t a = trange[2 * blockIdx.x], b = trange[2 * blockIdx.x + 1];
     if (a >= b) return;
     const uint32_t w = b - a < BT_WIN ? b - a : BT_WIN;
-    const uint32_t nbk = tile_buckets(keys, a, w, bshift, s_k, s_bs, s_tmp);
-    for (uint32_t g = (uint32_t)wave * 4; g < nbk; g += 16) {
-        uint32_t st[4], z[4], at[4];
-        bool small = true, any = false;
+    for (uint32_t i = tid; i < w; i += 256) s_f[i] = tflag[a + i];
+    const uint64_t id = keys[a] >> bshift;
+    __syncthreads();
+    // each thread a contiguous run of the window, so the list keeps order
+    constexpr uint32_t PER = (BT_WIN + 255) / 256;
+    const uint32_t i0 = tid * PER;
+    uint32_t flags = 0, cnt = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t j = g + r;
-            st[r] = 0;
-            z[r] = 0;
-            at[r] = 0;
-            if (j < nbk) {
-                st[r] = s_bs[j];
-                const uint32_t e = s_bs[j + 1];
-                const uint32_t id = (uint32_t)(s_k[st[r]] >> bshift);
-                const uint32_t zz = j + 1 < nbk || a + e == b ? e - st[r] : bend[id] - bstart[id];
-                at[r] = tpre[id];
-                const uint32_t next = id + 1 < nb ? tpre[id + 1] : ucap;
-                if (next != at[r] && zz >= 2 && zz <= BUCKET_CAP) z[r] = zz;
-            }
-            small = small && z[r] <= 64;
-            any = any || z[r] > 0;
-        }
-        if (!any) continue;
-        if (small) {
-            uint64_t k[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) k[r] = (uint32_t)lane < z[r] ? s_k[st[r] + lane] : ~0ull;
-            uint32_t cnt[4];
-            uint32_t dummy = 0;
-            const uint32_t rows = rows_ties<4>(k, z, kshort, 0xffffffffu, &dummy, cnt);
-            const uint64_t ltm = lanemask_lt();
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (at[r] + cnt[r] > ucap) {
-                    if (lane == 0) atomicOr(err, 512u);
-                    continue;
-                }
-                const bool t = (rows >> r) & 1u;
-                const uint64_t tb = __ballot(t);
-                if (t) U[at[r] + (uint32_t)__popcll(tb & ltm)] = a + st[r] + (uint32_t)lane;
-            }
-        } else {
-#pragma unroll 1
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t zz = z[r];
-                if (zz == 0) continue;
-                if (zz <= 64) wave_emit<1>(keys, a + st[r], zz, kshort, at[r], U, ucap, err);
-                else if (zz <= 128) wave_emit<2>(keys, a + st[r], zz, kshort, at[r], U, ucap, err);
-                else wave_emit<4>(keys, a + st[r], zz, kshort, at[r], U, ucap, err);
-            }
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t i = i0 + q;
+        if (i < w && s_f[i]) {
+            flags |= 1u << q;
+            ++cnt;
         }
     }
+    uint32_t tot;
+    uint32_t at = block_excl_sum256(cnt, s_tmp, &tot);
+    if (tot == 0) return;
+    if (id >= nb) {
+        if (tid == 0) atomicOr(err, 512u);
+        return;
+    }
+    const uint32_t base = tpre[id];
+    if (base + tot > ucap) {
+        if (tid == 0) atomicOr(err, 512u);
+        return;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q)
+        if ((flags >> q) & 1u) U[base + at++] = a + i0 + q;
 }
 
 // Gathered index j lies in the oversized bucket olist[q] with
@@ -788,9 +749,9 @@ hipError_t launch_bucket_bounds(const uint64_t *keys, uint32_t n, int bshift, ui
 hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, uint32_t n, const uint32_t *bstart,
                               const uint32_t *bend, uint32_t *trange, uint32_t nb, int bshift,
                               int kshort, uint32_t limit,
-                              uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint32_t *part,
-                              uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *err,
-                              hipStream_t s) {
+                              uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint8_t *tflag,
+                              uint32_t *part, uint32_t *res, uint32_t *olist, uint32_t *ooff,
+                              uint32_t *err, hipStream_t s) {
     const uint32_t ntiles = (uint32_t)div_up(nb, BT_TILE);
     if (ntiles > 4 * 1024) return hipErrorInvalidValue;
     fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(tcnt, nb, 0u);
@@ -800,7 +761,7 @@ hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, uint32_t n, const 
         tile_ranges_kernel<<<(unsigned)div_up(nt, 256), 256, 0, s>>>(keys, n, bshift, nb, bstart,
                                                                      bend, nt, trange);
         bucket_tile_sort_kernel<<<nt, 256, 0, s>>>(keys, vals, n, bshift, nb, bstart, bend, trange,
-                                                   kshort, limit, large, tcnt, osz, err);
+                                                   kshort, limit, large, tcnt, osz, tflag, err);
     }
     bucket_scan_up_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part);
     bucket_scan_top_kernel<<<1, 1024, 0, s>>>(part, ntiles, res);
@@ -808,14 +769,12 @@ hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, uint32_t n, const 
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_emit(const uint64_t *keys, uint32_t n, int bshift,
-                              const uint32_t *bstart, const uint32_t *bend,
-                              const uint32_t *trange, const uint32_t *tpre,
-                              uint32_t nb, int kshort, uint32_t *U, uint32_t ucap, uint32_t *err,
-                              hipStream_t s) {
+hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32_t n, int bshift,
+                              const uint32_t *trange, const uint32_t *tpre, uint32_t nb,
+                              uint32_t *U, uint32_t ucap, uint32_t *err, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    bucket_tile_emit_kernel<<<(unsigned)div_up(n, BT_T), 256, 0, s>>>(
-        keys, n, bshift, bstart, bend, trange, tpre, nb, kshort, U, ucap, err);
+    bucket_tile_emit_kernel<<<(unsigned)div_up(n, BT_T), 256, 0, s>>>(keys, tflag, bshift, trange,
+                                                                      tpre, nb, U, ucap, err);
     return hipGetLastError();
 }
 
