@@ -148,30 +148,29 @@ hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const ui
                              uint32_t *hist0, hipStream_t s);
 
 // Bucket finish of the first sort (k_bucket.hip).  After radix passes on the
-// top digits, keys sit in nb = 2^B buckets of equal bits above bshift, each
-// a contiguous run.  bucket_bounds: bstart/bend of every bucket that occurs
-// (bstart = ABSENT otherwise).  bucket_sort: every bucket of 2 .. BUCKET_CAP
-// suffixes sorted in place by one wave (*large set for a tied group above
-// limit); then per bucket tcnt = tied suffixes before it (exclusive prefix)
-// and osz = its size if above BUCKET_CAP; the oversized buckets in bucket
-// order in olist, their starts in the gathered array in ooff (ooff[count] =
-// total); res = {tied suffixes, oversized buckets, oversized suffixes}; part
-// holds 3 words per 4096 bucket ids; trange 2 words per 2048 positions;
-// tflag one byte per position of a tile's window (1 = tied).  bucket_emit
-// lists the tied suffixes of the sorted buckets in U (slot order) from tflag.  oversize_gather copies the oversized
-// buckets to ck/cv; once sorted there on the whole key, oversize_scatter puts
-// them back and oversize_ties_map appends their tied suffixes (gathered
-// indices U2[0 .. *nU2)) to U after the first `base`, setting *nU.
+// top digits, keys kin sit in nb = 2^B buckets of equal bits above bshift,
+// each a contiguous run.  bucket_sort: every bucket of 1 .. BUCKET_CAP
+// suffixes sorted by one wave into kout / vout at the same positions (*large
+// set for a tied group above limit); per bucket tcnt = tied suffixes before it
+// (exclusive prefix) and osz = its size if above BUCKET_CAP, with its start in
+// bstart (oversized buckets only); the oversized buckets in bucket order in
+// olist, their starts in the gathered array in ooff (ooff[count] = total); res
+// = {tied suffixes, oversized buckets, oversized suffixes}; part holds 3 words
+// per 4096 bucket ids; trange 2 words per 2048 positions; tflag one byte per
+// position (1 = tied).  bucket_emit lists the tied suffixes of the sorted
+// buckets in U (slot order) from tflag.  oversize_gather copies the oversized
+// buckets of kin to ck/cv; once sorted there on the whole key,
+// oversize_scatter puts them into kout / vout and oversize_ties_map appends
+// their tied suffixes (gathered indices U2[0 .. *nU2)) to U after the first
+// `base`, setting *nU.
 constexpr uint32_t BUCKET_CAP = 256;
 constexpr int BUCKET_MAX_BITS = 24;
-hipError_t launch_bucket_bounds(const uint64_t *keys, uint32_t n, int bshift, uint32_t nb,
-                                uint32_t *bstart, uint32_t *bend, uint32_t *err, hipStream_t s);
-hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, uint32_t n, const uint32_t *bstart,
-                              const uint32_t *bend, uint32_t *trange, uint32_t nb, int bshift,
-                              int kshort, uint32_t limit,
-                              uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint8_t *tflag,
-                              uint32_t *part, uint32_t *res, uint32_t *olist, uint32_t *ooff,
-                              uint32_t *err, hipStream_t s);
+hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                              uint32_t *vout, uint32_t n, uint32_t *bstart, uint32_t *trange,
+                              uint32_t nb, int bshift, int kshort, uint32_t limit, uint32_t *large,
+                              uint32_t *tcnt, uint32_t *osz, uint8_t *tflag, uint32_t *part,
+                              uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *err,
+                              hipStream_t s);
 hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32_t n, int bshift,
                               const uint32_t *trange, const uint32_t *tpre, uint32_t nb,
                               uint32_t *U, uint32_t ucap, uint32_t *err, hipStream_t s);

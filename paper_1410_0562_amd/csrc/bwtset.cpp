@@ -485,27 +485,32 @@ int block_prep(bwt_set *h, hipStream_t s, const uint64_t *off, uint32_t m_blk, u
 
 // Finishes a first sort whose radix passes covered only the top digits:
 // buckets of up to BUCKET_CAP suffixes are sorted by one wave each, larger
-// ones are gathered, radix-sorted on the whole key and put back; the tied
-// suffixes of both end up in U[0] (count in *nU, *large for a group above
-// REFINE_LIMIT).
-int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *ks, uint32_t *vs, uint32_t n, int sort_bits,
-                  int B, int kfirst, uint32_t *nU, bool *large) {
+// ones are gathered and radix-sorted on the whole key, all of them into the
+// other key / value pair, where ks / vs point on return; the tied suffixes of
+// both end up in U[0] (count in *nU, *large for a group above REFINE_LIMIT).
+int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint32_t n,
+                  int sort_bits, int B, int kfirst, uint32_t *nU, bool *large) {
     Workspace &w = h->ws;
     const uint32_t nb = 1u << B;
     const int bshift = sort_bits - B;
     const uint32_t W = w.bk_words;
-    uint32_t *bstart = w.bk, *bend = w.bk + W, *tcnt = w.bk + 2 * W, *osz = w.bk + 3 * W,
-             *olist = w.bk + 4 * W, *ooff = w.bk + 5 * W, *part = w.bk + 6 * W,
-             *trange = part + BK_PART;
+    uint32_t *bstart = w.bk, *tcnt = w.bk + 2 * W, *osz = w.bk + 3 * W, *olist = w.bk + 4 * W,
+             *ooff = w.bk + 5 * W, *part = w.bk + 6 * W, *trange = part + BK_PART;
     uint32_t *err = w.misc + MISC_ERR, *res = w.misc + MISC_BK;
+    // the radix passes left (ks, vs) in one of the (kA, v[0]) / (kB, v[1])
+    // pairs; the sorted buckets go to the other pair
+    if ((ks != w.kA && ks != w.kB) || (vs != w.v[0] && vs != w.v[1])) return fail(h, BWT_EHIP);
+    uint64_t *const kx = ks, *const ky = ks == w.kA ? w.kB : w.kA;
+    uint32_t *const vx = vs, *const vy = vs == w.v[0] ? w.v[1] : w.v[0];
+    ks = ky;
+    vs = vy;
     HIPCHK(h, launch_zero_u32(w.misc + MISC_NU, 2, s));  // tied count, large flag
     {
         Scope sk(h, s, SPAN_BUCKET);
-        HIPCHK(h, launch_bucket_bounds(ks, n, bshift, nb, bstart, bend, err, s));
-        HIPCHK(h, launch_bucket_sort(ks, vs, n, bstart, bend, trange, nb, bshift, kfirst,
+        HIPCHK(h, launch_bucket_sort(kx, vx, ky, vy, n, bstart, trange, nb, bshift, kfirst,
                                      REFINE_LIMIT, w.misc + MISC_LARGE, tcnt, osz, w.tflag, part,
                                      res, olist, ooff, err, s));
-        HIPCHK(h, launch_bucket_emit(ks, w.tflag, n, bshift, trange, tcnt, nb, w.U[0], n, err, s));
+        HIPCHK(h, launch_bucket_emit(kx, w.tflag, n, bshift, trange, tcnt, nb, w.U[0], n, err, s));
     }
     const uint32_t *pw = reinterpret_cast<const uint32_t *>(h->pinned);
     HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, (MISC_BK + 3 - MISC_NU) * 4,
@@ -517,25 +522,20 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *ks, uint32_t *vs, uint32_
     *large = pw[MISC_LARGE - MISC_NU] != 0;
     if (no == 0) return BWT_OK;
     if (no > n || nob == 0 || nob > nb || tied > n) return fail(h, BWT_EHIP);
-    // two key and two value buffers that hold neither the sorted block nor g
-    // (the doubling fallback may build the keys from g again)
-    uint64_t *kf[2];
-    uint32_t *vf[2];
-    {
-        int a = 0, b = 0;
-        for (uint64_t *p : {w.kA, w.kB, w.gsa})
-            if (p != ks && a < 2) kf[a++] = p;
-        for (uint32_t *p : w.v)
-            if (p != vs && b < 2) vf[b++] = p;
-    }
-    HIPCHK(h, launch_oversize_gather(ks, vs, bstart, olist, ooff, nob, no, n, kf[0], vf[0], err, s));
+    // the oversized buckets are sorted in two key and two value buffers that
+    // hold neither the sorted block nor g (the doubling fallback may build the
+    // keys from g again): the spare pair and the radix output, which is free
+    // once they are gathered
+    uint64_t *kf[2] = {w.gsa, kx};
+    uint32_t *vf[2] = {w.v[2], vx};
+    HIPCHK(h, launch_oversize_gather(kx, vx, bstart, olist, ooff, nob, no, n, kf[0], vf[0], err, s));
     uint64_t *ck;
     uint32_t *cv;
     int rc = radix_sort(h, s, kf[0], vf[0], kf[1], vf[1], no, sort_bits, false, &ck, &cv);
     if (rc) return rc;
     {
         Scope sk(h, s, SPAN_BUCKET);
-        HIPCHK(h, launch_oversize_scatter(ck, cv, no, bstart, olist, ooff, nob, n, ks, vs, err, s));
+        HIPCHK(h, launch_oversize_scatter(ck, cv, no, bstart, olist, ooff, nob, n, ky, vy, err, s));
         HIPCHK(h, launch_group_heads(ck, cv, nullptr, no, kfirst, cv, nullptr, w.U[1],
                                      w.misc + MISC_NU2, REFINE_LIMIT, w.misc + MISC_LARGE,
                                      w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(), err, s));
@@ -614,6 +614,9 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     bool large = false;
     if (buckets) {
         if ((rc = bucket_finish(h, s, ks, vs, n_blk, sort_bits, B, kfirst, &nU, &large))) return rc;
+        sa = vs;
+        *sa_out = sa;
+        *gkeys_out = ks;
     } else {
         HIPCHK(h, launch_zero_u32(w.misc + MISC_LARGE, 1, s));
         {

@@ -3,17 +3,19 @@
 // Radix passes on the top digits of the first key (see bwt_internal.hpp)
 // leave the suffixes in buckets of equal top B bits, each bucket a contiguous
 // run in position order (the passes are stable); B is chosen for about 32
-// suffixes per bucket.  One wavefront finishes a bucket of at most
-// BUCKET_CAP = 256 suffixes in registers (four buckets of at most 64 at
-// once, one per register row, so that their shuffles overlap): a bitonic network over
-// (key, index in the bucket) -- the index keeps equal keys in position order,
-// which is terminator order -- with 64 x E elements per wave (element
-// r * 64 + lane in register r of that lane), so the compare-exchanges at
-// distance >= 64 stay inside a lane and the shorter ones are lane shuffles;
-// no workgroup barrier is involved.  The wave then appends the bucket's tied
-// groups (equal keys that do not end at a terminator) to the list of
-// unresolved suffixes with one reservation, so every group stays contiguous
-// in the list.  Larger buckets are piles of identical short suffixes (every
+// suffixes per bucket.  A workgroup takes a tile of positions, finds the
+// bucket starts in it from the keys it loads, and one wavefront finishes a
+// bucket of at most BUCKET_CAP = 256 suffixes in registers (four buckets of
+// at most 64 at once, one per register row, so that their shuffles overlap):
+// a bitonic network over (key, index in the bucket) -- the index keeps equal
+// keys in position order, which is terminator order -- with 64 x E elements
+// per wave (element r * 64 + lane in register r of that lane), so the
+// compare-exchanges at distance >= 64 stay inside a lane and the shorter ones
+// are lane shuffles; no workgroup barrier is involved.  The wave flags the
+// bucket's tied suffixes (equal keys that do not end at a terminator); after
+// a scan of the per-bucket counts, the flags of each tile are listed in slot
+// order, so every tied group stays contiguous in the list of unresolved
+// suffixes.  Larger buckets are piles of identical short suffixes (every
 // read's terminator suffix has the same g, as have all suffixes "A$", ...):
 // they are gathered into one array, radix-sorted on the whole key with the
 // ordinary passes, put back, and their ties found by the ordinary scan.
@@ -23,36 +25,9 @@ namespace bwt {
 
 namespace {
 
-constexpr uint32_t ABSENT = 0xffffffffu;
-
 __global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t n, uint32_t v) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-__global__ void bucket_fill_kernel(uint32_t *__restrict__ bstart, uint32_t nb) {
-    uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < nb) bstart[b] = ABSENT;
-}
-
-// Keys sorted by their bits above bshift: bstart[b] / bend[b] = first / one
-// past the last position of bucket b (only for buckets that occur).
-__global__ void bucket_bounds_kernel(const uint64_t *__restrict__ keys, uint32_t n, int bshift,
-                                     uint32_t nb, uint32_t *__restrict__ bstart,
-                                     uint32_t *__restrict__ bend, uint32_t *__restrict__ err) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t b = keys[i] >> bshift;
-    if (b >= nb) {
-        atomicOr(err, 256u);
-        return;
-    }
-    const uint64_t bp = i > 0 ? keys[i - 1] >> bshift : ~0ull;
-    if (bp != b) {
-        bstart[(uint32_t)b] = i;
-        if (i > 0 && bp < nb) bend[(uint32_t)bp] = i;
-    }
-    if (i + 1 == n) bend[(uint32_t)b] = n;
 }
 
 // (key, index) order
@@ -233,11 +208,14 @@ __device__ __forceinline__ uint32_t rows_ties(const uint64_t (&k)[R], const uint
     return rows;
 }
 
-// One bucket of z (2 .. 64 * E) suffixes at s0, sorted by one wave and
-// written back; returns its number of tied suffixes.
+// One bucket of z (2 .. 64 * E) suffixes at window offset st (keys s_k,
+// values s_v in LDS), sorted by one wave and written to position p0 of
+// kout / vout; its tie flags go to s_f[st ..].  Returns its number of tied
+// suffixes.
 template <int E>
-__device__ uint32_t wave_bucket(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                uint32_t s0, uint32_t z, int kshort, uint32_t *__restrict__ s_v,
+__device__ uint32_t wave_bucket(const uint64_t *__restrict__ s_k, const uint32_t *__restrict__ s_v,
+                                uint32_t st, uint32_t z, uint64_t *__restrict__ kout,
+                                uint32_t *__restrict__ vout, uint32_t p0, int kshort,
                                 uint32_t limit, uint32_t *__restrict__ large,
                                 uint8_t *__restrict__ s_f) {
     const int lane = lane_id();
@@ -247,29 +225,22 @@ __device__ uint32_t wave_bucket(uint64_t *__restrict__ keys, uint32_t *__restric
     for (int r = 0; r < E; ++r) {
         const uint32_t i = (uint32_t)(r * 64 + lane);
         x[r] = i;
-        if (i < z) {
-            k[r] = keys[s0 + i];
-            s_v[i] = vals[s0 + i];
-        } else {
-            k[r] = ~0ull;  // a real key never has all length bits set
-        }
+        k[r] = i < z ? s_k[st + i] : ~0ull;  // a real key never has all length bits set
     }
     wave_bitonic<E>(k, x, lane);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t i = (uint32_t)(r * 64 + lane);
         if (i < z) {
-            keys[s0 + i] = k[r];
-            vals[s0 + i] = s_v[x[r]];
+            kout[p0 + i] = k[r];
+            vout[p0 + i] = s_v[st + x[r]];
         }
     }
     uint32_t cnt;
     const uint32_t rows = wave_ties<E>(k, z, kshort, limit, large, &cnt);
 #pragma unroll
     for (int r = 0; r < E; ++r)
-        if ((rows >> r) & 1u) s_f[r * 64 + lane] = 1;
+        if ((rows >> r) & 1u) s_f[st + r * 64 + lane] = 1;
     return cnt;
 }
 
@@ -377,100 +348,117 @@ __global__ __launch_bounds__(256) void bucket_scan_down_kernel(
 constexpr uint32_t BT_T = 2048;
 constexpr uint32_t BT_WIN = BT_T + BUCKET_CAP;
 
-// The owned range [a, b) of tile t: a = first bucket start at or after t * BT_T,
-// b = first bucket start at or after (t + 1) * BT_T (or n).
-__device__ __forceinline__ void tile_range(const uint64_t *__restrict__ keys, uint32_t n,
-                                           int bshift, uint32_t nb,
-                                           const uint32_t *__restrict__ bstart,
-                                           const uint32_t *__restrict__ bend, uint32_t t,
-                                           uint32_t *a, uint32_t *b) {
-    const uint32_t t0 = t * BT_T;
-    uint32_t x = t0 < n ? t0 : n, y = t0 + BT_T < n ? t0 + BT_T : n;
-    if (x < n) {
-        const uint64_t bb = keys[x] >> bshift;
-        if (bb >= nb) x = n;  // out of range keys were flagged by the bounds pass
-        else if (bstart[bb] != x) x = bend[bb];
+// First position in [lo, hi) whose bucket (key >> bshift) is not bkt, where
+// the positions of bucket bkt form a prefix of [lo, hi); hi if there is none.
+// One wave, 65-way steps: about five dependent loads for a whole block.
+__device__ uint32_t bucket_end_search(const uint64_t *__restrict__ keys, int bshift, uint64_t bkt,
+                                      uint32_t lo, uint32_t hi) {
+    const int lane = lane_id();
+    while (hi - lo > 64) {
+        const uint64_t span = hi - lo;
+        // strictly increasing probes inside (lo, hi)
+        const uint32_t pr = lo + (uint32_t)((span * (uint64_t)(lane + 1)) / 65u);
+        const bool eq = (keys[pr] >> bshift) == bkt;
+        const int c = __popcll(__ballot(eq));  // the equal lanes are a prefix
+        const uint32_t plo = __shfl(pr, c > 0 ? c - 1 : 0, 64);
+        const uint32_t phi = __shfl(pr, c < 64 ? c : 63, 64);
+        if (c > 0) lo = plo + 1;
+        if (c < 64) hi = phi;
     }
-    if (y < n) {
-        const uint64_t bb = keys[y] >> bshift;
-        if (bb >= nb) y = n;
-        else if (bstart[bb] != y) y = bend[bb];
-    }
-    *a = x;
-    *b = y < n ? y : n;
+    const uint32_t p = lo + (uint32_t)lane;
+    const bool ne = p < hi && (keys[p] >> bshift) != bkt;
+    const uint64_t m = __ballot(ne);
+    return m ? lo + (uint32_t)__builtin_ctzll(m) : hi;
 }
 
-// trange[2t], trange[2t + 1] = owned range of tile t, for every tile.
-__global__ void tile_ranges_kernel(const uint64_t *__restrict__ keys, uint32_t n, int bshift,
-                                   uint32_t nb, const uint32_t *__restrict__ bstart,
-                                   const uint32_t *__restrict__ bend, uint32_t ntiles,
-                                   uint32_t *__restrict__ trange) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
-    uint32_t a, b;
-    tile_range(keys, n, bshift, nb, bstart, bend, t, &a, &b);
-    trange[2 * t] = a;
-    trange[2 * t + 1] = b;
-}
-
-// Loads keys [a, a + w) of the owned range into s_k and lists the bucket
-// starts (window offsets) in s_bs, ending with w; returns the bucket count.
-// Contains barriers.
-__device__ uint32_t tile_buckets(const uint64_t *__restrict__ keys, uint32_t a, uint32_t w,
-                                 int bshift, uint64_t *__restrict__ s_k,
-                                 uint16_t *__restrict__ s_bs, uint32_t *__restrict__ s_tmp) {
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < w; i += 256) s_k[i] = keys[a + i];
-    __syncthreads();
-    // each thread a contiguous run of the window, so the list keeps order
-    constexpr uint32_t PER = (BT_WIN + 255) / 256;
-    const uint32_t i0 = tid * PER;
-    uint32_t flags = 0, cnt = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < PER; ++q) {
-        const uint32_t i = i0 + q;
-        if (i < w && (i == 0 || (s_k[i] >> bshift) != (s_k[i - 1] >> bshift))) {
-            flags |= 1u << q;
-            ++cnt;
-        }
-    }
-    uint32_t tot;
-    uint32_t at = block_excl_sum256(cnt, s_tmp, &tot);
-#pragma unroll
-    for (uint32_t q = 0; q < PER; ++q)
-        if ((flags >> q) & 1u) s_bs[at++] = (uint16_t)(i0 + q);
-    if (tid == 0) s_bs[tot] = (uint16_t)w;
-    __syncthreads();
-    return tot;
-}
-
-// Sorts the owned buckets of each tile: groups of four buckets of at most 64
-// suffixes in registers (one per row) straight from LDS, larger ones up to
-// BUCKET_CAP one at a time from global memory; records tcnt / osz for every
-// owned bucket (both tables zeroed beforehand) and one flag byte per position
-// of the tile's window (1 = tied, 0 = settled or in an oversized bucket).
+// One workgroup per tile of BT_T positions of the key array kin (sorted by
+// the top digits, so each bucket is a contiguous run).  It loads the window
+// [t0, t0 + BT_WIN) and finds the bucket starts in it; it owns the buckets
+// that start in [t0, t0 + BT_T), which end inside the window unless they are
+// oversized.  Those of at most BUCKET_CAP suffixes are sorted in registers:
+// groups of four buckets of at most 64 (one per row, or eight of at most 32
+// in half rows), larger ones one at a time, and written to kout / vout at the
+// same positions (kin is only read, so the windows that overlap the next tile
+// see unchanged keys).  Per owned bucket b it records tcnt[b] (tied suffixes)
+// and, when oversized, osz[b] (its size) and bstart[b] (its start); both
+// tables are zeroed beforehand.  trange[2t], trange[2t + 1] = the owned range
+// [a, e), and tflag[p] for p in [a, min(e, t0 + BT_WIN)) = 1 if the suffix is
+// tied, else 0.
 __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
-    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, uint32_t n, int bshift, uint32_t nb,
-    const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bend,
-    const uint32_t *__restrict__ trange, int kshort,
-    uint32_t limit, uint32_t *__restrict__ large, uint32_t *__restrict__ tcnt,
-    uint32_t *__restrict__ osz, uint8_t *__restrict__ tflag, uint32_t *__restrict__ err) {
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t n, int bshift, uint32_t nb,
+    uint32_t *__restrict__ bstart, uint32_t *__restrict__ trange, int kshort, uint32_t limit,
+    uint32_t *__restrict__ large, uint32_t *__restrict__ tcnt, uint32_t *__restrict__ osz,
+    uint8_t *__restrict__ tflag, uint32_t *__restrict__ err) {
     __shared__ uint64_t s_k[BT_WIN];
     __shared__ uint32_t s_v[BT_WIN];
     __shared__ uint16_t s_bs[BT_WIN + 1];
     __shared__ uint32_t s_tmp[4];
-    __shared__ uint32_t s_big[4][BUCKET_CAP];
     __shared__ uint8_t s_f[BT_WIN];
+    __shared__ uint32_t s_end;
     const uint32_t tid = threadIdx.x;
     const int wave = (int)(tid >> 6), lane = lane_id();
-    const uint32_t a = trange[2 * blockIdx.x], b = trange[2 * blockIdx.x + 1];
-    if (a >= b) return;
-    const uint32_t w = b - a < BT_WIN ? b - a : BT_WIN;
-    for (uint32_t i = tid; i < w; i += 256) {
-        s_v[i] = vals[a + i];
+    const uint32_t t0 = blockIdx.x * BT_T;
+    const uint32_t wl = n - t0 < BT_WIN ? n - t0 : BT_WIN;
+    const uint64_t bprev = t0 > 0 ? kin[t0 - 1] >> bshift : ~0ull;
+    for (uint32_t i = tid; i < wl; i += 256) {
+        s_k[i] = kin[t0 + i];
+        s_v[i] = vin[t0 + i];
         s_f[i] = 0;
     }
-    const uint32_t nbk = tile_buckets(keys, a, w, bshift, s_k, s_bs, s_tmp);
+    __syncthreads();
+    // bucket starts of the window, in order (each thread a contiguous run);
+    // nbk of them lie in the tile
+    uint32_t nbk;
+    {
+        constexpr uint32_t PER = (BT_WIN + 255) / 256;
+        const uint32_t i0 = tid * PER;
+        uint32_t flags = 0, cnt = 0, own = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint32_t i = i0 + q;
+            if (i < wl) {
+                const uint64_t bi = s_k[i] >> bshift;
+                if (bi != (i ? s_k[i - 1] >> bshift : bprev)) {
+                    flags |= 1u << q;
+                    ++cnt;
+                    own += i < BT_T ? 1u : 0u;
+                }
+                if (bi >= nb) atomicOr(err, 256u);
+            }
+        }
+        uint32_t tot;
+        uint32_t at = block_excl_sum256(cnt, s_tmp, &tot);
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q)
+            if ((flags >> q) & 1u) s_bs[at++] = (uint16_t)(i0 + q);
+        (void)block_excl_sum256(own, s_tmp, &nbk);
+        if (tid == 0) s_bs[tot] = (uint16_t)wl;
+    }
+    __syncthreads();
+    if (nbk == 0) {
+        if (tid == 0) {
+            trange[2 * blockIdx.x] = 0;
+            trange[2 * blockIdx.x + 1] = 0;
+        }
+        return;
+    }
+    // end of the last owned bucket: the next start in the window, else the
+    // window reaches the end of the keys, else the bucket is oversized and
+    // goes on past the window
+    if (wave == 0) {
+        const uint32_t e = s_bs[nbk];
+        uint32_t end = t0 + e;
+        if (e == wl && t0 + wl < n)
+            end = bucket_end_search(kin, bshift, s_k[s_bs[nbk - 1]] >> bshift, t0 + wl, n);
+        if (lane == 0) {
+            s_end = end;
+            trange[2 * blockIdx.x] = t0 + s_bs[0];
+            trange[2 * blockIdx.x + 1] = end;
+        }
+    }
+    __syncthreads();
+    const uint32_t tend = s_end - t0;  // may exceed the window (oversized)
     const bool composite = bshift <= 58;
     // chunks of eight consecutive buckets per wave: two per row (32 lanes
     // each) when all eight have at most 32 suffixes, else four per row pass
@@ -485,10 +473,8 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
             id[q] = 0;
             if (j < nbk) {
                 st[q] = s_bs[j];
-                const uint32_t e = s_bs[j + 1];
+                z[q] = (j + 1 < nbk ? (uint32_t)s_bs[j + 1] : tend) - st[q];
                 id[q] = (uint32_t)(s_k[st[q]] >> bshift);
-                // true size (the last bucket of the window may be cut off)
-                z[q] = j + 1 < nbk || a + e == b ? e - st[q] : bend[id[q]] - bstart[id[q]];
             }
             halves = halves && z[q] <= 32;
         }
@@ -513,8 +499,8 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                 const bool ok = hl < zh[r];
                 k[r] = ok ? ((uint64_t)idh[r] << bshift) + (c[r] >> 6) : ~0ull;
                 if (ok) {
-                    keys[a + sth[r] + hl] = k[r];
-                    vals[a + sth[r] + hl] = s_v[sth[r] + (uint32_t)(c[r] & 63u)];
+                    kout[t0 + sth[r] + hl] = k[r];
+                    vout[t0 + sth[r] + hl] = s_v[sth[r] + (uint32_t)(c[r] & 63u)];
                 }
             }
             // ties inside each 32-lane segment (groups are at most 32 long,
@@ -562,8 +548,8 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                         const bool ok = (uint32_t)lane < z4[r];
                         k[r] = ok ? ((uint64_t)id4[r] << bshift) + (c[r] >> 6) : ~0ull;
                         if (ok) {
-                            keys[a + st4[r] + lane] = k[r];
-                            vals[a + st4[r] + lane] = s_v[st4[r] + (uint32_t)(c[r] & 63u)];
+                            kout[t0 + st4[r] + lane] = k[r];
+                            vout[t0 + st4[r] + lane] = s_v[st4[r] + (uint32_t)(c[r] & 63u)];
                         }
                     }
                     const uint32_t rows = rows_ties<4>(k, z4, kshort, limit, large, t4);
@@ -573,16 +559,16 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                 } else {
 #pragma unroll 1
                     for (int r = 0; r < 4; ++r) {
-                        const uint32_t zz = z4[r];
-                        if (zz >= 2 && zz <= BUCKET_CAP) {
-                            uint32_t *sv = s_big[wave];
-                            const uint32_t s0 = a + st4[r];
-                            uint8_t *sf = s_f + st4[r];
-                            if (zz <= 64) t4[r] = wave_bucket<1>(keys, vals, s0, zz, kshort, sv, limit, large, sf);
-                            else if (zz <= 128) t4[r] = wave_bucket<2>(keys, vals, s0, zz, kshort, sv, limit, large, sf);
-                            else t4[r] = wave_bucket<4>(keys, vals, s0, zz, kshort, sv, limit, large, sf);
-                            __builtin_amdgcn_wave_barrier();
-                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        const uint32_t zz = z4[r], sr = st4[r];
+                        if (zz == 1) {
+                            if (lane == 0) {
+                                kout[t0 + sr] = s_k[sr];
+                                vout[t0 + sr] = s_v[sr];
+                            }
+                        } else if (zz >= 2 && zz <= BUCKET_CAP) {
+                            if (zz <= 64) t4[r] = wave_bucket<1>(s_k, s_v, sr, zz, kout, vout, t0 + sr, kshort, limit, large, s_f);
+                            else if (zz <= 128) t4[r] = wave_bucket<2>(s_k, s_v, sr, zz, kout, vout, t0 + sr, kshort, limit, large, s_f);
+                            else t4[r] = wave_bucket<4>(s_k, s_v, sr, zz, kout, vout, t0 + sr, kshort, limit, large, s_f);
                         }
                     }
                 }
@@ -591,26 +577,31 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
             }
         }
         // lane q < 8 records bucket g + q
-        uint32_t tr = 0, zr = 0, ir = 0;
+        uint32_t tr = 0, zr = 0, ir = 0, sr = 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
             if (lane == q) {
                 tr = ties[q];
                 zr = z[q];
                 ir = id[q];
+                sr = st[q];
             }
-        if (lane < 8 && g + lane < nbk) {
+        if (lane < 8 && g + lane < nbk && ir < nb) {
             tcnt[ir] = tr;
-            if (zr > BUCKET_CAP) osz[ir] = zr;
+            if (zr > BUCKET_CAP) {
+                osz[ir] = zr;
+                bstart[ir] = t0 + sr;
+            }
         }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < w; i += 256) tflag[a + i] = s_f[i];
+    const uint32_t fe = tend < wl ? tend : wl;
+    for (uint32_t i = s_bs[0] + tid; i < fe; i += 256) tflag[t0 + i] = s_f[i];
 }
 
 // Lists the tied suffixes of the owned buckets of each tile in slot order,
 // from U[tpre[b]] for the tile's first bucket b, using the flags the tile sort
-// left for the tile's window.
+// left for the owned part of the tile's window.
 __global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
     const uint64_t *__restrict__ keys, const uint8_t *__restrict__ tflag, int bshift,
     const uint32_t *__restrict__ trange, const uint32_t *__restrict__ tpre, uint32_t nb,
@@ -620,7 +611,8 @@ __global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
     const uint32_t tid = threadIdx.x;
     const uint32_t a = trange[2 * blockIdx.x], b = trange[2 * blockIdx.x + 1];
     if (a >= b) return;
-    const uint32_t w = b - a < BT_WIN ? b - a : BT_WIN;
+    const uint32_t t0 = blockIdx.x * BT_T;
+    const uint32_t w = (b - t0 < BT_WIN ? b : t0 + BT_WIN) - a;
     for (uint32_t i = tid; i < w; i += 256) s_f[i] = tflag[a + i];
     const uint64_t id = keys[a] >> bshift;
     __syncthreads();
@@ -737,32 +729,21 @@ __global__ void oversize_ties_map_kernel(const uint32_t *__restrict__ U2,
 
 }  // namespace
 
-hipError_t launch_bucket_bounds(const uint64_t *keys, uint32_t n, int bshift, uint32_t nb,
-                                uint32_t *bstart, uint32_t *bend, uint32_t *err, hipStream_t s) {
-    bucket_fill_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(bstart, nb);
-    if (n > 0)
-        bucket_bounds_kernel<<<(unsigned)div_up(n, 256), 256, 0, s>>>(keys, n, bshift, nb, bstart,
-                                                                     bend, err);
-    return hipGetLastError();
-}
-
-hipError_t launch_bucket_sort(uint64_t *keys, uint32_t *vals, uint32_t n, const uint32_t *bstart,
-                              const uint32_t *bend, uint32_t *trange, uint32_t nb, int bshift,
-                              int kshort, uint32_t limit,
-                              uint32_t *large, uint32_t *tcnt, uint32_t *osz, uint8_t *tflag,
-                              uint32_t *part, uint32_t *res, uint32_t *olist, uint32_t *ooff,
-                              uint32_t *err, hipStream_t s) {
+hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                              uint32_t *vout, uint32_t n, uint32_t *bstart, uint32_t *trange,
+                              uint32_t nb, int bshift, int kshort, uint32_t limit, uint32_t *large,
+                              uint32_t *tcnt, uint32_t *osz, uint8_t *tflag, uint32_t *part,
+                              uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *err,
+                              hipStream_t s) {
     const uint32_t ntiles = (uint32_t)div_up(nb, BT_TILE);
     if (ntiles > 4 * 1024) return hipErrorInvalidValue;
     fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(tcnt, nb, 0u);
     fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(osz, nb, 0u);
     const uint32_t nt = (uint32_t)div_up(n, BT_T);
-    if (nt > 0) {
-        tile_ranges_kernel<<<(unsigned)div_up(nt, 256), 256, 0, s>>>(keys, n, bshift, nb, bstart,
-                                                                     bend, nt, trange);
-        bucket_tile_sort_kernel<<<nt, 256, 0, s>>>(keys, vals, n, bshift, nb, bstart, bend, trange,
-                                                   kshort, limit, large, tcnt, osz, tflag, err);
-    }
+    if (nt > 0)
+        bucket_tile_sort_kernel<<<nt, 256, 0, s>>>(kin, vin, kout, vout, n, bshift, nb, bstart,
+                                                   trange, kshort, limit, large, tcnt, osz, tflag,
+                                                   err);
     bucket_scan_up_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part);
     bucket_scan_top_kernel<<<1, 1024, 0, s>>>(part, ntiles, res);
     bucket_scan_down_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part, res, olist, ooff);
