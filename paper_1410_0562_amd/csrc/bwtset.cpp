@@ -76,6 +76,7 @@ constexpr int MISC_ERR = 7;
 constexpr int MISC_SEG = 8;      // 2 words: queued segments, fallback reads
 constexpr int MISC_BK = 10;      // 3 words: tied suffixes, oversized buckets, their suffixes
 constexpr int MISC_NU2 = 13;     // tied suffixes among the oversized buckets
+constexpr int MISC_PILE = 14;    // 2 words: oversized buckets still to sort, their suffixes
 constexpr int BK_TABLES = 6;     // bucket starts, ends, tie counts, sizes; oversized list, offsets
 constexpr uint32_t BK_PART = 3 * 4096 + 16;  // tile partials of the bucket scans
 constexpr uint32_t MIN_SEG_LEN = 256;
@@ -494,8 +495,9 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
     const uint32_t nb = 1u << B;
     const int bshift = sort_bits - B;
     const uint32_t W = w.bk_words;
-    uint32_t *bstart = w.bk, *tcnt = w.bk + 2 * W, *osz = w.bk + 3 * W, *olist = w.bk + 4 * W,
-             *ooff = w.bk + 5 * W, *part = w.bk + 6 * W, *trange = part + BK_PART;
+    uint32_t *bstart = w.bk, *obad = w.bk + W, *tcnt = w.bk + 2 * W, *osz = w.bk + 3 * W,
+             *olist = w.bk + 4 * W, *ooff = w.bk + 5 * W, *part = w.bk + 6 * W,
+             *trange = part + BK_PART;
     uint32_t *err = w.misc + MISC_ERR, *res = w.misc + MISC_BK;
     // the radix passes left (ks, vs) in one of the (kA, v[0]) / (kB, v[1])
     // pairs; the sorted buckets go to the other pair
@@ -509,19 +511,37 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
         Scope sk(h, s, SPAN_BUCKET);
         HIPCHK(h, launch_bucket_sort(kx, vx, ky, vy, n, bstart, trange, nb, bshift, kfirst,
                                      REFINE_LIMIT, w.misc + MISC_LARGE, tcnt, osz, w.tflag, part,
-                                     res, olist, ooff, err, s));
+                                     res, olist, ooff, obad, err, s));
         HIPCHK(h, launch_bucket_emit(kx, w.tflag, n, bshift, trange, tcnt, nb, w.U[0], n, err, s));
     }
     const uint32_t *pw = reinterpret_cast<const uint32_t *>(h->pinned);
     HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, (MISC_BK + 3 - MISC_NU) * 4,
                              hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
-    const uint32_t tied = pw[MISC_BK - MISC_NU], nob = pw[MISC_BK + 1 - MISC_NU],
-                   no = pw[MISC_BK + 2 - MISC_NU];
+    const uint32_t tied = pw[MISC_BK - MISC_NU];
+    uint32_t nob = pw[MISC_BK + 1 - MISC_NU], no = pw[MISC_BK + 2 - MISC_NU];
     *nU = tied;
     *large = pw[MISC_LARGE - MISC_NU] != 0;
     if (no == 0) return BWT_OK;
     if (no > n || nob == 0 || nob > nb || tied > n) return fail(h, BWT_EHIP);
+    // Every oversized bucket is copied to the sorted pair; those that hold
+    // copies of one settled key (the short suffixes of the later blocks:
+    // every read's "$", every "A$", ...) are already final there.  The tables
+    // of tie counts and sizes are free by now and list the others.
+    uint32_t *const olist2 = tcnt, *const ooff2 = osz;
+    {
+        Scope sk(h, s, SPAN_BUCKET);
+        HIPCHK(h, launch_oversize_check(kx, vx, ky, vy, bstart, olist, ooff, nob, no, n, kfirst,
+                                        obad, olist2, ooff2, w.misc + MISC_PILE, err, s));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_PILE, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    nob = pw[0];
+    no = pw[1];
+    if (no == 0) return BWT_OK;
+    if (no > n || nob == 0 || nob > nb) return fail(h, BWT_EHIP);
+    olist = olist2;
+    ooff = ooff2;
     // the oversized buckets are sorted in two key and two value buffers that
     // hold neither the sorted block nor g (the doubling fallback may build the
     // keys from g again): the spare pair and the radix output, which is free

@@ -309,12 +309,12 @@ __global__ __launch_bounds__(1024) void bucket_scan_top_kernel(uint32_t *__restr
 }
 
 // tpre[b] = tied suffixes before bucket b (in place over tcnt); oversized
-// buckets listed in bucket order: olist[q] = b, ooff[q] = gathered start;
-// ooff[count] = total.
+// buckets listed in bucket order: olist[q] = b, ooff[q] = gathered start,
+// obad[q] = 0; ooff[count] = total.
 __global__ __launch_bounds__(256) void bucket_scan_down_kernel(
     uint32_t *__restrict__ tcnt, const uint32_t *__restrict__ osz, uint32_t nb,
     const uint32_t *__restrict__ part, const uint32_t *__restrict__ res,
-    uint32_t *__restrict__ olist, uint32_t *__restrict__ ooff) {
+    uint32_t *__restrict__ olist, uint32_t *__restrict__ ooff, uint32_t *__restrict__ obad) {
     __shared__ uint32_t s_tmp[4];
     const uint32_t t = blockIdx.x, tid = threadIdx.x;
     uint32_t ra = part[3 * t], rc = part[3 * t + 1], re = part[3 * t + 2];
@@ -334,6 +334,7 @@ __global__ __launch_bounds__(256) void bucket_scan_down_kernel(
             if (z) {
                 olist[rc + pc] = b;
                 ooff[rc + pc] = re + pe;
+                obad[rc + pc] = 0;
             }
         }
         ra += ta;
@@ -727,14 +728,100 @@ __global__ void oversize_ties_map_kernel(const uint32_t *__restrict__ U2,
     U[base + t] = bstart[olist[lo]] + (j - ooff[lo]);
 }
 
+// Oversized bucket q (gathered index j, as for the gather) copied from
+// (kx, vx) to (ky, vy) at the same positions; obad[q] is set when one of its
+// keys differs from its first key or does not end at a terminator.  A bucket
+// with obad[q] == 0 holds copies of one settled key: it is already in its
+// final order (position order, which the stable passes kept) and has no ties.
+__global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
+                                           const uint32_t *__restrict__ vx,
+                                           uint64_t *__restrict__ ky, uint32_t *__restrict__ vy,
+                                           const uint32_t *__restrict__ bstart,
+                                           const uint32_t *__restrict__ olist,
+                                           const uint32_t *__restrict__ ooff, uint32_t nob,
+                                           uint32_t no, uint32_t n, int kshort,
+                                           uint32_t *__restrict__ obad,
+                                           uint32_t *__restrict__ err) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    bool mis = false;
+    uint32_t q = 0;
+    if (j < no) {
+        uint32_t lo = 0, hi = nob - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (ooff[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        q = lo;
+        const uint32_t p0 = bstart[olist[q]], pos = p0 + (j - ooff[q]);
+        if (pos < n) {
+            const uint64_t k = kx[pos];
+            ky[pos] = k;
+            vy[pos] = vx[pos];
+            mis = k != kx[p0] || !short_key(k, kshort);
+        } else {
+            atomicOr(err, 256u);
+        }
+    }
+    // one flag update per bucket per wave (q does not decrease along the lanes)
+    const uint64_t m = __ballot(mis);
+    const uint64_t below = m & lanemask_lt();
+    const int prev = below ? 63 - __builtin_clzll(below) : lane;
+    const uint32_t qprev = __shfl(q, prev, 64);
+    if (mis && (below == 0 || qprev != q)) atomicOr(&obad[q], 1u);
+}
+
+// The oversized buckets with obad set, listed again in bucket order (one
+// workgroup of 1024 threads): olist2[c] = olist[q], ooff2[c] = their gathered
+// start; ooff2[count] = total; res2 = {count, total}.
+__global__ __launch_bounds__(1024) void oversize_compact_kernel(
+    const uint32_t *__restrict__ olist, const uint32_t *__restrict__ ooff,
+    const uint32_t *__restrict__ obad, uint32_t nob, uint32_t *__restrict__ olist2,
+    uint32_t *__restrict__ ooff2, uint32_t *__restrict__ res2) {
+    __shared__ uint32_t s_w[2][16];
+    const uint32_t tid = threadIdx.x, w = tid >> 6;
+    uint32_t rc = 0, re = 0;  // buckets and suffixes kept so far
+    for (uint32_t base = 0; base < nob; base += 1024) {
+        const uint32_t q = base + tid;
+        const uint32_t keep = q < nob && obad[q] ? 1u : 0u;
+        const uint32_t z = keep ? ooff[q + 1] - ooff[q] : 0u;
+        const uint32_t ic = wave_incl_sum(keep), ie = wave_incl_sum(z);
+        if ((tid & 63) == 63) {
+            s_w[0][w] = ic;
+            s_w[1][w] = ie;
+        }
+        __syncthreads();
+        uint32_t bc = 0, be = 0, tc = 0, te = 0;
+        for (uint32_t k = 0; k < 16; ++k) {
+            bc += k < w ? s_w[0][k] : 0u;
+            be += k < w ? s_w[1][k] : 0u;
+            tc += s_w[0][k];
+            te += s_w[1][k];
+        }
+        if (keep) {
+            olist2[rc + bc + ic - 1] = olist[q];
+            ooff2[rc + bc + ic - 1] = re + be + ie - z;
+        }
+        rc += tc;
+        re += te;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ooff2[rc] = re;
+        res2[0] = rc;
+        res2[1] = re;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                               uint32_t *vout, uint32_t n, uint32_t *bstart, uint32_t *trange,
                               uint32_t nb, int bshift, int kshort, uint32_t limit, uint32_t *large,
                               uint32_t *tcnt, uint32_t *osz, uint8_t *tflag, uint32_t *part,
-                              uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *err,
-                              hipStream_t s) {
+                              uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *obad,
+                              uint32_t *err, hipStream_t s) {
     const uint32_t ntiles = (uint32_t)div_up(nb, BT_TILE);
     if (ntiles > 4 * 1024) return hipErrorInvalidValue;
     fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(tcnt, nb, 0u);
@@ -746,7 +833,7 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
                                                    err);
     bucket_scan_up_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part);
     bucket_scan_top_kernel<<<1, 1024, 0, s>>>(part, ntiles, res);
-    bucket_scan_down_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part, res, olist, ooff);
+    bucket_scan_down_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part, res, olist, ooff, obad);
     return hipGetLastError();
 }
 
@@ -756,6 +843,18 @@ hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32
     if (n == 0) return hipSuccess;
     bucket_tile_emit_kernel<<<(unsigned)div_up(n, BT_T), 256, 0, s>>>(keys, tflag, bshift, trange,
                                                                       tpre, nb, U, ucap, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_oversize_check(const uint64_t *kx, const uint32_t *vx, uint64_t *ky,
+                                 uint32_t *vy, const uint32_t *bstart, const uint32_t *olist,
+                                 const uint32_t *ooff, uint32_t nob, uint32_t no, uint32_t n,
+                                 int kshort, uint32_t *obad, uint32_t *olist2, uint32_t *ooff2,
+                                 uint32_t *res2, uint32_t *err, hipStream_t s) {
+    if (no == 0 || nob == 0) return hipSuccess;
+    oversize_check_copy_kernel<<<(unsigned)div_up(no, 256), 256, 0, s>>>(
+        kx, vx, ky, vy, bstart, olist, ooff, nob, no, n, kshort, obad, err);
+    oversize_compact_kernel<<<1, 1024, 0, s>>>(olist, ooff, obad, nob, olist2, ooff2, res2);
     return hipGetLastError();
 }
 
