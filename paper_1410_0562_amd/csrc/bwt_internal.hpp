@@ -240,6 +240,8 @@ struct RankKeys {
     uint32_t *vals;
     int gshift;
     int kfirst;
+    uint32_t *hist;  // if set: counts of the key digit at bit hshift, added to
+    int hshift;      // the HIST_COPIES copies (zeroed by the caller)
 };
 hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                                 uint32_t m_blk, uint32_t n_blk, const Rec *recs,

@@ -569,19 +569,48 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
     return BWT_OK;
 }
 
-// Layout of a block's first sort key for gbits bits of g (see bwt_internal.hpp).
+// Layout of a block's first sort key for gbits bits of g (see bwt_internal.hpp),
+// and the digits its radix passes cover: with the bucket finish only the top
+// digits, B bucket bits, enough for about BUCKET_TARGET suffixes per bucket
+// (small blocks are latency-bound: fewer launches and host reads win there);
+// shift0 is the first pass's digit.
 struct KeyLayout {
     int key_bits, kfirst, gshift, sort_bits;
+    bool buckets;
+    int B, shift0;
 };
 
-KeyLayout key_layout(const bwt_set *h, int gbits) {
+KeyLayout key_layout(const bwt_set *h, int gbits, uint32_t n_blk) {
     KeyLayout L;
     L.key_bits = h->key_bits < gbits + 1 ? gbits + 1 : h->key_bits;
     if (L.key_bits > 64) L.key_bits = 64;
     L.kfirst = first_key_syms(gbits, L.key_bits);
     L.gshift = gbits ? L.key_bits - gbits : 64;
     L.sort_bits = gbits ? L.key_bits : 2 * L.kfirst + KEY_LEN_BITS;
+    L.buckets = h->sort_buckets && n_blk >= BUCKET_MIN_BLOCK;
+    L.B = 0;
+    L.shift0 = 0;
+    if (L.buckets) {
+        int B = 1;
+        while (B < BUCKET_MAX_BITS && ((uint64_t)BUCKET_TARGET << B) < n_blk &&
+               (2ull << B) + 16 <= h->ws.bk_words)
+            ++B;
+        if (B > L.sort_bits) B = L.sort_bits;
+        L.B = B;
+        L.shift0 = L.sort_bits - 8 * ((B + 7) / 8);
+        if (L.shift0 < 0) L.shift0 = 0;
+    }
     return L;
+}
+
+// The keys ComputeRanks writes for a block (g leading), with the counts of
+// the first radix pass's digit.
+RankKeys rank_keys(bwt_set *h, hipStream_t s, int gbits, uint32_t n_blk, int *rc) {
+    Workspace &w = h->ws;
+    const KeyLayout KL = key_layout(h, gbits, n_blk);
+    uint32_t *hist = w.misc + MISC_HIST;
+    *rc = launch_zero_u32(hist, HIST_COPIES * 256, s) == hipSuccess ? BWT_OK : BWT_EHIP;
+    return RankKeys{w.kA, w.v[0], KL.gshift, KL.kfirst, hist, KL.shift0};
 }
 
 // Suffix array of one block (after block_prep).  reads/off: device; off
@@ -595,26 +624,14 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     (void)m_blk;
     Workspace &w = h->ws;
     Scope sc(h, s, BWT_STAGE_SORT);
-    const KeyLayout KL = key_layout(h, gbits);
+    const KeyLayout KL = key_layout(h, gbits, n_blk);
     int key_bits = KL.key_bits;
     int kfirst = KL.kfirst;
     int gshift = KL.gshift;
     const int sort_bits = KL.sort_bits;
     uint32_t *hist = w.misc + MISC_HIST;
-    // With the bucket finish the radix passes cover only the top digits: B
-    // bucket bits, enough for about BUCKET_TARGET suffixes per bucket.
-    // (small blocks are latency-bound: fewer launches and host reads win there)
-    const bool buckets = h->sort_buckets && n_blk >= BUCKET_MIN_BLOCK;
-    int B = 0, shift0 = 0;
-    if (buckets) {
-        B = 1;
-        while (B < BUCKET_MAX_BITS && ((uint64_t)BUCKET_TARGET << B) < n_blk &&
-               (2ull << B) + 16 <= w.bk_words)
-            ++B;
-        if (B > sort_bits) B = sort_bits;
-        shift0 = sort_bits - 8 * ((B + 7) / 8);
-        if (shift0 < 0) shift0 = 0;
-    }
+    const bool buckets = KL.buckets;
+    const int B = KL.B, shift0 = KL.shift0;
     if (!keys_ready) {
         HIPCHK(h, launch_zero_u32(hist, HIST_COPIES * 256, s));
         Scope sk(h, s, SPAN_KEYS);
@@ -623,7 +640,8 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
     }
     uint64_t *ks;
     uint32_t *vs;
-    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, sort_bits, !keys_ready, &ks, &vs,
+    // the key producer (ComputeRanks or the key build) counted the first digit
+    int rc = radix_sort(h, s, w.kA, w.v[0], w.kB, w.v[1], n_blk, sort_bits, true, &ks, &vs,
                         shift0);
     if (rc) return rc;
     uint32_t *sa = vs;
@@ -909,8 +927,8 @@ int run_block(bwt_set *L, hipStream_t s, const DevBlock &B, const std::vector<Ho
     if (gbits > 0) {
         Scope sc(L, s, BWT_STAGE_RANKS);
         Scope sk(L, s, SPAN_RANKS_K, n_blk - m_blk);
-        const KeyLayout KL = key_layout(L, gbits);
-        const RankKeys kk{w.kA, w.v[0], KL.gshift, KL.kfirst};
+        const RankKeys kk = rank_keys(L, s, gbits, n_blk, &rc);
+        if (rc) return fail(L, rc);
         HIPCHK(L, launch_compute_ranks_units(in.reads, off, w.soff, m_blk, n_blk, rdev, nu, w.g,
                                              &kk, rank_segments(L), w.misc + MISC_ERR, s));
     }
@@ -1459,8 +1477,8 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
         if (gbits > 0) {
             Scope sc(h, s, BWT_STAGE_RANKS);
             Scope sk(h, s, SPAN_RANKS_K, n_blk - m_blk);
-            const KeyLayout KL = key_layout(h, gbits);
-            const RankKeys kk{w.kA, w.v[0], KL.gshift, KL.kfirst};
+            const RankKeys kk = rank_keys(h, s, gbits, n_blk, &rc);
+            if (rc) return fail(h, rc);
             HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
                                            S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
                                            rank_segments(h), w.misc + MISC_ERR, s));

@@ -95,6 +95,8 @@ struct Out {
     uint32_t *vals;
     int gshift, kfirst;
     bool vec, vvec;  // 64-byte aligned arrays: whole chunks may be written
+    uint32_t *hist;  // key mode: counts of the key digit at bit hshift (or null)
+    int hshift;
 };
 
 // The 8-byte word of packed input holding the current symbol, reloaded only
@@ -176,9 +178,11 @@ struct UnitIndex {
 // symbols after the current position in `win` (first symbol most
 // significant), and writes each position's value one step late, once the
 // symbol before it has been read.
+// sh (key mode, may be null): LDS counts of the digit at bit o.hshift of
+// every key written.
 template <bool KEYS>
 __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t len, uint64_t gb,
-                          const Out &o) {
+                          const Out &o, uint32_t *sh) {
     GBuf buf;
     buf.cnt = 0;
     VBuf vb;
@@ -189,6 +193,7 @@ __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t
     uint64_t i = W.lf.m_ext;
     uint32_t k = len;
     buf.push(KEYS ? (i + W.goff) << o.gshift : i + W.goff);  // terminator: no symbols
+    if (KEYS && sh) atomicAdd(&sh[(uint32_t)(buf.r0 >> o.hshift) & 255u], 1u);
     if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
     while (k > 0) {
         --k;
@@ -199,7 +204,9 @@ __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t
             if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
             if (o.kfirst > 0) win = (win >> 2) | ((uint64_t)c << top);
             const uint32_t t = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
-            buf.push(((i + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | t);
+            const uint64_t key = ((i + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | t;
+            buf.push(key);
+            if (sh) atomicAdd(&sh[(uint32_t)(key >> o.hshift) & 255u], 1u);
         } else {
             buf.push(i + W.goff);
         }
@@ -214,28 +221,72 @@ __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t
 
 // One lane per read.  Reads longer than `seg` symbols (seg > 0) are cut into
 // segments that are queued for rank_segments_kernel instead.
+// In key mode with o.hist set, the digit counts of the keys of the walked
+// reads are gathered in LDS and added once per workgroup to one of the
+// HIST_COPIES copies (the keys of queued reads are counted by
+// count_long_keys_kernel once they are final).
 template <class Src, bool KEYS>
 __global__ __launch_bounds__(256) void compute_ranks_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, Out o, uint32_t seg,
     uint64_t *__restrict__ seg_list, uint32_t *__restrict__ seg_count, uint32_t seg_cap,
     uint32_t *__restrict__ err) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m_blk) return;
-    const uint64_t s0 = off[j];
-    const uint32_t len = (uint32_t)(off[j + 1] - s0);
-    if (seg > 0 && len > seg) {
-        const uint32_t nseg = (len + seg - 1) / seg;
-        const uint32_t at = atomicAdd(seg_count, nseg);
-        if (at + nseg > seg_cap) {
-            atomicOr(err, 128u);
-            return;
-        }
-        for (uint32_t s = 0; s < nseg; ++s) seg_list[at + s] = ((uint64_t)j << 32) | s;
-        return;
+    __shared__ uint32_t s_h[KEYS ? 256 : 1];
+    const uint32_t tid = threadIdx.x;
+    const bool count = KEYS && o.hist != nullptr;
+    if (count) {
+        s_h[tid] = 0;
+        __syncthreads();
     }
-    SymReader sym{reads, 0, 0};
-    walk_read<KEYS>(src.at(j), sym, s0, len, soff[j], o);
+    const uint32_t j = blockIdx.x * blockDim.x + tid;
+    if (j < m_blk) {
+        const uint64_t s0 = off[j];
+        const uint32_t len = (uint32_t)(off[j + 1] - s0);
+        if (seg > 0 && len > seg) {
+            const uint32_t nseg = (len + seg - 1) / seg;
+            const uint32_t at = atomicAdd(seg_count, nseg);
+            if (at + nseg > seg_cap) {
+                atomicOr(err, 128u);
+            } else {
+                for (uint32_t s = 0; s < nseg; ++s) seg_list[at + s] = ((uint64_t)j << 32) | s;
+            }
+        } else {
+            SymReader sym{reads, 0, 0};
+            walk_read<KEYS>(src.at(j), sym, s0, len, soff[j], o, count ? s_h : nullptr);
+        }
+    }
+    if (count) {
+        __syncthreads();
+        if (s_h[tid]) atomicAdd(&o.hist[(blockIdx.x % HIST_COPIES) * 256 + tid], s_h[tid]);
+    }
+}
+
+// Digit counts (bit o.hshift) of the final keys of the reads that were cut
+// into segments: one workgroup per queued segment (j, s), which owns the
+// positions of symbols [s * seg, min(len, s * seg + seg)) of read j and, for
+// the last segment, the terminator position.
+__global__ __launch_bounds__(256) void count_long_keys_kernel(
+    const uint64_t *__restrict__ off, const uint32_t *__restrict__ soff, uint32_t m_blk,
+    uint32_t seg, const uint64_t *__restrict__ seg_list, const uint32_t *__restrict__ seg_count,
+    const uint64_t *__restrict__ keys, int hshift, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[256];
+    const uint32_t tid = threadIdx.x, t = blockIdx.x;
+    if (t >= *seg_count) return;
+    const uint64_t e_js = seg_list[t];
+    const uint32_t j = (uint32_t)(e_js >> 32), sg = (uint32_t)e_js;
+    if (j >= m_blk) return;  // only if the queue overflowed (already flagged)
+    const uint32_t len = (uint32_t)(off[j + 1] - off[j]);
+    const uint64_t gb = soff[j];
+    const uint32_t a = sg * seg;
+    if (a >= len) return;
+    const uint32_t b = a + seg < len ? a + seg : len;
+    s_h[tid] = 0;
+    __syncthreads();
+    const uint32_t cnt = b - a + (b == len ? 1u : 0u);  // positions gb + a .. gb + a + cnt - 1
+    for (uint32_t q = tid; q < cnt; q += 256)
+        atomicAdd(&s_h[(uint32_t)(keys[gb + a + q] >> hshift) & 255u], 1u);
+    __syncthreads();
+    if (s_h[tid]) atomicAdd(&hist[(t % HIST_COPIES) * 256 + tid], s_h[tid]);
 }
 
 // One lane per queued segment (j, s) of a long read: symbols [a, b) with
@@ -341,7 +392,7 @@ __global__ __launch_bounds__(256) void rank_fallback_kernel(
     const uint32_t j = fb_list[t];
     const uint64_t s0 = off[j];
     SymReader sym{reads, 0, 0};
-    walk_read<KEYS>(src.at(j), sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], o);
+    walk_read<KEYS>(src.at(j), sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], o, nullptr);
 }
 
 __global__ void zero_kernel(uint32_t *p, uint32_t n) {
@@ -371,6 +422,9 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
             sg.fb_list, sg.counters + 1, err);
         rank_fallback_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
             reads, off, soff, src, o, sg.fb_list, sg.counters + 1);
+        if (KEYS && o.hist)
+            count_long_keys_kernel<<<cap, 256, 0, s>>>(off, soff, m_blk, seg, sg.seg_list,
+                                                      sg.counters, o.keys, o.hshift, o.hist);
     }
     return hipGetLastError();
 }
@@ -389,6 +443,8 @@ hipError_t compute_ranks_any(const uint8_t *reads, const uint64_t *off, const ui
         o.kfirst = kk->kfirst;
         o.vec = (reinterpret_cast<uintptr_t>(o.keys) & 63) == 0;
         o.vvec = (reinterpret_cast<uintptr_t>(o.vals) & 63) == 0;
+        o.hist = kk->hist;
+        o.hshift = kk->hshift;
         return compute_ranks<Src, true>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s);
     }
     o.g = g;
