@@ -349,6 +349,58 @@ __global__ __launch_bounds__(256) void bucket_scan_down_kernel(
 constexpr uint32_t BT_T = 2048;
 constexpr uint32_t BT_WIN = BT_T + BUCKET_CAP;
 
+// Sorts up to four rows of whole consecutive buckets held in LDS (row r:
+// window offsets rst[r] .. rst[r] + rlen[r] - 1, first bucket rid[r]; rlen 0
+// = no row), one row per register, into kout / vout at t0 + offset.  Tied
+// suffixes get their flag in s_f, and the last lane of each bucket with ties
+// writes the bucket's tie count.
+__device__ __forceinline__ void sort_packed_rows(
+    const uint64_t *__restrict__ s_k, const uint32_t *__restrict__ s_v, const uint32_t (&rst)[4],
+    const uint32_t (&rlen)[4], const uint32_t (&rid)[4], uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, uint32_t t0, int bshift, int kshort, uint8_t *__restrict__ s_f,
+    uint32_t *__restrict__ tcnt) {
+    const int lane = lane_id();
+    const uint32_t l = (uint32_t)lane;
+    uint64_t c[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t base = (uint64_t)rid[r] << bshift;
+        c[r] = l < rlen[r] ? ((s_k[rst[r] + l] - base) << 6) | (uint64_t)l
+                           : ~0ull;  // a real key never has all length bits set
+    }
+    wave_sort_rows<4, 64>(c, lane);
+    const uint64_t le = lanemask_lt() | (1ull << lane);  // lanes up to this one
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const bool ok = l < rlen[r];
+        const uint64_t k = ok ? ((uint64_t)rid[r] << bshift) + (c[r] >> 6) : ~0ull;
+        if (ok) {
+            kout[t0 + rst[r] + l] = k;
+            vout[t0 + rst[r] + l] = s_v[rst[r] + (uint32_t)(c[r] & 63u)];
+        }
+        const uint64_t kp = __shfl_up(k, 1, 64);
+        const uint64_t kn = __shfl_down(k, 1, 64);
+        const bool eq_prev = ok && l > 0 && kp == k;
+        const bool eq_next = ok && l + 1 < rlen[r] && kn == k;
+        const bool t = ok && !short_key(k, kshort) && (eq_prev || eq_next);
+        if (t) s_f[rst[r] + l] = 1;
+        const uint64_t tb = __ballot(t);
+        if (tb) {
+            const uint64_t id = k >> bshift;
+            const bool head = ok && (l == 0 || (kp >> bshift) != id);
+            const bool last = ok && (l + 1 == rlen[r] || (kn >> bshift) != id);
+            const uint64_t hb = __ballot(head);
+            if (last) {
+                // lanes of this bucket: from its head (the highest head at or
+                // below this lane) up to this lane
+                const int first = 63 - __builtin_clzll(hb & le);
+                const uint32_t cnt = (uint32_t)__popcll(tb & le & ~((1ull << first) - 1ull));
+                if (cnt) tcnt[(uint32_t)id] = cnt;
+            }
+        }
+    }
+}
+
 // First position in [lo, hi) whose bucket (key >> bshift) is not bkt, where
 // the positions of bucket bkt form a prefix of [lo, hi); hi if there is none.
 // One wave, 65-way steps: about five dependent loads for a whole block.
@@ -460,140 +512,73 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     }
     __syncthreads();
     const uint32_t tend = s_end - t0;  // may exceed the window (oversized)
-    const bool composite = bshift <= 58;
-    // chunks of eight consecutive buckets per wave: two per row (32 lanes
-    // each) when all eight have at most 32 suffixes, else four per row pass
-    for (uint32_t g = (uint32_t)wave * 8; g < nbk; g += 32) {
-        uint32_t st[8], z[8], id[8];
-        bool halves = composite;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t j = g + q;
-            st[q] = 0;
-            z[q] = 0;
-            id[q] = 0;
-            if (j < nbk) {
-                st[q] = s_bs[j];
-                z[q] = (j + 1 < nbk ? (uint32_t)s_bs[j + 1] : tend) - st[q];
-                id[q] = (uint32_t)(s_k[st[q]] >> bshift);
+    // Each wave takes a quarter of the owned buckets in order and packs runs
+    // of whole consecutive buckets of at most 64 suffixes into rows of at
+    // most 64 lanes; four rows are sorted at once.  A row's words are
+    // (key - first bucket's base) << 6 | lane, so one sort orders its
+    // buckets apart and each bucket inside (buckets id0 .. id0 + span - 1 fit
+    // one word).  Larger buckets are sorted one at a time; oversized ones are
+    // only recorded.
+    const uint32_t span = bshift > 58 ? 0u : bshift >= 27 ? (1u << (58 - bshift)) : 0xffffffffu;
+    {
+        const uint32_t jb0 = nbk * (uint32_t)wave / 4, jb1 = nbk * (uint32_t)(wave + 1) / 4;
+        uint32_t rst[4] = {0, 0, 0, 0}, rlen[4] = {0, 0, 0, 0}, rid[4] = {0, 0, 0, 0};
+        uint32_t nr = 0;
+        uint32_t cst = 0, clen = 0, cid = 0;  // the open row (none while clen == 0)
+        for (uint32_t jb = jb0; jb < jb1; jb += 64) {
+            // lane q holds bucket jb + q of this batch
+            const uint32_t jl = jb + (uint32_t)lane;
+            uint32_t st_l = 0, z_l = 0, id_l = 0;
+            if (jl < jb1) {
+                st_l = s_bs[jl];
+                z_l = (jl + 1 < nbk ? (uint32_t)s_bs[jl + 1] : tend) - st_l;
+                id_l = (uint32_t)(s_k[st_l] >> bshift);
             }
-            halves = halves && z[q] <= 32;
-        }
-        uint32_t ties[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (halves) {
-            const bool hi = lane >= 32;
-            const uint32_t hl = (uint32_t)lane & 31u;
-            uint32_t sth[4], zh[4], idh[4];
-            uint64_t c[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                sth[r] = hi ? st[2 * r + 1] : st[2 * r];
-                zh[r] = hi ? z[2 * r + 1] : z[2 * r];
-                idh[r] = hi ? id[2 * r + 1] : id[2 * r];
-                const uint64_t base = (uint64_t)idh[r] << bshift;
-                c[r] = hl < zh[r] ? ((s_k[sth[r] + hl] - base) << 6) | (uint64_t)hl : ~0ull;
-            }
-            wave_sort_rows<4, 32>(c, lane);
-            uint64_t k[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const bool ok = hl < zh[r];
-                k[r] = ok ? ((uint64_t)idh[r] << bshift) + (c[r] >> 6) : ~0ull;
-                if (ok) {
-                    kout[t0 + sth[r] + hl] = k[r];
-                    vout[t0 + sth[r] + hl] = s_v[sth[r] + (uint32_t)(c[r] & 63u)];
+            const uint32_t cnt = jb1 - jb < 64 ? jb1 - jb : 64;
+            for (uint32_t q = 0; q < cnt; ++q) {
+                const uint32_t st = (uint32_t)__builtin_amdgcn_readlane((int)st_l, (int)q);
+                const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)z_l, (int)q);
+                const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)id_l, (int)q);
+                const bool small = span != 0 && z <= 64;
+                if (clen && (!small || clen + z > 64 || id - cid >= span)) {
+                    // close the open row
+                    rst[3] = rst[2]; rst[2] = rst[1]; rst[1] = rst[0]; rst[0] = cst;
+                    rlen[3] = rlen[2]; rlen[2] = rlen[1]; rlen[1] = rlen[0]; rlen[0] = clen;
+                    rid[3] = rid[2]; rid[2] = rid[1]; rid[1] = rid[0]; rid[0] = cid;
+                    clen = 0;
+                    if (++nr == 4) {
+                        sort_packed_rows(s_k, s_v, rst, rlen, rid, kout, vout, t0, bshift, kshort,
+                                         s_f, tcnt);
+                        nr = 0;
+                        rlen[0] = rlen[1] = rlen[2] = rlen[3] = 0;
+                    }
                 }
-            }
-            // ties inside each 32-lane segment (groups are at most 32 long,
-            // below any limit)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const bool ok = hl < zh[r];
-                const uint64_t kp = __shfl_up(k[r], 1, 64);
-                const uint64_t kn = __shfl_down(k[r], 1, 64);
-                const bool eq_prev = ok && hl > 0 && kp == k[r];
-                const bool eq_next = ok && hl + 1 < zh[r] && kn == k[r];
-                const bool t = ok && !short_key(k[r], kshort) && (eq_prev || eq_next);
-                const uint64_t tb = __ballot(t);
-                ties[2 * r] = (uint32_t)__popcll(tb & 0xffffffffull);
-                ties[2 * r + 1] = (uint32_t)__popcll(tb >> 32);
-                if (t) s_f[sth[r] + hl] = 1;
-            }
-            (void)limit;
-        } else {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint32_t st4[4], z4[4], id4[4];
-                bool small = composite;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    st4[r] = st[4 * h + r];
-                    z4[r] = z[4 * h + r];
-                    id4[r] = id[4 * h + r];
-                    small = small && z4[r] <= 64;
-                }
-                uint32_t t4[4] = {0, 0, 0, 0};
                 if (small) {
-                    uint64_t c[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const uint64_t base = (uint64_t)id4[r] << bshift;
-                        c[r] = (uint32_t)lane < z4[r]
-                                   ? ((s_k[st4[r] + lane] - base) << 6) | (uint64_t)lane
-                                   : ~0ull;  // a real key never has all length bits set
+                    if (!clen) {
+                        cst = st;
+                        cid = id;
                     }
-                    wave_sort_rows<4, 64>(c, lane);
-                    uint64_t k[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const bool ok = (uint32_t)lane < z4[r];
-                        k[r] = ok ? ((uint64_t)id4[r] << bshift) + (c[r] >> 6) : ~0ull;
-                        if (ok) {
-                            kout[t0 + st4[r] + lane] = k[r];
-                            vout[t0 + st4[r] + lane] = s_v[st4[r] + (uint32_t)(c[r] & 63u)];
-                        }
-                    }
-                    const uint32_t rows = rows_ties<4>(k, z4, kshort, limit, large, t4);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if ((rows >> r) & 1u) s_f[st4[r] + lane] = 1;
-                } else {
-#pragma unroll 1
-                    for (int r = 0; r < 4; ++r) {
-                        const uint32_t zz = z4[r], sr = st4[r];
-                        if (zz == 1) {
-                            if (lane == 0) {
-                                kout[t0 + sr] = s_k[sr];
-                                vout[t0 + sr] = s_v[sr];
-                            }
-                        } else if (zz >= 2 && zz <= BUCKET_CAP) {
-                            if (zz <= 64) t4[r] = wave_bucket<1>(s_k, s_v, sr, zz, kout, vout, t0 + sr, kshort, limit, large, s_f);
-                            else if (zz <= 128) t4[r] = wave_bucket<2>(s_k, s_v, sr, zz, kout, vout, t0 + sr, kshort, limit, large, s_f);
-                            else t4[r] = wave_bucket<4>(s_k, s_v, sr, zz, kout, vout, t0 + sr, kshort, limit, large, s_f);
-                        }
-                    }
+                    clen += z;
+                } else if (z <= BUCKET_CAP) {
+                    uint32_t tt;
+                    if (z <= 64) tt = wave_bucket<1>(s_k, s_v, st, z, kout, vout, t0 + st, kshort, limit, large, s_f);
+                    else if (z <= 128) tt = wave_bucket<2>(s_k, s_v, st, z, kout, vout, t0 + st, kshort, limit, large, s_f);
+                    else tt = wave_bucket<4>(s_k, s_v, st, z, kout, vout, t0 + st, kshort, limit, large, s_f);
+                    if (lane == 0 && tt && id < nb) tcnt[id] = tt;
+                } else if (lane == 0 && id < nb) {
+                    osz[id] = z;
+                    bstart[id] = t0 + st;
                 }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) ties[4 * h + r] = t4[r];
             }
         }
-        // lane q < 8 records bucket g + q
-        uint32_t tr = 0, zr = 0, ir = 0, sr = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (lane == q) {
-                tr = ties[q];
-                zr = z[q];
-                ir = id[q];
-                sr = st[q];
-            }
-        if (lane < 8 && g + lane < nbk && ir < nb) {
-            tcnt[ir] = tr;
-            if (zr > BUCKET_CAP) {
-                osz[ir] = zr;
-                bstart[ir] = t0 + sr;
-            }
+        if (clen) {
+            rst[3] = rst[2]; rst[2] = rst[1]; rst[1] = rst[0]; rst[0] = cst;
+            rlen[3] = rlen[2]; rlen[2] = rlen[1]; rlen[1] = rlen[0]; rlen[0] = clen;
+            rid[3] = rid[2]; rid[2] = rid[1]; rid[1] = rid[0]; rid[0] = cid;
+            ++nr;
         }
+        if (nr)
+            sort_packed_rows(s_k, s_v, rst, rlen, rid, kout, vout, t0, bshift, kshort, s_f, tcnt);
     }
     __syncthreads();
     const uint32_t fe = tend < wl ? tend : wl;

@@ -262,31 +262,34 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
 }
 
 // Digit counts (bit o.hshift) of the final keys of the reads that were cut
-// into segments: one workgroup per queued segment (j, s), which owns the
-// positions of symbols [s * seg, min(len, s * seg + seg)) of read j and, for
-// the last segment, the terminator position.
+// into segments: the workgroups stride over the queued segments (j, s); a
+// segment owns the positions of symbols [s * seg, min(len, s * seg + seg)) of
+// read j and, if it is the last one, the terminator position.
 __global__ __launch_bounds__(256) void count_long_keys_kernel(
     const uint64_t *__restrict__ off, const uint32_t *__restrict__ soff, uint32_t m_blk,
     uint32_t seg, const uint64_t *__restrict__ seg_list, const uint32_t *__restrict__ seg_count,
     const uint64_t *__restrict__ keys, int hshift, uint32_t *__restrict__ hist) {
     __shared__ uint32_t s_h[256];
-    const uint32_t tid = threadIdx.x, t = blockIdx.x;
-    if (t >= *seg_count) return;
-    const uint64_t e_js = seg_list[t];
-    const uint32_t j = (uint32_t)(e_js >> 32), sg = (uint32_t)e_js;
-    if (j >= m_blk) return;  // only if the queue overflowed (already flagged)
-    const uint32_t len = (uint32_t)(off[j + 1] - off[j]);
-    const uint64_t gb = soff[j];
-    const uint32_t a = sg * seg;
-    if (a >= len) return;
-    const uint32_t b = a + seg < len ? a + seg : len;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nq = *seg_count;
+    if (blockIdx.x >= nq) return;
     s_h[tid] = 0;
     __syncthreads();
-    const uint32_t cnt = b - a + (b == len ? 1u : 0u);  // positions gb + a .. gb + a + cnt - 1
-    for (uint32_t q = tid; q < cnt; q += 256)
-        atomicAdd(&s_h[(uint32_t)(keys[gb + a + q] >> hshift) & 255u], 1u);
+    for (uint32_t t = blockIdx.x; t < nq; t += gridDim.x) {
+        const uint64_t e_js = seg_list[t];
+        const uint32_t j = (uint32_t)(e_js >> 32), sg = (uint32_t)e_js;
+        if (j >= m_blk) continue;  // only if the queue overflowed (already flagged)
+        const uint32_t len = (uint32_t)(off[j + 1] - off[j]);
+        const uint64_t gb = soff[j];
+        const uint32_t a = sg * seg;
+        if (a >= len) continue;
+        const uint32_t b = a + seg < len ? a + seg : len;
+        const uint32_t cnt = b - a + (b == len ? 1u : 0u);  // positions gb + a ...
+        for (uint32_t q = tid; q < cnt; q += 256)
+            atomicAdd(&s_h[(uint32_t)(keys[gb + a + q] >> hshift) & 255u], 1u);
+    }
     __syncthreads();
-    if (s_h[tid]) atomicAdd(&hist[(t % HIST_COPIES) * 256 + tid], s_h[tid]);
+    if (s_h[tid]) atomicAdd(&hist[(blockIdx.x % HIST_COPIES) * 256 + tid], s_h[tid]);
 }
 
 // One lane per queued segment (j, s) of a long read: symbols [a, b) with
@@ -423,8 +426,8 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
         rank_fallback_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
             reads, off, soff, src, o, sg.fb_list, sg.counters + 1);
         if (KEYS && o.hist)
-            count_long_keys_kernel<<<cap, 256, 0, s>>>(off, soff, m_blk, seg, sg.seg_list,
-                                                      sg.counters, o.keys, o.hshift, o.hist);
+            count_long_keys_kernel<<<cap < 2048 ? cap : 2048, 256, 0, s>>>(
+                off, soff, m_blk, seg, sg.seg_list, sg.counters, o.keys, o.hshift, o.hist);
     }
     return hipGetLastError();
 }
