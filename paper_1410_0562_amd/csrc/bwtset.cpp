@@ -81,7 +81,7 @@ constexpr int BK_TABLES = 6;     // bucket starts, ends, tie counts, sizes; over
 constexpr uint32_t BK_PART = 3 * 4096 + 16;  // tile partials of the bucket scans
 constexpr uint32_t MIN_SEG_LEN = 256;
 constexpr int MAX_LANES = 4;
-constexpr uint32_t BUCKET_TARGET = 16;  // suffixes per bucket the bucket count aims at
+constexpr uint32_t BUCKET_TARGET = 32;  // suffixes per bucket the bucket count aims at
 constexpr uint32_t BUCKET_MIN_BLOCK = 1u << 20;  // smallest block that takes the bucket finish
 constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
 constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
