@@ -173,13 +173,14 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
                               uint32_t *err, hipStream_t s);
 // Copies every oversized bucket of (kx, vx) to (ky, vy) and lists in
 // olist2 / ooff2 (res2 = {count, suffixes}) those that still need sorting:
-// the others hold copies of one key that ends at its terminator.  obad is
-// one word per oversized bucket, zeroed by bucket_sort.
+// the others hold copies of one key that ends at its terminator.  The counts
+// are read on the device from the bucket scans' res; obad is one word per
+// oversized bucket, zeroed by bucket_sort.
 hipError_t launch_oversize_check(const uint64_t *kx, const uint32_t *vx, uint64_t *ky,
                                  uint32_t *vy, const uint32_t *bstart, const uint32_t *olist,
-                                 const uint32_t *ooff, uint32_t nob, uint32_t no, uint32_t n,
-                                 int kshort, uint32_t *obad, uint32_t *olist2, uint32_t *ooff2,
-                                 uint32_t *res2, uint32_t *err, hipStream_t s);
+                                 const uint32_t *ooff, const uint32_t *res, uint32_t nb,
+                                 uint32_t n, int kshort, uint32_t *obad, uint32_t *olist2,
+                                 uint32_t *ooff2, uint32_t *res2, uint32_t *err, hipStream_t s);
 hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32_t n, int bshift,
                               const uint32_t *trange, const uint32_t *tpre, uint32_t nb,
                               uint32_t *U, uint32_t ucap, uint32_t *err, hipStream_t s);

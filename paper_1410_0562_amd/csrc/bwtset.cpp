@@ -499,6 +499,7 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
              *olist = w.bk + 4 * W, *ooff = w.bk + 5 * W, *part = w.bk + 6 * W,
              *trange = part + BK_PART;
     uint32_t *err = w.misc + MISC_ERR, *res = w.misc + MISC_BK;
+    uint32_t *const olist2 = tcnt, *const ooff2 = osz;
     // the radix passes left (ks, vs) in one of the (kA, v[0]) / (kB, v[1])
     // pairs; the sorted buckets go to the other pair
     if ((ks != w.kA && ks != w.kB) || (vs != w.v[0] && vs != w.v[1])) return fail(h, BWT_EHIP);
@@ -513,9 +514,17 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
                                      REFINE_LIMIT, w.misc + MISC_LARGE, tcnt, osz, w.tflag, part,
                                      res, olist, ooff, obad, err, s));
         HIPCHK(h, launch_bucket_emit(kx, w.tflag, n, bshift, trange, tcnt, nb, w.U[0], n, err, s));
+        // Every oversized bucket is copied to the sorted pair; those that hold
+        // copies of one settled key (the short suffixes of the later blocks:
+        // every read's "$", every "A$", ...) are already final there.  The
+        // tables of tie counts and sizes are free by now and list the others.
+        HIPCHK(h, launch_oversize_check(kx, vx, ky, vy, bstart, olist, ooff, res, nb, n, kfirst,
+                                        obad, olist2, ooff2, w.misc + MISC_PILE, err, s));
     }
+    // one read of the counts: tied suffixes, large flag, oversized buckets
+    // and those still to sort
     const uint32_t *pw = reinterpret_cast<const uint32_t *>(h->pinned);
-    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, (MISC_BK + 3 - MISC_NU) * 4,
+    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, (MISC_PILE + 2 - MISC_NU) * 4,
                              hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     const uint32_t tied = pw[MISC_BK - MISC_NU];
@@ -524,20 +533,8 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
     *large = pw[MISC_LARGE - MISC_NU] != 0;
     if (no == 0) return BWT_OK;
     if (no > n || nob == 0 || nob > nb || tied > n) return fail(h, BWT_EHIP);
-    // Every oversized bucket is copied to the sorted pair; those that hold
-    // copies of one settled key (the short suffixes of the later blocks:
-    // every read's "$", every "A$", ...) are already final there.  The tables
-    // of tie counts and sizes are free by now and list the others.
-    uint32_t *const olist2 = tcnt, *const ooff2 = osz;
-    {
-        Scope sk(h, s, SPAN_BUCKET);
-        HIPCHK(h, launch_oversize_check(kx, vx, ky, vy, bstart, olist, ooff, nob, no, n, kfirst,
-                                        obad, olist2, ooff2, w.misc + MISC_PILE, err, s));
-    }
-    HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_PILE, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    nob = pw[0];
-    no = pw[1];
+    nob = pw[MISC_PILE - MISC_NU];
+    no = pw[MISC_PILE + 1 - MISC_NU];
     if (no == 0) return BWT_OK;
     if (no > n || nob == 0 || nob > nb) return fail(h, BWT_EHIP);
     olist = olist2;

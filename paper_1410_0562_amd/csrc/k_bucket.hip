@@ -718,54 +718,65 @@ __global__ void oversize_ties_map_kernel(const uint32_t *__restrict__ U2,
 // keys differs from its first key or does not end at a terminator.  A bucket
 // with obad[q] == 0 holds copies of one settled key: it is already in its
 // final order (position order, which the stable passes kept) and has no ties.
+// The counts come from the bucket scans (res[1] buckets, res[2] suffixes);
+// the grid strides over the gathered indices, a wave over 64 consecutive ones.
 __global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
                                            const uint32_t *__restrict__ vx,
                                            uint64_t *__restrict__ ky, uint32_t *__restrict__ vy,
                                            const uint32_t *__restrict__ bstart,
                                            const uint32_t *__restrict__ olist,
-                                           const uint32_t *__restrict__ ooff, uint32_t nob,
-                                           uint32_t no, uint32_t n, int kshort,
-                                           uint32_t *__restrict__ obad,
+                                           const uint32_t *__restrict__ ooff,
+                                           const uint32_t *__restrict__ res, uint32_t n,
+                                           int kshort, uint32_t *__restrict__ obad,
                                            uint32_t *__restrict__ err) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = lane_id();
-    bool mis = false;
-    uint32_t q = 0;
-    if (j < no) {
-        uint32_t lo = 0, hi = nob - 1;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi + 1) >> 1;
-            if (ooff[mid] <= j) lo = mid;
-            else hi = mid - 1;
-        }
-        q = lo;
-        const uint32_t p0 = bstart[olist[q]], pos = p0 + (j - ooff[q]);
-        if (pos < n) {
-            const uint64_t k = kx[pos];
-            ky[pos] = k;
-            vy[pos] = vx[pos];
-            mis = k != kx[p0] || !short_key(k, kshort);
-        } else {
-            atomicOr(err, 256u);
-        }
+    const uint32_t nob = res[1], no = res[2];
+    if (no > n || (no > 0 && nob == 0)) {  // cannot happen; keeps the indexing in bounds
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 256u);
+        return;
     }
-    // one flag update per bucket per wave (q does not decrease along the lanes)
-    const uint64_t m = __ballot(mis);
-    const uint64_t below = m & lanemask_lt();
-    const int prev = below ? 63 - __builtin_clzll(below) : lane;
-    const uint32_t qprev = __shfl(q, prev, 64);
-    if (mis && (below == 0 || qprev != q)) atomicOr(&obad[q], 1u);
+    const int lane = lane_id();
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < no; j0 += stride) {
+        const uint32_t j = j0 + threadIdx.x;
+        bool mis = false;
+        uint32_t q = 0;
+        if (j < no) {
+            uint32_t lo = 0, hi = nob - 1;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi + 1) >> 1;
+                if (ooff[mid] <= j) lo = mid;
+                else hi = mid - 1;
+            }
+            q = lo;
+            const uint32_t p0 = bstart[olist[q]], pos = p0 + (j - ooff[q]);
+            if (pos < n) {
+                const uint64_t k = kx[pos];
+                ky[pos] = k;
+                vy[pos] = vx[pos];
+                mis = k != kx[p0] || !short_key(k, kshort);
+            } else {
+                atomicOr(err, 256u);
+            }
+        }
+        // one flag update per bucket per wave (q does not decrease along the lanes)
+        const uint64_t m = __ballot(mis);
+        const uint64_t below = m & lanemask_lt();
+        const int prev = below ? 63 - __builtin_clzll(below) : lane;
+        const uint32_t qprev = __shfl(q, prev, 64);
+        if (mis && (below == 0 || qprev != q)) atomicOr(&obad[q], 1u);
+    }
 }
 
 // The oversized buckets with obad set, listed again in bucket order (one
-// workgroup of 1024 threads): olist2[c] = olist[q], ooff2[c] = their gathered
-// start; ooff2[count] = total; res2 = {count, total}.
+// workgroup of 1024 threads, res[1] buckets): olist2[c] = olist[q], ooff2[c] =
+// their gathered start; ooff2[count] = total; res2 = {count, total}.
 __global__ __launch_bounds__(1024) void oversize_compact_kernel(
     const uint32_t *__restrict__ olist, const uint32_t *__restrict__ ooff,
-    const uint32_t *__restrict__ obad, uint32_t nob, uint32_t *__restrict__ olist2,
-    uint32_t *__restrict__ ooff2, uint32_t *__restrict__ res2) {
+    const uint32_t *__restrict__ obad, const uint32_t *__restrict__ res, uint32_t nbmax,
+    uint32_t *__restrict__ olist2, uint32_t *__restrict__ ooff2, uint32_t *__restrict__ res2) {
     __shared__ uint32_t s_w[2][16];
     const uint32_t tid = threadIdx.x, w = tid >> 6;
+    const uint32_t nob = res[1] < nbmax ? res[1] : 0u;  // more cannot happen
     uint32_t rc = 0, re = 0;  // buckets and suffixes kept so far
     for (uint32_t base = 0; base < nob; base += 1024) {
         const uint32_t q = base + tid;
@@ -833,13 +844,13 @@ hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32
 
 hipError_t launch_oversize_check(const uint64_t *kx, const uint32_t *vx, uint64_t *ky,
                                  uint32_t *vy, const uint32_t *bstart, const uint32_t *olist,
-                                 const uint32_t *ooff, uint32_t nob, uint32_t no, uint32_t n,
-                                 int kshort, uint32_t *obad, uint32_t *olist2, uint32_t *ooff2,
-                                 uint32_t *res2, uint32_t *err, hipStream_t s) {
-    if (no == 0 || nob == 0) return hipSuccess;
-    oversize_check_copy_kernel<<<(unsigned)div_up(no, 256), 256, 0, s>>>(
-        kx, vx, ky, vy, bstart, olist, ooff, nob, no, n, kshort, obad, err);
-    oversize_compact_kernel<<<1, 1024, 0, s>>>(olist, ooff, obad, nob, olist2, ooff2, res2);
+                                 const uint32_t *ooff, const uint32_t *res, uint32_t nb,
+                                 uint32_t n, int kshort, uint32_t *obad, uint32_t *olist2,
+                                 uint32_t *ooff2, uint32_t *res2, uint32_t *err, hipStream_t s) {
+    const uint32_t want = (uint32_t)div_up(n, 256);
+    oversize_check_copy_kernel<<<want < 1024 ? (want ? want : 1) : 1024, 256, 0, s>>>(
+        kx, vx, ky, vy, bstart, olist, ooff, res, n, kshort, obad, err);
+    oversize_compact_kernel<<<1, 1024, 0, s>>>(olist, ooff, obad, res, nb, olist2, ooff2, res2);
     return hipGetLastError();
 }
 
