@@ -367,26 +367,50 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
     uint64_t ob = o0 + 32ull * lane - nb - r_lo * REC_SYMS;  // old row, relative to record r_lo
     const uint64_t ql = q0 + 32ull * lane;
     const uint32_t nvalid = ql < q1 ? (q1 - ql < 32 ? (uint32_t)(q1 - ql) : 32u) : 0u;
+    const uint32_t vmask0 = nvalid >= 32 ? 0xffffffffu : ((1u << nvalid) - 1u);
+    // The lane's old rows come in order from bit ob of each plane of the
+    // staged records: one 32-bit window per plane.  Every new row then opens
+    // a gap at its place (lowest first) that takes the new symbol.
     uint32_t lo_w = 0, hi_w = 0, dl_w = 0;
-    for (uint32_t u = 0; u < nvalid; ++u) {
-        int sym;
-        if ((word >> u) & 1u) {
-            sym = L.nsym[nb < INS_TILE_SYMS ? nb : INS_TILE_SYMS - 1];
-            ++nb;
-        } else {
-            uint32_t rr = (uint32_t)(ob >> REC_SHIFT);
-            const uint32_t bit = (uint32_t)(ob & 127), w = bit >> 6, b = bit & 63;
-            ++ob;
-            if (rr > INS_TILE_RECS) rr = INS_TILE_RECS;
-            const uint64_t *R = L.old + rr * 6;
-            sym = ((R[4 + w] >> b) & 1) ? 4 : (int)(((R[w] >> b) & 1) | (((R[2 + w] >> b) & 1) << 1));
+    if ((uint32_t)__popc(word & vmask0) < nvalid) {
+        constexpr uint32_t NW = (INS_TILE_RECS + 1) * 6;
+        const uint32_t sh = (uint32_t)(ob & 63);
+        const uint32_t r0 = (uint32_t)(ob >> 7), h0 = (uint32_t)(ob >> 6) & 1u;
+        const uint32_t r1 = (uint32_t)((ob + 64) >> 7), h1 = (uint32_t)((ob + 64) >> 6) & 1u;
+        uint32_t win[3];
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) {
+            uint32_t i0 = r0 * 6 + 2 * pl + h0, i1 = r1 * 6 + 2 * pl + h1;
+            i0 = i0 < NW ? i0 : NW - 1;  // only rows past the tile's old rows get clamped
+            i1 = i1 < NW ? i1 : NW - 1;
+            const uint64_t w0 = L.old[i0], w1 = L.old[i1];
+            win[pl] = (uint32_t)(sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0);
         }
-        if (sym == 4) dl_w |= 1u << u;
-        else {
-            lo_w |= (uint32_t)(sym & 1) << u;
-            hi_w |= (uint32_t)(sym >> 1) << u;
+        lo_w = win[0];
+        hi_w = win[1];
+        dl_w = win[2];
+    }
+    {
+        uint32_t m = word & vmask0, k = nb;
+        while (m) {
+            const uint32_t u = (uint32_t)__builtin_ctz(m);
+            m &= m - 1u;
+            const uint32_t below = (1u << u) - 1u;
+            lo_w = (lo_w & below) | ((lo_w & ~below) << 1);
+            hi_w = (hi_w & below) | ((hi_w & ~below) << 1);
+            dl_w = (dl_w & below) | ((dl_w & ~below) << 1);
+            const int sym = L.nsym[k < INS_TILE_SYMS ? k : INS_TILE_SYMS - 1];
+            ++k;
+            if (sym == 4) dl_w |= 1u << u;
+            else {
+                lo_w |= (uint32_t)(sym & 1) << u;
+                hi_w |= (uint32_t)(sym >> 1) << u;
+            }
         }
     }
+    lo_w &= vmask0;
+    hi_w &= vmask0;
+    dl_w &= vmask0;
     const uint32_t vmask = nvalid >= 32 ? 0xffffffffu : ((1u << nvalid) - 1u);
     // counts of each base before this lane's rows, then at each record start
     // (the record of lane l is l / 4; its first lane is l & ~3)
