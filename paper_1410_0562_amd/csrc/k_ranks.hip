@@ -25,6 +25,8 @@ namespace bwt {
 
 namespace {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // The values of one lane are written in descending order; they are kept in
 // an 8-entry shift register and written as one aligned 64-byte chunk when the
 // register covers indices [8q, 8q + 8), so the writes are whole half-lines
@@ -40,11 +42,12 @@ struct GBuf {
     // write the held values to g[idx .. idx + cnt)
     __device__ void flush(uint64_t *__restrict__ g, uint64_t idx, bool vec) {
         if (cnt == 8 && vec) {
-            uint4 *q = reinterpret_cast<uint4 *>(g + idx);
-            q[0] = make_uint4((uint32_t)r0, (uint32_t)(r0 >> 32), (uint32_t)r1, (uint32_t)(r1 >> 32));
-            q[1] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), (uint32_t)r3, (uint32_t)(r3 >> 32));
-            q[2] = make_uint4((uint32_t)r4, (uint32_t)(r4 >> 32), (uint32_t)r5, (uint32_t)(r5 >> 32));
-            q[3] = make_uint4((uint32_t)r6, (uint32_t)(r6 >> 32), (uint32_t)r7, (uint32_t)(r7 >> 32));
+            // streaming stores: the output is not read again by this kernel
+            u32x4 *q = reinterpret_cast<u32x4 *>(g + idx);
+            __builtin_nontemporal_store(u32x4{(uint32_t)r0, (uint32_t)(r0 >> 32), (uint32_t)r1, (uint32_t)(r1 >> 32)}, q + 0);
+            __builtin_nontemporal_store(u32x4{(uint32_t)r2, (uint32_t)(r2 >> 32), (uint32_t)r3, (uint32_t)(r3 >> 32)}, q + 1);
+            __builtin_nontemporal_store(u32x4{(uint32_t)r4, (uint32_t)(r4 >> 32), (uint32_t)r5, (uint32_t)(r5 >> 32)}, q + 2);
+            __builtin_nontemporal_store(u32x4{(uint32_t)r6, (uint32_t)(r6 >> 32), (uint32_t)r7, (uint32_t)(r7 >> 32)}, q + 3);
         } else {
             if (cnt > 0) g[idx] = r0;
             if (cnt > 1) g[idx + 1] = r1;
@@ -71,11 +74,11 @@ struct VBuf {
     }
     __device__ void flush(uint32_t *__restrict__ p, uint64_t idx, bool vec) {
         if (cnt == 16 && vec) {
-            uint4 *q = reinterpret_cast<uint4 *>(p + idx);
-            q[0] = make_uint4(r[0], r[1], r[2], r[3]);
-            q[1] = make_uint4(r[4], r[5], r[6], r[7]);
-            q[2] = make_uint4(r[8], r[9], r[10], r[11]);
-            q[3] = make_uint4(r[12], r[13], r[14], r[15]);
+            u32x4 *q = reinterpret_cast<u32x4 *>(p + idx);
+            __builtin_nontemporal_store(u32x4{r[0], r[1], r[2], r[3]}, q + 0);
+            __builtin_nontemporal_store(u32x4{r[4], r[5], r[6], r[7]}, q + 1);
+            __builtin_nontemporal_store(u32x4{r[8], r[9], r[10], r[11]}, q + 2);
+            __builtin_nontemporal_store(u32x4{r[12], r[13], r[14], r[15]}, q + 3);
         } else {
 #pragma unroll
             for (int q = 0; q < 16; ++q)
