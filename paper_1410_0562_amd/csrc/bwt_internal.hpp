@@ -156,7 +156,7 @@ hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const ui
 // bstart (oversized buckets only); the oversized buckets in bucket order in
 // olist, their starts in the gathered array in ooff (ooff[count] = total); res
 // = {tied suffixes, oversized buckets, oversized suffixes}; part holds 3 words
-// per 4096 bucket ids; trange 2 words per 2048 positions; tflag one byte per
+// per 4096 bucket ids; trange 3 words per 2048 positions; tflag one byte per
 // position (1 = tied).  bucket_emit lists the tied suffixes of the sorted
 // buckets in U (slot order) from tflag.  oversize_gather copies the oversized
 // buckets of kin to ck/cv; once sorted there on the whole key,
@@ -181,9 +181,9 @@ hipError_t launch_oversize_check(const uint64_t *kx, const uint32_t *vx, uint64_
                                  const uint32_t *ooff, const uint32_t *res, uint32_t nb,
                                  uint32_t n, int kshort, uint32_t *obad, uint32_t *olist2,
                                  uint32_t *ooff2, uint32_t *res2, uint32_t *err, hipStream_t s);
-hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32_t n, int bshift,
-                              const uint32_t *trange, const uint32_t *tpre, uint32_t nb,
-                              uint32_t *U, uint32_t ucap, uint32_t *err, hipStream_t s);
+hipError_t launch_bucket_emit(const uint8_t *tflag, uint32_t n, const uint32_t *trange,
+                              const uint32_t *tpre, uint32_t nb, uint32_t *U, uint32_t ucap,
+                              uint32_t *err, hipStream_t s);
 hipError_t launch_oversize_gather(const uint64_t *keys, const uint32_t *vals,
                                   const uint32_t *bstart, const uint32_t *olist,
                                   const uint32_t *ooff, uint32_t nob, uint32_t no, uint32_t n,

@@ -358,8 +358,8 @@ int ensure_ws(bwt_set *h, uint64_t need) {
         while ((uint64_t)nb * BUCKET_TARGET < cap && nb < (1u << BUCKET_MAX_BITS)) nb <<= 1;
         w.bk_words = nb + 16;
     }
-    // bucket tables, scan partials, and two words per 2048-position tile
-    ok &= dalloc(&w.bk, (uint64_t)BK_TABLES * w.bk_words + BK_PART + 2 * (cap / 2048 + 2)) ==
+    // bucket tables, scan partials, and three words per 2048-position tile
+    ok &= dalloc(&w.bk, (uint64_t)BK_TABLES * w.bk_words + BK_PART + 3 * (cap / 2048 + 2)) ==
           hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -513,7 +513,7 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
         HIPCHK(h, launch_bucket_sort(kx, vx, ky, vy, n, bstart, trange, nb, bshift, kfirst,
                                      REFINE_LIMIT, w.misc + MISC_LARGE, tcnt, osz, w.tflag, part,
                                      res, olist, ooff, obad, err, s));
-        HIPCHK(h, launch_bucket_emit(kx, w.tflag, n, bshift, trange, tcnt, nb, w.U[0], n, err, s));
+        HIPCHK(h, launch_bucket_emit(w.tflag, n, trange, tcnt, nb, w.U[0], n, err, s));
         // Every oversized bucket is copied to the sorted pair; those that hold
         // copies of one settled key (the short suffixes of the later blocks:
         // every read's "$", every "A$", ...) are already final there.  The

@@ -434,9 +434,9 @@ __device__ uint32_t bucket_end_search(const uint64_t *__restrict__ keys, int bsh
 // same positions (kin is only read, so the windows that overlap the next tile
 // see unchanged keys).  Per owned bucket b it records tcnt[b] (tied suffixes)
 // and, when oversized, osz[b] (its size) and bstart[b] (its start); both
-// tables are zeroed beforehand.  trange[2t], trange[2t + 1] = the owned range
-// [a, e), and tflag[p] for p in [a, min(e, t0 + BT_WIN)) = 1 if the suffix is
-// tied, else 0.
+// tables are zeroed beforehand.  trange[3t], trange[3t + 1] = the owned range
+// [a, e), trange[3t + 2] = its first bucket, and tflag[p] for p in
+// [a, min(e, t0 + BT_WIN)) = 1 if the suffix is tied, else 0.
 __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t n, int bshift, uint32_t nb,
@@ -491,8 +491,9 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     __syncthreads();
     if (nbk == 0) {
         if (tid == 0) {
-            trange[2 * blockIdx.x] = 0;
-            trange[2 * blockIdx.x + 1] = 0;
+            trange[3 * blockIdx.x] = 0;
+            trange[3 * blockIdx.x + 1] = 0;
+            trange[3 * blockIdx.x + 2] = 0;
         }
         return;
     }
@@ -506,8 +507,9 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
             end = bucket_end_search(kin, bshift, s_k[s_bs[nbk - 1]] >> bshift, t0 + wl, n);
         if (lane == 0) {
             s_end = end;
-            trange[2 * blockIdx.x] = t0 + s_bs[0];
-            trange[2 * blockIdx.x + 1] = end;
+            trange[3 * blockIdx.x] = t0 + s_bs[0];
+            trange[3 * blockIdx.x + 1] = end;
+            trange[3 * blockIdx.x + 2] = (uint32_t)(s_k[s_bs[0]] >> bshift);
         }
     }
     __syncthreads();
@@ -589,18 +591,19 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
 // from U[tpre[b]] for the tile's first bucket b, using the flags the tile sort
 // left for the owned part of the tile's window.
 __global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
-    const uint64_t *__restrict__ keys, const uint8_t *__restrict__ tflag, int bshift,
-    const uint32_t *__restrict__ trange, const uint32_t *__restrict__ tpre, uint32_t nb,
-    uint32_t *__restrict__ U, uint32_t ucap, uint32_t *__restrict__ err) {
+    const uint8_t *__restrict__ tflag, const uint32_t *__restrict__ trange,
+    const uint32_t *__restrict__ tpre, uint32_t nb, uint32_t *__restrict__ U, uint32_t ucap,
+    uint32_t *__restrict__ err) {
     __shared__ uint8_t s_f[BT_WIN];
     __shared__ uint32_t s_tmp[4];
     const uint32_t tid = threadIdx.x;
-    const uint32_t a = trange[2 * blockIdx.x], b = trange[2 * blockIdx.x + 1];
+    const uint32_t a = trange[3 * blockIdx.x], b = trange[3 * blockIdx.x + 1];
     if (a >= b) return;
+    const uint32_t id = trange[3 * blockIdx.x + 2];
+    const uint32_t base0 = id < nb ? tpre[id] : 0u;
     const uint32_t t0 = blockIdx.x * BT_T;
     const uint32_t w = (b - t0 < BT_WIN ? b : t0 + BT_WIN) - a;
     for (uint32_t i = tid; i < w; i += 256) s_f[i] = tflag[a + i];
-    const uint64_t id = keys[a] >> bshift;
     __syncthreads();
     // each thread a contiguous run of the window, so the list keeps order
     constexpr uint32_t PER = (BT_WIN + 255) / 256;
@@ -621,7 +624,7 @@ __global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
         if (tid == 0) atomicOr(err, 512u);
         return;
     }
-    const uint32_t base = tpre[id];
+    const uint32_t base = base0;
     if (base + tot > ucap) {
         if (tid == 0) atomicOr(err, 512u);
         return;
@@ -739,15 +742,22 @@ __global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
     for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < no; j0 += stride) {
         const uint32_t j = j0 + threadIdx.x;
         bool mis = false;
-        uint32_t q = 0;
-        if (j < no) {
+        // bucket of the wave's first index by one search; a bucket holds more
+        // than 64 suffixes, so the wave's other lanes are at most one further
+        const uint32_t jw = __shfl(j, 0, 64);
+        uint32_t qw = 0;
+        if (lane == 0 && jw < no) {
             uint32_t lo = 0, hi = nob - 1;
             while (lo < hi) {
                 uint32_t mid = (lo + hi + 1) >> 1;
-                if (ooff[mid] <= j) lo = mid;
+                if (ooff[mid] <= jw) lo = mid;
                 else hi = mid - 1;
             }
-            q = lo;
+            qw = lo;
+        }
+        uint32_t q = __shfl(qw, 0, 64);
+        if (j < no) {
+            while (q + 1 < nob && ooff[q + 1] <= j) ++q;
             const uint32_t p0 = bstart[olist[q]], pos = p0 + (j - ooff[q]);
             if (pos < n) {
                 const uint64_t k = kx[pos];
@@ -833,12 +843,12 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_emit(const uint64_t *keys, const uint8_t *tflag, uint32_t n, int bshift,
-                              const uint32_t *trange, const uint32_t *tpre, uint32_t nb,
-                              uint32_t *U, uint32_t ucap, uint32_t *err, hipStream_t s) {
+hipError_t launch_bucket_emit(const uint8_t *tflag, uint32_t n, const uint32_t *trange,
+                              const uint32_t *tpre, uint32_t nb, uint32_t *U, uint32_t ucap,
+                              uint32_t *err, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    bucket_tile_emit_kernel<<<(unsigned)div_up(n, BT_T), 256, 0, s>>>(keys, tflag, bshift, trange,
-                                                                      tpre, nb, U, ucap, err);
+    bucket_tile_emit_kernel<<<(unsigned)div_up(n, BT_T), 256, 0, s>>>(tflag, trange, tpre, nb, U,
+                                                                      ucap, err);
     return hipGetLastError();
 }
 
