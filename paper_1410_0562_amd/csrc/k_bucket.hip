@@ -454,10 +454,26 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     const uint32_t t0 = blockIdx.x * BT_T;
     const uint32_t wl = n - t0 < BT_WIN ? n - t0 : BT_WIN;
     const uint64_t bprev = t0 > 0 ? kin[t0 - 1] >> bshift : ~0ull;
-    for (uint32_t i = tid; i < wl; i += 256) {
-        s_k[i] = kin[t0 + i];
-        s_v[i] = vin[t0 + i];
-        s_f[i] = 0;
+    {
+        // all of a thread's loads go out before the first LDS store
+        constexpr uint32_t PER = (BT_WIN + 255) / 256;
+        uint64_t kr[PER];
+        uint32_t vr[PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint32_t i = tid + 256 * q;
+            kr[q] = i < wl ? kin[t0 + i] : 0ull;
+            vr[q] = i < wl ? vin[t0 + i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint32_t i = tid + 256 * q;
+            if (i < wl) {
+                s_k[i] = kr[q];
+                s_v[i] = vr[q];
+                s_f[i] = 0;
+            }
+        }
     }
     __syncthreads();
     // bucket starts of the window, in order (each thread a contiguous run);
@@ -603,7 +619,20 @@ __global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
     const uint32_t base0 = id < nb ? tpre[id] : 0u;
     const uint32_t t0 = blockIdx.x * BT_T;
     const uint32_t w = (b - t0 < BT_WIN ? b : t0 + BT_WIN) - a;
-    for (uint32_t i = tid; i < w; i += 256) s_f[i] = tflag[a + i];
+    {
+        constexpr uint32_t PER = (BT_WIN + 255) / 256;
+        uint8_t fr[PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint32_t i = tid + 256 * q;
+            fr[q] = i < w ? tflag[a + i] : (uint8_t)0;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint32_t i = tid + 256 * q;
+            if (i < w) s_f[i] = fr[q];
+        }
+    }
     __syncthreads();
     // each thread a contiguous run of the window, so the list keeps order
     constexpr uint32_t PER = (BT_WIN + 255) / 256;

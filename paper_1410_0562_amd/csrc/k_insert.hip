@@ -331,11 +331,29 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (uint64_t i = a0 + lane; i < a1; i += 64) {
-        const uint64_t pos = gsa_at(gkeys, gshift, sa0 + i, goff) + i - q0;
-        if (pos < INS_TILE_SYMS) atomicOr(&L.bm[pos >> 5], 1u << (pos & 31));
-        else atomicOr(err, 32u);
-        L.nsym[i - a0] = (uint8_t)code_at(vals, sa0 + i);
+    // the tile's new symbols, eight per lane at a time, their loads issued
+    // before any is used
+    for (uint64_t i0 = a0; i0 < a1; i0 += 8 * 64) {
+        constexpr int NB = 8;
+        uint64_t gk[NB];
+        uint32_t vv[NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            const uint64_t i = i0 + (uint64_t)e * 64 + lane;
+            gk[e] = i < a1 ? gkeys[sa0 + i] : 0ull;
+            vv[e] = i < a1 ? vals[sa0 + i] : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            const uint64_t i = i0 + (uint64_t)e * 64 + lane;
+            if (i < a1) {
+                const uint64_t g = gshift < 64 ? (gk[e] >> gshift) - goff : 0ull;
+                const uint64_t pos = g + i - q0;
+                if (pos < INS_TILE_SYMS) atomicOr(&L.bm[pos >> 5], 1u << (pos & 31));
+                else atomicOr(err, 32u);
+                L.nsym[i - a0] = (uint8_t)(vv[e] >> POS_BITS);
+            }
+        }
     }
     {
         // counts at the tile start: old part by a rank on B_ext, new part from
