@@ -255,14 +255,18 @@ __global__ __launch_bounds__(256) void bucket_scan_up_kernel(const uint32_t *__r
     __shared__ uint32_t s_tmp[4];
     const uint32_t t = blockIdx.x, tid = threadIdx.x;
     uint32_t a = 0, c = 0, e = 0;
+    uint32_t ar[BT_TILE / 256], zr[BT_TILE / 256];
+#pragma unroll
     for (uint32_t q = 0; q < BT_TILE / 256; ++q) {
         const uint32_t b = t * BT_TILE + q * 256 + tid;
-        if (b < nb) {
-            a += tcnt[b];
-            const uint32_t z = osz[b];
-            c += z ? 1u : 0u;
-            e += z;
-        }
+        ar[q] = b < nb ? tcnt[b] : 0u;
+        zr[q] = b < nb ? osz[b] : 0u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < BT_TILE / 256; ++q) {
+        a += ar[q];
+        c += zr[q] ? 1u : 0u;
+        e += zr[q];
     }
     uint32_t ta, tc, te;
     (void)block_excl_sum256(a, s_tmp, &ta);
@@ -316,30 +320,41 @@ __global__ __launch_bounds__(256) void bucket_scan_down_kernel(
     const uint32_t *__restrict__ part, const uint32_t *__restrict__ res,
     uint32_t *__restrict__ olist, uint32_t *__restrict__ ooff, uint32_t *__restrict__ obad) {
     __shared__ uint32_t s_tmp[4];
+    constexpr uint32_t PER = BT_TILE / 256;  // consecutive bucket ids per thread
     const uint32_t t = blockIdx.x, tid = threadIdx.x;
-    uint32_t ra = part[3 * t], rc = part[3 * t + 1], re = part[3 * t + 2];
-    for (uint32_t q = 0; q < BT_TILE / 256; ++q) {
-        const uint32_t b = t * BT_TILE + q * 256 + tid;
-        uint32_t a = 0, z = 0;
+    const uint32_t b0 = t * BT_TILE + tid * PER;
+    uint32_t ar[PER], zr[PER];
+    uint32_t sa = 0, sc = 0, se = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t b = b0 + q;
+        ar[q] = b < nb ? tcnt[b] : 0u;
+        zr[q] = b < nb ? osz[b] : 0u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        sa += ar[q];
+        sc += zr[q] ? 1u : 0u;
+        se += zr[q];
+    }
+    uint32_t ta, tc, te;
+    uint32_t ra = part[3 * t] + block_excl_sum256(sa, s_tmp, &ta);
+    uint32_t rc = part[3 * t + 1] + block_excl_sum256(sc, s_tmp, &tc);
+    uint32_t re = part[3 * t + 2] + block_excl_sum256(se, s_tmp, &te);
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t b = b0 + q;
         if (b < nb) {
-            a = tcnt[b];
-            z = osz[b];
-        }
-        uint32_t ta, tc, te;
-        const uint32_t pa = block_excl_sum256(a, s_tmp, &ta);
-        const uint32_t pc = block_excl_sum256(z ? 1u : 0u, s_tmp, &tc);
-        const uint32_t pe = block_excl_sum256(z, s_tmp, &te);
-        if (b < nb) {
-            tcnt[b] = ra + pa;
-            if (z) {
-                olist[rc + pc] = b;
-                ooff[rc + pc] = re + pe;
-                obad[rc + pc] = 0;
+            tcnt[b] = ra;
+            if (zr[q]) {
+                olist[rc] = b;
+                ooff[rc] = re;
+                obad[rc] = 0;
             }
         }
-        ra += ta;
-        rc += tc;
-        re += te;
+        ra += ar[q];
+        rc += zr[q] ? 1u : 0u;
+        re += zr[q];
     }
     if (t == 0 && tid == 0) ooff[res[1]] = res[2];
 }

@@ -325,9 +325,22 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
         return;
     }
     L.bm[lane] = 0;
-    for (uint32_t k = (uint32_t)lane; k < nr_old * 6; k += 64) {
-        const uint64_t *rw = reinterpret_cast<const uint64_t *>(orecs + r_lo + k / 6);
-        L.old[k] = rw[2 + k % 6];
+    {
+        // at most (INS_TILE_RECS + 1) * 6 = 102 words: two per lane, both
+        // loads issued before the stores
+        uint64_t ow[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const uint32_t k = (uint32_t)lane + 64u * e;
+            ow[e] = k < nr_old * 6
+                        ? reinterpret_cast<const uint64_t *>(orecs + r_lo + k / 6)[2 + k % 6]
+                        : 0ull;
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const uint32_t k = (uint32_t)lane + 64u * e;
+            if (k < nr_old * 6) L.old[k] = ow[e];
+        }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
