@@ -80,7 +80,7 @@ __host__ __device__ inline int first_key_syms(int gbits, int key_bits) {
 // groups of tied suffixes up to this size are finished in LDS by comparing
 // successive chunks; a block with a larger group uses prefix doubling
 constexpr int REFINE_LIMIT = 256;
-constexpr int REFINE_WINDOW = 1024;
+constexpr int REFINE_WINDOW = 512;
 
 constexpr int PREP_TILE_SHIFT = 8;   // positions per read-lookup tile
 constexpr int SCAN_TILE = 4096;      // elements per look-back scan tile
