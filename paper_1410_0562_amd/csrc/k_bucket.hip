@@ -765,8 +765,7 @@ __global__ void oversize_ties_map_kernel(const uint32_t *__restrict__ U2,
 // keys differs from its first key or does not end at a terminator.  A bucket
 // with obad[q] == 0 holds copies of one settled key: it is already in its
 // final order (position order, which the stable passes kept) and has no ties.
-// The counts come from the bucket scans (res[1] buckets, res[2] suffixes);
-// the grid strides over the gathered indices, a wave over 64 consecutive ones.
+// The counts come from the bucket scans (res[1] buckets, res[2] suffixes).
 __global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
                                            const uint32_t *__restrict__ vx,
                                            uint64_t *__restrict__ ky, uint32_t *__restrict__ vy,
@@ -782,25 +781,28 @@ __global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
         return;
     }
     const int lane = lane_id();
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < no; j0 += stride) {
+    // workgroup g takes the gathered indices [c0, c1), 256 at a time; each
+    // wave finds its bucket once and then only steps forward (a bucket holds
+    // more than 64 suffixes, so a step of 64 indices crosses at most one end)
+    const uint32_t per = (no + gridDim.x - 1) / gridDim.x;
+    const uint32_t c0 = blockIdx.x * per, c1 = c0 + per < no ? c0 + per : no;
+    const uint32_t wave_off = threadIdx.x & ~63u;
+    uint32_t qw = 0;
+    if (c0 + wave_off < c1 && lane == 0) {
+        const uint32_t jw = c0 + wave_off;
+        uint32_t lo = 0, hi = nob - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (ooff[mid] <= jw) lo = mid;
+            else hi = mid - 1;
+        }
+        qw = lo;
+    }
+    uint32_t q = __shfl(qw, 0, 64);
+    for (uint32_t j0 = c0; j0 < c1; j0 += blockDim.x) {
         const uint32_t j = j0 + threadIdx.x;
         bool mis = false;
-        // bucket of the wave's first index by one search; a bucket holds more
-        // than 64 suffixes, so the wave's other lanes are at most one further
-        const uint32_t jw = __shfl(j, 0, 64);
-        uint32_t qw = 0;
-        if (lane == 0 && jw < no) {
-            uint32_t lo = 0, hi = nob - 1;
-            while (lo < hi) {
-                uint32_t mid = (lo + hi + 1) >> 1;
-                if (ooff[mid] <= jw) lo = mid;
-                else hi = mid - 1;
-            }
-            qw = lo;
-        }
-        uint32_t q = __shfl(qw, 0, 64);
-        if (j < no) {
+        if (j < c1) {
             while (q + 1 < nob && ooff[q + 1] <= j) ++q;
             const uint32_t p0 = bstart[olist[q]], pos = p0 + (j - ooff[q]);
             if (pos < n) {
@@ -818,6 +820,8 @@ __global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
         const int prev = below ? 63 - __builtin_clzll(below) : lane;
         const uint32_t qprev = __shfl(q, prev, 64);
         if (mis && (below == 0 || qprev != q)) atomicOr(&obad[q], 1u);
+        // every lane takes the bucket of the wave's last lane into the next step
+        q = __shfl(q, 63, 64);
     }
 }
 
