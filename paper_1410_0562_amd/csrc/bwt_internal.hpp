@@ -115,22 +115,21 @@ __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a +
 
 // radix sort pieces (k_radix.hip).  Digit counts are spread over HIST_COPIES
 // copies so that many workgroups adding to the same hot digit do not queue on
-// one atomic word: hist[(pass * HIST_COPIES + copy) * 256 + digit].  Before
-// pass p, launch_radix_starts sums the copies into exclusive digit starts
-// (starts[p * 256 + digit]); pass p adds the next pass's counts.
+// one atomic word: hist[(pass * HIST_COPIES + copy) * 256 + digit].  Pass p
+// sums the copies of its counts into digit starts (hist_cur = pass p's copies)
+// and adds the next pass's counts.
 constexpr int HIST_COPIES = 32;
 constexpr uint32_t HIST_WORDS = 8 * HIST_COPIES * 256;
 hipError_t launch_radix_hist1(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
                               hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s);
-hipError_t launch_radix_starts(const uint32_t *hist_pass, uint32_t *starts_pass, hipStream_t s);
 // cfg selects the tile shape (see radix_tile_keys); the status array must
 // hold 256 words per tile of the smallest shape
 int radix_tile_keys(int cfg);
 constexpr int RADIX_CFGS = 9;
 constexpr int RADIX_MIN_TILE = 2048;
 hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                             uint32_t *vout, uint64_t n, int shift, const uint32_t *starts,
+                             uint32_t *vout, uint64_t n, int shift, const uint32_t *hist_cur,
                              uint32_t *hist_next, int shift_next, uint64_t *status,
                              uint32_t *counter, uint32_t epoch, uint32_t *err, int cfg,
                              hipStream_t s);

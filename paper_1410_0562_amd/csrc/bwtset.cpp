@@ -83,8 +83,7 @@ constexpr uint32_t MIN_SEG_LEN = 256;
 constexpr int MAX_LANES = 4;
 constexpr uint32_t BUCKET_TARGET = 32;  // suffixes per bucket the bucket count aims at
 constexpr uint32_t BUCKET_MIN_BLOCK = 1u << 20;  // smallest block that takes the bucket finish
-constexpr int MISC_STARTS = 64;               // 8 x 256 exclusive digit starts
-constexpr int MISC_HIST = MISC_STARTS + 8 * 256;  // HIST_WORDS digit counts
+constexpr int MISC_HIST = 64;                 // HIST_WORDS digit counts
 constexpr int MISC_WORDS = MISC_HIST + HIST_WORDS + 64;
 
 struct Timer {
@@ -410,17 +409,16 @@ int radix_sort(bwt_set *h, hipStream_t s, uint64_t *kin, uint32_t *vin, uint64_t
     *ko = kin;
     *vo = vin;
     if (n <= 1) return BWT_OK;
-    uint32_t *hist = w.misc + MISC_HIST, *starts = w.misc + MISC_STARTS;
+    uint32_t *hist = w.misc + MISC_HIST;
     const uint32_t per_pass = HIST_COPIES * 256;
     if (!counted0) HIPCHK(h, launch_radix_hist1(kin, n, shift0, hist, s));
     if (npass > 1) HIPCHK(h, launch_zero_u32(hist + per_pass, per_pass * (npass - 1), s));
     uint64_t *ka = kin, *kb = kalt;
     uint32_t *va = vin, *vb = valt;
     for (int p = 0; p < npass; ++p) {
-        HIPCHK(h, launch_radix_starts(hist + per_pass * p, starts + 256 * p, s));
         {
             Scope sc(h, s, SPAN_RADIX_PASS, n);
-            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, shift0 + 8 * p, starts + 256 * p,
+            HIPCHK(h, launch_radix_pass(ka, va, kb, vb, n, shift0 + 8 * p, hist + per_pass * p,
                                         p + 1 < npass ? hist + per_pass * (p + 1) : nullptr,
                                         shift0 + 8 * (p + 1), w.status_radix, w.misc + MISC_CNT_RADIX,
                                         next_epoch(), w.misc + MISC_ERR, h->radix_cfg, s));
@@ -462,10 +460,12 @@ int check_err(bwt_set *h, hipStream_t s) {
     return BWT_OK;
 }
 
-RankSegments rank_segments(bwt_set *h) {
+// Long-read segments for ComputeRanks; none when no read of the input is
+// longer than a segment (the segment kernels would find an empty queue).
+RankSegments rank_segments(bwt_set *h, uint64_t maxlen) {
     RankSegments sg;
     Workspace &w = h->ws;
-    sg.seg_len = h->seg_len;
+    sg.seg_len = maxlen > h->seg_len ? h->seg_len : 0;
     sg.overlap = h->seg_overlap;
     sg.seg_list = w.seg_list;
     sg.seg_cap = w.seg_cap;
@@ -927,7 +927,7 @@ int run_block(bwt_set *L, hipStream_t s, const DevBlock &B, const std::vector<Ho
         const RankKeys kk = rank_keys(L, s, gbits, n_blk, &rc);
         if (rc) return fail(L, rc);
         HIPCHK(L, launch_compute_ranks_units(in.reads, off, w.soff, m_blk, n_blk, rdev, nu, w.g,
-                                             &kk, rank_segments(L), w.misc + MISC_ERR, s));
+                                             &kk, rank_segments(L, in.maxlen), w.misc + MISC_ERR, s));
     }
     uint32_t *sa = nullptr;
     const uint64_t *gkeys = nullptr;
@@ -1478,7 +1478,7 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
             if (rc) return fail(h, rc);
             HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
                                            S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
-                                           rank_segments(h), w.misc + MISC_ERR, s));
+                                           rank_segments(h, P.maxlen), w.misc + MISC_ERR, s));
         }
         uint32_t *sa = nullptr;
         const uint64_t *gkeys = nullptr;
@@ -1824,7 +1824,7 @@ int bwt_set_compute_ranks(bwt_set_t h, const uint8_t *reads, const uint64_t *off
         HIPCHK(h, launch_compute_ranks(P.reads, P.off, h->ws.soff, (uint32_t)m,
                                        (uint32_t)P.total_suffixes, B.recs, B.sbc, B.meta,
                                        h->n >= (1ull << SB_SHIFT) ? 1 : 0, g_out, nullptr,
-                                       rank_segments(h), h->ws.misc + MISC_ERR, s));
+                                       rank_segments(h, P.maxlen), h->ws.misc + MISC_ERR, s));
     }
     HIPCHK(h, hipStreamSynchronize(s));
     if (h->timer.on) timer_collect(h);

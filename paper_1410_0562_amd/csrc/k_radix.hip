@@ -3,14 +3,15 @@
 // tiles (onesweep style), for the block suffix sort of set-bwte (Section 3:
 // any suffix sorting algorithm may build the block's suffix array).
 //
-// Per pass, a 256-thread workgroup takes a tile of 4096 keys (in tile order
-// from an atomic counter), ranks every key among equal digits of its tile
-// with 8 wave ballots per key (stable: tile order is wave, item, lane), gets
-// the count of each digit in all earlier tiles by look-back, stages the tile
-// in LDS in sorted order and writes each digit run contiguously.  Keys are
-// read once and written once per pass.  The digit totals a pass needs are
-// counted by the previous pass while it holds the keys in registers (the
-// first pass's by whoever built the keys), so no pass re-reads the keys.
+// Per pass, a workgroup takes a tile of keys (in tile order from an atomic
+// counter), ranks every key among equal digits of its tile with 8 wave
+// ballots per key (stable: tile order is wave, item, lane), gets the count of
+// each digit in all earlier tiles by look-back, stages the tile in LDS in
+// sorted order and writes each digit run contiguously.  Keys are read once
+// and written once per pass.  The digit totals a pass needs are counted by
+// the previous pass while it holds the keys in registers (the first pass's by
+// whoever built the keys), so no pass re-reads the keys; every tile sums the
+// copies of those counts into digit starts itself.
 #include "dev_util.hpp"
 
 namespace bwt {
@@ -39,17 +40,6 @@ __global__ __launch_bounds__(256) void radix_hist1_kernel(const uint64_t *__rest
     if (h[tid]) atomicAdd(&hist[(blockIdx.x % HIST_COPIES) * 256 + tid], h[tid]);
 }
 
-// Sums the copies of one pass's counts and turns them into exclusive starts.
-__global__ __launch_bounds__(256) void radix_starts_kernel(const uint32_t *__restrict__ hist,
-                                                           uint32_t *__restrict__ starts) {
-    __shared__ uint32_t tmp[4];
-    const int d = threadIdx.x;
-    uint32_t c = 0;
-    for (int k = 0; k < HIST_COPIES; ++k) c += hist[k * 256 + d];
-    uint32_t tot;
-    starts[d] = block_excl_sum256(c, tmp, &tot);
-}
-
 // Block-wide exclusive sum over THREADS threads (every thread calls it);
 // tmp holds THREADS/64 words.  Contains barriers.
 template <int THREADS>
@@ -75,7 +65,7 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp) {
 template <int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void radix_pass_kernel(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ starts,
+    uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ hist_cur,
     uint32_t *__restrict__ hist_next, int shift_next, uint64_t *__restrict__ status,
     uint32_t *__restrict__ counter, uint32_t ntiles, uint32_t epoch, uint32_t *__restrict__ err) {
     constexpr int WAVES = THREADS / WAVE;
@@ -111,6 +101,15 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(
         bool ok = idx < n;
         k[e] = ok ? kin[idx] : 0;
         v[e] = ok ? vin[idx] : 0;
+    }
+    // this pass's count of every digit: the sum of its HIST_COPIES copies
+    uint32_t dcount = 0;
+    if (tid < 256) {
+        uint32_t hc[HIST_COPIES];
+#pragma unroll
+        for (int c = 0; c < HIST_COPIES; ++c) hc[c] = hist_cur[c * 256 + tid];
+#pragma unroll
+        for (int c = 0; c < HIST_COPIES; ++c) dcount += hc[c];
     }
     if (hist_next) {
         // histogram of the next pass's digit while the keys are in registers
@@ -151,10 +150,11 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(
         }
     }
     const uint32_t lstart = block_excl_sum<THREADS>(tid < 256 ? total : 0u, s_tmp);
+    const uint32_t dstart = block_excl_sum<THREADS>(tid < 256 ? dcount : 0u, s_tmp);
     if (tid < 256) {
         s_lstart[tid] = lstart;
         uint32_t excl = lookback(status + tid, 256u, tile, epoch, total, OpSum(), 0u, err);
-        s_gbase[tid] = (int32_t)(starts[tid] + excl) - (int32_t)lstart;
+        s_gbase[tid] = (int32_t)(dstart + excl) - (int32_t)lstart;
         if (hist_next && s_next[tid])
             atomicAdd(&hist_next[(tile % HIST_COPIES) * 256 + tid], s_next[tid]);
     }
@@ -209,11 +209,6 @@ hipError_t launch_radix_hist1(const uint64_t *keys, uint64_t n, int shift, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_radix_starts(const uint32_t *hist_pass, uint32_t *starts_pass, hipStream_t s) {
-    radix_starts_kernel<<<1, 256, 0, s>>>(hist_pass, starts_pass);
-    return hipGetLastError();
-}
-
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t s) {
     radix_zero_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, (int)n);
     return hipGetLastError();
@@ -235,14 +230,14 @@ int radix_tile_keys(int cfg) {
 }
 
 hipError_t launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                             uint32_t *vout, uint64_t n, int shift, const uint32_t *starts,
+                             uint32_t *vout, uint64_t n, int shift, const uint32_t *hist_cur,
                              uint32_t *hist_next, int shift_next, uint64_t *status,
                              uint32_t *counter, uint32_t epoch, uint32_t *err, int cfg,
                              hipStream_t s) {
     const uint32_t ntiles = (uint32_t)div_up(n, (uint64_t)radix_tile_keys(cfg));
     if (ntiles == 0) return hipSuccess;
 #define BWT_PASS(T, I)                                                                      \
-    radix_pass_kernel<T, I><<<ntiles, T, 0, s>>>(kin, vin, kout, vout, n, shift, starts,    \
+    radix_pass_kernel<T, I><<<ntiles, T, 0, s>>>(kin, vin, kout, vout, n, shift, hist_cur,  \
                                                  hist_next, shift_next, status, counter,    \
                                                  ntiles, epoch, err)
     switch (cfg) {
