@@ -1658,7 +1658,7 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
         b += c * (8 * 4 + 4 * 6 + 1 + 4 * 2) + div_up(c, 64) * 16 +
              (2 * (div_up(c, 64 << BINT_SEG_SHIFT) + 2) + 1) * 16 + div_up(c, 4096) * 4 +
              tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4 +
-             4ull * (BK_TABLES * w.bk_words + BK_PART + 2 * (c / 2048 + 2));
+             4ull * (BK_TABLES * w.bk_words + BK_PART + 3 * (c / 2048 + 2));
     }
     b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
          h->stage_out_cap + h->btab_cap + h->bstage_cap;
