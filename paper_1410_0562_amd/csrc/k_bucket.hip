@@ -85,19 +85,20 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&x)[E],
 }
 
 // Value of lane (lane ^ J) of the wave.  Distances 1 and 2 stay inside a
-// quad (DPP quad_perm), 4 and 8 inside a row of 16 (DPP row shifts, one per
-// direction); 16 and 32 go through the LDS crossbar.
+// quad (DPP quad_perm); 4 is a mirror inside each half-row of 8 followed by a
+// reversal inside each quad (two DPP moves); 8 is a rotation by 8 inside a
+// row of 16 (DPP row_ror:8); 16 and 32 go through the LDS crossbar.
 template <int J>
 __device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
     if constexpr (J == 1) {
         return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
     } else if constexpr (J == 2) {
         return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
-    } else if constexpr (J == 4 || J == 8) {
-        // row_shl:J reads lane + J, row_shr:J reads lane - J (inside the row)
-        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + J, 0xF, 0xF, false);
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + J, 0xF, 0xF, false);
-        return (lane & J) ? dn : up;
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (J == 4) {
+        const int m = __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, false);
     } else {
         return (uint32_t)__shfl_xor((int)v, J, 64);
     }
