@@ -139,6 +139,49 @@ __device__ __forceinline__ void wave_sort_rows(uint64_t (&c)[R], int lane) {
     row_levels<2, R, S>(c, lane);
 }
 
+// Bitonic network over the 64 * E distinct words of one wave (element
+// r * 64 + lane in c[r]), ascending: compare-exchanges at distance >= 64 stay
+// inside a lane (registers r and r ^ (J / 64)), shorter ones use lane_xor.
+template <int E, int KK, int J>
+__device__ __forceinline__ void reg_stage(uint64_t (&c)[E], int lane) {
+    if constexpr (J >= 64) {
+        constexpr int D = J / 64;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if ((r & D) == 0) {
+                const int rr = r | D;
+                const bool up = ((r * 64) & KK) == 0;  // KK >= 128: uniform per register
+                const uint64_t a = c[r], b = c[rr];
+                if ((a > b) == up) {
+                    c[r] = b;
+                    c[rr] = a;
+                }
+            }
+        }
+    } else {
+        const bool lower = (lane & J) == 0;
+        uint64_t p[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const uint32_t lo = lane_xor<J>((uint32_t)c[r], lane);
+            const uint32_t hi = lane_xor<J>((uint32_t)(c[r] >> 32), lane);
+            p[r] = (uint64_t)lo | ((uint64_t)hi << 32);
+        }
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const bool up = (((uint32_t)(r * 64 + lane)) & (uint32_t)KK) == 0;
+            if ((lower == up) == (c[r] > p[r])) c[r] = p[r];
+        }
+    }
+    if constexpr (J > 1) reg_stage<E, KK, J / 2>(c, lane);
+}
+
+template <int E, int KK>
+__device__ __forceinline__ void reg_levels(uint64_t (&c)[E], int lane) {
+    reg_stage<E, KK, KK / 2>(c, lane);
+    if constexpr (KK < 64 * E) reg_levels<E, KK * 2>(c, lane);
+}
+
 // a key whose length field is below kshort ends at its terminator: never tied
 __device__ __forceinline__ bool short_key(uint64_t k, int kshort) {
     return (k & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)kshort;
@@ -216,19 +259,37 @@ __device__ __forceinline__ uint32_t rows_ties(const uint64_t (&k)[R], const uint
 template <int E>
 __device__ uint32_t wave_bucket(const uint64_t *__restrict__ s_k, const uint32_t *__restrict__ s_v,
                                 uint32_t st, uint32_t z, uint64_t *__restrict__ kout,
-                                uint32_t *__restrict__ vout, uint32_t p0, int kshort,
+                                uint32_t *__restrict__ vout, uint32_t p0, int bshift, int kshort,
                                 uint32_t limit, uint32_t *__restrict__ large,
                                 uint8_t *__restrict__ s_f) {
     const int lane = lane_id();
     uint64_t k[E];
     uint32_t x[E];
+    if (bshift <= 56) {
+        // one word per suffix: (key - bucket base) << 8 | index in the bucket
+        const uint64_t base = (s_k[st] >> bshift) << bshift;
+        uint64_t c[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const uint32_t i = (uint32_t)(r * 64 + lane);
-        x[r] = i;
-        k[r] = i < z ? s_k[st + i] : ~0ull;  // a real key never has all length bits set
+        for (int r = 0; r < E; ++r) {
+            const uint32_t i = (uint32_t)(r * 64 + lane);
+            c[r] = i < z ? ((s_k[st + i] - base) << 8) | (uint64_t)i : ~0ull;
+        }
+        reg_levels<E, 2>(c, lane);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const uint32_t i = (uint32_t)(r * 64 + lane);
+            k[r] = i < z ? base + (c[r] >> 8) : ~0ull;
+            x[r] = (uint32_t)(c[r] & 255u);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const uint32_t i = (uint32_t)(r * 64 + lane);
+            x[r] = i;
+            k[r] = i < z ? s_k[st + i] : ~0ull;  // a real key never has all length bits set
+        }
+        wave_bitonic<E>(k, x, lane);
     }
-    wave_bitonic<E>(k, x, lane);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t i = (uint32_t)(r * 64 + lane);
@@ -595,9 +656,9 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                     clen += z;
                 } else if (z <= BUCKET_CAP) {
                     uint32_t tt;
-                    if (z <= 64) tt = wave_bucket<1>(s_k, s_v, st, z, kout, vout, t0 + st, kshort, limit, large, s_f);
-                    else if (z <= 128) tt = wave_bucket<2>(s_k, s_v, st, z, kout, vout, t0 + st, kshort, limit, large, s_f);
-                    else tt = wave_bucket<4>(s_k, s_v, st, z, kout, vout, t0 + st, kshort, limit, large, s_f);
+                    if (z <= 64) tt = wave_bucket<1>(s_k, s_v, st, z, kout, vout, t0 + st, bshift, kshort, limit, large, s_f);
+                    else if (z <= 128) tt = wave_bucket<2>(s_k, s_v, st, z, kout, vout, t0 + st, bshift, kshort, limit, large, s_f);
+                    else tt = wave_bucket<4>(s_k, s_v, st, z, kout, vout, t0 + st, bshift, kshort, limit, large, s_f);
                     if (lane == 0 && tt && id < nb) tcnt[id] = tt;
                 } else if (lane == 0 && id < nb) {
                     osz[id] = z;
