@@ -182,6 +182,21 @@ __device__ __forceinline__ void reg_levels(uint64_t (&c)[E], int lane) {
     if constexpr (KK < 64 * E) reg_levels<E, KK * 2>(c, lane);
 }
 
+// Value of lane - 1 / lane + 1 of the wave (DPP wave_shr:1 / wave_shl:1);
+// lane 0 / lane 63 gets its own value.
+__device__ __forceinline__ uint64_t lane_prev(uint64_t v) {
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
+    return (uint64_t)a | ((uint64_t)b << 32);
+}
+__device__ __forceinline__ uint64_t lane_next(uint64_t v) {
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
+    return (uint64_t)a | ((uint64_t)b << 32);
+}
+
 // a key whose length field is below kshort ends at its terminator: never tied
 __device__ __forceinline__ bool short_key(uint64_t k, int kshort) {
     return (k & ((1u << KEY_LEN_BITS) - 1)) < (uint64_t)kshort;
@@ -201,8 +216,8 @@ __device__ __forceinline__ uint32_t wave_ties(const uint64_t (&k)[E], uint32_t z
     for (int r = 0; r < E; ++r) {
         const uint32_t i = (uint32_t)(r * 64 + lane);
         const bool ok = i < z;
-        uint64_t kp = __shfl_up(k[r], 1, 64);
-        uint64_t kn = __shfl_down(k[r], 1, 64);
+        uint64_t kp = lane_prev(k[r]);
+        uint64_t kn = lane_next(k[r]);
         const uint64_t last_prev = r > 0 ? __shfl(k[r > 0 ? r - 1 : 0], 63, 64) : 0ull;
         const uint64_t first_next = r + 1 < E ? __shfl(k[r + 1 < E ? r + 1 : r], 0, 64) : 0ull;
         if (lane == 0) kp = last_prev;
@@ -221,34 +236,6 @@ __device__ __forceinline__ uint32_t wave_ties(const uint64_t (&k)[E], uint32_t z
         if (t && !eq_next && i - hm + 1 > limit) atomicOr(large, 1u);
     }
     *count = run;
-    return rows;
-}
-
-// Tied elements of R sorted buckets held one per row (z[r] <= 64 keys,
-// element = lane): bit r of the result is this lane's element of row r;
-// cnt[r] = tied elements of row r (wave-uniform).
-template <int R>
-__device__ __forceinline__ uint32_t rows_ties(const uint64_t (&k)[R], const uint32_t (&z)[R],
-                                              int kshort, uint32_t limit,
-                                              uint32_t *__restrict__ large, uint32_t (&cnt)[R]) {
-    const int lane = lane_id();
-    uint32_t rows = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = (uint32_t)lane;
-        const bool ok = i < z[r];
-        const uint64_t kp = __shfl_up(k[r], 1, 64);
-        const uint64_t kn = __shfl_down(k[r], 1, 64);
-        const bool eq_prev = ok && i > 0 && kp == k[r];
-        const bool eq_next = ok && i + 1 < z[r] && kn == k[r];
-        const bool t = ok && !short_key(k[r], kshort) && (eq_prev || eq_next);
-        cnt[r] = (uint32_t)__popcll(__ballot(t));
-        rows |= (t ? 1u : 0u) << r;
-        if (limit < 64) {
-            const uint32_t hm = wave_incl_max((ok && !eq_prev) ? i : 0u);
-            if (t && !eq_next && i - hm + 1 > limit) atomicOr(large, 1u);
-        }
-    }
     return rows;
 }
 
@@ -455,8 +442,8 @@ __device__ __forceinline__ void sort_packed_rows(
             kout[t0 + rst[r] + l] = k;
             vout[t0 + rst[r] + l] = s_v[rst[r] + (uint32_t)(c[r] & 63u)];
         }
-        const uint64_t kp = __shfl_up(k, 1, 64);
-        const uint64_t kn = __shfl_down(k, 1, 64);
+        const uint64_t kp = lane_prev(k);
+        const uint64_t kn = lane_next(k);
         const bool eq_prev = ok && l > 0 && kp == k;
         const bool eq_next = ok && l + 1 < rlen[r] && kn == k;
         const bool t = ok && !short_key(k, kshort) && (eq_prev || eq_next);
