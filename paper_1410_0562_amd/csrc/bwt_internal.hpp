@@ -170,19 +170,20 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
                               uint32_t *tcnt, uint32_t *osz, uint8_t *tflag, uint32_t *part,
                               uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *obad,
                               uint32_t *err, hipStream_t s);
-// Copies every oversized bucket of (kx, vx) to (ky, vy) and lists in
-// olist2 / ooff2 (res2 = {count, suffixes}) those that still need sorting:
-// the others hold copies of one key that ends at its terminator.  The counts
-// are read on the device from the bucket scans' res; obad is one word per
-// oversized bucket, zeroed by bucket_sort.
-hipError_t launch_oversize_check(const uint64_t *kx, const uint32_t *vx, uint64_t *ky,
+// emit_and_check: bucket_emit (the tied suffixes of the sorted buckets listed
+// in U, slot order, from tflag) and, side by side in the same launch, the
+// copy of every oversized bucket of (kx, vx) to (ky, vy); then the oversized
+// buckets that still need sorting are listed in olist2 / ooff2 (res2 =
+// {count, suffixes}): the others hold copies of one key that ends at its
+// terminator.  The counts are read on the device from the bucket scans' res;
+// obad is one word per oversized bucket, zeroed by bucket_sort.
+hipError_t launch_emit_and_check(const uint8_t *tflag, uint32_t n, const uint32_t *trange,
+                                 const uint32_t *tpre, uint32_t nb, uint32_t *U, uint32_t ucap,
+                                 const uint64_t *kx, const uint32_t *vx, uint64_t *ky,
                                  uint32_t *vy, const uint32_t *bstart, const uint32_t *olist,
-                                 const uint32_t *ooff, const uint32_t *res, uint32_t nb,
-                                 uint32_t n, int kshort, uint32_t *obad, uint32_t *olist2,
-                                 uint32_t *ooff2, uint32_t *res2, uint32_t *err, hipStream_t s);
-hipError_t launch_bucket_emit(const uint8_t *tflag, uint32_t n, const uint32_t *trange,
-                              const uint32_t *tpre, uint32_t nb, uint32_t *U, uint32_t ucap,
-                              uint32_t *err, hipStream_t s);
+                                 const uint32_t *ooff, const uint32_t *res, int kshort,
+                                 uint32_t *obad, uint32_t *olist2, uint32_t *ooff2,
+                                 uint32_t *res2, uint32_t *err, hipStream_t s);
 hipError_t launch_oversize_gather(const uint64_t *keys, const uint32_t *vals,
                                   const uint32_t *bstart, const uint32_t *olist,
                                   const uint32_t *ooff, uint32_t nob, uint32_t no, uint32_t n,

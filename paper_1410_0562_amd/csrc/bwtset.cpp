@@ -513,13 +513,14 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
         HIPCHK(h, launch_bucket_sort(kx, vx, ky, vy, n, bstart, trange, nb, bshift, kfirst,
                                      REFINE_LIMIT, w.misc + MISC_LARGE, tcnt, osz, w.tflag, part,
                                      res, olist, ooff, obad, err, s));
-        HIPCHK(h, launch_bucket_emit(w.tflag, n, trange, tcnt, nb, w.U[0], n, err, s));
-        // Every oversized bucket is copied to the sorted pair; those that hold
-        // copies of one settled key (the short suffixes of the later blocks:
-        // every read's "$", every "A$", ...) are already final there.  The
-        // tables of tie counts and sizes are free by now and list the others.
-        HIPCHK(h, launch_oversize_check(kx, vx, ky, vy, bstart, olist, ooff, res, nb, n, kfirst,
-                                        obad, olist2, ooff2, w.misc + MISC_PILE, err, s));
+        // The tied suffixes go to U; beside that, every oversized bucket is
+        // copied to the sorted pair, and those that hold copies of one
+        // settled key (the short suffixes of the later blocks: every read's
+        // "$", every "A$", ...) are already final there.  The tables of tie
+        // counts and sizes are free by then and list the others.
+        HIPCHK(h, launch_emit_and_check(w.tflag, n, trange, tcnt, nb, w.U[0], n, kx, vx, ky, vy,
+                                        bstart, olist, ooff, res, kfirst, obad, olist2, ooff2,
+                                        w.misc + MISC_PILE, err, s));
     }
     // one read of the counts: tied suffixes, large flag, oversized buckets
     // and those still to sort

@@ -667,21 +667,20 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     for (uint32_t i = s_bs[0] + tid; i < fe; i += 256) tflag[t0 + i] = s_f[i];
 }
 
-// Lists the tied suffixes of the owned buckets of each tile in slot order,
-// from U[tpre[b]] for the tile's first bucket b, using the flags the tile sort
-// left for the owned part of the tile's window.
-__global__ __launch_bounds__(256) void bucket_tile_emit_kernel(
-    const uint8_t *__restrict__ tflag, const uint32_t *__restrict__ trange,
-    const uint32_t *__restrict__ tpre, uint32_t nb, uint32_t *__restrict__ U, uint32_t ucap,
-    uint32_t *__restrict__ err) {
-    __shared__ uint8_t s_f[BT_WIN];
-    __shared__ uint32_t s_tmp[4];
+// Lists the tied suffixes of the owned buckets of tile t in slot order, from
+// U[tpre[b]] for the tile's first bucket b, using the flags the tile sort left
+// for the owned part of the tile's window (one workgroup; s_f holds BT_WIN
+// bytes, s_tmp 4 words).
+__device__ void emit_tile(const uint8_t *__restrict__ tflag, const uint32_t *__restrict__ trange,
+                          const uint32_t *__restrict__ tpre, uint32_t nb, uint32_t *__restrict__ U,
+                          uint32_t ucap, uint32_t *__restrict__ err, uint32_t t,
+                          uint8_t *__restrict__ s_f, uint32_t *__restrict__ s_tmp) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t a = trange[3 * blockIdx.x], b = trange[3 * blockIdx.x + 1];
+    const uint32_t a = trange[3 * t], b = trange[3 * t + 1];
     if (a >= b) return;
-    const uint32_t id = trange[3 * blockIdx.x + 2];
+    const uint32_t id = trange[3 * t + 2];
     const uint32_t base0 = id < nb ? tpre[id] : 0u;
-    const uint32_t t0 = blockIdx.x * BT_T;
+    const uint32_t t0 = t * BT_T;
     const uint32_t w = (b - t0 < BT_WIN ? b : t0 + BT_WIN) - a;
     {
         constexpr uint32_t PER = (BT_WIN + 255) / 256;
@@ -815,26 +814,23 @@ __global__ void oversize_ties_map_kernel(const uint32_t *__restrict__ U2,
 // with obad[q] == 0 holds copies of one settled key: it is already in its
 // final order (position order, which the stable passes kept) and has no ties.
 // The counts come from the bucket scans (res[1] buckets, res[2] suffixes).
-__global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
-                                           const uint32_t *__restrict__ vx,
-                                           uint64_t *__restrict__ ky, uint32_t *__restrict__ vy,
-                                           const uint32_t *__restrict__ bstart,
-                                           const uint32_t *__restrict__ olist,
-                                           const uint32_t *__restrict__ ooff,
-                                           const uint32_t *__restrict__ res, uint32_t n,
-                                           int kshort, uint32_t *__restrict__ obad,
-                                           uint32_t *__restrict__ err) {
+__device__ void check_chunk(const uint64_t *__restrict__ kx, const uint32_t *__restrict__ vx,
+                            uint64_t *__restrict__ ky, uint32_t *__restrict__ vy,
+                            const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ olist,
+                            const uint32_t *__restrict__ ooff, const uint32_t *__restrict__ res,
+                            uint32_t n, int kshort, uint32_t *__restrict__ obad,
+                            uint32_t *__restrict__ err, uint32_t g, uint32_t G) {
     const uint32_t nob = res[1], no = res[2];
     if (no > n || (no > 0 && nob == 0)) {  // cannot happen; keeps the indexing in bounds
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 256u);
+        if (g == 0 && threadIdx.x == 0) atomicOr(err, 256u);
         return;
     }
     const int lane = lane_id();
-    // workgroup g takes the gathered indices [c0, c1), 256 at a time; each
+    // workgroup g of G takes the gathered indices [c0, c1), 256 at a time; each
     // wave finds its bucket once and then only steps forward (a bucket holds
     // more than 64 suffixes, so a step of 64 indices crosses at most one end)
-    const uint32_t per = (no + gridDim.x - 1) / gridDim.x;
-    const uint32_t c0 = blockIdx.x * per, c1 = c0 + per < no ? c0 + per : no;
+    const uint32_t per = (no + G - 1) / G;
+    const uint32_t c0 = g * per, c1 = c0 + per < no ? c0 + per : no;
     const uint32_t wave_off = threadIdx.x & ~63u;
     uint32_t qw = 0;
     if (c0 + wave_off < c1 && lane == 0) {
@@ -872,6 +868,27 @@ __global__ void oversize_check_copy_kernel(const uint64_t *__restrict__ kx,
         // every lane takes the bucket of the wave's last lane into the next step
         q = __shfl(q, 63, 64);
     }
+}
+
+// The emit of every tile and the copy and check of the oversized buckets in
+// one launch: both need only the bucket scans, so they run side by side.
+// Workgroups below ntiles emit tile blockIdx.x; the others take chunk
+// blockIdx.x - ntiles of G.
+__global__ __launch_bounds__(256) void emit_and_check_kernel(
+    const uint8_t *__restrict__ tflag, const uint32_t *__restrict__ trange,
+    const uint32_t *__restrict__ tpre, uint32_t nb, uint32_t *__restrict__ U, uint32_t ucap,
+    uint32_t ntiles, const uint64_t *__restrict__ kx, const uint32_t *__restrict__ vx,
+    uint64_t *__restrict__ ky, uint32_t *__restrict__ vy, const uint32_t *__restrict__ bstart,
+    const uint32_t *__restrict__ olist, const uint32_t *__restrict__ ooff,
+    const uint32_t *__restrict__ res, uint32_t n, int kshort, uint32_t *__restrict__ obad,
+    uint32_t G, uint32_t *__restrict__ err) {
+    __shared__ uint8_t s_f[BT_WIN];
+    __shared__ uint32_t s_tmp[4];
+    if (blockIdx.x < ntiles)
+        emit_tile(tflag, trange, tpre, nb, U, ucap, err, blockIdx.x, s_f, s_tmp);
+    else
+        check_chunk(kx, vx, ky, vy, bstart, olist, ooff, res, n, kshort, obad, err,
+                    blockIdx.x - ntiles, G);
 }
 
 // The oversized buckets with obad set, listed again in bucket order (one
@@ -940,23 +957,20 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_emit(const uint8_t *tflag, uint32_t n, const uint32_t *trange,
-                              const uint32_t *tpre, uint32_t nb, uint32_t *U, uint32_t ucap,
-                              uint32_t *err, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    bucket_tile_emit_kernel<<<(unsigned)div_up(n, BT_T), 256, 0, s>>>(tflag, trange, tpre, nb, U,
-                                                                      ucap, err);
-    return hipGetLastError();
-}
-
-hipError_t launch_oversize_check(const uint64_t *kx, const uint32_t *vx, uint64_t *ky,
+hipError_t launch_emit_and_check(const uint8_t *tflag, uint32_t n, const uint32_t *trange,
+                                 const uint32_t *tpre, uint32_t nb, uint32_t *U, uint32_t ucap,
+                                 const uint64_t *kx, const uint32_t *vx, uint64_t *ky,
                                  uint32_t *vy, const uint32_t *bstart, const uint32_t *olist,
-                                 const uint32_t *ooff, const uint32_t *res, uint32_t nb,
-                                 uint32_t n, int kshort, uint32_t *obad, uint32_t *olist2,
-                                 uint32_t *ooff2, uint32_t *res2, uint32_t *err, hipStream_t s) {
+                                 const uint32_t *ooff, const uint32_t *res, int kshort,
+                                 uint32_t *obad, uint32_t *olist2, uint32_t *ooff2,
+                                 uint32_t *res2, uint32_t *err, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t ntiles = (uint32_t)div_up(n, BT_T);
     const uint32_t want = (uint32_t)div_up(n, 256);
-    oversize_check_copy_kernel<<<want < 1024 ? (want ? want : 1) : 1024, 256, 0, s>>>(
-        kx, vx, ky, vy, bstart, olist, ooff, res, n, kshort, obad, err);
+    const uint32_t G = want < 1024 ? want : 1024;
+    emit_and_check_kernel<<<ntiles + G, 256, 0, s>>>(tflag, trange, tpre, nb, U, ucap, ntiles, kx,
+                                                     vx, ky, vy, bstart, olist, ooff, res, n,
+                                                     kshort, obad, G, err);
     oversize_compact_kernel<<<1, 1024, 0, s>>>(olist, ooff, obad, res, nb, olist2, ooff2, res2);
     return hipGetLastError();
 }
