@@ -43,11 +43,14 @@ def source_digest(files):
 
 KERNEL_SOURCES = {
     "compute_ranks_kernel": ["paper_1410_0562_amd/csrc/k_ranks.hip",
-                             "paper_1410_0562_amd/csrc/dev_util.hpp"],
+                             "paper_1410_0562_amd/csrc/dev_util.hpp",
+                             "paper_1410_0562_amd/csrc/bwt_internal.hpp"],
     "radix_pass_kernel": ["paper_1410_0562_amd/csrc/k_radix.hip",
-                          "paper_1410_0562_amd/csrc/dev_util.hpp"],
+                          "paper_1410_0562_amd/csrc/dev_util.hpp",
+                          "paper_1410_0562_amd/csrc/bwt_internal.hpp"],
     "insert_kernel": ["paper_1410_0562_amd/csrc/k_insert.hip",
-                      "paper_1410_0562_amd/csrc/dev_util.hpp"],
+                      "paper_1410_0562_amd/csrc/dev_util.hpp",
+                      "paper_1410_0562_amd/csrc/bwt_internal.hpp"],
 }
 
 
