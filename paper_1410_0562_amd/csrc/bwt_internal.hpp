@@ -156,8 +156,8 @@ hipError_t launch_block_keys(const uint8_t *reads, const uint64_t *off, const ui
 // olist, their starts in the gathered array in ooff (ooff[count] = total); res
 // = {tied suffixes, oversized buckets, oversized suffixes}; part holds 3 words
 // per 4096 bucket ids; trange 3 words per 2048 positions; tflag one byte per
-// position (1 = tied).  bucket_emit lists the tied suffixes of the sorted
-// buckets in U (slot order) from tflag.  oversize_gather copies the oversized
+// position (1 = tied).  emit_and_check (below) lists the tied suffixes of the
+// sorted buckets in U (slot order) from tflag.  oversize_gather copies the oversized
 // buckets of kin to ck/cv; once sorted there on the whole key,
 // oversize_scatter puts them into kout / vout and oversize_ties_map appends
 // their tied suffixes (gathered indices U2[0 .. *nU2)) to U after the first
@@ -170,8 +170,8 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
                               uint32_t *tcnt, uint32_t *osz, uint8_t *tflag, uint32_t *part,
                               uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *obad,
                               uint32_t *err, hipStream_t s);
-// emit_and_check: bucket_emit (the tied suffixes of the sorted buckets listed
-// in U, slot order, from tflag) and, side by side in the same launch, the
+// emit_and_check: the tied suffixes of the sorted buckets listed in U (slot
+// order, from tflag) and, side by side in the same launch, the
 // copy of every oversized bucket of (kx, vx) to (ky, vy); then the oversized
 // buckets that still need sorting are listed in olist2 / ooff2 (res2 =
 // {count, suffixes}): the others hold copies of one key that ends at its
