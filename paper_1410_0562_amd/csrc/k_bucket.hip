@@ -967,7 +967,7 @@ hipError_t launch_emit_and_check(const uint8_t *tflag, uint32_t n, const uint32_
     if (n == 0) return hipSuccess;
     const uint32_t ntiles = (uint32_t)div_up(n, BT_T);
     const uint32_t want = (uint32_t)div_up(n, 256);
-    const uint32_t G = want < 1024 ? want : 1024;
+    const uint32_t G = want < 8192 ? want : 8192;
     emit_and_check_kernel<<<ntiles + G, 256, 0, s>>>(tflag, trange, tpre, nb, U, ucap, ntiles, kx,
                                                      vx, ky, vy, bstart, olist, ooff, res, n,
                                                      kshort, obad, G, err);
