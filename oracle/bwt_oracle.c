@@ -23,28 +23,30 @@
  * Functions (all single-threaded unless stated):
  *   oracle_sa            suffix array by comparison sort (definition of SA,
  *                        Section 2)
+ *   oracle_sa_threads    the same comparison sort, run as `threads` sorted
+ *                        runs merged pairwise (same comparator, same result)
  *   oracle_bwt           B[i] = T[(SA[i]-1) mod n]   (Eq. 1)
  *   oracle_count_smaller number of suffixes of T smaller than T^p, by brute
  *                        force against every suffix (rank of one row, O(n))
  *   oracle_lf_invert     walks B backwards from row j with C[c] + rank(c,r),
  *                        the LF step of Lemma 1 applied inside one BWT; spells
  *                        each string reversed.  Used as an invariant check.
- *   oracle_compute_ranks ComputeRanks (Algorithm 2, with the readings: the walk
- *                        starts at i = m_ext, and g is indexed off_j + k with
- *                        off the exclusive prefix sum of |P_j|+1)
  *   oracle_count_old_smaller  brute-force definition of what ComputeRanks
  *                        returns: for a new suffix, the number of old suffixes
  *                        smaller than it (hypothesis of Lemma 1)
+ *
+ * What ComputeRanks returns for a whole block is computed in oracle.py from
+ * its definition (old suffixes smaller than each new one, read off one suffix
+ * array of the old and new text together); nothing here walks LF steps to
+ * produce it.
  */
+#define _GNU_SOURCE
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-/* qsort has no context argument; the oracle is single-threaded, so the text
- * being sorted is held in file-scope state for the duration of one call. */
-static const uint8_t *g_text;
-
-/* Compare suffixes a and b of g_text under the order stated above. */
+/* Compare suffixes a and b of T under the order stated above. */
 static int cmp_suffix_at(const uint8_t *T, uint64_t a, uint64_t b)
 {
     if (a == b) return 0;
@@ -55,19 +57,129 @@ static int cmp_suffix_at(const uint8_t *T, uint64_t a, uint64_t b)
     }
 }
 
-static int qsort_cmp(const void *pa, const void *pb)
+static int qsort_cmp(const void *pa, const void *pb, void *text)
 {
     uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
-    return cmp_suffix_at(g_text, a, b);
+    return cmp_suffix_at((const uint8_t *)text, a, b);
 }
 
 /* Suffix array of T[0..n) (T[n-1] must be 0). */
 void oracle_sa(const uint8_t *T, uint64_t n, uint64_t *sa)
 {
     for (uint64_t i = 0; i < n; ++i) sa[i] = i;
-    g_text = T;
-    qsort(sa, (size_t)n, sizeof(uint64_t), qsort_cmp);
-    g_text = NULL;
+    qsort_r(sa, (size_t)n, sizeof(uint64_t), qsort_cmp, (void *)T);
+}
+
+/* ---- the same sort on several threads ----------------------------------
+ * The positions are cut into `threads` contiguous runs; each run is sorted
+ * by qsort_r with the comparator above, then neighbouring runs are merged
+ * pairwise, round by round, until one run is left.  The suffixes are all
+ * distinct, so the merged order is the one oracle_sa gives. */
+struct sort_job {
+    const uint8_t *T;
+    uint64_t *a;
+    uint64_t n;
+};
+
+static void *sort_run(void *p)
+{
+    struct sort_job *j = (struct sort_job *)p;
+    qsort_r(j->a, (size_t)j->n, sizeof(uint64_t), qsort_cmp, (void *)j->T);
+    return NULL;
+}
+
+struct merge_job {
+    const uint8_t *T;
+    const uint64_t *x, *y;
+    uint64_t nx, ny;
+    uint64_t *out;
+};
+
+static void *merge_runs(void *p)
+{
+    struct merge_job *j = (struct merge_job *)p;
+    uint64_t i = 0, k = 0, o = 0;
+    while (i < j->nx && k < j->ny) {
+        if (cmp_suffix_at(j->T, j->x[i], j->y[k]) < 0) j->out[o++] = j->x[i++];
+        else j->out[o++] = j->y[k++];
+    }
+    while (i < j->nx) j->out[o++] = j->x[i++];
+    while (k < j->ny) j->out[o++] = j->y[k++];
+    return NULL;
+}
+
+/* Returns 0, or -1 when memory or threads could not be had (sa is then
+ * unspecified). */
+int oracle_sa_threads(const uint8_t *T, uint64_t n, uint64_t *sa, int threads)
+{
+    if (threads < 1) threads = 1;
+    if ((uint64_t)threads > n) threads = n ? (int)n : 1;
+    if (threads == 1) {
+        oracle_sa(T, n, sa);
+        return 0;
+    }
+    for (uint64_t i = 0; i < n; ++i) sa[i] = i;
+    uint64_t *bound = (uint64_t *)malloc(sizeof(uint64_t) * (threads + 1));
+    uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
+    struct sort_job *sj = (struct sort_job *)malloc(sizeof(struct sort_job) * threads);
+    struct merge_job *mj = (struct merge_job *)malloc(sizeof(struct merge_job) * threads);
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+    int rc = -1;
+    if (!bound || !tmp || !sj || !mj || !th) goto done;
+    for (int t = 0; t <= threads; ++t) bound[t] = n * (uint64_t)t / (uint64_t)threads;
+    for (int t = 0; t < threads; ++t) {
+        sj[t].T = T;
+        sj[t].a = sa + bound[t];
+        sj[t].n = bound[t + 1] - bound[t];
+        if (pthread_create(&th[t], NULL, sort_run, &sj[t]) != 0) {
+            for (int u = 0; u < t; ++u) pthread_join(th[u], NULL);
+            goto done;
+        }
+    }
+    for (int t = 0; t < threads; ++t) pthread_join(th[t], NULL);
+    {
+        uint64_t *src = sa, *dst = tmp;
+        int runs = threads;
+        while (runs > 1) {
+            int pairs = runs / 2, started = 0, ok = 1;
+            for (int q = 0; q < pairs; ++q) {
+                uint64_t a0 = bound[2 * q], a1 = bound[2 * q + 1], a2 = bound[2 * q + 2];
+                mj[q].T = T;
+                mj[q].x = src + a0;
+                mj[q].nx = a1 - a0;
+                mj[q].y = src + a1;
+                mj[q].ny = a2 - a1;
+                mj[q].out = dst + a0;
+                if (pthread_create(&th[q], NULL, merge_runs, &mj[q]) != 0) {
+                    ok = 0;
+                    break;
+                }
+                ++started;
+            }
+            for (int q = 0; q < started; ++q) pthread_join(th[q], NULL);
+            if (!ok) goto done;
+            if (runs & 1) {  /* the odd last run is carried over as it is */
+                uint64_t a0 = bound[runs - 1], a1 = bound[runs];
+                memcpy(dst + a0, src + a0, (size_t)(a1 - a0) * sizeof(uint64_t));
+            }
+            int nr = 0;
+            for (int q = 0; q < runs; q += 2) bound[nr++] = bound[q];
+            bound[nr] = n;
+            runs = nr;
+            uint64_t *sw = src;
+            src = dst;
+            dst = sw;
+        }
+        if (src != sa) memcpy(sa, src, (size_t)n * sizeof(uint64_t));
+    }
+    rc = 0;
+done:
+    free(bound);
+    free(tmp);
+    free(sj);
+    free(mj);
+    free(th);
+    return rc;
 }
 
 /* Eq. 1: B[i] = T[(SA[i]-1) mod n], written as ASCII with every terminator
@@ -165,51 +277,6 @@ int oracle_lf_invert(const uint8_t *B, uint64_t n, const uint64_t *rows,
             r = C[c] + occ_rank(B, occ, c, r);
         }
         lens[t] = len;
-    }
-    free(occ);
-    return 0;
-}
-
-/*
- * ComputeRanks (Section 4, Lemma 1 and Algorithm 2).
- *
- *   Bext  : the current BWT B_ext, ASCII, n_ext symbols, m_ext of them '$'.
- *   text  : the block's text, codes as described at the top of this file
- *           (terminators 0), laid out P_0 $ P_1 $ ... P_{mb-1} $.
- *   soff  : soff[j] = position of P_j's first symbol in `text` (that is, the
- *           exclusive prefix sum of |P_j|+1), soff[mb] = length of text.
- *   g     : output, one entry per position of `text`: g[soff[j]+k] is the
- *           number of suffixes of B_ext smaller than the suffix P_j^k $_j.
- *
- * For each string the walk starts from its terminator suffix, which is larger
- * than exactly the m_ext old terminator suffixes and smaller than every old
- * suffix that begins with a base, so i = m_ext; then, going left one symbol at
- * a time with c = P_j[k-1], i becomes C[c] + rank(c, i, B_ext) (Lemma 1),
- * where C[c] counts the symbols of B_ext smaller than c (terminators count as
- * smaller than every base).  Returns 0, or -1 on allocation failure.
- */
-int oracle_compute_ranks(const uint8_t *Bext, uint64_t n_ext,
-                         const uint8_t *text, const uint64_t *soff, uint64_t mb,
-                         uint64_t *g)
-{
-    uint64_t *occ = build_occ(Bext, n_ext);
-    if (!occ) return -1;
-    uint64_t cnt[5], C[5];
-    for (int c = 0; c < 5; ++c) cnt[c] = occ_rank(Bext, occ, c, n_ext);
-    C[0] = 0;
-    for (int c = 1; c < 5; ++c) C[c] = C[c - 1] + cnt[c - 1];
-    uint64_t m_ext = cnt[0];
-    for (uint64_t j = 0; j < mb; ++j) {
-        uint64_t off = soff[j];
-        uint64_t k = soff[j + 1] - soff[j] - 1;   /* |P_j| */
-        uint64_t i = m_ext;
-        g[off + k] = i;
-        while (k > 0) {
-            k = k - 1;
-            int c = text[off + k];                  /* 1..4 */
-            i = C[c] + occ_rank(Bext, occ, c, i);
-            g[off + k] = i;
-        }
     }
     free(occ);
     return 0;

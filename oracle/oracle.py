@@ -11,15 +11,18 @@ Everything here follows Pantaleoni, arXiv:1410.0562:
 * rank(c, k, B) counts c in B[0..k) (Eq. 2);
 * set-bwte (Algorithm 1) adds blocks of whole strings to a partial BWT B_ext:
   suffix-sort the block, take the preceding symbol of every sorted suffix
-  (B_int), rank every block suffix among the suffixes of B_ext (ComputeRanks,
-  Lemma 1 / Algorithm 2), reorder the ranks into suffix order (g_sa), and insert
-  B_int[i] into B_ext before old row g_sa[i] (Insert, Section 5).
+  (B_int), rank every block suffix among the old suffixes (ComputeRanks,
+  Section 4), reorder the ranks into suffix order (g_sa), and insert B_int[i]
+  into B_ext before old row g_sa[i] (Insert, Section 5).
+
+The ranks are taken from their definition -- the number of old suffixes smaller
+than each new suffix -- out of one suffix array of the old and new text
+together, not by LF steps; Lemma 1's recurrence is only a cross-check in the
+tests.
 
 Readings taken where the paper is silent or inconsistent (each listed with its
 reason in the design notes of the repository):
 
-* the LF walk of a string starts at i = m_ext (the number of strings already in
-  B_ext), because the new terminator is larger than exactly the old ones;
 * g is indexed by off_j + k where off is the exclusive prefix sum of |P_j|+1;
 * every terminator is printed as '$';
 * strings appended later get larger terminators (arrival order);
@@ -54,7 +57,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC])
+            ["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lpthread"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -72,14 +75,14 @@ def _load():
     u64 = ctypes.c_uint64
     lib.oracle_sa.argtypes = [u8p, u64, u64p]
     lib.oracle_sa.restype = None
+    lib.oracle_sa_threads.argtypes = [u8p, u64, u64p, ctypes.c_int]
+    lib.oracle_sa_threads.restype = ctypes.c_int
     lib.oracle_bwt.argtypes = [u8p, u64, u64p, u8p]
     lib.oracle_bwt.restype = None
     lib.oracle_count_smaller.argtypes = [u8p, u64, u64]
     lib.oracle_count_smaller.restype = u64
     lib.oracle_lf_invert.argtypes = [u8p, u64, u64p, u64, u64p, u8p, u64p]
     lib.oracle_lf_invert.restype = ctypes.c_int
-    lib.oracle_compute_ranks.argtypes = [u8p, u64, u8p, u64p, u64, u64p]
-    lib.oracle_compute_ranks.restype = ctypes.c_int
     lib.oracle_count_old_smaller.argtypes = [u8p, u64, u64]
     lib.oracle_count_old_smaller.restype = u64
     _lib = lib
@@ -152,33 +155,38 @@ def concat_text(codes: np.ndarray, offsets: np.ndarray) -> tuple[np.ndarray, np.
 # The definition: suffix array and BWT of the whole set
 # --------------------------------------------------------------------------
 
-def suffix_array(T: np.ndarray) -> np.ndarray:
-    """SA of T (terminators 0, T[-1] == 0) by comparison sort."""
+def suffix_array(T: np.ndarray, threads: int = 1) -> np.ndarray:
+    """SA of T (terminators 0, T[-1] == 0) by comparison sort; with threads >
+    1, sorted runs merged pairwise (the same order)."""
     T = np.ascontiguousarray(T, dtype=np.uint8)
     n = len(T)
     sa = np.empty(n, dtype=np.uint64)
     if n:
-        _load().oracle_sa(_p8(T), n, _p64(sa))
+        if threads > 1:
+            if _load().oracle_sa_threads(_p8(T), n, _p64(sa), int(threads)) != 0:
+                raise MemoryError("oracle_sa_threads")
+        else:
+            _load().oracle_sa(_p8(T), n, _p64(sa))
     return sa
 
 
-def bwt_from_text(T: np.ndarray, sa: np.ndarray | None = None) -> bytes:
+def bwt_from_text(T: np.ndarray, sa: np.ndarray | None = None, threads: int = 1) -> bytes:
     """Eq. 1 over T, every terminator printed '$'."""
     T = np.ascontiguousarray(T, dtype=np.uint8)
     n = len(T)
     if n == 0:
         return b""
     if sa is None:
-        sa = suffix_array(T)
+        sa = suffix_array(T, threads)
     sa = np.ascontiguousarray(sa, dtype=np.uint64)
     B = np.empty(n, dtype=np.uint8)
     _load().oracle_bwt(_p8(T), n, _p64(sa), _p8(B))
     return B.tobytes()
 
 
-def bwt_of_codes(codes: np.ndarray, offsets: np.ndarray) -> bytes:
+def bwt_of_codes(codes: np.ndarray, offsets: np.ndarray, threads: int = 1) -> bytes:
     T, _ = concat_text(codes, offsets)
-    return bwt_from_text(T)
+    return bwt_from_text(T, threads=threads)
 
 
 def bwt(reads: Sequence[str]) -> bytes:
@@ -267,19 +275,29 @@ def b_int(T_block: np.ndarray, sa_int: np.ndarray) -> bytes:
     return ASCII[prev].tobytes()
 
 
-def compute_ranks(B_ext: bytes, T_block: np.ndarray, soff: np.ndarray) -> np.ndarray:
-    """ComputeRanks (Algorithm 2 with Lemma 1): g[p] for every block position p
-    = number of suffixes of B_ext smaller than the block suffix at p."""
-    Bn = np.frombuffer(B_ext, dtype=np.uint8).copy() if B_ext else np.zeros(1, np.uint8)
-    T = np.ascontiguousarray(T_block, dtype=np.uint8)
-    soff = np.ascontiguousarray(soff, dtype=np.uint64)
-    g = np.zeros(max(1, len(T)), dtype=np.uint64)
-    mb = len(soff) - 1
-    if mb:
-        rc = _load().oracle_compute_ranks(_p8(Bn), len(B_ext), _p8(T), _p64(soff), mb, _p64(g))
-        if rc != 0:
-            raise MemoryError("oracle_compute_ranks")
-    return g[:len(T)]
+def compute_ranks(T_old: np.ndarray, T_block: np.ndarray, threads: int = 1) -> np.ndarray:
+    """What ComputeRanks returns (Section 4, the quantity Lemma 1 computes):
+    g[p] for every block position p = the number of suffixes of the old strings
+    that are smaller than the block suffix at p.
+
+    Taken from its definition: the old text T_old (every string already in the
+    index, terminators 0) and the block text are laid end to end, so the block's
+    terminators come after the old ones (strings added later get larger
+    terminators), and one suffix array of the whole is sorted.  A suffix that
+    starts in the old text ends at its own terminator, so it compares with a
+    block suffix exactly as in the set's text.  g of a block suffix is then the
+    number of old suffixes that precede it in that order."""
+    T_old = np.ascontiguousarray(T_old, dtype=np.uint8)
+    T_block = np.ascontiguousarray(T_block, dtype=np.uint8)
+    n_old = len(T_old)
+    G = np.concatenate([T_old, T_block])
+    sa = suffix_array(G, threads).astype(np.int64)
+    is_old = sa < n_old
+    old_before = np.cumsum(is_old, dtype=np.int64) - is_old
+    g = np.zeros(len(T_block), dtype=np.uint64)
+    new_rows = ~is_old
+    g[sa[new_rows] - n_old] = old_before[new_rows].astype(np.uint64)
+    return g
 
 
 def count_old_smaller(G: np.ndarray, n_old: int, p: int) -> int:
@@ -304,24 +322,30 @@ def insert(B_ext: bytes, B_int: bytes, g_sa: np.ndarray) -> bytes:
     return np.insert(old, idx, new).tobytes()
 
 
-def set_bwte(codes: np.ndarray, offsets: np.ndarray, M: int, B_ext: bytes = b"",
-             trace: list | None = None) -> bytes:
-    """Algorithm 1 over the strings (codes 1..4, offsets), starting from B_ext.
-    When `trace` is a list, each block appends a dict of its intermediates."""
+def set_bwte(codes: np.ndarray, offsets: np.ndarray, M: int,
+             prior: tuple | None = None, trace: list | None = None) -> bytes:
+    """Algorithm 1 over the strings (codes 1..4, offsets).  prior = (B_ext,
+    T_old): the index built so far and the text of the strings in it (for the
+    definition of g); None for an empty index.  When `trace` is a list, each
+    block appends a dict of its intermediates."""
     offsets = np.asarray(offsets, dtype=np.uint64)
     base = int(offsets[0]) if len(offsets) else 0
+    if prior is None:
+        B_ext, T_old = b"", np.zeros(0, dtype=np.uint8)
+    else:
+        B_ext, T_old = prior
     for (j0, j1) in split_blocks(offsets, M):
         bo = offsets[j0:j1 + 1] - offsets[j0]
         bc = codes[int(offsets[j0]) - base:int(offsets[j1]) - base]
         sa_int, T_blk = construct_sa(bc, bo)
         bint = b_int(T_blk, sa_int)
-        _, soff = concat_text(bc, bo)
-        g = compute_ranks(B_ext, T_blk, soff)
+        g = compute_ranks(T_old, T_blk)
         g_sa = reorder(g, sa_int)
         if trace is not None:
             trace.append(dict(block=(j0, j1), sa_int=sa_int, b_int=bint, g=g,
                               g_sa=g_sa, B_ext_before=B_ext))
         B_ext = insert(B_ext, bint, g_sa)
+        T_old = np.concatenate([T_old, T_blk])
     return B_ext
 
 

@@ -154,9 +154,10 @@ def test_compute_ranks_vs_oracle(B, torch_dev, oracle_mod):
     (pa, oa), (pb, ob) = _split(packed, offs, 9_000)
     ca, oa2 = _oracle_inputs(oracle_mod, pa, oa)
     B_ext = oracle_mod.bwt_of_codes(ca, oa2)
+    T_old, _ = oracle_mod.concat_text(ca, oa2)
     cb, ob2 = _oracle_inputs(oracle_mod, pb, ob)
     T, soff = oracle_mod.concat_text(cb, ob2)
-    want = oracle_mod.compute_ranks(B_ext, T, soff)
+    want = oracle_mod.compute_ranks(T_old, T)
     g = torch.empty(len(T), dtype=torch.int64, device="cuda")
     with B.BwtSet() as idx:
         idx.append(pa, oa)
@@ -174,8 +175,8 @@ def test_insert_vs_oracle(B, torch_dev, oracle_mod):
     cb, ob2 = _oracle_inputs(oracle_mod, pb, ob)
     sa_int, T = oracle_mod.construct_sa(cb, ob2)
     bint = oracle_mod.b_int(T, sa_int)
-    _, soff = oracle_mod.concat_text(cb, ob2)
-    g = oracle_mod.compute_ranks(B_ext, T, soff)
+    T_old, _ = oracle_mod.concat_text(ca, oa2)
+    g = oracle_mod.compute_ranks(T_old, T)
     gsa = oracle_mod.reorder(g, sa_int)
     want = oracle_mod.insert(B_ext, bint, gsa)
     codes_all, o_all = _oracle_inputs(oracle_mod, packed, offs)
@@ -437,9 +438,10 @@ def test_segmented_compute_ranks(B, torch_dev, oracle_mod, seg, ov):
     (pa, oa), (pb, ob) = _split(packed, offs, 130)
     ca, oa2 = _oracle_inputs(oracle_mod, pa, oa)
     B_ext = oracle_mod.bwt_of_codes(ca, oa2)
+    T_old, _ = oracle_mod.concat_text(ca, oa2)
     cb, ob2 = _oracle_inputs(oracle_mod, pb, ob)
     T, soff = oracle_mod.concat_text(cb, ob2)
-    want = oracle_mod.compute_ranks(B_ext, T, soff)
+    want = oracle_mod.compute_ranks(T_old, T)
     g = torch.empty(len(T), dtype=torch.int64, device="cuda")
     with B.BwtSet() as idx:
         idx.set_param(B.BWT_PARAM_RANK_SEGMENT, seg)

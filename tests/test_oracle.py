@@ -182,46 +182,65 @@ def test_incremental_step_pin(oracle_mod):
 
 
 def test_compute_ranks_vs_brute_force(oracle_mod):
-    # Lemma 1: the LF walk returns, for every new suffix, the number of old
-    # suffixes smaller than it.  Checked against direct counting two ways.
+    # g from its definition (one joint suffix array) against direct counting,
+    # two independent ways: the C brute-force row count and the pure-Python
+    # rotation sort.
     rng = random.Random(5)
     for _ in range(120):
         old = ["".join(rng.choice("ACG") for _ in range(rng.randint(0, 7))) for _ in range(rng.randint(1, 5))]
         new = ["".join(rng.choice("ACG") for _ in range(rng.randint(0, 7))) for _ in range(rng.randint(1, 4))]
-        B_ext = oracle_mod.bwt(old)
+        T_old, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(old))
         bc, bo = oracle_mod.strings_to_codes(new)
         T_blk, soff = oracle_mod.concat_text(bc, bo)
-        g = [int(x) for x in oracle_mod.compute_ranks(B_ext, T_blk, soff)]
+        g = [int(x) for x in oracle_mod.compute_ranks(T_old, T_blk)]
         assert g == brute.old_smaller(old, new), (old, new)
         G, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(old + new))
         n_old = sum(len(s) + 1 for s in old)
         assert g == [oracle_mod.count_old_smaller(G, n_old, n_old + p) for p in range(len(T_blk))]
 
 
-def _walk_from(O, B_ext, T_blk, soff, start):
-    # Algorithm 2 as printed with a chosen initial i (planted variant)
-    Bn = B_ext
-    cnt = {c: Bn.count(c.encode()) for c in "$ACGT"}  # B_ext is bytes
+def _lemma1_ranks(O, B_ext, T_blk, soff, start):
+    # Lemma 1 used as a recurrence: if X has rank r among the old suffixes,
+    # then cX has rank C[c] + rank(c, r, B_ext).  Every string's terminator
+    # suffix is given the rank `start`, and the recurrence is applied from the
+    # string's end towards its beginning.
+    cnt = {c: B_ext.count(c.encode()) for c in "$ACGT"}
     C, acc = {}, 0
     for c in "$ACGT":
         C[c] = acc
         acc += cnt[c]
     g = [0] * len(T_blk)
     for j in range(len(soff) - 1):
-        off = int(soff[j])
-        k = int(soff[j + 1]) - off - 1
-        i = start
-        g[off + k] = i
-        while k > 0:
-            k -= 1
-            c = "$ACGT"[int(T_blk[off + k])]
-            i = C[c] + O.rank(Bn, c, i)
-            g[off + k] = i
+        a, e = int(soff[j]), int(soff[j + 1]) - 1     # e: the terminator
+        r = start
+        g[e] = r
+        for p in range(e - 1, a - 1, -1):
+            c = "$ACGT"[int(T_blk[p])]
+            r = C[c] + O.rank(B_ext, c, r)
+            g[p] = r
     return g
 
 
+def test_lemma1_matches_definition(oracle_mod):
+    # Cross-check: Lemma 1's recurrence from the terminator rank m_ext gives
+    # the definition of g on random sets (this is what the GPU walks compute).
+    rng = random.Random(55)
+    for _ in range(80):
+        old = _rand_reads(rng, rng.randint(1, 8), 0, 9, "ACGT")
+        new = _rand_reads(rng, rng.randint(1, 6), 0, 9, "ACGT")
+        T_old, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(old))
+        B_ext = oracle_mod.bwt(old)
+        T_blk, soff = oracle_mod.concat_text(*oracle_mod.strings_to_codes(new))
+        want = [int(x) for x in oracle_mod.compute_ranks(T_old, T_blk)]
+        assert _lemma1_ranks(oracle_mod, B_ext, T_blk, soff, len(old)) == want
+
+
+def _rand_reads(rng, m, lo, hi, alpha):
+    return ["".join(rng.choice(alpha) for _ in range(rng.randint(lo, hi))) for _ in range(m)]
+
+
 def test_printed_lf_start_is_wrong_reading(oracle_mod):
-    # The walk printed in Algorithm 2 starts at i = n_ext; with the terminator
+    # Algorithm 2 as printed starts each walk at i = n_ext; with the terminator
     # order of Section 2 the new terminator beats only the m_ext old ones, so
     # the start must be m_ext.  The planted variant fails the brute force.
     old, new = ["AC"], ["A"]
@@ -231,9 +250,10 @@ def test_printed_lf_start_is_wrong_reading(oracle_mod):
     T_blk, soff = oracle_mod.concat_text(bc, bo)
     truth = brute.old_smaller(old, new)
     assert truth == [1, 1]
-    assert _walk_from(oracle_mod, B_ext, T_blk, soff, 1) == truth   # m_ext
-    assert _walk_from(oracle_mod, B_ext, T_blk, soff, 3) != truth   # n_ext
-    assert [int(x) for x in oracle_mod.compute_ranks(B_ext, T_blk, soff)] == truth
+    assert _lemma1_ranks(oracle_mod, B_ext, T_blk, soff, 1) == truth   # m_ext
+    assert _lemma1_ranks(oracle_mod, B_ext, T_blk, soff, 3) != truth   # n_ext
+    T_old, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(old))
+    assert [int(x) for x in oracle_mod.compute_ranks(T_old, T_blk)] == truth
 
 
 def test_set_bwte_blocking_invariance(oracle_mod):
@@ -255,10 +275,12 @@ def test_append_split_invariance(oracle_mod):
         m = rng.randint(2, 12)
         reads = ["".join(rng.choice("ACGT") for _ in range(rng.randint(0, 8))) for _ in range(m)]
         cut = rng.randint(1, m - 1)
-        B = b""
+        prior = None
         for part in (reads[:cut], reads[cut:]):
             c, o = oracle_mod.strings_to_codes(part)
-            B = oracle_mod.set_bwte(c, o, rng.randint(1, 30), B_ext=B)
+            B = oracle_mod.set_bwte(c, o, rng.randint(1, 30), prior=prior)
+            T_part, _ = oracle_mod.concat_text(c, o)
+            prior = (B, T_part if prior is None else np.concatenate([prior[1], T_part]))
         assert B == oracle_mod.bwt(reads)
 
 
@@ -268,6 +290,46 @@ def test_split_blocks_rule(oracle_mod):
     assert oracle_mod.split_blocks(offs, 8) == [(0, 2), (2, 3), (3, 4), (4, 5)]
     assert oracle_mod.split_blocks(offs, 9) == [(0, 3), (3, 4), (4, 5)]
     assert oracle_mod.split_blocks(offs, 100) == [(0, 5)]
+
+
+def test_unpack_literal_bytes(oracle_mod):
+    # The input layout written out by hand: code = index in "ACGT", symbol s
+    # in byte s >> 2 at bits 2(s & 3), lowest bits first.  "ACGT" is
+    # 00 01 10 11 read from bit 0 up, i.e. 0b11100100 = 0xE4; "TTGA" is
+    # 11 11 10 00 from bit 0 up = 0b00101111 = 0x2F.
+    assert list(oracle_mod.unpack_2bit(np.array([0xE4], np.uint8), 4)) == [0, 1, 2, 3]
+    assert list(oracle_mod.unpack_2bit(np.array([0x2F], np.uint8), 4)) == [3, 3, 2, 0]
+    assert list(oracle_mod.unpack_2bit(np.array([0xE4, 0x03], np.uint8), 5)) == [0, 1, 2, 3, 3]
+    codes, offs = oracle_mod.reads_from_packed(np.array([0xE4, 0x2F], np.uint8),
+                                                np.array([0, 4, 8], np.uint64))
+    assert list(codes) == [1, 2, 3, 4, 4, 4, 3, 1]
+    # the BWT of "ACGT" from the literal byte, rotations written out by hand:
+    # $ACGT T | ACGT$ $ | CGT$A A | GT$AC C | T$ACG G  -> T$ACG
+    c1, o1 = oracle_mod.reads_from_packed(np.array([0xE4], np.uint8), np.array([0, 4], np.uint64))
+    assert oracle_mod.bwt_of_codes(c1, o1) == b"T$ACG"
+
+
+def test_pack_literal_bytes():
+    from paper_1410_0562_amd import synth
+    assert list(synth.pack_codes(np.array([0, 1, 2, 3], np.uint8))) == [0xE4]
+    assert list(synth.pack_codes(np.array([3, 3, 2, 0, 3], np.uint8))) == [0x2F, 0x03]
+    p, o = synth.strings_to_input(["ACGT", "TTGA"])
+    assert list(p) == [0xE4, 0x2F] and list(o) == [0, 4, 8]
+
+
+def test_threaded_sort_is_the_same_order(oracle_mod):
+    # Sorted runs merged pairwise give the single-threaded comparison sort,
+    # for run counts that do and do not divide the input evenly.
+    rng = random.Random(21)
+    for trial in range(12):
+        reads = _rand_reads(rng, rng.randint(1, 300), 0, rng.choice([5, 30, 120]),
+                            rng.choice(["ACGT", "AC", "A"]))
+        T, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(reads))
+        want = oracle_mod.suffix_array(T)
+        for th in (2, 3, 5, 8):
+            assert np.array_equal(oracle_mod.suffix_array(T, threads=th), want), (trial, th)
+    T, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(["GATTACA"]))
+    assert [int(x) for x in oracle_mod.suffix_array(T, threads=3)] == [7, 6, 4, 1, 5, 0, 3, 2]
 
 
 def test_unpack_roundtrip(oracle_mod):
