@@ -191,37 +191,247 @@ def take_reads(packed: np.ndarray, offsets: np.ndarray, j0: int, j1: int):
     return pack_codes(codes), (offsets[j0:j1 + 1] - np.uint64(s0)).astype(np.uint64)
 
 
-def served_requests_gpu(tenants: int = 16, count: int = 512, ref_len: int = 100_000_000,
-                        min_reads: int = 10_000, max_reads: int = 1_000_000, length: int = 150,
-                        sub_rate: float = 0.01, seed: int = SEED_BASE + 5):
-    """Workload 5 drawn on the GPU with torch: per-tenant uniform random
-    references, `count` requests to uniformly drawn tenants with
-    log-uniform read counts, reads sampled at uniform positions (forward
-    strand) with i.i.d. substitutions.  Returns (tenant ids, list of
-    (packed device tensor, offsets device int64 tensor, bases))."""
-    import torch
+# ---------------------------------------------------------------------------
+# Counter-based draws for the batched and served workloads.
+#
+# These two workloads are drawn on the GPU (billions of bases), and their
+# full-size expected BWTs are computed offline on the CPU, so every random
+# value must come out the same from numpy on the host and from torch on the
+# device.  Each value is a pure function of (stream key, index): MurmurHash3's
+# 32-bit finalizer (Appleby, "fmix32") applied twice to the index mixed with
+# the key.  Every step is a 64-bit integer operation whose result stays below
+# 2^63 (the 32x32-bit products are split into 16-bit halves), so numpy and
+# torch, on either device, compute exactly the same bits.
+# ---------------------------------------------------------------------------
+_M32 = 0xFFFFFFFF
+_SUB_THRESHOLD = 42_949_673          # round(0.01 * 2^32): a 1% substitution draw
+
+
+def _mul32(x, c: int):
+    """(x * c) mod 2^32 for x in [0, 2^32) held in int64, c a 32-bit constant."""
+    return (x * (c & 0xFFFF) + (((x * (c >> 16)) & 0xFFFF) << 16)) & _M32
+
+
+def fmix32(h):
+    """MurmurHash3's 32-bit finalizer on values in [0, 2^32) (int64 arrays or
+    tensors, or Python ints)."""
+    h = h ^ (h >> 16)
+    h = _mul32(h, 0x85EBCA6B)
+    h = h ^ (h >> 13)
+    h = _mul32(h, 0xC2B2AE35)
+    return h ^ (h >> 16)
+
+
+def stream_key(*parts: int) -> int:
+    """A 32-bit stream key from small non-negative integers (seed, set, purpose)."""
+    k = 0x9E3779B9
+    for p in parts:
+        k = fmix32((k ^ (int(p) & _M32)) & _M32)
+        k = fmix32((k + 0x7F4A7C15) & _M32)
+    return k
+
+
+def counter_u32(key: int, i):
+    """Uniform 32-bit value number i (0 <= i < 2^32) of stream `key`."""
+    k1 = fmix32(key & _M32)
+    k2 = fmix32((key ^ 0x85EBCA77) & _M32)
+    return fmix32(fmix32(i ^ k1) ^ k2)
+
+
+def uniform_below(key: int, i, bound):
+    """floor(u * bound / 2^32) for u = counter_u32(key, i): an integer in
+    [0, bound) for bound < 2^31 (scalar or array)."""
+    return (counter_u32(key, i) * bound) >> 32
+
+
+class _NumpyOps:
+    device = "cpu"
+
+    def arange(self, a, b=None):
+        return np.arange(a, b, dtype=np.int64) if b is not None else np.arange(a, dtype=np.int64)
+
+    def cumsum0(self, x):
+        out = np.zeros(len(x) + 1, dtype=np.int64)
+        out[1:] = np.cumsum(x)
+        return out
+
+    def repeat(self, x, counts):
+        return np.repeat(x, counts)
+
+    def where(self, c, a, b):
+        return np.where(c, a, b)
+
+    def u8(self, x):
+        return x.astype(np.uint8)
+
+    def cat(self, xs):
+        return np.concatenate(xs)
+
+    def scalar(self, x):
+        return int(x)
+
+
+class _TorchOps:
+    def __init__(self, device):
+        import torch
+        self.t = torch
+        self.device = device
+
+    def arange(self, a, b=None):
+        t = self.t
+        if b is None:
+            return t.arange(a, dtype=t.int64, device=self.device)
+        return t.arange(a, b, dtype=t.int64, device=self.device)
+
+    def cumsum0(self, x):
+        t = self.t
+        out = t.zeros(x.numel() + 1, dtype=t.int64, device=self.device)
+        t.cumsum(x, 0, out=out[1:])
+        return out
+
+    def repeat(self, x, counts):
+        return self.t.repeat_interleave(x, counts)
+
+    def where(self, c, a, b):
+        return self.t.where(c, a, b)
+
+    def u8(self, x):
+        return x.to(self.t.uint8)
+
+    def cat(self, xs):
+        return self.t.cat(xs)
+
+    def scalar(self, x):
+        return int(x.item())
+
+
+def _ops(device):
+    return _NumpyOps() if device is None or device == "numpy" else _TorchOps(device)
+
+
+def _reference(ops, key: int, ref_len: int):
+    """A uniform random reference: base i = top two bits of draw i."""
+    out = []
+    step = 1 << 26
+    for a in range(0, ref_len, step):
+        out.append(ops.u8(counter_u32(key, ops.arange(a, min(ref_len, a + step))) >> 30))
+    return ops.cat(out)
+
+
+def _substitute_counter(ops, codes, pos, key_hit: int, key_delta: int):
+    """1% i.i.d. substitutions to one of the other three bases; the draws of
+    base number `pos` (an int64 array the shape of codes)."""
+    hit = counter_u32(key_hit, pos) < _SUB_THRESHOLD
+    delta = 1 + uniform_below(key_delta, pos, 3)
+    return ops.where(hit, (codes + delta) & 3, codes)
+
+
+def batch_set_codes(s: int, m: int, ref_len: int = 10_000_000, min_len: int = 36,
+                    max_len: int = 250, seed: int = SEED_BASE + 4, device=None,
+                    chunk: int = 1 << 18):
+    """Set s of the batched workload with m reads: its own uniform reference of
+    ref_len bases; read r has length uniform in [min_len, max_len], a start
+    uniform over the positions it fits, the minus strand (reverse complement)
+    with probability 1/2, and 1% substitutions.  device None: numpy arrays;
+    otherwise torch tensors on that device.  Returns (codes 0..3 as uint8,
+    offsets int64[m + 1]); the values do not depend on the device or chunk."""
+    ops = _ops(device)
+    ref = _reference(ops, stream_key(seed, s, 0), ref_len)
+    r = ops.arange(m)
+    span = max_len - min_len + 1
+    lens = min_len + uniform_below(stream_key(seed, s, 1), r, span)
+    starts = uniform_below(stream_key(seed, s, 2), r, ref_len - lens + 1)
+    minus = (counter_u32(stream_key(seed, s, 3), r) >> 31) == 1
+    offs = ops.cumsum0(lens)
+    total = ops.scalar(offs[-1])
+    if total >= 1 << 32:
+        raise ValueError("set too large for 32-bit draw indices")
+    parts = []
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        L = lens[r0:r1]
+        rid = ops.repeat(ops.arange(r0, r1), L)
+        pos = ops.arange(ops.scalar(offs[r0]), ops.scalar(offs[r1]))
+        within = pos - offs[rid]
+        fwd = starts[rid] + within
+        rev = starts[rid] + lens[rid] - 1 - within
+        mr = minus[rid]
+        c = ref[ops.where(mr, rev, fwd)]
+        c = ops.where(mr, 3 - c, c)
+        c = _substitute_counter(ops, c, pos, stream_key(seed, s, 4), stream_key(seed, s, 5))
+        parts.append(ops.u8(c))
+    codes = ops.cat(parts) if parts else ops.u8(ops.arange(0))
+    return codes, offs
+
+
+def batch_sizes(count: int = 64, min_reads: int = 1_000, max_reads: int = 2_000_000,
+                seed: int = SEED_BASE + 4):
+    """Reads per set of the batched workload: floor(exp(U(ln min, ln max)))."""
+    rng = np.random.default_rng(seed)
+    return np.floor(np.exp(rng.uniform(np.log(min_reads), np.log(max_reads), count))).astype(np.int64)
+
+
+def served_plan(tenants: int = 16, count: int = 512, min_reads: int = 10_000,
+                max_reads: int = 1_000_000, seed: int = SEED_BASE + 5):
+    """Tenant and read count of every request of the served workload."""
     rng = np.random.default_rng(seed)
     tids = rng.integers(0, tenants, count)
     ms = np.floor(np.exp(rng.uniform(np.log(min_reads), np.log(max_reads), count))).astype(np.int64)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(int(seed))
-    refs = [torch.randint(0, 4, (ref_len,), dtype=torch.uint8, device="cuda", generator=gen)
-            for _ in range(tenants)]
-    ar = torch.arange(length, device="cuda", dtype=torch.int64)
-    shifts = torch.tensor([0, 2, 4, 6], device="cuda", dtype=torch.uint8)
+    return tids, ms
+
+
+def served_reference(t: int, ref_len: int = 100_000_000, seed: int = SEED_BASE + 5, device=None):
+    return _reference(_ops(device), stream_key(seed, 1_000_000 + t, 0), ref_len)
+
+
+def served_request_codes(k: int, ref, m: int, length: int = 150, seed: int = SEED_BASE + 5,
+                         device=None, chunk: int = 1 << 18):
+    """Request k of the served workload against its tenant's reference `ref`:
+    m reads x length bp at uniform forward-strand starts, 1% substitutions.
+    Returns (codes uint8, offsets int64[m + 1]) as numpy (device None) or torch."""
+    ops = _ops(device)
+    ref_len = int(ref.shape[0])
+    r = ops.arange(m)
+    starts = uniform_below(stream_key(seed, k, 2), r, ref_len - length + 1)
+    offs = ops.arange(m + 1) * length
+    if m * length >= 1 << 32:
+        raise ValueError("request too large for 32-bit draw indices")
+    parts = []
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        pos = ops.arange(r0 * length, r1 * length)
+        rid = pos // length
+        c = ref[starts[rid] + (pos - rid * length)]
+        c = _substitute_counter(ops, c, pos, stream_key(seed, k, 4), stream_key(seed, k, 5))
+        parts.append(ops.u8(c))
+    codes = ops.cat(parts) if parts else ops.u8(ops.arange(0))
+    return codes, offs
+
+
+def _pack_torch(codes):
+    import torch
+    shifts = torch.tensor([0, 2, 4, 6], device=codes.device, dtype=torch.uint8)
+    pad = (-codes.numel()) % 4
+    if pad:
+        codes = torch.cat([codes, torch.zeros(pad, dtype=torch.uint8, device=codes.device)])
+    return (codes.view(-1, 4) << shifts).sum(dim=1, dtype=torch.uint8)
+
+
+def served_requests_gpu(tenants: int = 16, count: int = 512, ref_len: int = 100_000_000,
+                        min_reads: int = 10_000, max_reads: int = 1_000_000, length: int = 150,
+                        seed: int = SEED_BASE + 5):
+    """Workload 5 drawn on the GPU: per-tenant uniform random references,
+    `count` requests to uniformly drawn tenants with log-uniform read counts,
+    reads sampled at uniform positions (forward strand) with i.i.d.
+    substitutions (the counter-based draws above, so the host can draw the
+    same requests).  Returns (tenant ids, list of (packed device tensor,
+    offsets device int64 tensor, bases))."""
+    tids, ms = served_plan(tenants, count, min_reads, max_reads, seed)
+    refs = [served_reference(t, ref_len, seed, device="cuda") for t in range(tenants)]
     out = []
-    for t, m in zip(tids, ms):
-        starts = torch.randint(0, ref_len - length + 1, (int(m),), device="cuda", generator=gen)
-        codes = refs[int(t)][starts[:, None] + ar[None, :]].reshape(-1)
-        hit = torch.rand(codes.shape, device="cuda", generator=gen) < sub_rate
-        delta = torch.randint(1, 4, codes.shape, dtype=torch.uint8, device="cuda", generator=gen)
-        codes = torch.where(hit, (codes + delta) & 3, codes)
-        pad = (-codes.numel()) % 4
-        if pad:
-            codes = torch.cat([codes, torch.zeros(pad, dtype=torch.uint8, device="cuda")])
-        packed = (codes.view(-1, 4) << shifts).sum(dim=1, dtype=torch.uint8)
-        offs = torch.arange(int(m) + 1, device="cuda", dtype=torch.int64) * length
-        out.append((packed, offs, int(m) * length))
+    for k, (t, m) in enumerate(zip(tids, ms)):
+        codes, offs = served_request_codes(k, refs[int(t)], int(m), length, seed, device="cuda")
+        out.append((_pack_torch(codes), offs, int(m) * length))
     del refs
     return tids, out
 
@@ -229,46 +439,16 @@ def served_requests_gpu(tenants: int = 16, count: int = 512, ref_len: int = 100_
 def batch_sets_gpu(count: int = 64, ref_len: int = 10_000_000, min_reads: int = 1_000,
                    max_reads: int = 2_000_000, min_len: int = 36, max_len: int = 250,
                    sub_rate: float = 0.01, seed: int = SEED_BASE + 4):
-    """Workload 4 drawn on the GPU with torch: `count` independent sets, each
-    with its own uniform random reference of ref_len bases and
-    floor(exp(U(ln min_reads, ln max_reads))) reads of uniform integer
-    length in [min_len, max_len], sampled at uniform positions on a random
-    strand (reverse complement for the minus strand) with i.i.d.
-    substitutions to one of the other three bases.  Returns a list of
-    (packed device tensor, offsets device int64 tensor, bases)."""
-    import torch
-    rng = np.random.default_rng(seed)
-    ms = np.floor(np.exp(rng.uniform(np.log(min_reads), np.log(max_reads), count))).astype(np.int64)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(int(seed))
-    shifts = torch.tensor([0, 2, 4, 6], device="cuda", dtype=torch.uint8)
+    """Workload 4 drawn on the GPU: `count` independent sets, each with its own
+    uniform random reference of ref_len bases and floor(exp(U(ln min_reads,
+    ln max_reads))) reads (batch_set_codes, the same values the host draws).
+    Returns a list of (packed device tensor, offsets device int64 tensor, bases)."""
+    if sub_rate != 0.01:
+        raise ValueError("the counter-based draws use a 1% substitution rate")
+    ms = batch_sizes(count, min_reads, max_reads, seed)
     out = []
-    for m in ms:
-        m = int(m)
-        ref = torch.randint(0, 4, (ref_len,), dtype=torch.uint8, device="cuda", generator=gen)
-        lens = torch.randint(min_len, max_len + 1, (m,), device="cuda", generator=gen)
-        offs = torch.zeros(m + 1, dtype=torch.int64, device="cuda")
-        torch.cumsum(lens, 0, out=offs[1:])
-        total = int(offs[-1].item())
-        starts = (torch.rand(m, device="cuda", generator=gen, dtype=torch.float64) *
-                  (ref_len - lens + 1).to(torch.float64)).to(torch.int64)
-        minus = torch.rand(m, device="cuda", generator=gen) < 0.5
-        rid = torch.repeat_interleave(torch.arange(m, device="cuda"), lens)
-        within = torch.arange(total, device="cuda", dtype=torch.int64) - offs[:-1][rid]
-        fwd = starts[rid] + within
-        rev = starts[rid] + lens[rid] - 1 - within
-        mr = minus[rid]
-        codes = ref[torch.where(mr, rev, fwd)]
-        codes = torch.where(mr, 3 - codes, codes)
-        del rid, within, fwd, rev, mr
-        hit = torch.rand(total, device="cuda", generator=gen) < sub_rate
-        delta = torch.randint(1, 4, (total,), dtype=torch.uint8, device="cuda", generator=gen)
-        codes = torch.where(hit, (codes + delta) & 3, codes)
-        del hit, delta
-        pad = (-total) % 4
-        if pad:
-            codes = torch.cat([codes, torch.zeros(pad, dtype=torch.uint8, device="cuda")])
-        packed = (codes.view(-1, 4) << shifts).sum(dim=1, dtype=torch.uint8)
-        out.append((packed, offs, total))
-        del ref, codes
+    for s, m in enumerate(ms):
+        codes, offs = batch_set_codes(s, int(m), ref_len, min_len, max_len, seed, device="cuda")
+        out.append((_pack_torch(codes), offs, int(offs[-1].item())))
+        del codes
     return out
