@@ -1,18 +1,25 @@
 """Benchmark: incremental BWT construction (set-bwte, Algorithm 1) on one GPU.
 
-One step = build the index of the whole short-read workload from empty:
-4,000,000 reads x 100 bp sampled from a random 50 Mbp reference (both strands,
-1% substitutions), appended in blocks of M = 2^26 suffixes (7 blocks), i.e.
-every stage of the hot path -- suffix sort, ComputeRanks, g_sa gather, Insert
-with the occurrence-counter rebuild -- over 400 Mbp.  Inputs are resident in
-HBM before the timed region.  Prints one JSON line.
+One step = build the index of a whole workload from empty, every stage of the
+hot path -- suffix sort, ComputeRanks, g_sa, Insert with the occurrence-counter
+rebuild -- over all of its blocks.  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+The headline is the largest plain workload that fits one GPU: 250,000 long
+reads, lognormal lengths (mean 5 kbp, clipped to 1-50 kbp) from a random 100
+Mbp reference with 10% noise, about 1.25 Gbp in blocks of M = 2^27 suffixes.
+The short-read workload (4,000,000 x 100 bp from a random 50 Mbp reference,
+both strands, 1% substitutions, M = 2^26) is measured after it and reported
+under "also".
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload long|short|uniform]
+    python bench.py --batched | --served
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -22,11 +29,30 @@ if ROOT not in sys.path:
 
 METRIC = "input bases indexed/sec (incremental BWT) + HBM GB/s fraction; p99 append latency"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-RANKS_BYTES_PER_STEP = 64 + 8 + 4 + 0.25   # one index record, key and value writes, one 2-bit symbol
+# Algorithmic bytes: what the method must move, over-fetch excluded.
+RANKS_BYTES_PER_STEP = 64 + 4 + 0.25   # one 64-byte rank record, a 4-byte rank, one 2-bit base
 RADIX_BYTES_PER_KEY = 24               # read and write a 64-bit key and a 32-bit value
-INSERT_BYTES_PER_RECORD = 64           # each index record read (old) or written (new)
-INSERT_BYTES_PER_NEW = 9               # one B_int byte and one 64-bit g_sa per new symbol
+TILE_SORT_BYTES_PER_KEY = 25           # the same, plus one tie-flag byte written
+# Insert per launch: n_ext/4 read + n_out/4 written (2-bit symbols) + n_out/8
+# (occurrence counters at one bit per symbol) + 5 per new symbol (4-byte g_sa,
+# one B_int byte) + 8 per new terminator (its position)
+SEG_LEN = 1024                          # library default: reads longer than this are
+                                        # walked in segments (rank_segments_kernel)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "full_size_sha256.json")
+CPU_THREADS_MAX = 16                    # the host share of one GPU on the box
+
+WORKLOADS = {
+    # name: (key in the traffic and golden files, default block, description)
+    "long": ("long_reads_250k", 1 << 27,
+             "long reads: %d reads, lognormal lengths (mean 5 kbp, 1-50 kbp) from a random "
+             "100 Mbp reference, both strands, 10%% noise; block M=%d suffixes"),
+    "short": ("short_reads_4M", 1 << 26,
+              "short reads: %d x 100 bp from a random 50 Mbp reference, both strands, 1%% "
+              "substitutions; block M=%d suffixes"),
+    "uniform": ("uniform_10k", 1 << 18,
+                "uniform reads: %d x 100 bp i.i.d.; block M=%d suffixes"),
+}
 
 
 def log(msg):
@@ -41,45 +67,108 @@ def source_digest(files):
     return h.hexdigest()[:16]
 
 
+_COMMON = ["paper_1410_0562_amd/csrc/dev_util.hpp", "paper_1410_0562_amd/csrc/bwt_internal.hpp"]
 KERNEL_SOURCES = {
-    "compute_ranks_kernel": ["paper_1410_0562_amd/csrc/k_ranks.hip",
-                             "paper_1410_0562_amd/csrc/dev_util.hpp",
-                             "paper_1410_0562_amd/csrc/bwt_internal.hpp"],
-    "radix_pass_kernel": ["paper_1410_0562_amd/csrc/k_radix.hip",
-                          "paper_1410_0562_amd/csrc/dev_util.hpp",
-                          "paper_1410_0562_amd/csrc/bwt_internal.hpp"],
-    "insert_kernel": ["paper_1410_0562_amd/csrc/k_insert.hip",
-                      "paper_1410_0562_amd/csrc/dev_util.hpp",
-                      "paper_1410_0562_amd/csrc/bwt_internal.hpp"],
+    "compute_ranks_kernel": ["paper_1410_0562_amd/csrc/k_ranks.hip"] + _COMMON,
+    "rank_segments_kernel": ["paper_1410_0562_amd/csrc/k_ranks.hip"] + _COMMON,
+    "radix_pass_kernel": ["paper_1410_0562_amd/csrc/k_radix.hip"] + _COMMON,
+    "insert_kernel": ["paper_1410_0562_amd/csrc/k_insert.hip"] + _COMMON,
+    "bucket_tile_sort_kernel": ["paper_1410_0562_amd/csrc/k_bucket.hip"] + _COMMON,
 }
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when there is none or the kernel source changed since."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when there is none or the kernel source
+    changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    e = t.get(kernel)
+    e = t.get(workload, {}).get(kernel)
     if not e or e.get("source_digest") != source_digest(KERNEL_SOURCES[kernel]):
         return None
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(packed, offs, nreads):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(packed, offs, sample_bases, golden_key):
+    """The oracle (a comparison sort of all suffixes, Section 2's order, then
+    Eq. 1) on the host cores, on the first reads of the workload holding about
+    sample_bases bases."""
+    import numpy as np
     from oracle import oracle
     from paper_1410_0562_amd import synth
+    offs = np.asarray(offs, dtype=np.uint64)
+    nreads = int(np.searchsorted(offs, np.uint64(int(offs[0]) + sample_bases), side="right")) - 1
+    nreads = max(1, min(len(offs) - 1, nreads))
     p, o = synth.take_reads(packed, offs, 0, nreads)
     codes, oo = oracle.reads_from_packed(p, o)
+    T, _ = oracle.concat_text(codes, oo)
+    del codes
     bases = int(oo[-1])
+    threads = max(1, min(CPU_THREADS_MAX, os.cpu_count() or 1))
     t0 = time.perf_counter()
-    oracle.bwt_of_codes(codes, oo)
+    oracle.bwt_from_text(T, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": bases / dt, "unit": "bases/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d reads (%d bases) of the same workload; single-threaded "
-                      "comparison sort of all suffixes (%.1f s)" % (nreads, bases, dt)}
+    out = {"value": bases / dt, "unit": "bases/s", "cores": threads, "kind": "oracle",
+           "sample": "first %d reads (%d bases) of the same workload; comparison sort of all "
+                     "suffixes as %d sorted runs merged pairwise (%.1f s)"
+                     % (nreads, bases, threads, dt),
+           "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+    try:
+        with open(GOLDEN_FILE) as f:
+            g = json.load(f)
+        e = g.get(golden_key)
+        if e:
+            host = g.get("host", {})
+            out["full_size"] = {"oracle_s": e["oracle_s"], "bases": e["bases"],
+                                "bases_per_s": e["bases"] / e["oracle_s"],
+                                "threads": host.get("threads"), "cpu_model": host.get("cpu_model"),
+                                "note": "the whole workload, timed when its parity digest was "
+                                        "written (tests/golden/make_full_size.py)"}
+    except (OSError, ValueError, KeyError):
+        pass
+    return out
+
+
+def block_cuts(lens, M):
+    """Blocks of whole reads, cut greedily before the read that would take a
+    block past M suffixes (a read longer than M is a block by itself): the
+    library's rule, repeated here to attribute the LF steps to kernels."""
+    import numpy as np
+    cs = np.zeros(len(lens) + 1, dtype=np.int64)
+    cs[1:] = np.cumsum(lens + 1)
+    cuts = [0]
+    j = 0
+    while j < len(lens):
+        k = int(np.searchsorted(cs, cs[j] + M, side="right")) - 1
+        k = max(k, j + 1)
+        cuts.append(k)
+        j = k
+    return cuts
+
+
+def ranks_split(offs, M):
+    """LF steps per step of the build, as (one-lane-per-read walks, segment
+    walks): every base of every block but the first (which has no index to
+    rank against), split by read length."""
+    import numpy as np
+    lens = np.diff(np.asarray(offs, dtype=np.int64))
+    cuts = block_cuts(lens, M)
+    ranked = lens[cuts[1]:] if len(cuts) > 2 else lens[:0]
+    return int(ranked[ranked <= SEG_LEN].sum()), int(ranked[ranked > SEG_LEN].sum())
 
 
 def run_batched(args, torch, bwtset, synth):
@@ -248,16 +337,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["short", "long", "uniform"], default="short",
-                    help="short: 4M x 100 bp (default, the headline); long: 250k lognormal "
-                         "reads, mean 5 kbp, M = 2^27; uniform: 10k x 100 bp, M = 2^18")
+    ap.add_argument("--workload", choices=["short", "long", "uniform"], default="long",
+                    help="long: 250k lognormal reads, mean 5 kbp, M = 2^27 (default, the "
+                         "headline); short: 4M x 100 bp, M = 2^26; uniform: 10k x 100 bp, "
+                         "M = 2^18")
+    ap.add_argument("--no-also", action="store_true",
+                    help="with the long workload: skip the short-read measurement after it")
     ap.add_argument("--reads", type=int, default=None)
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--key-bits", type=int, default=None,
                     help="width of the first suffix-sort key (library default if omitted)")
     ap.add_argument("--radix-tile", type=int, default=None,
                     help="radix pass tile shape (library default if omitted)")
-    ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
+    ap.add_argument("--cpu-sample-bases", type=int, default=None,
+                    help="bases of the oracle's sample (default: a quarter of the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
@@ -279,8 +372,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the per-block path on a single "
-              "MI355X (sharding across GPUs is described in DESIGN.md, not built)",
+        print("bench.py measures one GPU only: the per-block path runs on a single MI355X "
+              "(how it would shard across GPUs is described in the design notes, not built)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -311,22 +404,30 @@ def main():
     if args.batched:
         return run_batched(args, torch, bwtset, synth)
 
-    log("generating workload")
-    if args.workload == "short":
-        packed, offs = synth.short_reads(m=args.reads or 4_000_000)
-        block = args.block or (1 << 26)
-        wdesc = ("short reads: %d x 100 bp from a random 50 Mbp reference, both strands, 1%% "
-                 "substitutions; block M=%d suffixes")
-    elif args.workload == "long":
-        packed, offs = synth.long_reads(m=args.reads or 250_000, threads=16)
-        block = args.block or (1 << 27)
-        wdesc = ("long reads: %d reads, lognormal lengths (mean 5 kbp, 1-50 kbp) from a random "
-                 "100 Mbp reference, both strands, 10%% noise; block M=%d suffixes")
+    res = run_plain(args, torch, bwtset, synth, args.workload, args.steps, args.warmup,
+                    cpu=not args.no_cpu_baseline)
+    if not args.no_also and args.workload == "long":
+        log("also: the short-read workload")
+        extra = run_plain(args, torch, bwtset, synth, "short", args.steps, args.warmup, cpu=False)
+        res["also"] = {"short_reads_4M": {k: extra[k] for k in (
+            "value", "unit", "ms_per_step", "config", "roofline", "kernels", "stages_ms_per_step")}}
+    print(json.dumps(res), flush=True)
+
+
+def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
+    """Whole builds of one plain workload; returns the JSON object."""
+    import numpy as np
+    key, default_block, wdesc = WORKLOADS[workload]
+    own = workload == args.workload          # --block / --reads apply to the headline only
+    block = (args.block if own else None) or default_block
+    nreads = args.reads if own else None
+    log("generating the %s workload" % workload)
+    if workload == "short":
+        packed, offs = synth.short_reads(m=nreads or 4_000_000)
+    elif workload == "long":
+        packed, offs = synth.long_reads(m=nreads or 250_000, threads=CPU_THREADS_MAX)
     else:
-        packed, offs = synth.uniform_reads(m=args.reads or 10_000)
-        block = args.block or (1 << 18)
-        wdesc = "uniform reads: %d x 100 bp i.i.d.; block M=%d suffixes"
-    args.block = block
+        packed, offs = synth.uniform_reads(m=nreads or 10_000)
     bases = int(offs[-1]) - int(offs[0])
     m = len(offs) - 1
     dev_reads = torch.from_numpy(packed).cuda()
@@ -334,12 +435,12 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    idx = bwtset.BwtSet(block_size=args.block)
+    idx = bwtset.BwtSet(block_size=block)
     if args.key_bits is not None:
         idx.set_key_bits(args.key_bits)
     if args.radix_tile is not None:
         idx.set_param(bwtset.BWT_PARAM_RADIX_TILE, args.radix_tile)
-    for w in range(args.warmup):
+    for w in range(warmup):
         idx.reset()
         idx.append(dev_reads, dev_offs, stream)
         log("warmup %d done" % w)
@@ -347,7 +448,7 @@ def main():
     idx.enable_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         idx.reset()
         idx.append(dev_reads, dev_offs, stream)
     torch.cuda.synchronize()
@@ -356,70 +457,83 @@ def main():
     n, mm = idx.size()
     assert n == bases + m and mm == m
     dt = t1 - t0
-    log("timed %d steps in %.3f s" % (args.steps, dt))
+    log("timed %d steps in %.3f s" % (steps, dt))
 
+    main_steps, seg_steps = ranks_split(offs, block)
     kernels = {}
     if st["ranks_launches"]:
         kernels["compute_ranks_kernel"] = (st["ranks_kernel_ms"], st["ranks_launches"],
-                                           st["ranks_steps"] * RANKS_BYTES_PER_STEP)
+                                           main_steps * steps * RANKS_BYTES_PER_STEP)
+    if st["ranks_seg_launches"] and seg_steps:
+        kernels["rank_segments_kernel"] = (st["ranks_seg_ms"], st["ranks_seg_launches"],
+                                           seg_steps * steps * RANKS_BYTES_PER_STEP)
     if st["sort_pass_launches"]:
         kernels["radix_pass_kernel"] = (st["sort_pass_ms"], st["sort_pass_launches"],
                                         st["sort_pass_keys"] * RADIX_BYTES_PER_KEY)
+    if st["tile_sort_launches"]:
+        kernels["bucket_tile_sort_kernel"] = (st["tile_sort_ms"], st["tile_sort_launches"],
+                                              st["tile_sort_keys"] * TILE_SORT_BYTES_PER_KEY)
     if st["insert_launches"]:
+        n_old, n_new = st["insert_old_symbols"], st["insert_new_symbols"]
         kernels["insert_kernel"] = (
             st["insert_kernel_ms"], st["insert_launches"],
-            (st["insert_records_in"] + st["insert_records_out"]) * INSERT_BYTES_PER_RECORD +
-            st["insert_new_symbols"] * INSERT_BYTES_PER_NEW)
+            n_old / 4 + (n_old + n_new) / 4 + (n_old + n_new) / 8 + 5 * n_new +
+            8 * st["insert_terminators"])
     kinfo = {}
     for name, (ms, launches, nbytes) in kernels.items():
         gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        kinfo[name] = {"ms_per_step": ms / args.steps, "launches_per_step": launches / args.steps,
+        kinfo[name] = {"ms_per_step": ms / steps, "launches_per_step": launches / steps,
                        "avg_launch_ms": ms / launches, "bytes_per_launch": nbytes / launches,
                        "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
     dom = max(kinfo, key=lambda k: kinfo[k]["ms_per_step"])
     d = kinfo[dom]
-    traffic = measured_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["achieved_GBs"], 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["frac"], 4),
-                "traffic": traffic}
-
+                "traffic": measured_traffic(key, dom)}
     out = {
         "metric": METRIC,
-        "value": bases * args.steps / dt,
+        "value": bases * steps / dt,
         "unit": "bases/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": dt / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": wdesc % (m, args.block),
-                   "reads": m, "bases": bases, "block_suffixes": args.block,
-                   "blocks": st["blocks"] // args.steps, "key_bits": args.key_bits,
+        "config": {"workload": wdesc % (m, block),
+                   "reads": m, "bases": bases, "block_suffixes": block,
+                   "blocks": st["blocks"] // steps, "key_bits": args.key_bits,
                    "radix_tile": args.radix_tile},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
-        "stages_ms_per_step": {s: round(st["ms"][s] / args.steps, 3) for s in bwtset.STAGES},
+        "stages_ms_per_step": {s: round(st["ms"][s] / steps, 3) for s in bwtset.STAGES},
         "sort_detail_ms_per_step": {
-            "keys": round(st["keys_ms"] / args.steps, 3),
-            "radix_passes": round(st["sort_pass_ms"] / args.steps, 3),
-            "tie_detection": round(st["heads_ms"] / args.steps, 3),
-            "bucket_finish": round(st["bucket_ms"] / args.steps, 3),
-            "refine": round(st["refine_ms"] / args.steps, 3)},
-        "tied_fraction": st["tied_suffixes"] / float(args.steps * (bases + m)),
-        "fallback_blocks_per_step": st["fallback_blocks"] / args.steps,
-        "doubling_rounds_per_step": st["doubling_rounds"] / args.steps,
+            "keys": round(st["keys_ms"] / steps, 3),
+            "radix_passes": round(st["sort_pass_ms"] / steps, 3),
+            "tie_detection": round(st["heads_ms"] / steps, 3),
+            "bucket_finish": round(st["bucket_ms"] / steps, 3),
+            "refine": round(st["refine_ms"] / steps, 3)},
+        "ranks_detail_ms_per_step": {
+            "read_walks": round(st["ranks_kernel_ms"] / steps, 3),
+            "segment_walks": round(st["ranks_seg_ms"] / steps, 3),
+            "fallback_and_counts": round(st["ranks_fb_ms"] / steps, 3)},
+        "tied_fraction": st["tied_suffixes"] / float(steps * (bases + m)),
+        "fallback_blocks_per_step": st["fallback_blocks"] / steps,
+        "doubling_rounds_per_step": st["doubling_rounds"] / steps,
     }
     idx.close()
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(packed, offs, min(args.cpu_sample_reads, m))
+    del dev_reads, dev_offs
+    torch.cuda.empty_cache()
+    if cpu:
+        sample = args.cpu_sample_bases or max(1, bases // 4)
+        log("timing the CPU oracle on a sample of %d bases" % sample)
+        out["cpu_baseline"] = cpu_baseline(packed, offs, sample, key)
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

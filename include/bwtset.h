@@ -211,7 +211,7 @@ enum {
 typedef struct {
     double ms[BWT_NSTAGES];         /* summed GPU time per stage (HIP events) */
     uint64_t launches[BWT_NSTAGES]; /* timed intervals per stage */
-    double ranks_kernel_ms;         /* ComputeRanks kernel alone */
+    double ranks_kernel_ms;         /* ComputeRanks: the one-lane-per-read walks alone */
     uint64_t ranks_launches;
     uint64_t ranks_steps;           /* LF steps performed (symbols walked) */
     double insert_kernel_ms;        /* Insert merge kernel alone */
@@ -230,6 +230,15 @@ typedef struct {
     uint64_t tied_suffixes;         /* suffixes left tied by the first sort */
     uint64_t fallback_blocks;       /* blocks sorted by prefix doubling */
     double bucket_ms;               /* LDS bucket finish of the first sort */
+    double ranks_seg_ms;            /* ComputeRanks: segment walks of long reads alone */
+    uint64_t ranks_seg_launches;
+    double ranks_fb_ms;             /* ComputeRanks: whole-read fallback walks and long-read
+                                       key counts */
+    double tile_sort_ms;            /* bucket finish: the per-tile sort kernel alone */
+    uint64_t tile_sort_launches;
+    uint64_t tile_sort_keys;        /* suffixes passed through it */
+    uint64_t insert_old_symbols;    /* sum over Insert launches of the index size before it */
+    uint64_t insert_terminators;    /* terminators merged in */
 } bwt_stats_t;
 
 /* Turns per-stage HIP-event timing on (1) or off (0).  Timing adds event

@@ -51,6 +51,14 @@ class Stats(ctypes.Structure):
         ("tied_suffixes", ctypes.c_uint64),
         ("fallback_blocks", ctypes.c_uint64),
         ("bucket_ms", ctypes.c_double),
+        ("ranks_seg_ms", ctypes.c_double),
+        ("ranks_seg_launches", ctypes.c_uint64),
+        ("ranks_fb_ms", ctypes.c_double),
+        ("tile_sort_ms", ctypes.c_double),
+        ("tile_sort_launches", ctypes.c_uint64),
+        ("tile_sort_keys", ctypes.c_uint64),
+        ("insert_old_symbols", ctypes.c_uint64),
+        ("insert_terminators", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

@@ -107,6 +107,20 @@ __host__ __device__ inline int bits_for_value(uint64_t v) {  // bits to hold 0..
 
 __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
+// Optional per-kernel timing.  A launcher that takes Marks records a[k] just
+// before and b[k] just after the kernel(s) of its span k (documented at the
+// launcher), on the stream it launches on; null events are skipped.
+struct Marks {
+    hipEvent_t a[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t b[3] = {nullptr, nullptr, nullptr};
+    static void begin(const Marks *m, int k, hipStream_t s) {
+        if (m && m->a[k]) (void)hipEventRecord(m->a[k], s);
+    }
+    static void end(const Marks *m, int k, hipStream_t s) {
+        if (m && m->b[k]) (void)hipEventRecord(m->b[k], s);
+    }
+};
+
 // ----------------------------------------------------------------- launchers
 // Every launcher enqueues on `s` and returns hipGetLastError().  `err` is a
 // device word into which kernels OR a bit when an internal consistency check
@@ -169,7 +183,8 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
                               uint32_t nb, int bshift, int kshort, uint32_t limit, uint32_t *large,
                               uint32_t *tcnt, uint32_t *osz, uint8_t *tflag, uint32_t *part,
                               uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *obad,
-                              uint32_t *err, hipStream_t s);
+                              uint32_t *err, hipStream_t s, const Marks *mk = nullptr);
+// (marks: span 0 = the per-tile sort kernel)
 // emit_and_check: the tied suffixes of the sorted buckets listed in U (slot
 // order, from tflag) and, side by side in the same launch, the
 // copy of every oversized bucket of (kx, vx) to (ky, vy); then the oversized
@@ -244,11 +259,14 @@ struct RankKeys {
     uint32_t *hist;  // if set: counts of the key digit at bit hshift, added to
     int hshift;      // the HIST_COPIES copies (zeroed by the caller)
 };
+// Marks: span 0 = the one-lane-per-read walks, 1 = the long-read segment
+// walks, 2 = the whole-read fallback walks and the key counts of long reads
+// (spans 1 and 2 are empty when no read is cut into segments).
 hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                                 uint32_t m_blk, uint32_t n_blk, const Rec *recs,
                                 const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
                                 const RankKeys *kk, const RankSegments &sg, uint32_t *err,
-                                hipStream_t s);
+                                hipStream_t s, const Marks *mk = nullptr);
 
 // ---------------------------------------------------------------------------
 // Batched form: one block holds reads of several independent sets (units).
@@ -273,7 +291,7 @@ hipError_t launch_compute_ranks_units(const uint8_t *reads, const uint64_t *off,
                                       const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
                                       const RankUnit *units, uint32_t nunits, uint64_t *g,
                                       const RankKeys *kk, const RankSegments &sg, uint32_t *err,
-                                      hipStream_t s);
+                                      hipStream_t s, const Marks *mk = nullptr);
 
 struct InsertUnit {
     const Rec *orecs;

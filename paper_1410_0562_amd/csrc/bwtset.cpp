@@ -116,7 +116,10 @@ enum {
     SPAN_KEYS = 103,
     SPAN_HEADS = 104,
     SPAN_REFINE = 105,
-    SPAN_BUCKET = 106
+    SPAN_BUCKET = 106,
+    SPAN_RANKS_SEG = 107,
+    SPAN_RANKS_FB = 108,
+    SPAN_TILE_SORT = 109
 };
 
 }  // namespace
@@ -231,6 +234,35 @@ struct Scope {
     }
 };
 
+// Events for the spans of a launcher that takes Marks (timing on only);
+// add() turns the recorded pairs into spans once the launcher has returned.
+struct MarkSet {
+    bwt_set *h;
+    Marks m;
+    explicit MarkSet(bwt_set *h_, int spans) : h(h_) {
+        if (!h->timer.on) return;
+        for (int k = 0; k < spans; ++k) {
+            m.a[k] = h->timer.get();
+            m.b[k] = m.a[k] ? h->timer.get() : nullptr;
+            if (m.a[k] && !m.b[k]) {
+                h->timer.pool.push_back(m.a[k]);
+                m.a[k] = nullptr;
+            }
+        }
+    }
+    const Marks *get() const { return h->timer.on ? &m : nullptr; }
+    void add(int k, int stage, uint64_t units) {
+        if (m.a[k] && m.b[k]) h->timer.open.push_back({stage, m.a[k], m.b[k], units});
+        m.a[k] = m.b[k] = nullptr;
+    }
+    ~MarkSet() {  // events of spans never added go back to the pool
+        for (int k = 0; k < 3; ++k) {
+            if (m.a[k]) h->timer.pool.push_back(m.a[k]);
+            if (m.b[k]) h->timer.pool.push_back(m.b[k]);
+        }
+    }
+};
+
 // Called after the stream has been synchronized.
 void timer_collect(bwt_set *h) {
     Timer &T = h->timer;
@@ -262,6 +294,15 @@ void timer_collect(bwt_set *h) {
             T.acc.refine_ms += ms;
         } else if (sp.stage == SPAN_BUCKET) {
             T.acc.bucket_ms += ms;
+        } else if (sp.stage == SPAN_RANKS_SEG) {
+            T.acc.ranks_seg_ms += ms;
+            T.acc.ranks_seg_launches += 1;
+        } else if (sp.stage == SPAN_RANKS_FB) {
+            T.acc.ranks_fb_ms += ms;
+        } else if (sp.stage == SPAN_TILE_SORT) {
+            T.acc.tile_sort_ms += ms;
+            T.acc.tile_sort_launches += 1;
+            T.acc.tile_sort_keys += sp.units;
         }
         T.pool.push_back(sp.a);
         T.pool.push_back(sp.b);
@@ -510,9 +551,11 @@ int bucket_finish(bwt_set *h, hipStream_t s, uint64_t *&ks, uint32_t *&vs, uint3
     HIPCHK(h, launch_zero_u32(w.misc + MISC_NU, 2, s));  // tied count, large flag
     {
         Scope sk(h, s, SPAN_BUCKET);
+        MarkSet mk(h, 1);
         HIPCHK(h, launch_bucket_sort(kx, vx, ky, vy, n, bstart, trange, nb, bshift, kfirst,
                                      REFINE_LIMIT, w.misc + MISC_LARGE, tcnt, osz, w.tflag, part,
-                                     res, olist, ooff, obad, err, s));
+                                     res, olist, ooff, obad, err, s, mk.get()));
+        mk.add(0, SPAN_TILE_SORT, n);
         // The tied suffixes go to U; beside that, every oversized bucket is
         // copied to the sorted pair, and those that hold copies of one
         // settled key (the short suffixes of the later blocks: every read's
@@ -737,9 +780,11 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
 
 // ---- Insert ------------------------------------------------------------------
 // Merges the n_new sorted block symbols (gkeys/gbits give g_sa, vals the
-// symbol codes) into src, writing dst.
+// symbol codes; m_new of them terminators, when known, for the statistics)
+// into src, writing dst.
 int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, uint64_t n_ext,
-                 const uint64_t *gkeys, int gshift, const uint32_t *vals, uint64_t n_new) {
+                 const uint64_t *gkeys, int gshift, const uint32_t *vals, uint64_t n_new,
+                 uint64_t m_new) {
     Workspace &w = h->ws;
     const uint64_t n_out = n_ext + n_new;
     const uint64_t ntiles = div_up(records_for(n_out), INS_TILE_RECS);
@@ -760,6 +805,8 @@ int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, 
         h->timer.acc.insert_records_out += records_for(n_out);
         h->timer.acc.insert_records_in += records_for(n_ext);
         h->timer.acc.insert_new_symbols += n_new;
+        h->timer.acc.insert_old_symbols += n_ext;
+        h->timer.acc.insert_terminators += m_new;
     }
     return BWT_OK;
 }
@@ -924,11 +971,15 @@ int run_block(bwt_set *L, hipStream_t s, const DevBlock &B, const std::vector<Ho
     const int gbits = bits_for_value(B.gtotal - 1);
     if (gbits > 0) {
         Scope sc(L, s, BWT_STAGE_RANKS);
-        Scope sk(L, s, SPAN_RANKS_K, n_blk - m_blk);
         const RankKeys kk = rank_keys(L, s, gbits, n_blk, &rc);
         if (rc) return fail(L, rc);
+        MarkSet mk(L, 3);
         HIPCHK(L, launch_compute_ranks_units(in.reads, off, w.soff, m_blk, n_blk, rdev, nu, w.g,
-                                             &kk, rank_segments(L, in.maxlen), w.misc + MISC_ERR, s));
+                                             &kk, rank_segments(L, in.maxlen), w.misc + MISC_ERR, s,
+                                             mk.get()));
+        mk.add(0, SPAN_RANKS_K, n_blk - m_blk);
+        mk.add(1, SPAN_RANKS_SEG, 0);
+        mk.add(2, SPAN_RANKS_FB, 0);
     }
     uint32_t *sa = nullptr;
     const uint64_t *gkeys = nullptr;
@@ -951,8 +1002,10 @@ int run_block(bwt_set *L, hipStream_t s, const DevBlock &B, const std::vector<Ho
         for (uint32_t k = B.u0; k < B.u1; ++k) {
             L->timer.acc.insert_records_out += records_for(units[k].n_ext + units[k].nsuf);
             L->timer.acc.insert_records_in += records_for(units[k].n_ext);
+            L->timer.acc.insert_old_symbols += units[k].n_ext;
         }
         L->timer.acc.insert_new_symbols += n_blk;
+        L->timer.acc.insert_terminators += m_blk;
     }
     L->timer.acc.blocks += 1;
     return BWT_OK;
@@ -982,6 +1035,14 @@ void stats_add(bwt_stats_t &a, const bwt_stats_t &b) {
     a.bucket_ms += b.bucket_ms;
     a.tied_suffixes += b.tied_suffixes;
     a.fallback_blocks += b.fallback_blocks;
+    a.ranks_seg_ms += b.ranks_seg_ms;
+    a.ranks_seg_launches += b.ranks_seg_launches;
+    a.ranks_fb_ms += b.ranks_fb_ms;
+    a.tile_sort_ms += b.tile_sort_ms;
+    a.tile_sort_launches += b.tile_sort_launches;
+    a.tile_sort_keys += b.tile_sort_keys;
+    a.insert_old_symbols += b.insert_old_symbols;
+    a.insert_terminators += b.insert_terminators;
 }
 
 template <class T>
@@ -1474,12 +1535,16 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
         const int gbits = bits_for_value(n_cur);
         if (gbits > 0) {
             Scope sc(h, s, BWT_STAGE_RANKS);
-            Scope sk(h, s, SPAN_RANKS_K, n_blk - m_blk);
             const RankKeys kk = rank_keys(h, s, gbits, n_blk, &rc);
             if (rc) return fail(h, rc);
+            MarkSet mk(h, 3);
             HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
                                            S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
-                                           rank_segments(h, P.maxlen), w.misc + MISC_ERR, s));
+                                           rank_segments(h, P.maxlen), w.misc + MISC_ERR, s,
+                                           mk.get()));
+            mk.add(0, SPAN_RANKS_K, n_blk - m_blk);
+            mk.add(1, SPAN_RANKS_SEG, 0);
+            mk.add(2, SPAN_RANKS_FB, 0);
         }
         uint32_t *sa = nullptr;
         const uint64_t *gkeys = nullptr;
@@ -1489,7 +1554,8 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
                              &gshift)))
             return rc;
         const int dst = other[b & 1];
-        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gshift, sa, n_blk))) return rc;
+        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gshift, sa, n_blk, m_blk)))
+            return rc;
         n_cur += n_blk;
         h->timer.acc.blocks += 1;
         src = dst;
@@ -1628,7 +1694,7 @@ int bwt_set_import(bwt_set_t h, const uint8_t *B, uint64_t n, void *stream) {
         if ((rc = read_u32(h, s, w.misc + MISC_BAD, &bad))) return rc;
         if (bad) return fail(h, BWT_EINVAL);
         HIPCHK(h, launch_pack_user_insert(chunk, w.kA, cnt, 0, w.kA, w.v[0], s));
-        if ((rc = insert_block(h, s, h->buf[src], h->buf[dst], n_cur, w.kA, 0, w.v[0], cnt)))
+        if ((rc = insert_block(h, s, h->buf[src], h->buf[dst], n_cur, w.kA, 0, w.v[0], cnt, 0)))
             return rc;
         if (!dev) HIPCHK(h, hipStreamSynchronize(s));  // the staging buffer is reused
         n_cur += cnt;
@@ -1819,17 +1885,22 @@ int bwt_set_compute_ranks(bwt_set_t h, const uint8_t *reads, const uint64_t *off
     if (P.total_suffixes > MAX_BLOCK) return fail(h, BWT_EINVAL);
     if ((rc = ensure_ws(h, P.total_suffixes))) return rc;
     IndexBuf &B = h->buf[h->cur];
+    if ((rc = clear_err(h, s))) return rc;
     HIPCHK(h, launch_block_soff(P.off, (uint32_t)m, h->ws.soff, s));
     {
-        Scope sk(h, s, SPAN_RANKS_K, P.total_suffixes - m);
+        MarkSet mk(h, 3);
         HIPCHK(h, launch_compute_ranks(P.reads, P.off, h->ws.soff, (uint32_t)m,
                                        (uint32_t)P.total_suffixes, B.recs, B.sbc, B.meta,
                                        h->n >= (1ull << SB_SHIFT) ? 1 : 0, g_out, nullptr,
-                                       rank_segments(h, P.maxlen), h->ws.misc + MISC_ERR, s));
+                                       rank_segments(h, P.maxlen), h->ws.misc + MISC_ERR, s,
+                                       mk.get()));
+        mk.add(0, SPAN_RANKS_K, P.total_suffixes - m);
+        mk.add(1, SPAN_RANKS_SEG, 0);
+        mk.add(2, SPAN_RANKS_FB, 0);
     }
     HIPCHK(h, hipStreamSynchronize(s));
     if (h->timer.on) timer_collect(h);
-    return BWT_OK;
+    return check_err(h, s);
 }
 
 int bwt_set_insert(bwt_set_t h, const uint8_t *bint, const uint64_t *gsa, uint64_t n_new,
@@ -1855,7 +1926,8 @@ int bwt_set_insert(bwt_set_t h, const uint8_t *bint, const uint64_t *gsa, uint64
     const int gbits = bits_for_value(h->n);
     const int gshift = gbits ? 64 - gbits : 64;
     HIPCHK(h, launch_pack_user_insert(bint, gsa, n_new, gshift, w.kA, w.v[0], s));
-    if ((rc = insert_block(h, s, h->buf[h->cur], h->buf[dst], h->n, w.kA, gshift, w.v[0], n_new)))
+    if ((rc = insert_block(h, s, h->buf[h->cur], h->buf[dst], h->n, w.kA, gshift, w.v[0], n_new,
+                            0)))
         return rc;
     // the number of terminators merged in comes from the new counts
     HIPCHK(h, hipMemcpyAsync(h->pinned, h->buf[dst].meta, META_WORDS * 8, hipMemcpyDeviceToHost, s));

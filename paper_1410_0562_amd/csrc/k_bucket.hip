@@ -941,16 +941,18 @@ hipError_t launch_bucket_sort(const uint64_t *kin, const uint32_t *vin, uint64_t
                               uint32_t nb, int bshift, int kshort, uint32_t limit, uint32_t *large,
                               uint32_t *tcnt, uint32_t *osz, uint8_t *tflag, uint32_t *part,
                               uint32_t *res, uint32_t *olist, uint32_t *ooff, uint32_t *obad,
-                              uint32_t *err, hipStream_t s) {
+                              uint32_t *err, hipStream_t s, const Marks *mk) {
     const uint32_t ntiles = (uint32_t)div_up(nb, BT_TILE);
     if (ntiles > 4 * 1024) return hipErrorInvalidValue;
     fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(tcnt, nb, 0u);
     fill_u32_kernel<<<(unsigned)div_up(nb, 256), 256, 0, s>>>(osz, nb, 0u);
     const uint32_t nt = (uint32_t)div_up(n, BT_T);
+    Marks::begin(mk, 0, s);
     if (nt > 0)
         bucket_tile_sort_kernel<<<nt, 256, 0, s>>>(kin, vin, kout, vout, n, bshift, nb, bstart,
                                                    trange, kshort, limit, large, tcnt, osz, tflag,
                                                    err);
+    Marks::end(mk, 0, s);
     bucket_scan_up_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part);
     bucket_scan_top_kernel<<<1, 1024, 0, s>>>(part, ntiles, res);
     bucket_scan_down_kernel<<<ntiles, 256, 0, s>>>(tcnt, osz, nb, part, res, olist, ooff, obad);

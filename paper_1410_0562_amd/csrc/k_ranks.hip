@@ -123,7 +123,8 @@ struct SymReader {
 struct LF {
     uint64_t C0, C1, C2, C3, m_ext, n_ext;
     bool big;
-    __device__ LF(const uint64_t *__restrict__ meta, int big_) {
+    uint32_t *err;
+    __device__ LF(const uint64_t *__restrict__ meta, int big_, uint32_t *err_) {
         m_ext = meta[5];
         n_ext = meta[4];
         C0 = m_ext;               // every terminator is smaller than A
@@ -131,15 +132,23 @@ struct LF {
         C2 = C1 + meta[1];
         C3 = C2 + meta[2];
         big = big_ != 0;
+        err = err_;
     }
-    // Lemma 1: C[c] + rank(c, i, B_ext); a consistent index never needs the
-    // clamp.  Against an empty index every rank is 0 (no record is read).
+    // Lemma 1: C[c] + rank(c, i, B_ext), at most n_ext in a consistent
+    // index.  A larger value means counts and symbols disagree: the call is
+    // failed through the err word (bit 1024), and the walk goes on clamped so
+    // that it stays inside the index.  Against an empty index every rank is 0
+    // (no record is read).
     __device__ uint64_t step(const Rec *__restrict__ recs, const uint64_t *__restrict__ sbc,
                              uint64_t i, int c) const {
         if (n_ext == 0) return 0;
         uint64_t Cc = c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : C3;
         uint64_t r = Cc + rank_base(recs, sbc, i, c, big);
-        return r < n_ext ? r : n_ext;
+        if (r > n_ext) {
+            atomicOr(err, 1024u);
+            r = n_ext;
+        }
+        return r;
     }
 };
 
@@ -157,13 +166,15 @@ struct OneIndex {
     const uint64_t *sbc;
     const uint64_t *meta;
     int big;
-    __device__ Walker at(uint32_t) const { return Walker{recs, sbc, LF(meta, big), 0}; }
+    uint32_t *err;
+    __device__ Walker at(uint32_t) const { return Walker{recs, sbc, LF(meta, big, err), 0}; }
 };
 
 // Read j against the index of its unit (the last unit with read0 <= j).
 struct UnitIndex {
     const RankUnit *units;
     uint32_t n;
+    uint32_t *err;
     __device__ Walker at(uint32_t j) const {
         uint32_t lo = 0, hi = n - 1;
         while (lo < hi) {
@@ -172,7 +183,7 @@ struct UnitIndex {
             else hi = mid - 1;
         }
         const RankUnit &u = units[lo];
-        return Walker{u.recs, u.sbc, LF(u.meta, (int)u.big), u.goff};
+        return Walker{u.recs, u.sbc, LF(u.meta, (int)u.big, err), u.goff};
     }
 };
 
@@ -409,7 +420,7 @@ __global__ void zero_kernel(uint32_t *p, uint32_t n) {
 template <class Src, bool KEYS>
 hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                          uint32_t m_blk, uint32_t n_blk, Src src, const Out &o,
-                         const RankSegments &sg, uint32_t *err, hipStream_t s) {
+                         const RankSegments &sg, uint32_t *err, hipStream_t s, const Marks *mk) {
     uint32_t seg = sg.seg_len;
     uint32_t cap = 0;
     if (seg > 0) {
@@ -420,18 +431,25 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
         zero_kernel<<<1, 64, 0, s>>>(sg.counters, 2);
         zero_kernel<<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(sg.fb_flag, m_blk);
     }
+    Marks::begin(mk, 0, s);
     compute_ranks_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
         reads, off, soff, m_blk, src, o, seg, sg.seg_list, sg.counters, cap, err);
-    if (seg > 0) {
+    Marks::end(mk, 0, s);
+    Marks::begin(mk, 1, s);
+    if (seg > 0)
         rank_segments_kernel<Src, KEYS><<<(unsigned)div_up(cap, 256), 256, 0, s>>>(
             reads, off, soff, m_blk, src, o, seg, sg.overlap, sg.seg_list, sg.counters, sg.fb_flag,
             sg.fb_list, sg.counters + 1, err);
+    Marks::end(mk, 1, s);
+    Marks::begin(mk, 2, s);
+    if (seg > 0) {
         rank_fallback_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
             reads, off, soff, src, o, sg.fb_list, sg.counters + 1);
         if (KEYS && o.hist)
             count_long_keys_kernel<<<cap < 2048 ? cap : 2048, 256, 0, s>>>(
                 off, soff, m_blk, seg, sg.seg_list, sg.counters, o.keys, o.hshift, o.hist);
     }
+    Marks::end(mk, 2, s);
     return hipGetLastError();
 }
 
@@ -439,7 +457,7 @@ template <class Src>
 hipError_t compute_ranks_any(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
                              uint32_t m_blk, uint32_t n_blk, Src src, uint64_t *g,
                              const RankKeys *kk, const RankSegments &sg, uint32_t *err,
-                             hipStream_t s) {
+                             hipStream_t s, const Marks *mk) {
     if (m_blk == 0) return hipSuccess;
     Out o{};
     if (kk) {
@@ -451,11 +469,11 @@ hipError_t compute_ranks_any(const uint8_t *reads, const uint64_t *off, const ui
         o.vvec = (reinterpret_cast<uintptr_t>(o.vals) & 63) == 0;
         o.hist = kk->hist;
         o.hshift = kk->hshift;
-        return compute_ranks<Src, true>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s);
+        return compute_ranks<Src, true>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s, mk);
     }
     o.g = g;
     o.vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
-    return compute_ranks<Src, false>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s);
+    return compute_ranks<Src, false>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s, mk);
 }
 
 }  // namespace
@@ -464,19 +482,19 @@ hipError_t launch_compute_ranks(const uint8_t *reads, const uint64_t *off, const
                                 uint32_t m_blk, uint32_t n_blk, const Rec *recs,
                                 const uint64_t *sbc, const uint64_t *meta, int big, uint64_t *g,
                                 const RankKeys *kk, const RankSegments &sg, uint32_t *err,
-                                hipStream_t s) {
-    return compute_ranks_any(reads, off, soff, m_blk, n_blk, OneIndex{recs, sbc, meta, big}, g, kk,
-                             sg, err, s);
+                                hipStream_t s, const Marks *mk) {
+    return compute_ranks_any(reads, off, soff, m_blk, n_blk, OneIndex{recs, sbc, meta, big, err},
+                             g, kk, sg, err, s, mk);
 }
 
 hipError_t launch_compute_ranks_units(const uint8_t *reads, const uint64_t *off,
                                       const uint32_t *soff, uint32_t m_blk, uint32_t n_blk,
                                       const RankUnit *units, uint32_t nunits, uint64_t *g,
                                       const RankKeys *kk, const RankSegments &sg, uint32_t *err,
-                                      hipStream_t s) {
+                                      hipStream_t s, const Marks *mk) {
     if (nunits == 0) return hipSuccess;
-    return compute_ranks_any(reads, off, soff, m_blk, n_blk, UnitIndex{units, nunits}, g, kk, sg,
-                             err, s);
+    return compute_ranks_any(reads, off, soff, m_blk, n_blk, UnitIndex{units, nunits, err}, g,
+                             kk, sg, err, s, mk);
 }
 
 }  // namespace bwt

@@ -3,15 +3,22 @@
 Each tenant owns one incremental index (a ``BwtSet``).  Append requests
 arrive over time; a tenant's appends are applied in arrival order (the order
 fixes the terminator numbering, so it fixes the result), while appends of
-different tenants run concurrently: a pool of worker threads each drives one
-append at a time through the C ABI on the tenant handle's own HIP stream, so
-their kernels overlap on the device.  A request is admitted as soon as a
-worker is free, its tenant has nothing in flight, and the device memory
-budget allows it; to make room, idle tenants are first trimmed (workspace and
-spare buffers freed) and then spilled: the index is exported to pinned host
-memory and the device copy released; the next request of a spilled tenant
-restores it with ``import_bwt`` before appending.  Every step of the BWT work
-runs in the library's kernels; this module only schedules.
+different tenants are batched: a worker takes the queued requests of up to
+``max_batch`` idle tenants that fit the device memory budget and runs them as
+one ``bwt_set_append_many`` call, whose blocks hold the reads of several
+tenants at once (each ranked against and merged into its own index).  A pool
+of workers runs such batches side by side, each on the first tenant handle's
+own HIP stream, so their kernels also overlap on the device.  To make room,
+idle tenants are first trimmed (workspace and spare buffers freed) and then
+spilled: the index is exported to pinned host memory and the device copy
+released; the next request of a spilled tenant restores it with
+``import_bwt`` before appending.  Every step of the BWT work runs in the
+library's kernels; this module only schedules.
+
+A failed append leaves its index unchanged.  The tenant is then marked
+failed, and its later requests fail too (with ``TenantFailed``) instead of
+being applied without the failed one, which would renumber their strings;
+``resume(tenant)`` accepts requests again.
 
 Latency of a request = completion time - arrival time.
 """
@@ -46,37 +53,46 @@ class Request:
         return self.finish - self.arrival
 
 
+class TenantFailed(RuntimeError):
+    """A request not applied because an earlier request of its tenant failed."""
+
+
 class _Tenant:
     def __init__(self, tid: int):
         self.tid = tid
         self.index: Optional[bwtset.BwtSet] = None
         self.spill = None            # pinned host copy of B while spilled
-        self.pending = collections.deque()
         self.busy = False
         self.last_used = 0.0
         self.trimmed = True
+        self.failed: Optional[BaseException] = None   # first failure, until resume()
 
 
 class BwtService:
     """Continuous-batching append service over `tenants` indices.
 
     budget_bytes: device memory the tenants' handles may hold together.
-    workers: appends in flight at once (one per tenant at most).
+    workers: batches in flight at once.
+    max_batch: tenants whose queued requests one batch may take (one request
+    per tenant, the oldest, so that each tenant's order is kept).
     """
 
     def __init__(self, tenants: int, budget_bytes: int, workers: int = 4,
-                 block_size: int = 1 << 26, per_append_bytes: Optional[int] = None):
+                 block_size: int = 1 << 26, per_append_bytes: Optional[int] = None,
+                 max_batch: int = 8):
         import torch
         self.torch = torch
         self.tenants = [_Tenant(t) for t in range(tenants)]
         self.budget = int(budget_bytes)
         self.block_size = int(block_size)
+        self.max_batch = max(1, int(max_batch))
         # device bytes an append needs beyond the resident index: the block
-        # workspace (about 90 bytes per suffix of a block) plus staging
+        # workspace (about 90 bytes per suffix of a block) plus staging; a
+        # batch shares one workspace
         self.per_append = int(per_append_bytes or 96 * min(self.block_size, 1 << 26))
         self.lock = threading.Condition()
         self.queue = collections.deque()      # arrival order
-        self.reserved = 0                     # bytes promised to appends in flight
+        self.reserved = 0                     # bytes promised to batches in flight
         self.stats = collections.Counter()
         self.completed = []
         self._stop = False
@@ -133,18 +149,31 @@ class BwtService:
                 return bytes(t.spill.numpy().tobytes())
             return b""
 
+    def failure(self, tenant: int) -> Optional[BaseException]:
+        """The error that stopped the tenant's requests, or None."""
+        with self.lock:
+            return self.tenants[tenant].failed
+
+    def resume(self, tenant: int) -> None:
+        """Accept the tenant's requests again after a failure; its index is
+        the one left by its last successful append."""
+        with self.lock:
+            self.tenants[tenant].failed = None
+            self.lock.notify_all()
+
     # ----------------------------------------------------------- scheduling
     def _resident_bytes(self) -> int:
         return self.reserved + sum(t.index.memory() for t in self.tenants
                                    if t.index is not None and not t.busy)
 
-    def _make_room(self, need: int, keep: _Tenant) -> bool:
-        """Trim, then spill, idle tenants (least recently used first) until
-        `need` more bytes fit the budget.  Called with the lock held."""
+    def _make_room(self, need: int, keep) -> bool:
+        """Trim, then spill, idle tenants (least recently used first, none in
+        `keep`) until `need` more bytes fit the budget.  Called with the lock
+        held."""
         if self._resident_bytes() + need <= self.budget:
             return True
         idle = sorted((t for t in self.tenants
-                       if t is not keep and not t.busy and t.index is not None),
+                       if t not in keep and not t.busy and t.index is not None),
                       key=lambda t: t.last_used)
         for t in idle:
             if not t.trimmed:
@@ -170,79 +199,132 @@ class BwtService:
         self.stats["spills"] += 1
 
     def _restore(self, t: _Tenant) -> None:
-        t.index = bwtset.BwtSet(block_size=self.block_size)
+        """Bring a spilled (or never used) tenant's index onto the device.  The
+        tenant keeps its spill copy until the import has succeeded."""
+        idx = bwtset.BwtSet(block_size=self.block_size)
+        try:
+            if t.spill is not None and len(t.spill):
+                idx.import_bwt(t.spill.numpy())
+        except BaseException:
+            idx.close()
+            raise
         if t.spill is not None:
-            if len(t.spill):
-                t.index.import_bwt(t.spill.numpy())
-            t.spill = None
             self.stats["restores"] += 1
+        t.index = idx
+        t.spill = None
         t.trimmed = False
 
-    def _next_admissible(self) -> Optional[Request]:
-        """First queued request (arrival order) whose tenant is idle and that
-        fits the budget.  Called with the lock held."""
+    def _finish(self, req: Request, err: Optional[BaseException]) -> None:
+        """Record a request as done.  Called with the lock held."""
+        req.error = err
+        req.finish = time.perf_counter()
+        self.stats["completed"] += 1
+        self.completed.append(req)
+        req.done.set()
+
+    def _admit(self) -> list:
+        """The oldest queued request of each idle tenant, in arrival order, up
+        to max_batch of them and as long as they fit the budget together (the
+        batch shares one workspace).  Requests of a failed tenant are failed
+        here.  Called with the lock held."""
+        batch = []
+        keep = set()
         seen = set()
-        for i, req in enumerate(self.queue):
+        i = 0
+        while i < len(self.queue) and len(batch) < self.max_batch:
+            req = self.queue[i]
             t = self.tenants[req.tenant]
             if req.tenant in seen or t.busy:
                 seen.add(req.tenant)       # keep per-tenant order
+                i += 1
                 continue
             seen.add(req.tenant)
+            if t.failed is not None:
+                del self.queue[i]
+                self._finish(req, TenantFailed("tenant %d: an earlier request failed: %s"
+                                               % (req.tenant, t.failed)))
+                self.stats["failed_after"] += 1
+                continue
             grow = 2 * (req.bases + 2 * len(req.offsets))  # index growth, 3 buffers
             resident = 0 if t.index is None else t.index.memory()
             restore = 0 if t.index is not None else (
                 int(len(t.spill) * 1.6) if t.spill is not None else 0)
-            need = self.per_append + grow + restore
+            need = grow + restore + (0 if batch else self.per_append)
             if t.index is not None and not t.trimmed:
                 need = max(0, need - resident)
-            fits = self._make_room(need, t)
-            if not fits and not any(x.busy for x in self.tenants):
+            fits = self._make_room(need, keep | {t})
+            if not fits and not batch and not any(x.busy for x in self.tenants):
                 # larger than the whole budget: run it alone rather than never
                 fits = True
                 self.stats["oversize"] += 1
-            if fits:
-                del self.queue[i]
-                req.reserved = need + (resident if t.index is not None else 0)
-                self.reserved += req.reserved
-                return req
-            self.stats["deferred"] += 1
-            return None
-        return None
+            if not fits:
+                if not batch:
+                    self.stats["deferred"] += 1
+                break
+            del self.queue[i]
+            req.reserved = need + (resident if t.index is not None else 0)
+            self.reserved += req.reserved
+            t.busy = True
+            keep.add(t)
+            batch.append(req)
+        return batch
+
+    def _run_batch(self, batch: list) -> None:
+        """Restore, then append every request of the batch (one call).
+        Outside the lock; the batch's tenants are marked busy."""
+        ready = []
+        for req in batch:
+            t = self.tenants[req.tenant]
+            req.start = time.perf_counter()
+            if t.index is None:
+                try:
+                    self._restore(t)
+                except BaseException as e:  # noqa: BLE001
+                    req.error = e
+                    continue
+            ready.append(req)
+        if not ready:
+            return
+        idx = [self.tenants[r.tenant].index for r in ready]
+        try:
+            if len(ready) == 1:
+                idx[0].append(ready[0].reads, ready[0].offsets)
+            else:
+                bwtset.append_many(idx, [r.reads for r in ready], [r.offsets for r in ready])
+        except BaseException as e:  # noqa: BLE001
+            for r in ready:
+                r.error = e
+            return
+        for r in ready:
+            self.tenants[r.tenant].trimmed = False
 
     def _worker(self) -> None:
         torch = self.torch
         torch.cuda.set_device(self._device)
         while True:
             with self.lock:
-                req = None
+                batch = []
                 while not self._stop:
-                    req = self._next_admissible()
-                    if req is not None:
+                    batch = self._admit()
+                    if batch:
                         break
                     self.lock.wait(timeout=0.05)
-                if req is None:
+                if not batch:
                     return
-                t = self.tenants[req.tenant]
-                t.busy = True
-            # restore and append outside the lock: other workers keep
-            # admitting and running other tenants meanwhile
-            req.start = time.perf_counter()
-            try:
-                if t.index is None:
-                    self._restore(t)
-                t.index.append(req.reads, req.offsets)
-                t.trimmed = False
-            except BaseException as e:  # noqa: BLE001
-                req.error = e
-            req.finish = time.perf_counter()
+                self.stats["batches"] += 1
+                self.stats["batched_requests"] += len(batch)
+            # outside the lock: other workers keep admitting meanwhile
+            self._run_batch(batch)
             with self.lock:
-                self.reserved -= req.reserved
-                t.busy = False
-                t.last_used = req.finish
-                self.stats["completed"] += 1
-                self.completed.append(req)
+                for req in batch:
+                    t = self.tenants[req.tenant]
+                    self.reserved -= req.reserved
+                    t.busy = False
+                    t.last_used = time.perf_counter()
+                    if req.error is not None and t.failed is None:
+                        t.failed = req.error
+                    self._finish(req, req.error)
                 self.lock.notify_all()
-            req.done.set()
 
     # -------------------------------------------------------------- reports
     def latency_summary(self) -> dict:
@@ -258,5 +340,8 @@ class BwtService:
                 "mean_ms": float(lat.mean() * 1e3),
                 "bases_per_s": bases / (t1 - t0) if t1 > t0 else 0.0,
                 "spills": int(self.stats["spills"]), "restores": int(self.stats["restores"]),
-                "trims": int(self.stats["trims"]), "errors": sum(1 for r in self.completed
-                                                                 if r.error is not None)}
+                "trims": int(self.stats["trims"]),
+                "batches": int(self.stats["batches"]),
+                "mean_batch": (self.stats["batched_requests"] / self.stats["batches"]
+                               if self.stats["batches"] else 0.0),
+                "errors": sum(1 for r in self.completed if r.error is not None)}

@@ -141,3 +141,79 @@ def test_served_generator_through_service(torch_dev, oracle_mod):
         svc.close()
     for t in range(tenants):
         assert out[t] == _oracle_of(oracle_mod, host, t), t
+
+
+def test_failed_restore_keeps_the_spill_and_stops_the_tenant(torch_dev, oracle_mod, monkeypatch):
+    """An import that fails while a spilled tenant is restored (as it may under
+    the memory pressure that caused the spill) must leave the tenant spilled
+    with its index intact, fail its later requests rather than apply them
+    without the failed one, and serve it again after resume()."""
+    from paper_1410_0562_amd import bwtset
+    from paper_1410_0562_amd.serve import BwtService, TenantFailed
+    tenants = 3
+    reqs = _requests(9, tenants, 12)
+    real_import = bwtset.BwtSet.import_bwt
+    calls = {"n": 0}
+
+    def flaky_import(self, B, stream=None):
+        calls["n"] += 1
+        if calls["n"] == 1:
+            raise bwtset.BwtSetError(bwtset.BWT_ENOMEM, "bwt_set_import")
+        return real_import(self, B, stream)
+
+    monkeypatch.setattr(bwtset.BwtSet, "import_bwt", flaky_import)
+    svc = BwtService(tenants, budget_bytes=24 << 20, workers=1, block_size=1 << 18,
+                     per_append_bytes=16 << 20)
+    try:
+        handles = [svc.submit(t, p, o) for (t, p, o) in reqs]
+        svc.drain(timeout=120)
+        failed = [k for k, r in enumerate(handles) if r.error is not None]
+        assert failed, "the injected import failure did not happen"
+        first = failed[0]
+        bad_t = reqs[first][0]
+        assert isinstance(handles[first].error, bwtset.BwtSetError)
+        assert svc.failure(bad_t) is not None
+        # every later request of that tenant failed, none of another tenant
+        for k, r in enumerate(handles):
+            if reqs[k][0] == bad_t and k > first:
+                assert isinstance(r.error, TenantFailed), k
+            elif reqs[k][0] != bad_t:
+                assert r.error is None, k
+        # the tenant still holds exactly its requests before the failure
+        done = [r for k, r in enumerate(reqs) if r[0] != bad_t or k < first]
+        assert svc.export(bad_t) == _oracle_of(oracle_mod, done, bad_t)
+        # after resume, the failed and later requests go through in order
+        svc.resume(bad_t)
+        for k in range(first, len(reqs)):
+            if reqs[k][0] == bad_t:
+                svc.submit(*reqs[k])
+        svc.drain(timeout=120)
+        assert svc.failure(bad_t) is None
+        out = [svc.export(t) for t in range(tenants)]
+    finally:
+        svc.close()
+    for t in range(tenants):
+        assert out[t] == _oracle_of(oracle_mod, reqs, t), t
+
+
+def test_queued_requests_share_one_batch(torch_dev, oracle_mod):
+    """Requests of different tenants queued together run as one batched
+    append (bwt_set_append_many), and each tenant's index is still the oracle
+    BWT of its own requests."""
+    from paper_1410_0562_amd.serve import BwtService
+    tenants = 6
+    reqs = _requests(11, tenants, 36)
+    svc = BwtService(tenants, budget_bytes=64 << 30, workers=1, block_size=1 << 20, max_batch=6)
+    try:
+        # one worker: whatever queues while it runs a batch forms the next one
+        for (t, p, o) in reqs:
+            svc.submit(t, p, o)
+        svc.drain(timeout=120)
+        summ = svc.latency_summary()
+        out = [svc.export(t) for t in range(tenants)]
+    finally:
+        svc.close()
+    assert summ["errors"] == 0 and summ["requests"] == len(reqs)
+    assert summ["mean_batch"] > 1.5, summ
+    for t in range(tenants):
+        assert out[t] == _oracle_of(oracle_mod, reqs, t), t
