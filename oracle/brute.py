@@ -59,3 +59,36 @@ def old_smaller(old: Sequence[str], new: Sequence[str]) -> list:
         sp = T[p:]
         res.append(sum(1 for q in range(n_old) if T[q:] < sp))
     return res
+
+
+def occurrences(reads: Sequence[str], pattern: str) -> int:
+    """Occurrences of pattern inside the strings (overlaps counted); the
+    empty pattern occurs once per suffix, terminators included."""
+    if pattern == "":
+        return sum(len(s) + 1 for s in reads)
+    L = len(pattern)
+    return sum(1 for s in reads for i in range(len(s) - L + 1) if s[i:i + L] == pattern)
+
+
+def rows_below(reads: Sequence[str], pattern: str) -> int:
+    """Suffixes smaller than the pattern: the suffix (up to and including its
+    terminator, the smallest symbols) compared with the pattern's symbols,
+    a suffix that has the pattern as a prefix not counted."""
+    m = len(reads)
+    T = tokens(reads)
+    P = [m + 1 + _BASES.index(ch) for ch in pattern]
+    below = 0
+    for p in range(len(T)):
+        end = p
+        while T[end] >= m + 1:
+            end += 1
+        head = T[p:end + 1][:len(P)]
+        # a suffix shorter than P ends in its terminator, which differs from
+        # (and is smaller than) the pattern's base at that offset
+        if head != P and head < P:
+            below += 1
+    return below
+
+
+def reverse_complement(s: str) -> str:
+    return s[::-1].translate(str.maketrans("ACGT", "TGCA"))

@@ -34,6 +34,10 @@
  *   oracle_count_old_smaller  brute-force definition of what ComputeRanks
  *                        returns: for a new suffix, the number of old suffixes
  *                        smaller than it (hypothesis of Lemma 1)
+ *   oracle_pattern_rows  for a pattern P over the bases, by a scan over every
+ *                        suffix: how many suffixes are smaller than P and how
+ *                        many start with P (the rows of the sorted suffixes
+ *                        prefixed by P, i.e. the FM-index interval of P)
  *
  * What ComputeRanks returns for a whole block is computed in oracle.py from
  * its definition (old suffixes smaller than each new one, read off one suffix
@@ -295,4 +299,36 @@ uint64_t oracle_count_old_smaller(const uint8_t *G, uint64_t n_old, uint64_t p)
     for (uint64_t q = 0; q < n_old; ++q)
         if (cmp_suffix_at(G, q, p) < 0) ++c;
     return c;
+}
+
+/*
+ * The rows of the suffix array whose suffix starts with P (codes 1..4, L >= 0
+ * symbols): *below = the number of suffixes smaller than P, where a suffix
+ * that reaches a terminator before it differs from P is smaller (a terminator
+ * is smaller than every base), and *count = the number of suffixes that start
+ * with P, i.e. the occurrences of P in the strings (P holds no terminator, so
+ * an occurrence never crosses one).  Those suffixes are consecutive in sorted
+ * order, so they are the rows [below, below + count).  One scan over all n
+ * suffixes, stopping each comparison at the first difference.
+ */
+void oracle_pattern_rows(const uint8_t *T, uint64_t n, const uint8_t *P, uint64_t L,
+                         uint64_t *below, uint64_t *count)
+{
+    uint64_t lo = 0, cnt = 0;
+    for (uint64_t q = 0; q < n; ++q) {
+        int cmp = 0;
+        for (uint64_t t = 0; t < L; ++t) {
+            uint8_t x = T[q + t];
+            if (x != P[t]) {
+                cmp = x < P[t] ? -1 : 1;
+                break;
+            }
+            /* x == P[t] is a base, so the walk has not met a terminator and
+             * T[q + t + 1] exists (T ends with one) */
+        }
+        if (cmp < 0) ++lo;
+        else if (cmp == 0) ++cnt;
+    }
+    *below = lo;
+    *count = cnt;
 }

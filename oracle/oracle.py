@@ -15,6 +15,15 @@ Everything here follows Pantaleoni, arXiv:1410.0562:
   Section 4), reorder the ranks into suffix order (g_sa), and insert B_int[i]
   into B_ext before old row g_sa[i] (Insert, Section 5).
 
+Beyond the construction, two things the paper names around it:
+
+* the FM-index use of the BWT (the BWT with rank, Eq. 2): for a pattern, the
+  rows of the sorted suffixes that start with it, by a scan over every suffix
+  (pattern_rows);
+* reversal, which Section 2 notes is possible, and the set with every string's
+  reverse complement beside it (reverse_strings, with_reverse_complements),
+  as plain transformations of the input strings.
+
 The ranks are taken from their definition -- the number of old suffixes smaller
 than each new suffix -- out of one suffix array of the old and new text
 together, not by LF steps; Lemma 1's recurrence is only a cross-check in the
@@ -85,6 +94,8 @@ def _load():
     lib.oracle_lf_invert.restype = ctypes.c_int
     lib.oracle_count_old_smaller.argtypes = [u8p, u64, u64]
     lib.oracle_count_old_smaller.restype = u64
+    lib.oracle_pattern_rows.argtypes = [u8p, u64, u8p, u64, u64p, u64p]
+    lib.oracle_pattern_rows.restype = None
     _lib = lib
     return lib
 
@@ -356,3 +367,58 @@ def bwt_rank_all(B: bytes, c: str) -> np.ndarray:
     out = np.zeros(len(Bn) + 1, dtype=np.uint64)
     out[1:] = np.cumsum(hits)
     return out
+
+
+# --------------------------------------------------------------------------
+# FM-index queries (the BWT and its rank function form an FM-index; Eq. 2)
+# --------------------------------------------------------------------------
+
+def pattern_rows(T: np.ndarray, pattern: np.ndarray) -> tuple[int, int]:
+    """(lo, hi): the rows of the sorted suffixes of T that start with the
+    pattern (codes 1..4).  lo = suffixes smaller than the pattern, hi - lo =
+    occurrences of the pattern in the strings.  The empty pattern gives all
+    rows [0, n)."""
+    T = np.ascontiguousarray(T, dtype=np.uint8)
+    P = np.ascontiguousarray(pattern, dtype=np.uint8)
+    if len(P) == 0:
+        return 0, len(T)
+    lo = np.zeros(1, dtype=np.uint64)
+    cnt = np.zeros(1, dtype=np.uint64)
+    Pb = P if len(P) else np.zeros(1, np.uint8)
+    _load().oracle_pattern_rows(_p8(T), len(T), _p8(Pb), len(P), _p64(lo), _p64(cnt))
+    return int(lo[0]), int(lo[0] + cnt[0])
+
+
+# --------------------------------------------------------------------------
+# Strand variants of the input (Section 2 notes that reversal is possible)
+# --------------------------------------------------------------------------
+
+def _strings(codes: np.ndarray, offsets: np.ndarray) -> list:
+    offsets = np.asarray(offsets, dtype=np.int64)
+    base = int(offsets[0]) if len(offsets) else 0
+    return [codes[int(offsets[j]) - base:int(offsets[j + 1]) - base]
+            for j in range(len(offsets) - 1)]
+
+
+def _from_strings(strs: list) -> tuple[np.ndarray, np.ndarray]:
+    offsets = np.zeros(len(strs) + 1, dtype=np.uint64)
+    if strs:
+        offsets[1:] = np.cumsum([len(x) for x in strs], dtype=np.uint64)
+    codes = np.concatenate(strs).astype(np.uint8) if strs else np.zeros(0, np.uint8)
+    return codes, offsets
+
+
+def reverse_strings(codes: np.ndarray, offsets: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Every string written backwards, in the same order (codes 1..4)."""
+    return _from_strings([x[::-1] for x in _strings(codes, offsets)])
+
+
+def with_reverse_complements(codes: np.ndarray,
+                             offsets: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Every string followed by its reverse complement (A<->T, C<->G, read
+    backwards): strings 2j and 2j + 1 come from string j (codes 1..4)."""
+    out = []
+    for x in _strings(codes, offsets):
+        out.append(x)
+        out.append((5 - x[::-1]).astype(np.uint8))
+    return _from_strings(out)

@@ -339,3 +339,81 @@ def test_unpack_roundtrip(oracle_mod):
     codes, o2 = oracle_mod.reads_from_packed(packed, offs)
     c2, o3 = oracle_mod.strings_to_codes(reads)
     assert np.array_equal(codes, c2) and np.array_equal(o2, o3)
+
+
+# ---- FM-index rows of a pattern (count queries) ---------------------------
+
+def _rows(oracle_mod, reads, pattern):
+    T, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(reads))
+    P = oracle_mod.strings_to_codes([pattern])[0] if pattern else np.zeros(0, np.uint8)
+    return oracle_mod.pattern_rows(T, P)
+
+
+def test_pattern_rows_vs_brute_force(oracle_mod):
+    rng = random.Random(562)
+    for _ in range(300):
+        m = rng.randint(1, 5)
+        alpha = rng.choice(["AC", "ACGT", "GT"])
+        reads = ["".join(rng.choice(alpha) for _ in range(rng.randint(0, 9))) for _ in range(m)]
+        for _ in range(4):
+            P = "".join(rng.choice("ACGT") for _ in range(rng.randint(0, 4)))
+            lo, hi = _rows(oracle_mod, reads, P)
+            assert hi - lo == brute.occurrences(reads, P), (reads, P)
+            assert lo == brute.rows_below(reads, P), (reads, P)
+
+
+def test_pattern_rows_are_the_sa_rows_with_that_prefix(oracle_mod):
+    reads = ["ACGTTACG", "CGTA", "", "TTAC", "ACG"]
+    T, _ = oracle_mod.concat_text(*oracle_mod.strings_to_codes(reads))
+    sa = oracle_mod.suffix_array(T).astype(np.int64)
+    for P in ["A", "AC", "ACG", "CG", "T", "TA", "GTT", "CCC"]:
+        lo, hi = _rows(oracle_mod, reads, P)
+        Pc = [" ACGT".index(ch) for ch in P]
+        pref = [list(T[p:p + len(P)]) == Pc for p in sa]
+        assert [i for i, x in enumerate(pref) if x] == list(range(lo, hi)), P
+
+
+def test_pattern_rows_closed_form(oracle_mod):
+    # m copies of ACGT: rows are $ (m), ACGT$ (m), CGT$ (m), GT$ (m), T$ (m)
+    m = 7
+    reads = ["ACGT"] * m
+    assert _rows(oracle_mod, reads, "") == (0, 5 * m)
+    assert _rows(oracle_mod, reads, "A") == (m, 2 * m)
+    assert _rows(oracle_mod, reads, "CG") == (2 * m, 3 * m)
+    assert _rows(oracle_mod, reads, "GT") == (3 * m, 4 * m)
+    assert _rows(oracle_mod, reads, "TA") == (5 * m, 5 * m)
+    assert _rows(oracle_mod, reads, "AA") == (m, m)
+
+
+# ---- strand variants ------------------------------------------------------
+
+def test_reverse_and_reverse_complement_by_hand(oracle_mod):
+    codes, offs = oracle_mod.strings_to_codes(["ACG", "", "TTA"])
+    rc, ro = oracle_mod.reverse_strings(codes, offs)
+    assert list(ro) == [0, 3, 3, 6] and "".join(" ACGT"[c] for c in rc) == "GCAATT"
+    wc, wo = oracle_mod.with_reverse_complements(codes, offs)
+    assert list(wo) == [0, 3, 6, 6, 6, 9, 12]
+    assert "".join(" ACGT"[c] for c in wc) == "ACGCGTTTATAA"
+    assert brute.reverse_complement("ACGTT") == "AACGT"
+    # AC with its reverse complement GT: T = A C $0 G T $1, sorted suffixes
+    # $0 $1 AC$0 C$0 GT$1 T$1, preceded by C T $ A $ G
+    wc, wo = oracle_mod.with_reverse_complements(*oracle_mod.strings_to_codes(["AC"]))
+    assert oracle_mod.bwt_of_codes(wc, wo) == b"CT$A$G" == brute.bwt(["AC", "GT"]).encode()
+
+
+def test_reverse_complement_set_is_strand_symmetric(oracle_mod):
+    # with every string's reverse complement in the set, every pattern occurs
+    # as often as its reverse complement
+    rng = random.Random(1014)
+    reads = ["".join(rng.choice("ACGT") for _ in range(rng.randint(0, 12))) for _ in range(6)]
+    codes, offs = oracle_mod.strings_to_codes(reads)
+    wc, wo = oracle_mod.with_reverse_complements(codes, offs)
+    T, _ = oracle_mod.concat_text(wc, wo)
+    for _ in range(60):
+        P = "".join(rng.choice("ACGT") for _ in range(rng.randint(1, 4)))
+        a = oracle_mod.pattern_rows(T, oracle_mod.strings_to_codes([P])[0])
+        b = oracle_mod.pattern_rows(T, oracle_mod.strings_to_codes([brute.reverse_complement(P)])[0])
+        assert a[1] - a[0] == b[1] - b[0], P
+    rs = [brute.reverse_complement(r) for r in reads]
+    both = [x for pair in zip(reads, rs) for x in pair]
+    assert oracle_mod.bwt_of_codes(wc, wo).decode() == brute.bwt(both)
