@@ -30,11 +30,13 @@ __global__ void rank_many_kernel(const Rec *__restrict__ recs, const uint64_t *_
     out[t] = r;
 }
 
+// A bounded grid strides over the rows, so indices of 2^32 symbols and more
+// (beyond one launch's 32-bit work-item count) are covered.
 __global__ void export_kernel(const Rec *__restrict__ recs, uint64_t n, uint8_t *__restrict__ out) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const char ascii[5] = {'A', 'C', 'G', 'T', '$'};
-    out[i] = (uint8_t)ascii[rec_symbol(recs, i)];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = (uint8_t)ascii[rec_symbol(recs, i)];
 }
 
 __global__ void zero_words_kernel(uint64_t *p, int n) {
@@ -233,7 +235,9 @@ hipError_t launch_rank_many(const Rec *recs, const uint64_t *sbc, const uint64_t
 
 hipError_t launch_export(const Rec *recs, uint64_t n, uint8_t *out, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    export_kernel<<<(unsigned)div_up(n, 256), 256, 0, s>>>(recs, n, out);
+    if (n == 0) return hipSuccess;
+    const uint64_t want = div_up(n, 256);
+    export_kernel<<<(unsigned)(want < (1u << 20) ? want : (1u << 20)), 256, 0, s>>>(recs, n, out);
     return hipGetLastError();
 }
 
