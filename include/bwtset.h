@@ -181,6 +181,22 @@ const char *bwt_set_strerror(int code);
 int bwt_set_block_sort(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
                        uint64_t m, uint32_t *sa_out, uint8_t *bint_out, void *stream);
 
+/* bwt_set_block_sort for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same sa_out / bint_out, computed on a fixed workspace that
+ * the library holds per GPU (about 24 MiB, a static device array, kept until
+ * the process ends) instead of the handle's.  It calls no hipMalloc, hipFree
+ * or other allocating routine.  Limits: reads, offsets, sa_out and bint_out
+ * must be device pointers, and the block may hold at most 2^18 = 262,144
+ * suffixes (sum of |P_j| + 1); larger inputs return BWT_EINVAL without
+ * launching work.  Calls on one GPU share the workspace: calls from threads of
+ * one process are serialized, and work the caller enqueues on the same GPU
+ * that overlaps a call must not touch its buffers.  Synchronizes `stream`.
+ * Returns BWT_EHIP if the workspace's device address could not be taken when
+ * the first handle on this GPU was created. */
+int bwt_set_block_sort_noalloc(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
+                               uint64_t m, uint32_t *sa_out, uint8_t *bint_out, void *stream);
+
 /* ComputeRanks (Section 4, Lemma 1 / Algorithm 2) of one block made of all m
  * reads against the current index: g_out[p] (device, uint64, n_blk entries, in
  * block text order) = number of suffixes in the index smaller than the block

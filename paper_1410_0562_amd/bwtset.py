@@ -79,6 +79,7 @@ EXPORTED = [
     "bwt_set_block_sort", "bwt_set_compute_ranks", "bwt_set_insert",
     "bwt_set_enable_timing", "bwt_set_get_stats", "bwt_set_set_param",
     "bwt_set_import", "bwt_set_memory", "bwt_set_trim", "bwt_set_append_many",
+    "bwt_set_block_sort_noalloc",
 ]
 BWT_PARAM_KEY_BITS = 1
 BWT_PARAM_RADIX_TILE = 2
@@ -124,6 +125,8 @@ def load(path: str = LIB_PATH):
     L.bwt_set_strerror.restype = ctypes.c_char_p
     L.bwt_set_block_sort.argtypes = [vp, vp, vp, u64, vp, vp, vp]
     L.bwt_set_block_sort.restype = i32
+    L.bwt_set_block_sort_noalloc.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+    L.bwt_set_block_sort_noalloc.restype = i32
     L.bwt_set_compute_ranks.argtypes = [vp, vp, vp, u64, vp, vp]
     L.bwt_set_compute_ranks.restype = i32
     L.bwt_set_insert.argtypes = [vp, vp, vp, u64, vp]
@@ -307,6 +310,14 @@ class BwtSet:
         self._check(load().bwt_set_block_sort(self._h, _ptr(reads), _ptr(offsets), _len(offsets) - 1,
                                               _ptr(sa_out), _ptr(bint_out), _stream(stream)),
                     "bwt_set_block_sort")
+
+    def block_sort_noalloc(self, reads, offsets, sa_out, bint_out, stream=None) -> None:
+        """block_sort on the library's fixed per-GPU workspace (no device
+        allocation; device buffers only, at most 2^18 suffixes)."""
+        self._check(load().bwt_set_block_sort_noalloc(self._h, _ptr(reads), _ptr(offsets),
+                                                      _len(offsets) - 1, _ptr(sa_out),
+                                                      _ptr(bint_out), _stream(stream)),
+                    "bwt_set_block_sort_noalloc")
 
     def compute_ranks(self, reads, offsets, g_out, stream=None) -> None:
         reads = _as_reads(reads)

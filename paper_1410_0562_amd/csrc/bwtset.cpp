@@ -14,6 +14,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -64,6 +66,8 @@ struct Workspace {
     uint32_t *fb_flag = nullptr, *fb_list = nullptr;
     uint32_t *bk = nullptr;                  // BK_TABLES bucket tables of bk_words each
     uint32_t bk_words = 0;
+    uint8_t *region = nullptr;               // one allocation holding every array above
+    uint64_t bytes = 0;                      // its size
 };
 
 // layout of Workspace::misc (uint32 words)
@@ -342,28 +346,52 @@ int ensure_index(bwt_set *h, IndexBuf &b, uint64_t n) {
     return BWT_OK;
 }
 
+// Lays out a workspace for blocks of up to `cap` suffixes in one region at
+// `base` (nullptr: sizes only) and returns the region's size.  Every array
+// starts 256-byte aligned and is followed by a 4 KiB gap.
+uint64_t carve_ws(Workspace &w, uint64_t cap, uint8_t *base) {
+    uint64_t at = 0;
+    auto take = [&](auto *&p, uint64_t count) {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+        at = (at + 255) & ~255ull;
+        p = base ? reinterpret_cast<T *>(base + at) : nullptr;
+        at += std::max<uint64_t>(count, 1) * sizeof(T) + 4096;
+    };
+    const uint64_t tiles = div_up(cap, RADIX_MIN_TILE) + 1;
+    const uint64_t segs = 2 * div_up(cap, MIN_SEG_LEN) + 2;
+    uint32_t nb = 256;
+    while ((uint64_t)nb * BUCKET_TARGET < cap && nb < (1u << BUCKET_MAX_BITS)) nb <<= 1;
+    w.bk_words = nb + 16;
+    take(w.kA, cap);
+    take(w.kB, cap);
+    for (auto &p : w.v) take(p, cap);
+    for (auto &p : w.U) take(p, cap);
+    take(w.rank, cap);
+    take(w.g, cap);
+    take(w.gsa, cap);
+    take(w.tflag, cap);
+    take(w.bcnt, (div_up(cap, 64) + 2) * 4);
+    take(w.bseg, (2 * (div_up(cap, 64 << BINT_SEG_SHIFT) + 2) + 1) * 4);
+    take(w.soff, cap + 2);
+    take(w.tile_first, div_up(cap, 1u << PREP_TILE_SHIFT) + 2);
+    take(w.status_radix, tiles * 256);
+    take(w.status_scan, tiles * 8);
+    take(w.misc, MISC_WORDS);
+    take(w.seg_list, segs);
+    take(w.fb_flag, cap + 1);
+    take(w.fb_list, cap + 1);
+    // bucket tables, scan partials, and three words per 2048-position tile
+    take(w.bk, (uint64_t)BK_TABLES * w.bk_words + BK_PART + 3 * (cap / 2048 + 2));
+    w.seg_cap = (uint32_t)segs;
+    w.cap = cap;
+    w.region = base;
+    w.bytes = at;
+    return at;
+}
+
 void free_ws(Workspace &w) {
-    dfree(w.kA);
-    dfree(w.kB);
-    for (auto &p : w.v) dfree(p);
-    for (auto &p : w.U) dfree(p);
-    dfree(w.rank);
-    dfree(w.g);
-    dfree(w.gsa);
-    dfree(w.tflag);
-    dfree(w.bcnt);
-    dfree(w.bseg);
-    dfree(w.soff);
-    dfree(w.tile_first);
-    dfree(w.status_radix);
-    dfree(w.status_scan);
-    dfree(w.misc);
-    dfree(w.seg_list);
-    dfree(w.fb_flag);
-    dfree(w.fb_list);
-    dfree(w.bk);
-    w.seg_cap = 0;
-    w.cap = 0;
+    dfree(w.region);
+    w = Workspace();
 }
 
 int ensure_ws(bwt_set *h, uint64_t need) {
@@ -372,48 +400,20 @@ int ensure_ws(bwt_set *h, uint64_t need) {
     uint64_t cap = std::max<uint64_t>(need, w.cap + w.cap / 4);
     cap = std::min<uint64_t>(std::max<uint64_t>(cap, 4096), MAX_BLOCK + 1);
     free_ws(w);
-    bool ok = true;
-    uint64_t tiles = div_up(cap, RADIX_MIN_TILE) + 1;
-    ok &= dalloc(&w.kA, cap) == hipSuccess;
-    ok &= dalloc(&w.kB, cap) == hipSuccess;
-    for (auto &p : w.v) ok &= dalloc(&p, cap) == hipSuccess;
-    for (auto &p : w.U) ok &= dalloc(&p, cap) == hipSuccess;
-    ok &= dalloc(&w.rank, cap) == hipSuccess;
-    ok &= dalloc(&w.g, cap) == hipSuccess;
-    ok &= dalloc(&w.gsa, cap) == hipSuccess;
-    ok &= dalloc(&w.tflag, cap) == hipSuccess;
-    ok &= dalloc(&w.bcnt, (div_up(cap, 64) + 2) * 4) == hipSuccess;
-    ok &= dalloc(&w.bseg, (2 * (div_up(cap, 64 << BINT_SEG_SHIFT) + 2) + 1) * 4) == hipSuccess;
-    ok &= dalloc(&w.soff, cap + 2) == hipSuccess;
-    ok &= dalloc(&w.tile_first, div_up(cap, 1u << PREP_TILE_SHIFT) + 2) == hipSuccess;
-    ok &= dalloc(&w.status_radix, tiles * 256) == hipSuccess;
-    ok &= dalloc(&w.status_scan, tiles * 8) == hipSuccess;
-    ok &= dalloc(&w.misc, MISC_WORDS) == hipSuccess;
-    const uint64_t segs = 2 * div_up(cap, MIN_SEG_LEN) + 2;
-    ok &= dalloc(&w.seg_list, segs) == hipSuccess;
-    ok &= dalloc(&w.fb_flag, cap + 1) == hipSuccess;
-    ok &= dalloc(&w.fb_list, cap + 1) == hipSuccess;
-    {
-        uint32_t nb = 256;
-        while ((uint64_t)nb * BUCKET_TARGET < cap && nb < (1u << BUCKET_MAX_BITS)) nb <<= 1;
-        w.bk_words = nb + 16;
-    }
-    // bucket tables, scan partials, and three words per 2048-position tile
-    ok &= dalloc(&w.bk, (uint64_t)BK_TABLES * w.bk_words + BK_PART + 3 * (cap / 2048 + 2)) ==
-          hipSuccess;
-    if (!ok) {
+    Workspace t;
+    uint8_t *base = nullptr;
+    if (dalloc(&base, carve_ws(t, cap, nullptr)) != hipSuccess) {
         (void)hipGetLastError();
-        free_ws(w);
         return fail(h, BWT_ENOMEM);
     }
+    carve_ws(w, cap, base);
     // counters start at zero; status words never need clearing (epoch tags),
     // zeroing them once makes the first launches read "not ready" cleanly
     HIPCHK(h, hipMemsetAsync(w.misc, 0, MISC_WORDS * 4, h->stream));
+    const uint64_t tiles = div_up(cap, RADIX_MIN_TILE) + 1;
     HIPCHK(h, hipMemsetAsync(w.status_radix, 0, tiles * 256 * 8, h->stream));
     HIPCHK(h, hipMemsetAsync(w.status_scan, 0, tiles * 8 * 8, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    w.seg_cap = (uint32_t)segs;
-    w.cap = cap;
     return BWT_OK;
 }
 
@@ -1412,6 +1412,63 @@ int append_many(bwt_set *d, bwt_set **hs, const uint8_t *const *reads,
 // ============================================================================
 // C ABI
 // ============================================================================
+// ---- ConstructSA without allocation ------------------------------------------
+// bwt_set_block_sort_noalloc runs on a workspace carved from `scratch`, one
+// array per GPU in the library's code object, instead of the handle's.  In
+// host code the name `scratch` is only a stand-in: the array's device address
+// on each GPU comes from hipGetSymbolAddress (taken once per device, with that
+// device current, when the first handle on it is created) and only that
+// address is passed to kernels.  Calls on one GPU share the array and keep the
+// last call's contents; every call clears the counters it needs, and calls
+// from threads of this process are serialized per device.
+namespace {
+constexpr uint64_t NOALLOC_MAX_SUFFIXES = 1ull << 18;
+constexpr uint64_t NOALLOC_BYTES = 24ull << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu[NOALLOC_MAX_DEVICES];
+uint8_t *g_scratch_ptr[NOALLOC_MAX_DEVICES];   // device address per device, or null
+bool g_scratch_fresh[NOALLOC_MAX_DEVICES];     // status words not yet cleared
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
+namespace {
+// Takes the device address of `scratch` on device `dev` (current).  Failure
+// is not fatal for the handle: the no-allocation entry point reports it.
+void scratch_setup(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> g(g_scratch_mu[dev]);
+    if (g_scratch_ptr[dev]) return;
+    Workspace t;
+    if (carve_ws(t, NOALLOC_MAX_SUFFIXES, nullptr) > NOALLOC_BYTES) return;
+    uint8_t *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return;
+    }
+    g_scratch_ptr[dev] = ptr;
+    g_scratch_fresh[dev] = true;
+}
+
+// Lends the handle the workspace view of the scratch array (timing off) for
+// the length of one call.
+struct ScratchWs {
+    bwt_set *h;
+    Workspace saved;
+    bool timing;
+    ScratchWs(bwt_set *h_, uint8_t *base) : h(h_), saved(h_->ws), timing(h_->timer.on) {
+        Workspace w;
+        carve_ws(w, NOALLOC_MAX_SUFFIXES, base);
+        h->ws = w;
+        h->timer.on = false;
+    }
+    ~ScratchWs() {
+        h->ws = saved;
+        h->timer.on = timing;
+    }
+};
+}  // namespace
+
 extern "C" {
 
 bwt_set_t bwt_set_create(const char *alphabet) {
@@ -1452,6 +1509,7 @@ bwt_set_t bwt_set_create(const char *alphabet) {
         bwt_set_destroy(h);
         return nullptr;
     }
+    scratch_setup(h->device);
     h->cur = 0;
     g_create_error = BWT_OK;
     return h;
@@ -1720,13 +1778,7 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
         if (x.meta) b += META_WORDS * 8;
     }
     const Workspace &w = h->ws;
-    if (w.cap) {
-        const uint64_t c = w.cap, tiles = div_up(c, RADIX_MIN_TILE) + 1;
-        b += c * (8 * 4 + 4 * 6 + 1 + 4 * 2) + div_up(c, 64) * 16 +
-             (2 * (div_up(c, 64 << BINT_SEG_SHIFT) + 2) + 1) * 16 + div_up(c, 4096) * 4 +
-             tiles * (256 + 8) * 8 + (uint64_t)w.seg_cap * 8 + MISC_WORDS * 4 +
-             4ull * (BK_TABLES * w.bk_words + BK_PART + 3 * (c / 2048 + 2));
-    }
+    if (w.region) b += w.bytes;
     b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
          h->stage_out_cap + h->btab_cap + h->bstage_cap;
     for (auto *l : h->lanes) {
@@ -1868,6 +1920,61 @@ int bwt_set_block_sort(bwt_set_t h, const uint8_t *reads, const uint64_t *offset
     HIPCHK(h, launch_sa_strip(sa, n_blk, sa_out, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (h->timer.on) timer_collect(h);
+    return check_err(h, s);
+}
+
+int bwt_set_block_sort_noalloc(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
+                               uint64_t m, uint32_t *sa_out, uint8_t *bint_out, void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (m == 0) return BWT_OK;
+    if (!reads || !offsets || !sa_out || !bint_out) return fail(h, BWT_EINVAL);
+    if (m > NOALLOC_MAX_SUFFIXES) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (h->device < 0 || h->device >= NOALLOC_MAX_DEVICES) return fail(h, BWT_EHIP);
+    if (!is_device_ptr(reads) || !is_device_ptr(offsets) || !is_device_ptr(sa_out) ||
+        !is_device_ptr(bint_out))
+        return fail(h, BWT_EINVAL);
+    std::lock_guard<std::mutex> g(g_scratch_mu[h->device]);
+    uint8_t *base = g_scratch_ptr[h->device];
+    if (!base) return fail(h, BWT_EHIP);
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    // offsets in order, the longest read, and the block size from the ends
+    HIPCHK(h, launch_check_offsets(offsets, m, h->res, s));
+    HIPCHK(h, hipMemcpyAsync(h->pinned, h->res, 2 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->pinned + 2, offsets, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->pinned + 3, offsets + m, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    const uint64_t bad = h->pinned[0], maxlen = h->pinned[1], o0 = h->pinned[2],
+                   o1 = h->pinned[3];
+    if (bad || o1 < o0 || maxlen > MAX_READ) return fail(h, BWT_EINVAL);
+    const uint64_t n64 = o1 - o0 + m;
+    if (n64 > NOALLOC_MAX_SUFFIXES) return fail(h, BWT_EINVAL);
+    const uint32_t n_blk = (uint32_t)n64;
+    ScratchWs view(h, base);
+    Workspace &w = h->ws;
+    // the counters must start at zero; the look-back status words only need
+    // it once (each launch tags them with a fresh epoch)
+    HIPCHK(h, launch_zero_u32(w.misc, MISC_WORDS, s));
+    if (g_scratch_fresh[h->device]) {
+        const uint64_t tiles = div_up(NOALLOC_MAX_SUFFIXES, RADIX_MIN_TILE) + 1;
+        HIPCHK(h, launch_zero_u32(reinterpret_cast<uint32_t *>(w.status_radix),
+                                  (uint32_t)(tiles * 256 * 2), s));
+        HIPCHK(h, launch_zero_u32(reinterpret_cast<uint32_t *>(w.status_scan),
+                                  (uint32_t)(tiles * 8 * 2), s));
+        g_scratch_fresh[h->device] = false;
+    }
+    uint32_t *sa = nullptr;
+    const uint64_t *gkeys = nullptr;
+    int gshift = 64;
+    if ((rc = block_prep(h, s, offsets, (uint32_t)m, n_blk))) return rc;
+    if ((rc = block_sort(h, s, reads, offsets, (uint32_t)m, n_blk, maxlen, nullptr, 0, false, &sa,
+                         &gkeys, &gshift)))
+        return rc;
+    HIPCHK(h, launch_vals_to_ascii(sa, n_blk, bint_out, s));
+    HIPCHK(h, launch_sa_strip(sa, n_blk, sa_out, s));
+    HIPCHK(h, hipStreamSynchronize(s));
     return check_err(h, s);
 }
 
