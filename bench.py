@@ -41,6 +41,7 @@ SEG_LEN = 1024                          # library default: reads longer than thi
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "full_size_sha256.json")
 CPU_THREADS_MAX = 16                    # the host share of one GPU on the box
+COPY_BYTES = 1 << 30                    # the calibration copy (--calibrate-copy)
 
 WORKLOADS = {
     # name: (key in the traffic and golden files, default block, description)
@@ -90,6 +91,113 @@ def measured_traffic(workload, kernel):
     if not e or e.get("source_digest") != source_digest(KERNEL_SOURCES[kernel]):
         return None
     return e.get("bytes_per_launch")
+
+
+def _kernel_base(full):
+    """Short kernel name (no return type, namespace, template or arguments)
+    and the name with its template arguments."""
+    s = full.replace("(anonymous namespace)::", "").split("(")[0].strip()
+    if s.startswith("void "):
+        s = s[5:]
+    s = s.replace("bwt::", "")
+    return s.split("<")[0].split("::")[-1].strip(), s
+
+
+def _csv_rows(folder, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(folder, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit("no *%s under %s" % (suffix, folder))
+    return rows
+
+
+def _counter_per_kernel(folder, counter):
+    """{kernel base name: (dispatches, summed counter value)} from one
+    rocprofv3 --pmc run."""
+    acc = {}
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        base, _ = _kernel_base(r["Kernel_Name"])
+        n, v = acc.get(base, (0, 0.0))
+        acc[base] = (n + 1, v + float(r["Counter_Value"]))
+    return acc
+
+
+def summarize_profile(root, workload, command_note):
+    """Turns the rocprofv3 output of one workload into the committed
+    summaries: <key>_kernel_stats.md (kernel trace), <key>_hbm_traffic.md and
+    the workload's entry of profiles/traffic.json (FETCH_SIZE and WRITE_SIZE
+    per dispatch, scaled by what the same counters read for a plain 1 GiB
+    device copy).  root holds the runs' folders: stats/, fetch/, write/,
+    copy_fetch/, copy_write/."""
+    key = WORKLOADS[workload][0]
+    prof = os.path.join(ROOT, "profiles")
+    rows = _csv_rows(os.path.join(root, "stats"), "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel time per kernel, %s" % key, "",
+             "Commands (repository root = `$R` on the GPU box):", "", "```", command_note.strip(),
+             "```", "", "| kernel | calls | total ms | avg us | min us | max us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        _, name = _kernel_base(r["Name"])
+        lines.append("| %s | %d | %.2f | %.1f | %.1f | %.1f | %.1f |" % (
+            name, int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    with open(os.path.join(prof, key + "_kernel_stats.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    fetch = _counter_per_kernel(os.path.join(root, "fetch"), "FETCH_SIZE")
+    write = _counter_per_kernel(os.path.join(root, "write"), "WRITE_SIZE")
+    cf = _counter_per_kernel(os.path.join(root, "copy_fetch"), "FETCH_SIZE")
+    cw = _counter_per_kernel(os.path.join(root, "copy_write"), "WRITE_SIZE")
+    copy = [k for k in cf if "copyBuffer" in k]
+    if not copy or copy[0] not in cw:
+        raise SystemExit("no copy kernel in the calibration runs")
+    n, v = cf[copy[0]]
+    f_scale = COPY_BYTES / (v / n * 1024)          # bytes per counter KiB, reads
+    n, v = cw[copy[0]]
+    w_scale = COPY_BYTES / (v / n * 1024)          # bytes per counter KiB, writes
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        t = {}
+    t = {k: v for k, v in t.items() if isinstance(v, dict) and k in
+         {w[0] for w in WORKLOADS.values()}}
+    entry = {"_note": "HBM bytes per launch, one index build of the workload: FETCH_SIZE x %.3f "
+                      "+ WRITE_SIZE x %.3f (KiB x 1024), the factors being what a plain 1 GiB "
+                      "device copy reads on the same counters" % (f_scale, w_scale)}
+    table = ["# HBM traffic per kernel launch, %s" % key, "",
+             "Commands (repository root = `$R` on the GPU box; each counter in a run of its own):",
+             "", "```", command_note.strip(), "```", "",
+             "Scale: a plain 1 GiB device copy reads FETCH_SIZE x 1024 x %.3f and WRITE_SIZE x "
+             "1024 x %.3f bytes per launch." % (f_scale, w_scale), "",
+             "| kernel | launches | fetch MB/launch | write MB/launch | total MB/launch |",
+             "|---|---:|---:|---:|---:|"]
+    order = sorted(fetch, key=lambda k: -(fetch[k][1] * f_scale +
+                                          write.get(k, (1, 0.0))[1] * w_scale))
+    for k in order:
+        nf, vf = fetch[k]
+        nw, vw = write.get(k, (nf, 0.0))
+        fb = vf / nf * 1024 * f_scale
+        wb = vw / max(nw, 1) * 1024 * w_scale
+        table.append("| %s | %d | %.1f | %.1f | %.1f |" % (k, nf, fb / 1e6, wb / 1e6,
+                                                          (fb + wb) / 1e6))
+        if k in KERNEL_SOURCES:
+            entry[k] = {"launches": nf, "fetch_bytes_per_launch": int(fb),
+                        "write_bytes_per_launch": int(wb), "bytes_per_launch": int(fb + wb),
+                        "source_digest": source_digest(KERNEL_SOURCES[k])}
+    t[key] = entry
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(t, f, indent=1, sort_keys=True)
+        f.write("\n")
+    with open(os.path.join(prof, key + "_hbm_traffic.md"), "w") as f:
+        f.write("\n".join(table) + "\n")
 
 
 def cpu_model():
@@ -354,6 +462,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
+    ap.add_argument("--summarize-profile", metavar="DIR", default=None,
+                    help="no GPU work: write profiles/ summaries for --workload from the "
+                         "rocprofv3 runs under DIR (stats/, fetch/, write/, copy_fetch/, "
+                         "copy_write/)")
+    ap.add_argument("--profile-commands", metavar="FILE", default=None,
+                    help="with --summarize-profile: text file holding the commands that made "
+                         "the runs")
     ap.add_argument("--served", action="store_true",
                     help="served form: 16 tenants, Poisson append requests (p50/p99 latency)")
     ap.add_argument("--requests", type=int, default=512)
@@ -370,6 +485,10 @@ def main():
     ap.add_argument("--set-reads", type=str, default=None,
                     help="batched form: MIN,MAX reads per set (default 1000,2000000)")
     args = ap.parse_args()
+    if args.summarize_profile:
+        note = open(args.profile_commands).read() if args.profile_commands else ""
+        summarize_profile(args.summarize_profile, args.workload, note)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the per-block path runs on a single MI355X "
@@ -391,12 +510,12 @@ def main():
     if args.calibrate_copy:
         # a plain copy of known size: the HBM byte counters read on it give the
         # factor between counter units and bytes moved (1 GiB read + 1 GiB written)
-        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        src = torch.ones(COPY_BYTES, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": 1 << 30, "launches": 3}))
+        print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}))
         return
 
     if args.served:
