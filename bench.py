@@ -36,8 +36,6 @@ TILE_SORT_BYTES_PER_KEY = 25           # the same, plus one tie-flag byte writte
 # Insert per launch: n_ext/4 read + n_out/4 written (2-bit symbols) + n_out/8
 # (occurrence counters at one bit per symbol) + 5 per new symbol (4-byte g_sa,
 # one B_int byte) + 8 per new terminator (its position)
-SEG_LEN = 1024                          # library default: reads longer than this are
-                                        # walked in segments (rank_segments_kernel)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "full_size_sha256.json")
 CPU_THREADS_MAX = 16                    # the host share of one GPU on the box
@@ -249,34 +247,6 @@ def cpu_baseline(packed, offs, sample_bases, golden_key):
     except (OSError, ValueError, KeyError):
         pass
     return out
-
-
-def block_cuts(lens, M):
-    """Blocks of whole reads, cut greedily before the read that would take a
-    block past M suffixes (a read longer than M is a block by itself): the
-    library's rule, repeated here to attribute the LF steps to kernels."""
-    import numpy as np
-    cs = np.zeros(len(lens) + 1, dtype=np.int64)
-    cs[1:] = np.cumsum(lens + 1)
-    cuts = [0]
-    j = 0
-    while j < len(lens):
-        k = int(np.searchsorted(cs, cs[j] + M, side="right")) - 1
-        k = max(k, j + 1)
-        cuts.append(k)
-        j = k
-    return cuts
-
-
-def ranks_split(offs, M):
-    """LF steps per step of the build, as (one-lane-per-read walks, segment
-    walks): every base of every block but the first (which has no index to
-    rank against), split by read length."""
-    import numpy as np
-    lens = np.diff(np.asarray(offs, dtype=np.int64))
-    cuts = block_cuts(lens, M)
-    ranked = lens[cuts[1]:] if len(cuts) > 2 else lens[:0]
-    return int(ranked[ranked <= SEG_LEN].sum()), int(ranked[ranked > SEG_LEN].sum())
 
 
 def run_batched(args, torch, bwtset, synth):
@@ -578,14 +548,17 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
     dt = t1 - t0
     log("timed %d steps in %.3f s" % (steps, dt))
 
-    main_steps, seg_steps = ranks_split(offs, block)
+    # LF steps: every base of every block with an index to rank against; the
+    # library counts those of the reads its segment kernel walked
+    seg_steps = st["ranks_seg_symbols"]
+    main_steps = st["ranks_steps"] - seg_steps
     kernels = {}
     if st["ranks_launches"]:
         kernels["compute_ranks_kernel"] = (st["ranks_kernel_ms"], st["ranks_launches"],
-                                           main_steps * steps * RANKS_BYTES_PER_STEP)
+                                           main_steps * RANKS_BYTES_PER_STEP)
     if st["ranks_seg_launches"] and seg_steps:
         kernels["rank_segments_kernel"] = (st["ranks_seg_ms"], st["ranks_seg_launches"],
-                                           seg_steps * steps * RANKS_BYTES_PER_STEP)
+                                           seg_steps * RANKS_BYTES_PER_STEP)
     if st["sort_pass_launches"]:
         kernels["radix_pass_kernel"] = (st["sort_pass_ms"], st["sort_pass_launches"],
                                         st["sort_pass_keys"] * RADIX_BYTES_PER_KEY)
@@ -638,7 +611,9 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         "ranks_detail_ms_per_step": {
             "read_walks": round(st["ranks_kernel_ms"] / steps, 3),
             "segment_walks": round(st["ranks_seg_ms"] / steps, 3),
-            "fallback_and_counts": round(st["ranks_fb_ms"] / steps, 3)},
+            "fallback_and_counts": round(st["ranks_fb_ms"] / steps, 3),
+            "segment_retries": st["ranks_retries"] / steps,
+            "whole_read_fallbacks": st["ranks_fallback_reads"] / steps},
         "tied_fraction": st["tied_suffixes"] / float(steps * (bases + m)),
         "fallback_blocks_per_step": st["fallback_blocks"] / steps,
         "doubling_rounds_per_step": st["doubling_rounds"] / steps,

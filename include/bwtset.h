@@ -144,8 +144,9 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     search (FM-index interval) BWT_PARAM_RANK_OVERLAP symbols past its end
  *     and continued by Lemma 1 once the interval holds no old suffix; reads
  *     with a longer repeat fall back to one whole walk.  0 = never (256 ..
- *     2^24, default 1024).
- *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 128).
+ *     2^24, default 768).  A segment whose interval is still open at its
+ *     end starts once more with 16 times the overlap (at least 256).
+ *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 64).
  *   BWT_PARAM_BATCH_LANES: blocks of one level of a batch (bwt_set_append_many
  *     on this handle as hs[0]) that run side by side, each on its own stream
  *     and workspace (1 .. 4, default 2).
@@ -255,6 +256,11 @@ typedef struct {
     uint64_t tile_sort_keys;        /* suffixes passed through it */
     uint64_t insert_old_symbols;    /* sum over Insert launches of the index size before it */
     uint64_t insert_terminators;    /* terminators merged in */
+    uint64_t ranks_retries;         /* ComputeRanks segments started again with a longer
+                                       overlap (interval still open at their end) */
+    uint64_t ranks_fallback_reads;  /* reads walked whole after a retry failed too */
+    uint64_t ranks_seg_symbols;     /* symbols of the reads ranked by the segment kernel
+                                       (the others by the one-lane-per-read walks) */
 } bwt_stats_t;
 
 /* Turns per-stage HIP-event timing on (1) or off (0).  Timing adds event

@@ -59,6 +59,9 @@ class Stats(ctypes.Structure):
         ("tile_sort_keys", ctypes.c_uint64),
         ("insert_old_symbols", ctypes.c_uint64),
         ("insert_terminators", ctypes.c_uint64),
+        ("ranks_retries", ctypes.c_uint64),
+        ("ranks_fallback_reads", ctypes.c_uint64),
+        ("ranks_seg_symbols", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

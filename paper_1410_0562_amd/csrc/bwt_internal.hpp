@@ -247,7 +247,13 @@ struct RankSegments {
     uint32_t *fb_flag = nullptr;
     uint32_t *fb_list = nullptr;
     uint32_t *counters = nullptr;
+    uint32_t *stats = nullptr;   // running totals: segment retries, whole-read fallbacks,
+                                 // and (64-bit, words 2-3) symbols ranked by segment walks
 };
+// A segment whose FM-index interval is still open at its end starts again
+// with its overlap times RETRY_FACTOR (at least RETRY_MIN_OVERLAP).
+constexpr uint32_t RETRY_FACTOR = 16;
+constexpr uint32_t RETRY_MIN_OVERLAP = 256;
 // Key mode (kk != null): instead of g, the walks write the first sort key of
 // every block position, g << gshift | its next kfirst symbols << 5 | their
 // count (what launch_block_keys builds), and its sort value (see below).

@@ -81,6 +81,8 @@ constexpr int MISC_SEG = 8;      // 2 words: queued segments, fallback reads
 constexpr int MISC_BK = 10;      // 3 words: tied suffixes, oversized buckets, their suffixes
 constexpr int MISC_NU2 = 13;     // tied suffixes among the oversized buckets
 constexpr int MISC_PILE = 14;    // 2 words: oversized buckets still to sort, their suffixes
+constexpr int MISC_STATS = 16;   // running totals of ComputeRanks: segment retries, fallback
+                                 // reads, then (words 18-19, 64-bit) symbols of queued reads
 constexpr int BK_TABLES = 6;     // bucket starts, ends, tie counts, sizes; oversized list, offsets
 constexpr uint32_t BK_PART = 3 * 4096 + 16;  // tile partials of the bucket scans
 constexpr uint32_t MIN_SEG_LEN = 256;
@@ -138,8 +140,8 @@ struct bwt_set {
     uint64_t M = 1ull << 26;
     int key_bits = 64;               // width of the first suffix-sort key
     int radix_cfg = 3;               // radix pass tile shape (512 threads x 12 keys)
-    uint32_t seg_len = 1024;         // ComputeRanks segment length for long reads
-    uint32_t seg_overlap = 128;      // symbols a segment walk starts past its end
+    uint32_t seg_len = 768;          // ComputeRanks segment length for long reads
+    uint32_t seg_overlap = 64;       // symbols a segment walk starts past its end
     bool sort_buckets = true;        // first sort: top digits + LDS bucket finish
     uint64_t *first_new = nullptr;
     uint64_t first_new_cap = 0;
@@ -270,6 +272,20 @@ struct MarkSet {
 // Called after the stream has been synchronized.
 void timer_collect(bwt_set *h) {
     Timer &T = h->timer;
+    if (h->ws.misc) {
+        // the device's running totals, taken and cleared
+        uint32_t *pw = reinterpret_cast<uint32_t *>(h->pinned);
+        if (hipMemcpyAsync(pw, h->ws.misc + MISC_STATS, 16, hipMemcpyDeviceToHost, h->stream) ==
+                hipSuccess &&
+            hipMemsetAsync(h->ws.misc + MISC_STATS, 0, 16, h->stream) == hipSuccess &&
+            hipStreamSynchronize(h->stream) == hipSuccess) {
+            T.acc.ranks_retries += pw[0];
+            T.acc.ranks_fallback_reads += pw[1];
+            T.acc.ranks_seg_symbols += (uint64_t)pw[2] | (uint64_t)pw[3] << 32;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     for (auto &sp : T.open) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) {
@@ -513,6 +529,7 @@ RankSegments rank_segments(bwt_set *h, uint64_t maxlen) {
     sg.fb_flag = w.fb_flag;
     sg.fb_list = w.fb_list;
     sg.counters = w.misc + MISC_SEG;
+    sg.stats = w.misc + MISC_STATS;
     return sg;
 }
 
@@ -1043,6 +1060,9 @@ void stats_add(bwt_stats_t &a, const bwt_stats_t &b) {
     a.tile_sort_keys += b.tile_sort_keys;
     a.insert_old_symbols += b.insert_old_symbols;
     a.insert_terminators += b.insert_terminators;
+    a.ranks_retries += b.ranks_retries;
+    a.ranks_fallback_reads += b.ranks_fallback_reads;
+    a.ranks_seg_symbols += b.ranks_seg_symbols;
 }
 
 template <class T>
@@ -2050,6 +2070,13 @@ int bwt_set_insert(bwt_set_t h, const uint8_t *bint, const uint64_t *gsa, uint64
 
 int bwt_set_enable_timing(bwt_set_t h, int on) {
     if (!h) return BWT_EINVAL;
+    if (on && !h->timer.on && h->ws.misc) {
+        // the device's running totals restart with the timing
+        int rc = set_device(h);
+        if (rc) return rc;
+        HIPCHK(h, hipMemsetAsync(h->ws.misc + MISC_STATS, 0, 16, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
     h->timer.on = on != 0;
     return BWT_OK;
 }

@@ -16,9 +16,13 @@
 // far, starting from all rows.  Once no old suffix has that prefix (lo ==
 // hi), lo is exactly the number of old suffixes smaller than the new suffix,
 // and the walk continues as Lemma 1's single rank.  A segment whose interval
-// has not closed by the time it reaches b (a repeat longer than ov) hands its
-// read to a last kernel that walks the whole read from its end, so the result
-// is exact in every case.
+// has not closed by the time it reaches b (a repeat longer than ov) starts
+// once more from further out; if that fails too, it hands its read to a last
+// kernel that walks the whole read from its end, so the result is exact in
+// every case.  When the queue has room, the short reads of a block with long
+// ones are queued as one segment each, so that every walk of the block runs
+// in the one launch (a walk takes as long as its dependent steps, so a lane
+// walking a read alone while the segments wait would add its whole length).
 #include "dev_util.hpp"
 
 namespace bwt {
@@ -234,7 +238,10 @@ __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t
 }
 
 // One lane per read.  Reads longer than `seg` symbols (seg > 0) are cut into
-// segments that are queued for rank_segments_kernel instead.
+// segments that are queued for rank_segments_kernel instead; with queue_all,
+// every read is queued (a short read as one segment, which that kernel walks
+// exactly from its terminator), so that no lane walks a read here while the
+// segments wait for this launch to end.
 // In key mode with o.hist set, the digit counts of the keys of the walked
 // reads are gathered in LDS and added once per workgroup to one of the
 // HIST_COPIES copies (the keys of queued reads are counted by
@@ -243,8 +250,8 @@ template <class Src, bool KEYS>
 __global__ __launch_bounds__(256) void compute_ranks_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, Out o, uint32_t seg,
-    uint64_t *__restrict__ seg_list, uint32_t *__restrict__ seg_count, uint32_t seg_cap,
-    uint32_t *__restrict__ err) {
+    bool queue_all, uint64_t *__restrict__ seg_list, uint32_t *__restrict__ seg_count,
+    uint32_t seg_cap, unsigned long long *__restrict__ seg_syms, uint32_t *__restrict__ err) {
     __shared__ uint32_t s_h[KEYS ? 256 : 1];
     const uint32_t tid = threadIdx.x;
     const bool count = KEYS && o.hist != nullptr;
@@ -256,9 +263,10 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
     if (j < m_blk) {
         const uint64_t s0 = off[j];
         const uint32_t len = (uint32_t)(off[j + 1] - s0);
-        if (seg > 0 && len > seg) {
-            const uint32_t nseg = (len + seg - 1) / seg;
+        if (seg > 0 && (len > seg || queue_all)) {
+            const uint32_t nseg = len > seg ? (len + seg - 1) / seg : 1u;
             const uint32_t at = atomicAdd(seg_count, nseg);
+            if (len) atomicAdd(seg_syms, (unsigned long long)len);
             if (at + nseg > seg_cap) {
                 atomicOr(err, 128u);
             } else {
@@ -296,7 +304,7 @@ __global__ __launch_bounds__(256) void count_long_keys_kernel(
         const uint32_t len = (uint32_t)(off[j + 1] - off[j]);
         const uint64_t gb = soff[j];
         const uint32_t a = sg * seg;
-        if (a >= len) continue;
+        if (sg > 0 && a >= len) continue;  // (an empty read is queued as segment 0)
         const uint32_t b = a + seg < len ? a + seg : len;
         const uint32_t cnt = b - a + (b == len ? 1u : 0u);  // positions gb + a ...
         for (uint32_t q = tid; q < cnt; q += 256)
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
     const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, Out o, uint32_t seg, uint32_t ov,
     const uint64_t *__restrict__ seg_list, const uint32_t *__restrict__ seg_count,
     uint32_t *__restrict__ fb_flag, uint32_t *__restrict__ fb_list,
-    uint32_t *__restrict__ fb_count, uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ fb_count, uint32_t *__restrict__ stats, uint32_t *__restrict__ err) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *seg_count) return;
     const uint64_t e_js = seg_list[t];
@@ -326,7 +334,7 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
     const uint64_t s0 = off[j];
     const uint32_t len = (uint32_t)(off[j + 1] - s0);
     const uint64_t gb = soff[j];
-    if ((uint64_t)s * seg >= len) {
+    if (s > 0 && (uint64_t)s * seg >= len) {  // (an empty read is queued as segment 0)
         atomicOr(err, 128u);
         return;
     }
@@ -334,60 +342,81 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
     const LF &lf = W.lf;
     const uint32_t a = s * seg;
     const uint32_t b = a + seg < len ? a + seg : len;
-    const uint32_t e = b + ov < len ? b + ov : len;
     uint64_t *dst = KEYS ? o.keys : o.g;
     SymReader sym{reads, 0, 0};
     GBuf buf;
     buf.cnt = 0;
     VBuf vb;
     vb.cnt = 0;
-    uint64_t win = 0;
     const int top = 2 * (o.kfirst - 1);
-    if (KEYS && o.kfirst > 0) {
-        // the symbols a key of [a, b) needs beyond the walk's start
-        const uint32_t need = b + (uint32_t)o.kfirst < len ? b + (uint32_t)o.kfirst : len;
-        for (uint32_t q = need; q > e;) {
-            --q;
-            win = (win >> 2) | ((uint64_t)sym.get(s0 + q) << top);
-        }
-    }
-    uint64_t lo, hi;
-    if (e == len) {
-        lo = hi = lf.m_ext;  // exact start at the terminator suffix
-        if (b == len) {
-            buf.push(KEYS ? (lo + W.goff) << o.gshift : lo + W.goff);
-            if (((gb + len) & 7) == 0) buf.flush(dst, gb + len, o.vec);
-        }
-    } else {
-        lo = 0;             // the empty prefix: every row of B_ext
-        hi = lf.n_ext;
-    }
-    uint32_t k = e;
-    while (k > a) {
-        --k;
-        const int c = sym.get(s0 + k);
-        const uint64_t nlo = lf.step(W.recs, W.sbc, lo, c);
-        hi = (lo == hi) ? nlo : lf.step(W.recs, W.sbc, hi, c);
-        lo = nlo;
-        if (KEYS && o.kfirst > 0) win = (win >> 2) | ((uint64_t)c << top);
-        if (k < b) {
-            if (lo != hi) {
-                // a repeat longer than ov: the whole read is walked exactly
-                if (atomicExch(&fb_flag[j], 1u) == 0u) fb_list[atomicAdd(fb_count, 1u)] = j;
-                return;
+    // First attempt with overlap ov; a segment whose interval is still open at
+    // b (a repeat longer than ov) starts once more, RETRY_FACTOR times further
+    // out, before its read is handed to the whole-read walk.  Nothing of the
+    // segment has been written when the interval is found open (that happens
+    // at its first position), so a restart only resets the walk.
+    uint32_t ovs = ov;
+    for (int attempt = 0;; ++attempt) {
+        const uint32_t e = len - b > ovs ? b + ovs : len;
+        uint64_t win = 0;
+        if (KEYS && o.kfirst > 0) {
+            // the symbols a key of [a, b) needs beyond the walk's start
+            const uint32_t need = b + (uint32_t)o.kfirst < len ? b + (uint32_t)o.kfirst : len;
+            for (uint32_t q = need; q > e;) {
+                --q;
+                win = (win >> 2) | ((uint64_t)sym.get(s0 + q) << top);
             }
-            if constexpr (KEYS) {
-                if (k + 1 < b || k + 1 == len) {
-                    vb.push((uint32_t)(gb + k + 1) | ((uint32_t)c << POS_BITS));
-                    if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
+        }
+        uint64_t lo, hi;
+        if (e == len) {
+            lo = hi = lf.m_ext;  // exact start at the terminator suffix
+            if (b == len) {
+                buf.push(KEYS ? (lo + W.goff) << o.gshift : lo + W.goff);
+                if (((gb + len) & 7) == 0) buf.flush(dst, gb + len, o.vec);
+            }
+        } else {
+            lo = 0;             // the empty prefix: every row of B_ext
+            hi = lf.n_ext;
+        }
+        bool open = false;
+        uint32_t k = e;
+        while (k > a) {
+            --k;
+            const int c = sym.get(s0 + k);
+            const uint64_t nlo = lf.step(W.recs, W.sbc, lo, c);
+            hi = (lo == hi) ? nlo : lf.step(W.recs, W.sbc, hi, c);
+            lo = nlo;
+            if (KEYS && o.kfirst > 0) win = (win >> 2) | ((uint64_t)c << top);
+            if (k < b) {
+                if (lo != hi) {
+                    open = true;
+                    break;
                 }
-                const uint32_t tt = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
-                buf.push(((lo + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | tt);
-            } else {
-                buf.push(lo + W.goff);
+                if constexpr (KEYS) {
+                    if (k + 1 < b || k + 1 == len) {
+                        vb.push((uint32_t)(gb + k + 1) | ((uint32_t)c << POS_BITS));
+                        if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
+                    }
+                    const uint32_t tt = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
+                    buf.push(((lo + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | tt);
+                } else {
+                    buf.push(lo + W.goff);
+                }
+                if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
             }
-            if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
         }
+        if (!open) break;
+        if (attempt > 0 || e == len) {
+            // a repeat longer than the retry's overlap: the whole read is
+            // walked exactly
+            if (atomicExch(&fb_flag[j], 1u) == 0u) {
+                fb_list[atomicAdd(fb_count, 1u)] = j;
+                atomicAdd(stats + 1, 1u);
+            }
+            return;
+        }
+        ovs = ov < RETRY_MIN_OVERLAP / RETRY_FACTOR ? RETRY_MIN_OVERLAP
+              : ov > (1u << 24) ? (1u << 28) : ov * RETRY_FACTOR;
+        atomicAdd(stats, 1u);
     }
     buf.flush(dst, gb + a, false);
     if constexpr (KEYS) {
@@ -423,9 +452,17 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
                          const RankSegments &sg, uint32_t *err, hipStream_t s, const Marks *mk) {
     uint32_t seg = sg.seg_len;
     uint32_t cap = 0;
+    bool queue_all = false;
     if (seg > 0) {
         cap = (uint32_t)(2 * div_up(n_blk, seg) + 2);
-        if (cap > sg.seg_cap) seg = 0;  // no room to queue segments: whole-read walks
+        // every read in the queue when it has room (a segment per short read)
+        const uint64_t all = (uint64_t)m_blk + div_up(n_blk, seg) + 2;
+        if (all <= sg.seg_cap) {
+            queue_all = true;
+            cap = (uint32_t)all;
+        } else if (cap > sg.seg_cap) {
+            seg = 0;  // no room to queue segments: whole-read walks
+        }
     }
     if (seg > 0) {
         zero_kernel<<<1, 64, 0, s>>>(sg.counters, 2);
@@ -433,13 +470,14 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
     }
     Marks::begin(mk, 0, s);
     compute_ranks_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
-        reads, off, soff, m_blk, src, o, seg, sg.seg_list, sg.counters, cap, err);
+        reads, off, soff, m_blk, src, o, seg, queue_all, sg.seg_list, sg.counters, cap,
+        reinterpret_cast<unsigned long long *>(sg.stats + 2), err);
     Marks::end(mk, 0, s);
     Marks::begin(mk, 1, s);
     if (seg > 0)
         rank_segments_kernel<Src, KEYS><<<(unsigned)div_up(cap, 256), 256, 0, s>>>(
             reads, off, soff, m_blk, src, o, seg, sg.overlap, sg.seg_list, sg.counters, sg.fb_flag,
-            sg.fb_list, sg.counters + 1, err);
+            sg.fb_list, sg.counters + 1, sg.stats, err);
     Marks::end(mk, 1, s);
     Marks::begin(mk, 2, s);
     if (seg > 0) {

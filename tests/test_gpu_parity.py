@@ -453,6 +453,69 @@ def test_segmented_compute_ranks(B, torch_dev, oracle_mod, seg, ov):
         assert idx.export() == oracle_mod.bwt_of_codes(*_oracle_inputs(oracle_mod, packed, offs))
 
 
+@pytest.mark.parametrize("seg,ov,exact_copies", [(256, 16, False), (512, 8, True),
+                                                  (300, 0, True)])
+def test_segment_retry_and_fallback(B, torch_dev, oracle_mod, seg, ov, exact_copies):
+    """Segments whose FM-index interval is still open at their end start
+    again with a 16x longer overlap (at least 256); a read with a repeat
+    longer than that (an exact copy of an old string) is walked whole.  Noisy
+    copies of one region (5% substitutions) make the first attempts of short
+    overlaps fail; the ranks are exact either way, and the statistics show
+    that both paths ran."""
+    torch = torch_dev
+    rng = np.random.default_rng(57)
+    ref = rng.integers(0, 4, 20_000, dtype=np.uint8)
+
+    def noisy(n):
+        out = []
+        for _ in range(n):
+            a = int(rng.integers(0, 15_000))
+            r = ref[a:a + int(rng.integers(600, 5000))].copy()
+            hit = rng.random(len(r)) < 0.05
+            r[hit] = (r[hit] + 1) & 3
+            out.append(r)
+        return out
+
+    old = noisy(40)
+    new = noisy(30)
+    if exact_copies:
+        new += [old[k][100:100 + 2500].copy() for k in range(3) if len(old[k]) > 2700]
+        new += [rng.integers(0, 4, int(rng.integers(0, 50)), dtype=np.uint8) for _ in range(20)]
+
+    def pack(rs):
+        codes = np.concatenate(rs)
+        offs = np.zeros(len(rs) + 1, np.uint64)
+        offs[1:] = np.cumsum([len(x) for x in rs])
+        return synth.pack_codes(codes), offs
+
+    pa, oa = pack(old)
+    pb, ob = pack(new)
+    ca, oa2 = _oracle_inputs(oracle_mod, pa, oa)
+    T_old, _ = oracle_mod.concat_text(ca, oa2)
+    cb, ob2 = _oracle_inputs(oracle_mod, pb, ob)
+    T, _ = oracle_mod.concat_text(cb, ob2)
+    want = oracle_mod.compute_ranks(T_old, T)
+    g = torch.empty(len(T), dtype=torch.int64, device="cuda")
+    with B.BwtSet() as idx:
+        idx.set_param(B.BWT_PARAM_RANK_SEGMENT, seg)
+        idx.set_param(B.BWT_PARAM_RANK_OVERLAP, ov)
+        idx.append(pa, oa)
+        idx.enable_timing(True)
+        idx.stats(reset=True)
+        idx.compute_ranks(pb, ob, g)
+        st = idx.stats(reset=True)
+        assert np.array_equal(g.cpu().numpy().astype(np.uint64), want)
+        assert st["ranks_retries"] > 0
+        if exact_copies:
+            assert st["ranks_fallback_reads"] >= 1
+        # every base of the new reads was ranked by the segment kernel (all
+        # reads fit the queue)
+        assert st["ranks_seg_symbols"] == int(ob[-1])
+        idx.append(pb, ob)
+        allc = pack(old + new)
+        assert idx.export() == oracle_mod.bwt_of_codes(*_oracle_inputs(oracle_mod, *allc))
+
+
 @pytest.mark.parametrize("buckets", [0, 1])
 def test_sort_modes_agree(B, torch_dev, oracle_mod, buckets):
     """The first sort either runs radix passes over the whole key, or only
