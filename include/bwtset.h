@@ -71,6 +71,25 @@ void bwt_set_destroy(bwt_set_t h);
 int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
                    uint64_t m, void *stream);
 
+/* Strand variants of an append (Section 2 notes that the strings may also be
+ * indexed reversed):
+ *   BWT_STRAND_FORWARD: the same as bwt_set_append;
+ *   BWT_STRAND_REVERSE: every read is indexed written backwards (m strings,
+ *     in input order);
+ *   BWT_STRAND_BOTH: every read is followed by its reverse complement (read
+ *     backwards with A<->T, C<->G), 2m strings: string 2j is read j and
+ *     2j + 1 its reverse complement, so every pattern then occurs as often as
+ *     its reverse complement.
+ * reads/offsets as for bwt_set_append (host or device; offsets checked
+ * before any symbol is read).  The repacked reads are staged on the device
+ * (held by the handle until bwt_set_trim) and appended as one call, so the
+ * index is the BWT of the concatenation of all strings appended so far with
+ * these in the stated order.  Returns BWT_OK or a negative code (BWT_EINVAL
+ * for another mode); on error the index is unchanged. */
+enum { BWT_STRAND_FORWARD = 0, BWT_STRAND_REVERSE = 1, BWT_STRAND_BOTH = 2 };
+int bwt_set_append_strands(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
+                           uint64_t m, int mode, void *stream);
+
 /* Batched form: appends reads[i]/offsets[i] (m[i] strings) to hs[i] for every
  * i < count, with the same result on each handle as bwt_set_append.  The sets
  * are cut into blocks as bwt_set_append cuts them (Algorithm 1), and blocks of
@@ -99,6 +118,20 @@ uint64_t bwt_set_rank(bwt_set_t h, char c, uint64_t k);
  * its slot.  Enqueued on `stream`; returns without waiting. */
 int bwt_set_rank_many(bwt_set_t h, const uint8_t *cs, const uint64_t *ks,
                       uint64_t *out, uint64_t count, void *stream);
+
+/* FM-index count by backward search (the BWT with its rank function, Eq. 2,
+ * is an FM-index; Lemma 1's step C[c] + rank(c, i, B) applied to both ends of
+ * the interval of rows whose suffixes start with the symbols read so far,
+ * from the pattern's last symbol to its first).  Pattern q < count is symbols
+ * [offsets[q], offsets[q+1]) of pats, 2-bit packed as the reads are.  On
+ * completion lo_out[q] is the number of suffixes smaller than the pattern
+ * (terminators before A) and hi_out[q] - lo_out[q] the number of its
+ * occurrences in the strings; the empty pattern gives [0, n).  pats, offsets,
+ * lo_out, hi_out: device pointers.  A pattern whose offsets decrease yields
+ * UINT64_MAX in both slots.  Enqueued on `stream`; returns without waiting;
+ * the index must not change until the work has finished. */
+int bwt_set_count_many(bwt_set_t h, const uint8_t *pats, const uint64_t *offsets,
+                       uint64_t count, uint64_t *lo_out, uint64_t *hi_out, void *stream);
 
 /* Writes B as n ASCII bytes ('A','C','G','T','$') to out (host or device).
  * out == NULL: returns n without writing (length query).  Returns n or a

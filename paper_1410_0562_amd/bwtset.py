@@ -82,8 +82,11 @@ EXPORTED = [
     "bwt_set_block_sort", "bwt_set_compute_ranks", "bwt_set_insert",
     "bwt_set_enable_timing", "bwt_set_get_stats", "bwt_set_set_param",
     "bwt_set_import", "bwt_set_memory", "bwt_set_trim", "bwt_set_append_many",
-    "bwt_set_block_sort_noalloc",
+    "bwt_set_block_sort_noalloc", "bwt_set_count_many", "bwt_set_append_strands",
 ]
+BWT_STRAND_FORWARD = 0
+BWT_STRAND_REVERSE = 1
+BWT_STRAND_BOTH = 2
 BWT_PARAM_KEY_BITS = 1
 BWT_PARAM_RADIX_TILE = 2
 BWT_PARAM_RANK_SEGMENT = 3
@@ -130,6 +133,10 @@ def load(path: str = LIB_PATH):
     L.bwt_set_block_sort.restype = i32
     L.bwt_set_block_sort_noalloc.argtypes = [vp, vp, vp, u64, vp, vp, vp]
     L.bwt_set_block_sort_noalloc.restype = i32
+    L.bwt_set_count_many.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+    L.bwt_set_count_many.restype = i32
+    L.bwt_set_append_strands.argtypes = [vp, vp, vp, u64, i32, vp]
+    L.bwt_set_append_strands.restype = i32
     L.bwt_set_compute_ranks.argtypes = [vp, vp, vp, u64, vp, vp]
     L.bwt_set_compute_ranks.restype = i32
     L.bwt_set_insert.argtypes = [vp, vp, vp, u64, vp]
@@ -258,6 +265,18 @@ class BwtSet:
         self._check(load().bwt_set_append(self._h, _ptr(reads), _ptr(offsets), m, _stream(stream)),
                     "bwt_set_append")
 
+    def append_strands(self, reads, offsets, mode: int, stream=None) -> None:
+        """Append the reads reversed (BWT_STRAND_REVERSE) or each followed by
+        its reverse complement (BWT_STRAND_BOTH)."""
+        reads = _as_reads(reads)
+        offsets = _as_offsets(offsets)
+        m = _len(offsets) - 1
+        if m <= 0:
+            return
+        self._check(load().bwt_set_append_strands(self._h, _ptr(reads), _ptr(offsets), m,
+                                                  int(mode), _stream(stream)),
+                    "bwt_set_append_strands")
+
     def rank(self, c: str, k: int) -> int:
         r = load().bwt_set_rank(self._h, c.encode("ascii"), int(k))
         if r == U64_MAX:
@@ -268,6 +287,14 @@ class BwtSet:
         """Device tensors: cs uint8 (ASCII), ks int64, out int64 (same length)."""
         self._check(load().bwt_set_rank_many(self._h, _ptr(cs), _ptr(ks), _ptr(out), _len(ks),
                                              _stream(stream)), "bwt_set_rank_many")
+
+    def count_many(self, pats, offsets, lo_out, hi_out, stream=None) -> None:
+        """FM-index count: device tensors pats (2-bit packed uint8), offsets
+        (int64, count + 1), lo_out / hi_out (int64, count)."""
+        offsets = _as_offsets(offsets)
+        self._check(load().bwt_set_count_many(self._h, _ptr(pats), _ptr(offsets),
+                                              _len(offsets) - 1, _ptr(lo_out), _ptr(hi_out),
+                                              _stream(stream)), "bwt_set_count_many")
 
     def size(self) -> tuple:
         n, m = ctypes.c_uint64(), ctypes.c_uint64()

@@ -382,6 +382,17 @@ hipError_t launch_rank_many(const Rec *recs, const uint64_t *sbc, const uint64_t
                             const uint8_t *cs, const uint64_t *ks, uint64_t *out, uint64_t count,
                             hipStream_t s);
 hipError_t launch_export(const Rec *recs, uint64_t n, uint8_t *out, hipStream_t s);
+// strand variants: mode 1 every read reversed, mode 2 every read followed by
+// its reverse complement; out_off gets m (mode 1) or 2m (mode 2) + 1 offsets
+// from 0, out the packed symbols (total of them, 4-byte aligned buffer);
+// input symbol p is at p - in_base of `in`; offsets must be non-decreasing
+hipError_t launch_strands(const uint8_t *in, uint64_t in_base, const uint64_t *off, uint64_t m,
+                          int mode, uint64_t *out_off, uint64_t total, uint8_t *out,
+                          hipStream_t s);
+// FM-index count: lo/hi per pattern (2-bit packed pats, count + 1 offsets)
+hipError_t launch_count(const Rec *recs, const uint64_t *sbc, const uint64_t *meta,
+                        const uint8_t *pats, const uint64_t *poff, uint64_t count,
+                        uint64_t *lo, uint64_t *hi, hipStream_t s);
 hipError_t launch_check_offsets(const uint64_t *off, uint64_t m, uint64_t *res, hipStream_t s);
 hipError_t launch_plan_blocks(const uint64_t *off, uint64_t m, uint64_t M, uint64_t *cuts,
                               uint64_t *res, hipStream_t s);

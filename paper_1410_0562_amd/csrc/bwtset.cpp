@@ -154,6 +154,11 @@ struct bwt_set {
     uint64_t cuts_cap = 0;
     uint8_t *stage_out = nullptr;
     uint64_t stage_out_cap = 0;
+    // strand variants: the repacked reads and their offsets
+    uint8_t *strand_reads = nullptr;
+    uint64_t strand_reads_cap = 0;
+    uint64_t *strand_off = nullptr;
+    uint64_t strand_off_cap = 0;
     // batched form (when this handle drives a batch): device tables, staged
     // host inputs
     uint8_t *btab = nullptr;
@@ -1549,6 +1554,8 @@ void bwt_set_destroy(bwt_set_t h) {
     dfree(h->stage_off);
     dfree(h->cuts);
     dfree(h->stage_out);
+    dfree(h->strand_reads);
+    dfree(h->strand_off);
     dfree(h->btab);
     dfree(h->bstage);
     for (auto *l : h->lanes) bwt_set_destroy(l);
@@ -1715,6 +1722,77 @@ int bwt_set_rank_many(bwt_set_t h, const uint8_t *cs, const uint64_t *ks, uint64
     return BWT_OK;
 }
 
+int bwt_set_append_strands(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets,
+                           uint64_t m, int mode, void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (mode == BWT_STRAND_FORWARD) return bwt_set_append(h, reads, offsets, m, stream);
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (mode != BWT_STRAND_REVERSE && mode != BWT_STRAND_BOTH) return fail(h, BWT_EINVAL);
+    if (m == 0) return BWT_OK;
+    if (!reads || !offsets) return fail(h, BWT_EINVAL);
+    if (m > (1ull << 40)) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    // the input on the device, its offsets checked before anything reads
+    // symbols through them
+    const bool off_dev = is_device_ptr(offsets), reads_dev = is_device_ptr(reads);
+    const uint64_t *doff = offsets;
+    uint64_t first = 0, last = 0;
+    if (!off_dev) {
+        for (uint64_t j = 0; j < m; ++j)
+            if (offsets[j + 1] < offsets[j]) return fail(h, BWT_EINVAL);
+        first = offsets[0];
+        last = offsets[m];
+        if ((rc = ensure_buf(h, h->stage_off, h->stage_off_cap, m + 1))) return rc;
+        HIPCHK(h, hipMemcpyAsync(h->stage_off, offsets, (m + 1) * 8, hipMemcpyHostToDevice, s));
+        doff = h->stage_off;
+    } else {
+        HIPCHK(h, launch_check_offsets(offsets, m, h->res, s));
+        HIPCHK(h, hipMemcpyAsync(h->pinned, h->res, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(h->pinned + 1, offsets, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(h->pinned + 2, offsets + m, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->pinned[0]) return fail(h, BWT_EINVAL);
+        first = h->pinned[1];
+        last = h->pinned[2];
+    }
+    const uint64_t syms = last - first;
+    const uint8_t *din = reads;
+    uint64_t in_base = 0;
+    if (!reads_dev) {
+        in_base = first & ~3ull;
+        const uint64_t nbytes = (last + 3) / 4 - in_base / 4;
+        if ((rc = ensure_buf(h, h->stage_reads, h->stage_reads_cap, nbytes + 16))) return rc;
+        HIPCHK(h, hipMemcpyAsync(h->stage_reads, reads + in_base / 4, nbytes,
+                                 hipMemcpyHostToDevice, s));
+        din = h->stage_reads;
+    }
+    const uint64_t total = mode == BWT_STRAND_BOTH ? 2 * syms : syms;
+    const uint64_t mo = mode == BWT_STRAND_BOTH ? 2 * m : m;
+    if ((rc = ensure_buf(h, h->strand_reads, h->strand_reads_cap, div_up(total, 16) * 4 + 16)))
+        return rc;
+    if ((rc = ensure_buf(h, h->strand_off, h->strand_off_cap, mo + 1))) return rc;
+    HIPCHK(h, launch_strands(din, in_base, doff, m, mode, h->strand_off, total, h->strand_reads, s));
+    // the staged copies are complete before the append plans on its own
+    HIPCHK(h, hipStreamSynchronize(s));
+    return bwt_set_append(h, h->strand_reads, h->strand_off, mo, stream);
+}
+
+int bwt_set_count_many(bwt_set_t h, const uint8_t *pats, const uint64_t *offsets,
+                       uint64_t count, uint64_t *lo_out, uint64_t *hi_out, void *stream) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (count == 0) return BWT_OK;
+    if (!pats || !offsets || !lo_out || !hi_out) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    IndexBuf &B = h->buf[h->cur];
+    HIPCHK(h, launch_count(B.recs, B.sbc, B.meta, pats, offsets, count, lo_out, hi_out, s));
+    return BWT_OK;
+}
+
 int64_t bwt_set_export(bwt_set_t h, uint8_t *out) {
     if (!h) return BWT_EINVAL;
     if (h->broken) return fail(h, BWT_ESTATE);
@@ -1800,7 +1878,8 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
     const Workspace &w = h->ws;
     if (w.region) b += w.bytes;
     b += h->first_new_cap * 8 + h->stage_reads_cap + h->stage_off_cap * 8 + h->cuts_cap * 8 +
-         h->stage_out_cap + h->btab_cap + h->bstage_cap;
+         h->stage_out_cap + h->btab_cap + h->bstage_cap + h->strand_reads_cap +
+         h->strand_off_cap * 8;
     for (auto *l : h->lanes) {
         uint64_t lb = 0;
         if (bwt_set_memory(l, &lb) == BWT_OK) b += lb;
@@ -1831,6 +1910,10 @@ int bwt_set_trim(bwt_set_t h) {
     h->cuts_cap = 0;
     dfree(h->stage_out);
     h->stage_out_cap = 0;
+    dfree(h->strand_reads);
+    h->strand_reads_cap = 0;
+    dfree(h->strand_off);
+    h->strand_off_cap = 0;
     dfree(h->btab);
     h->btab_cap = 0;
     dfree(h->bstage);

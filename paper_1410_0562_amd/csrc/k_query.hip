@@ -30,6 +30,40 @@ __global__ void rank_many_kernel(const Rec *__restrict__ recs, const uint64_t *_
     out[t] = r;
 }
 
+// FM-index count by backward search: Lemma 1's step C[c] + rank(c, i) taken
+// at both ends of the interval of rows whose suffixes start with the symbols
+// read so far (Section 2: the BWT and its rank function, Eq. 2, form an
+// FM-index).  Pattern t is symbols [poff[t], poff[t+1]) of the 2-bit packed
+// pats, read from its last symbol; the interval starts as all n rows.  On
+// return [lo, hi) are the rows whose suffix starts with the pattern: hi - lo
+// occurrences, lo suffixes smaller than the pattern.  Once the interval is
+// empty its ends move together, so one rank per step is enough.
+__global__ void count_kernel(const Rec *__restrict__ recs, const uint64_t *__restrict__ sbc,
+                             const uint64_t *__restrict__ meta, const uint8_t *__restrict__ pats,
+                             const uint64_t *__restrict__ poff, uint64_t count,
+                             uint64_t *__restrict__ lo_out, uint64_t *__restrict__ hi_out) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const uint64_t a = poff[t], b = poff[t + 1];
+    if (b < a) {
+        lo_out[t] = hi_out[t] = ~0ull;
+        return;
+    }
+    const uint64_t C0 = meta[5];            // every terminator sorts before A
+    const uint64_t C1 = C0 + meta[0], C2 = C1 + meta[1], C3 = C2 + meta[2];
+    uint64_t lo = 0, hi = meta[4];
+    for (uint64_t k = b; k > a;) {
+        --k;
+        const int c = load_sym(pats, k);
+        const uint64_t Cc = c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : C3;
+        const uint64_t nlo = Cc + rank_base(recs, sbc, lo, c, true);
+        hi = lo == hi ? nlo : Cc + rank_base(recs, sbc, hi, c, true);
+        lo = nlo;
+    }
+    lo_out[t] = lo;
+    hi_out[t] = hi;
+}
+
 // A bounded grid strides over the rows, so indices of 2^32 symbols and more
 // (beyond one launch's 32-bit work-item count) are covered.
 __global__ void export_kernel(const Rec *__restrict__ recs, uint64_t n, uint8_t *__restrict__ out) {
@@ -222,7 +256,72 @@ __global__ void gather_reads_kernel(const GatherUnit *__restrict__ units, uint32
     dst[w] = word;
 }
 
+// Strand variants of an input (Section 2 notes that the strings may also be
+// indexed reversed).  mode 1: every read written backwards; mode 2: every
+// read followed by its reverse complement (read backwards, code x -> 3 - x),
+// so output string 2j is read j and 2j + 1 its reverse complement.  Output
+// offsets start at 0; input symbol p is at p - in_base of `in`.
+__global__ void strand_offsets_kernel(const uint64_t *__restrict__ off, uint64_t m, int mode,
+                                      uint64_t *__restrict__ out_off) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > m) return;
+    const uint64_t x = off[j] - off[0];
+    if (mode == 2) {
+        out_off[2 * j] = 2 * x;
+        if (j < m) out_off[2 * j + 1] = 2 * x + (off[j + 1] - off[j]);
+    } else {
+        out_off[j] = x;
+    }
+}
+
+// one thread per 16 output symbols (one 32-bit word of the packed output)
+__global__ void strand_pack_kernel(const uint8_t *__restrict__ in, uint64_t in_base,
+                                   const uint64_t *__restrict__ off, int mode,
+                                   const uint64_t *__restrict__ out_off, uint64_t mo,
+                                   uint64_t total, uint32_t *__restrict__ dst) {
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t q0 = w * 16;
+    if (q0 >= total) return;
+    // the last output string starting at or before q0
+    uint64_t lo = 0, hi = mo - 1;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (out_off[mid] <= q0) lo = mid;
+        else hi = mid - 1;
+    }
+    uint64_t r = lo;
+    uint32_t word = 0;
+    for (int k = 0; k < 16; ++k) {
+        const uint64_t q = q0 + k;
+        if (q >= total) break;
+        while (q >= out_off[r + 1]) ++r;  // later strings (skipping empty ones)
+        const uint64_t j = mode == 2 ? r >> 1 : r;
+        const bool rc = mode == 2 && (r & 1);
+        const bool rev = mode == 1 || rc;
+        const uint64_t a = off[j], len = off[j + 1] - a, t = q - out_off[r];
+        const uint64_t p = (rev ? a + len - 1 - t : a + t) - in_base;
+        uint32_t c = (in[p >> 2] >> (2 * (p & 3))) & 3u;
+        if (rc) c = 3u - c;
+        word |= c << (2 * k);
+    }
+    dst[w] = word;
+}
+
 }  // namespace
+
+hipError_t launch_strands(const uint8_t *in, uint64_t in_base, const uint64_t *off, uint64_t m,
+                          int mode, uint64_t *out_off, uint64_t total, uint8_t *out,
+                          hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    strand_offsets_kernel<<<(unsigned)div_up(m + 1, 256), 256, 0, s>>>(off, m, mode, out_off);
+    const uint64_t mo = mode == 2 ? 2 * m : m;
+    if (total > 0) {
+        const uint64_t words = div_up(total, 16);
+        strand_pack_kernel<<<(unsigned)div_up(words, 256), 256, 0, s>>>(
+            in, in_base, off, mode, out_off, mo, total, reinterpret_cast<uint32_t *>(out));
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_rank_many(const Rec *recs, const uint64_t *sbc, const uint64_t *meta,
                             const uint8_t *cs, const uint64_t *ks, uint64_t *out, uint64_t count,
@@ -233,8 +332,16 @@ hipError_t launch_rank_many(const Rec *recs, const uint64_t *sbc, const uint64_t
     return hipGetLastError();
 }
 
+hipError_t launch_count(const Rec *recs, const uint64_t *sbc, const uint64_t *meta,
+                        const uint8_t *pats, const uint64_t *poff, uint64_t count,
+                        uint64_t *lo, uint64_t *hi, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    count_kernel<<<(unsigned)div_up(count, 256), 256, 0, s>>>(recs, sbc, meta, pats, poff, count,
+                                                              lo, hi);
+    return hipGetLastError();
+}
+
 hipError_t launch_export(const Rec *recs, uint64_t n, uint8_t *out, hipStream_t s) {
-    if (n == 0) return hipSuccess;
     if (n == 0) return hipSuccess;
     const uint64_t want = div_up(n, 256);
     export_kernel<<<(unsigned)(want < (1u << 20) ? want : (1u << 20)), 256, 0, s>>>(recs, n, out);
