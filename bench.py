@@ -427,6 +427,8 @@ def main():
                     help="width of the first suffix-sort key (library default if omitted)")
     ap.add_argument("--radix-tile", type=int, default=None,
                     help="radix pass tile shape (library default if omitted)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each append in a HIP graph and replay it (BWT_PARAM_GRAPH)")
     ap.add_argument("--cpu-sample-bases", type=int, default=None,
                     help="bases of the oracle's sample (default: a quarter of the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -525,6 +527,8 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
     torch.cuda.synchronize()
 
     idx = bwtset.BwtSet(block_size=block)
+    if args.graph and own:
+        idx.set_param(bwtset.BWT_PARAM_GRAPH, 1)
     if args.key_bits is not None:
         idx.set_key_bits(args.key_bits)
     if args.radix_tile is not None:
@@ -598,7 +602,8 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         "config": {"workload": wdesc % (m, block),
                    "reads": m, "bases": bases, "block_suffixes": block,
                    "blocks": st["blocks"] // steps, "key_bits": args.key_bits,
-                   "radix_tile": args.radix_tile},
+                   "radix_tile": args.radix_tile, "graph": bool(args.graph and own),
+                   "graph_replays": st["graph_replays"]},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
         "stages_ms_per_step": {s: round(st["ms"][s] / steps, 3) for s in bwtset.STAGES},

@@ -188,13 +188,24 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     bucket of equal top bits) and one wavefront finishes each bucket in
  *     registers (blocks of 2^20 suffixes or more); 0 = radix passes over the
  *     whole key. */
+/*   BWT_PARAM_GRAPH: 1 = bwt_set_append captures its blocks (every kernel of
+ *     ConstructSA, ComputeRanks and Insert, with the tied-suffix count read on
+ *     the device by a persistent refinement) into a HIP graph the first time
+ *     it meets an input plan and index state, and replays the graph while
+ *     they stay the same (same input buffers and block cut, same index size
+ *     and buffers, no reallocation in between; the symbols may change).  The
+ *     first sort then runs full-width radix passes (no bucket finish).  A
+ *     block with a tied group too large for the refinement makes that call
+ *     run again eagerly.  Up to 4 graphs are kept per handle.  0 (default) =
+ *     no capture. */
 enum {
     BWT_PARAM_KEY_BITS = 1,
     BWT_PARAM_RADIX_TILE = 2,
     BWT_PARAM_RANK_SEGMENT = 3,
     BWT_PARAM_RANK_OVERLAP = 4,
     BWT_PARAM_BATCH_LANES = 5,
-    BWT_PARAM_SORT_BUCKETS = 6
+    BWT_PARAM_SORT_BUCKETS = 6,
+    BWT_PARAM_GRAPH = 7
 };
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
 
@@ -294,6 +305,10 @@ typedef struct {
     uint64_t ranks_fallback_reads;  /* reads walked whole after a retry failed too */
     uint64_t ranks_seg_symbols;     /* symbols of the reads ranked by the segment kernel
                                        (the others by the one-lane-per-read walks) */
+    uint64_t graph_captures;        /* appends captured into a HIP graph (BWT_PARAM_GRAPH) */
+    uint64_t graph_replays;         /* captured appends launched */
+    uint64_t graph_redos;           /* replays run again eagerly (a tied group needed
+                                       prefix doubling) */
 } bwt_stats_t;
 
 /* Turns per-stage HIP-event timing on (1) or off (0).  Timing adds event

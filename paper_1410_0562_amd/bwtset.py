@@ -62,6 +62,9 @@ class Stats(ctypes.Structure):
         ("ranks_retries", ctypes.c_uint64),
         ("ranks_fallback_reads", ctypes.c_uint64),
         ("ranks_seg_symbols", ctypes.c_uint64),
+        ("graph_captures", ctypes.c_uint64),
+        ("graph_replays", ctypes.c_uint64),
+        ("graph_redos", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -93,6 +96,7 @@ BWT_PARAM_RANK_SEGMENT = 3
 BWT_PARAM_RANK_OVERLAP = 4
 BWT_PARAM_BATCH_LANES = 5
 BWT_PARAM_SORT_BUCKETS = 6
+BWT_PARAM_GRAPH = 7
 
 _lib = None
 

@@ -228,6 +228,16 @@ hipError_t launch_refine(const uint8_t *reads, const uint64_t *off, const uint32
                          const uint32_t *tile_first, const uint64_t *keys, const uint32_t *U,
                          uint32_t nU, uint32_t *sa, int kfirst, uint32_t max_iter, uint32_t *err,
                          hipStream_t s);
+// The same with the count of tied suffixes on the device (*nUp, at most n_max)
+// and a fixed grid of workgroups striding over the windows; with *largep set
+// nothing is refined and REFINE_REDO is set in *err.
+constexpr uint32_t REFINE_REDO = 1u << 20;
+constexpr unsigned REFINE_MAX_GRID = 2048;
+hipError_t launch_refine_dev(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                             const uint32_t *tile_first, const uint64_t *keys, const uint32_t *U,
+                             const uint32_t *nUp, const uint32_t *largep, uint32_t n_max,
+                             uint32_t *sa, int kfirst, uint32_t max_iter, uint32_t *err,
+                             hipStream_t s);
 // B_int as ASCII from sorted values, and the plain suffix array
 hipError_t launch_vals_to_ascii(const uint32_t *sa, uint32_t n, uint8_t *bint, hipStream_t s);
 // g in text order back from sorted first keys: g[vals[i] & POS_MASK] = keys[i] >> gshift

@@ -174,9 +174,28 @@ struct bwt_set {
     int last_error = BWT_OK;
     bool broken = false;
     Timer timer;
+    // captured appends (BWT_PARAM_GRAPH): executable graphs keyed by
+    // everything the enqueued work depends on; `capturing` makes the block
+    // path take its data-dependent decisions on the device
+    bool graph = false;
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;
+    struct GraphEntry {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+        int src = 0;        // index buffer holding the result
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_replays = 0, graph_captures = 0, graph_redos = 0;
 };
 
 namespace {
+
+void drop_graphs(bwt_set *h) {
+    for (auto &g : h->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
 
 int fail(bwt_set *h, int code) {
     if (h) {
@@ -197,16 +216,24 @@ int fail(bwt_set *h, int code) {
         }                                                                   \
     } while (0)
 
+// Bumped by every device allocation and free of the library: a captured
+// append is replayed only while no buffer it names can have moved.
+std::atomic<uint64_t> g_alloc_gen{1};
+
 template <class T>
 hipError_t dalloc(T **p, uint64_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
+    g_alloc_gen.fetch_add(1);
     return hipMalloc((void **)p, count * sizeof(T));
 }
 
 template <class T>
 void dfree(T *&p) {
-    if (p) (void)hipFree(p);
+    if (p) {
+        g_alloc_gen.fetch_add(1);
+        (void)hipFree(p);
+    }
     p = nullptr;
 }
 
@@ -650,7 +677,7 @@ KeyLayout key_layout(const bwt_set *h, int gbits, uint32_t n_blk) {
     L.kfirst = first_key_syms(gbits, L.key_bits);
     L.gshift = gbits ? L.key_bits - gbits : 64;
     L.sort_bits = gbits ? L.key_bits : 2 * L.kfirst + KEY_LEN_BITS;
-    L.buckets = h->sort_buckets && n_blk >= BUCKET_MIN_BLOCK;
+    L.buckets = h->sort_buckets && !h->capturing && n_blk >= BUCKET_MIN_BLOCK;
     L.B = 0;
     L.shift0 = 0;
     if (L.buckets) {
@@ -726,6 +753,16 @@ int block_sort(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
                                          w.misc + MISC_NU, REFINE_LIMIT, w.misc + MISC_LARGE,
                                          w.status_scan, w.misc + MISC_CNT_HEADS, next_epoch(),
                                          w.misc + MISC_ERR, s));
+        }
+        if (h->capturing) {
+            // the tied count stays on the device: a persistent refinement
+            // reads it there; a group too large for it flags the call for a
+            // run that decides on the host (prefix doubling)
+            const uint32_t max_iter = (uint32_t)(maxlen / KEY_K + 2);
+            HIPCHK(h, launch_refine_dev(reads, off, w.soff, w.tile_first, ks, w.U[0],
+                                        w.misc + MISC_NU, w.misc + MISC_LARGE, n_blk, sa, kfirst,
+                                        max_iter, w.misc + MISC_ERR, s));
+            return BWT_OK;
         }
         HIPCHK(h, hipMemcpyAsync(h->pinned, w.misc + MISC_NU, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
@@ -1560,6 +1597,8 @@ void bwt_set_destroy(bwt_set_t h) {
     dfree(h->bstage);
     for (auto *l : h->lanes) bwt_set_destroy(l);
     h->lanes.clear();
+    drop_graphs(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     dfree(h->res);
     if (h->pinned) (void)hipHostFree(h->pinned);
     for (auto e : h->timer.pool) (void)hipEventDestroy(e);
@@ -1570,6 +1609,130 @@ void bwt_set_destroy(bwt_set_t h) {
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
+
+}  // extern "C"
+
+namespace {
+
+// The blocks of one planned append, enqueued on s: block b reads the index
+// written by block b-1 (the current one for b = 0) and writes other[b & 1].
+// Nothing here waits for the device while h->capturing is set.  *src_out is
+// the buffer that holds the result.
+int enqueue_blocks(bwt_set *h, hipStream_t s, const Plan &P, const int other[2], int *src_out) {
+    Workspace &w = h->ws;
+    int src = h->cur, rc;
+    uint64_t n_cur = h->n;
+    const size_t K = P.cut_j.size() - 1;
+    for (size_t b = 0; b < K; ++b) {
+        const uint64_t j0 = P.cut_j[b], j1 = P.cut_j[b + 1];
+        const uint32_t m_blk = (uint32_t)(j1 - j0);
+        const uint32_t n_blk = (uint32_t)(P.cut_s[b + 1] - P.cut_s[b]);
+        const uint64_t *off = P.off + j0;
+        IndexBuf &S = h->buf[src];
+        if ((rc = block_prep(h, s, off, m_blk, n_blk))) return rc;
+        // ComputeRanks first: g leads the suffix sort key (an empty index
+        // ranks every suffix 0, so the first block skips it)
+        const int gbits = bits_for_value(n_cur);
+        if (gbits > 0) {
+            Scope sc(h, s, BWT_STAGE_RANKS);
+            const RankKeys kk = rank_keys(h, s, gbits, n_blk, &rc);
+            if (rc) return fail(h, rc);
+            MarkSet mk(h, 3);
+            HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
+                                           S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
+                                           rank_segments(h, P.maxlen), w.misc + MISC_ERR, s,
+                                           mk.get()));
+            mk.add(0, SPAN_RANKS_K, n_blk - m_blk);
+            mk.add(1, SPAN_RANKS_SEG, 0);
+            mk.add(2, SPAN_RANKS_FB, 0);
+        }
+        uint32_t *sa = nullptr;
+        const uint64_t *gkeys = nullptr;
+        int gshift = 64;
+        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, gbits > 0, &sa,
+                             &gkeys, &gshift)))
+            return rc;
+        const int dst = other[b & 1];
+        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gshift, sa, n_blk, m_blk)))
+            return rc;
+        n_cur += n_blk;
+        h->timer.acc.blocks += 1;
+        src = dst;
+    }
+    *src_out = src;
+    return BWT_OK;
+}
+
+// Everything a captured append depends on besides the symbols themselves.
+std::vector<uint64_t> graph_key(const bwt_set *h, const Plan &P) {
+    std::vector<uint64_t> k = {(uint64_t)(uintptr_t)P.reads, (uint64_t)(uintptr_t)P.off,
+                               P.maxlen, P.total_suffixes, h->n, h->m, (uint64_t)h->cur, h->M,
+                               (uint64_t)h->key_bits, (uint64_t)h->radix_cfg, h->seg_len,
+                               h->seg_overlap, g_alloc_gen.load()};
+    k.insert(k.end(), P.cut_j.begin(), P.cut_j.end());
+    k.insert(k.end(), P.cut_s.begin(), P.cut_s.end());
+    return k;
+}
+
+constexpr size_t MAX_GRAPHS = 4;
+
+// Captures the blocks of a planned append into an executable graph (or finds
+// the one captured for the same key).  Returns the entry, or null when
+// capture failed (the caller then runs the append eagerly).
+bwt_set::GraphEntry *captured_append(bwt_set *h, const Plan &P, const int other[2]) {
+    std::vector<uint64_t> key = graph_key(h, P);
+    for (auto &g : h->graphs)
+        if (g.key == key) return &g;
+    if (!h->cap_stream &&
+        hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        h->cap_stream = nullptr;
+        return nullptr;
+    }
+    hipStream_t cs = h->cap_stream;
+    const bool timing = h->timer.on;
+    h->timer.on = false;
+    h->capturing = true;
+    int src = h->cur;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        Workspace &w = h->ws;
+        // every replay starts from cleared look-back words and counters
+        // (fill kernels: memset nodes are kept out of graphs), so the epochs
+        // fixed at capture are fresh again
+        const uint64_t tiles = div_up(w.cap, RADIX_MIN_TILE) + 1;
+        ok = launch_zero_u32(reinterpret_cast<uint32_t *>(w.status_radix),
+                             (uint32_t)(tiles * 256 * 2), cs) == hipSuccess &&
+             launch_zero_u32(reinterpret_cast<uint32_t *>(w.status_scan), (uint32_t)(tiles * 8 * 2),
+                             cs) == hipSuccess &&
+             launch_zero_u32(w.misc, MISC_HIST, cs) == hipSuccess;
+        ok = ok && enqueue_blocks(h, cs, P, other, &src) == BWT_OK;
+        hipGraph_t g = nullptr;
+        const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess && g;
+        ok = ok && ended;
+        hipGraphExec_t exec = nullptr;
+        if (ok) ok = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (ok) {
+            if (h->graphs.size() >= MAX_GRAPHS) {
+                (void)hipGraphExecDestroy(h->graphs.front().exec);
+                h->graphs.erase(h->graphs.begin());
+            }
+            h->graphs.push_back({std::move(key), exec, src});
+            h->graph_captures += 1;
+        }
+    }
+    if (!ok) (void)hipGetLastError();
+    h->capturing = false;
+    h->timer.on = timing;
+    h->broken = false;   // a capture failure is not a device failure
+    h->last_error = BWT_OK;
+    return ok ? &h->graphs.back() : nullptr;
+}
+
+}  // namespace
+
+extern "C" {
 
 int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, uint64_t m,
                    void *stream) {
@@ -1600,54 +1763,36 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
     for (int b : other)
         if ((rc = ensure_index(h, h->buf[b], n_final))) return rc;
     if ((rc = ensure_ws(h, max_block(P)))) return rc;
-    Workspace &w = h->ws;
-    if ((rc = clear_err(h, s))) return rc;
-
-    // block b reads the index written by block b-1 (the current one for
-    // b = 0) and writes other[b & 1]
     int src = h->cur;
-    uint64_t n_cur = h->n;
-    const size_t K = P.cut_j.size() - 1;
-    for (size_t b = 0; b < K; ++b) {
-        const uint64_t j0 = P.cut_j[b], j1 = P.cut_j[b + 1];
-        const uint32_t m_blk = (uint32_t)(j1 - j0);
-        const uint32_t n_blk = (uint32_t)(P.cut_s[b + 1] - P.cut_s[b]);
-        const uint64_t *off = P.off + j0;
-        IndexBuf &S = h->buf[src];
-        if ((rc = block_prep(h, s, off, m_blk, n_blk))) return rc;
-        // ComputeRanks first: g leads the suffix sort key (an empty index
-        // ranks every suffix 0, so the first block skips it)
-        const int gbits = bits_for_value(n_cur);
-        if (gbits > 0) {
-            Scope sc(h, s, BWT_STAGE_RANKS);
-            const RankKeys kk = rank_keys(h, s, gbits, n_blk, &rc);
-            if (rc) return fail(h, rc);
-            MarkSet mk(h, 3);
-            HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
-                                           S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
-                                           rank_segments(h, P.maxlen), w.misc + MISC_ERR, s,
-                                           mk.get()));
-            mk.add(0, SPAN_RANKS_K, n_blk - m_blk);
-            mk.add(1, SPAN_RANKS_SEG, 0);
-            mk.add(2, SPAN_RANKS_FB, 0);
+    bool done = false;
+    if (h->graph) {
+        // a captured schedule: every buffer it names exists before capture
+        const uint64_t nt = div_up(records_for(n_final), INS_TILE_RECS);
+        if ((rc = ensure_buf(h, h->first_new, h->first_new_cap, nt + 2))) return rc;
+        bwt_set::GraphEntry *ge = captured_append(h, P, other);
+        if (ge) {
+            HIPCHK(h, hipGraphLaunch(ge->exec, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            uint32_t e = 0;
+            if ((rc = read_u32(h, s, h->ws.misc + MISC_ERR, &e))) return rc;
+            h->graph_replays += 1;
+            if (e == 0) {
+                src = ge->src;
+                done = true;
+            } else if (e & REFINE_REDO) {
+                h->graph_redos += 1;   // a tied group needs prefix doubling
+            } else {
+                if ((rc = check_err(h, s))) return rc;
+            }
         }
-        uint32_t *sa = nullptr;
-        const uint64_t *gkeys = nullptr;
-        int gshift = 64;
-        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, gbits > 0, &sa,
-                             &gkeys,
-                             &gshift)))
-            return rc;
-        const int dst = other[b & 1];
-        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gshift, sa, n_blk, m_blk)))
-            return rc;
-        n_cur += n_blk;
-        h->timer.acc.blocks += 1;
-        src = dst;
     }
-    HIPCHK(h, hipStreamSynchronize(s));
-    if (h->timer.on) timer_collect(h);
-    if ((rc = check_err(h, s))) return rc;
+    if (!done) {
+        if ((rc = clear_err(h, s))) return rc;
+        if ((rc = enqueue_blocks(h, s, P, other, &src))) return rc;
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->timer.on) timer_collect(h);
+        if ((rc = check_err(h, s))) return rc;
+    }
     h->cur = src;
     h->n = n_final;
     h->m += m;
@@ -1891,6 +2036,7 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
 int bwt_set_trim(bwt_set_t h) {
     if (!h) return BWT_EINVAL;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
     for (int b = 0; b < 3; ++b) {
         if (b == h->cur) continue;
         IndexBuf &x = h->buf[b];
@@ -1969,6 +2115,11 @@ int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
     case BWT_PARAM_RANK_OVERLAP:
         if (value < 0 || value > (1 << 24)) return fail(h, BWT_EINVAL);
         h->seg_overlap = (uint32_t)value;
+        return BWT_OK;
+    case BWT_PARAM_GRAPH:
+        if (value != 0 && value != 1) return fail(h, BWT_EINVAL);
+        h->graph = value != 0;
+        if (!h->graph) drop_graphs(h);
         return BWT_OK;
     case BWT_PARAM_SORT_BUCKETS:
         if (value != 0 && value != 1) return fail(h, BWT_EINVAL);
@@ -2167,7 +2318,13 @@ int bwt_set_enable_timing(bwt_set_t h, int on) {
 int bwt_set_get_stats(bwt_set_t h, bwt_stats_t *out, int reset) {
     if (!h || !out) return BWT_EINVAL;
     *out = h->timer.acc;
-    if (reset) memset(&h->timer.acc, 0, sizeof h->timer.acc);
+    out->graph_captures = h->graph_captures;
+    out->graph_replays = h->graph_replays;
+    out->graph_redos = h->graph_redos;
+    if (reset) {
+        memset(&h->timer.acc, 0, sizeof h->timer.acc);
+        h->graph_captures = h->graph_replays = h->graph_redos = 0;
+    }
     return BWT_OK;
 }
 

@@ -284,11 +284,13 @@ __device__ __forceinline__ bool group_start(const uint32_t *__restrict__ U,
 // subgroup is settled when it has one member or its key reaches the
 // terminator.  d grows by RF_K per pass, so a group settles within
 // (longest read / RF_K) + 1 passes.
-__global__ __launch_bounds__(256) void refine_kernel(
+// One window (number `win`) of the tied suffixes U[0 .. nU).
+__device__ __forceinline__ void refine_window(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first,
     const uint64_t *__restrict__ keys, const uint32_t *__restrict__ U, uint32_t nU,
-    uint32_t *__restrict__ sa, int kfirst, uint32_t max_iter, uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ sa, int kfirst, uint32_t max_iter, uint32_t *__restrict__ err,
+    uint32_t win) {
     __shared__ uint32_t s_val[RF_CAP];
     __shared__ uint64_t s_pos[RF_CAP];   // global symbol index of the suffix start
     __shared__ uint32_t s_rem[RF_CAP];   // symbols before its terminator
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(256) void refine_kernel(
         // start (at most REFINE_LIMIT places on, or the end of U), 64 places
         // per step
         const int wv = tid >> 6, ln = tid & 63;
-        uint64_t x0 = (uint64_t)blockIdx.x * REFINE_WINDOW + (wv ? REFINE_WINDOW : 0);
+        uint64_t x0 = (uint64_t)win * REFINE_WINDOW + (wv ? REFINE_WINDOW : 0);
         x0 = x0 < nU ? x0 : nU;
         uint64_t r = x0 + REFINE_LIMIT < nU ? x0 + REFINE_LIMIT : nU;
         for (uint64_t y0 = x0; y0 < r; y0 += 64) {
@@ -551,6 +553,29 @@ __global__ __launch_bounds__(256) void refine_kernel(
     }
 }
 
+// Workgroups stride over the windows of the tied suffixes.  nUp (when set)
+// holds the count on the device, so a grid sized for the largest count can
+// be launched before the count exists (a captured schedule); a set *largep
+// (a tied group too large for the windows: prefix doubling needed) makes the
+// launch do nothing and sets REFINE_REDO in *err, and the caller runs the
+// block again on the path that decides on the host.
+__global__ __launch_bounds__(256) void refine_kernel(
+    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ soff, const uint32_t *__restrict__ tile_first,
+    const uint64_t *__restrict__ keys, const uint32_t *__restrict__ U, uint32_t nU_val,
+    const uint32_t *__restrict__ nUp, const uint32_t *__restrict__ largep,
+    uint32_t *__restrict__ sa, int kfirst, uint32_t max_iter, uint32_t *__restrict__ err) {
+    const uint32_t nU = nUp ? *nUp : nU_val;
+    if (largep && *largep) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, REFINE_REDO);
+        return;
+    }
+    for (uint32_t win = blockIdx.x; (uint64_t)win * REFINE_WINDOW < nU; win += gridDim.x) {
+        refine_window(reads, off, soff, tile_first, keys, U, nU, sa, kfirst, max_iter, err, win);
+        __syncthreads();  // the next window reuses the LDS arrays
+    }
+}
+
 __global__ void vals_to_ascii_kernel(const uint32_t *__restrict__ sa, uint32_t n,
                                      uint8_t *__restrict__ bint) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -625,8 +650,20 @@ hipError_t launch_refine(const uint8_t *reads, const uint64_t *off, const uint32
                          uint32_t nU, uint32_t *sa, int kfirst, uint32_t max_iter, uint32_t *err,
                          hipStream_t s) {
     if (nU == 0) return hipSuccess;
-    refine_kernel<<<grid_for(nU, REFINE_WINDOW), 256, 0, s>>>(reads, off, soff, tile_first, keys, U,
-                                                              nU, sa, kfirst, max_iter, err);
+    refine_kernel<<<grid_for(nU, REFINE_WINDOW), 256, 0, s>>>(
+        reads, off, soff, tile_first, keys, U, nU, nullptr, nullptr, sa, kfirst, max_iter, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_dev(const uint8_t *reads, const uint64_t *off, const uint32_t *soff,
+                             const uint32_t *tile_first, const uint64_t *keys, const uint32_t *U,
+                             const uint32_t *nUp, const uint32_t *largep, uint32_t n_max,
+                             uint32_t *sa, int kfirst, uint32_t max_iter, uint32_t *err,
+                             hipStream_t s) {
+    if (n_max == 0) return hipSuccess;
+    const unsigned want = grid_for(n_max, REFINE_WINDOW);
+    refine_kernel<<<want < REFINE_MAX_GRID ? want : REFINE_MAX_GRID, 256, 0, s>>>(
+        reads, off, soff, tile_first, keys, U, 0u, nUp, largep, sa, kfirst, max_iter, err);
     return hipGetLastError();
 }
 

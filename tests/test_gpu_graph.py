@@ -1,0 +1,122 @@
+"""Captured appends (BWT_PARAM_GRAPH): the blocks of an append are captured
+into a HIP graph once per input plan and index state and replayed.  Every
+replay is checked against the eager append and the oracle, with eager work
+and synchronizations of the program between the replays."""
+import numpy as np
+import pytest
+
+from paper_1410_0562_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _log(msg):
+    print("[graph] " + msg, flush=True)
+
+
+def _dev(torch, packed, offs):
+    return (torch.from_numpy(packed).cuda(),
+            torch.from_numpy(np.asarray(offs, np.uint64).view(np.int64)).cuda())
+
+
+def test_replays_equal_eager_and_oracle(torch_dev, oracle_mod):
+    torch = torch_dev
+    from paper_1410_0562_amd import bwtset
+    packed, offs = synth.uniform_reads(m=10_000)            # 4 blocks of M = 2^18
+    want = oracle_mod.bwt_of_codes(*oracle_mod.reads_from_packed(packed, offs))
+    dr, do = _dev(torch, packed, offs)
+    other_p, other_o = synth.random_reads(101, 500, 0, 120)
+    with bwtset.BwtSet(block_size=1 << 18) as g, bwtset.BwtSet(block_size=1 << 18) as e:
+        g.set_param(bwtset.BWT_PARAM_GRAPH, 1)
+        e.append(dr, do)
+        eager = e.export()
+        assert eager == want
+        g.stats(reset=True)
+        for rep in range(6):
+            _log("replay %d" % rep)
+            g.reset()
+            g.append(dr, do)
+            got = g.export()
+            assert got == eager, rep
+            # the program's own eager work between replays
+            e.reset()
+            e.append(other_p, other_o)
+            torch.cuda.synchronize()
+            assert g.rank("A", len(want) // 2) == oracle_mod.rank(want, "A", len(want) // 2)
+        st = g.stats()
+        assert st["graph_replays"] == 6 and st["graph_redos"] == 0
+        # the current buffer cycles through the three index buffers, so at
+        # most three plans are captured
+        assert 1 <= st["graph_captures"] <= 3
+
+
+def test_replay_reads_new_symbols_under_the_same_plan(torch_dev, oracle_mod):
+    torch = torch_dev
+    from paper_1410_0562_amd import bwtset
+    packed, offs = synth.random_reads(102, 3000, 0, 150)
+    dr, do = _dev(torch, packed, offs)
+    with bwtset.BwtSet(block_size=100_000) as g:
+        g.set_param(bwtset.BWT_PARAM_GRAPH, 1)
+        for rep in range(4):
+            # new symbols in the same buffer: same offsets, same plan
+            codes = np.random.default_rng(200 + rep).integers(0, 4, int(offs[-1]), dtype=np.uint8)
+            dr.copy_(torch.from_numpy(synth.pack_codes(codes)[:dr.numel()]).cuda())
+            torch.cuda.synchronize()
+            g.reset()
+            g.append(dr, do)
+            want = oracle_mod.bwt_of_codes(*oracle_mod.reads_from_packed(dr.cpu().numpy(), offs))
+            assert g.export() == want, rep
+        assert g.stats()["graph_replays"] == 4
+
+
+def test_large_tied_group_runs_again_eagerly(torch_dev, oracle_mod):
+    """Thousands of copies of one read make a tied group larger than the
+    refinement holds: the replay flags it and the call runs eagerly."""
+    torch = torch_dev
+    from paper_1410_0562_amd import bwtset
+    rng = np.random.default_rng(103)
+    one = rng.integers(0, 4, 80, dtype=np.uint8)
+    reads = [one] * 3000 + [rng.integers(0, 4, 60, dtype=np.uint8) for _ in range(500)]
+    codes = np.concatenate(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(r) for r in reads])
+    packed = synth.pack_codes(codes)
+    want = oracle_mod.bwt_of_codes(*oracle_mod.reads_from_packed(packed, offs))
+    dr, do = _dev(torch, packed, offs)
+    with bwtset.BwtSet(block_size=150_000) as g:
+        g.set_param(bwtset.BWT_PARAM_GRAPH, 1)
+        for rep in range(2):
+            g.reset()
+            g.append(dr, do)
+            assert g.export() == want, rep
+        assert g.stats()["graph_redos"] >= 1
+
+
+def test_incremental_appends_and_host_inputs(torch_dev, oracle_mod):
+    torch = torch_dev
+    from paper_1410_0562_amd import bwtset
+    parts = [synth.random_reads(104 + k, 800, 0, 200) for k in range(3)]
+    allc = [oracle_mod.reads_from_packed(p, o) for p, o in parts]
+    codes = np.concatenate([c for c, _ in allc])
+    offs = np.zeros(sum(len(o) - 1 for _, o in allc) + 1, np.uint64)
+    offs[1:] = np.cumsum(np.concatenate([np.diff(o.astype(np.int64)) for _, o in allc]))
+    want = oracle_mod.bwt_of_codes(codes, offs)
+    with bwtset.BwtSet(block_size=40_000) as g:
+        g.set_param(bwtset.BWT_PARAM_GRAPH, 1)
+        for rep in range(3):
+            g.reset()
+            for k, (p, o) in enumerate(parts):
+                if k == 1:
+                    g.append(p, o)                         # host buffers (staged)
+                else:
+                    g.append(*_dev(torch, p, o))
+            assert g.export() == want, rep
+        assert g.stats()["graph_replays"] == 9
