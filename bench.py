@@ -269,6 +269,8 @@ def run_batched(args, torch, bwtset, synth):
     hl = [bwtset.BwtSet(block_size=block) for _ in sets]
     if args.lanes is not None:
         hb[0].set_param(bwtset.BWT_PARAM_BATCH_LANES, args.lanes)
+    if args.graph:
+        hb[0].set_param(bwtset.BWT_PARAM_GRAPH, 1)
     for h in hb + hl:
         if args.key_bits is not None:
             h.set_key_bits(args.key_bits)
@@ -332,7 +334,7 @@ def run_batched(args, torch, bwtset, synth):
                                "strands, 1%% substitutions; block M=%d suffixes" % (
                                    len(sets), lo_r, hi_r, block),
                    "sets": len(sets), "reads": reads, "bases": bases, "block_suffixes": block,
-                   "lanes": args.lanes},
+                   "lanes": args.lanes, "graph": bool(args.graph)},
         "batched": {"per_set_loop_bases_per_s": v_loop,
                     "per_set_loop_ms_per_step": t_loop / args.steps * 1e3,
                     "speedup_vs_per_set_loop": v_batch / v_loop,
@@ -429,6 +431,8 @@ def main():
                     help="radix pass tile shape (library default if omitted)")
     ap.add_argument("--graph", action="store_true",
                     help="capture each append in a HIP graph and replay it (BWT_PARAM_GRAPH)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner on the workload first (untimed)")
     ap.add_argument("--cpu-sample-bases", type=int, default=None,
                     help="bases of the oracle's sample (default: a quarter of the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -533,12 +537,17 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         idx.set_key_bits(args.key_bits)
     if args.radix_tile is not None:
         idx.set_param(bwtset.BWT_PARAM_RADIX_TILE, args.radix_tile)
+    tune = None
+    if args.autotune and own:
+        tune = idx.autotune(dev_reads, dev_offs)
+        log("autotune: %s" % tune)
     for w in range(warmup):
         idx.reset()
         idx.append(dev_reads, dev_offs, stream)
         log("warmup %d done" % w)
+    # the timed steps run without per-kernel events; the same steps are then
+    # run again with them for the kernel and stage breakdown
     idx.stats(reset=True)
-    idx.enable_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -546,11 +555,22 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         idx.append(dev_reads, dev_offs, stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    st = idx.stats()
+    graph_replays = idx.stats(reset=True)["graph_replays"]
     n, mm = idx.size()
     assert n == bases + m and mm == m
     dt = t1 - t0
     log("timed %d steps in %.3f s" % (steps, dt))
+    if args.graph and own:
+        # captured appends record no per-kernel events: the breakdown comes
+        # from the same steps run eagerly
+        idx.set_param(bwtset.BWT_PARAM_GRAPH, 0)
+    idx.enable_timing(True)
+    for k in range(steps):
+        idx.reset()
+        idx.append(dev_reads, dev_offs, stream)
+    torch.cuda.synchronize()
+    st = idx.stats()
+    idx.enable_timing(False)
 
     # LF steps: every base of every block with an index to rank against; the
     # library counts those of the reads its segment kernel walked
@@ -581,11 +601,14 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         kinfo[name] = {"ms_per_step": ms / steps, "launches_per_step": launches / steps,
                        "avg_launch_ms": ms / launches, "bytes_per_launch": nbytes / launches,
                        "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
-    dom = max(kinfo, key=lambda k: kinfo[k]["ms_per_step"])
-    d = kinfo[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["achieved_GBs"], 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["frac"], 4),
-                "traffic": measured_traffic(key, dom)}
+    if kinfo:
+        dom = max(kinfo, key=lambda k: kinfo[k]["ms_per_step"])
+        d = kinfo[dom]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["achieved_GBs"], 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["frac"], 4),
+                    "traffic": measured_traffic(key, dom)}
+    else:
+        roofline = None
     out = {
         "metric": METRIC,
         "value": bases * steps / dt,
@@ -603,7 +626,7 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
                    "reads": m, "bases": bases, "block_suffixes": block,
                    "blocks": st["blocks"] // steps, "key_bits": args.key_bits,
                    "radix_tile": args.radix_tile, "graph": bool(args.graph and own),
-                   "graph_replays": st["graph_replays"]},
+                   "graph_replays": graph_replays, "autotune": tune},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
         "stages_ms_per_step": {s: round(st["ms"][s] / steps, 3) for s in bwtset.STAGES},

@@ -176,7 +176,7 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     symbols in segments of this length, each one started by a backward
  *     search (FM-index interval) BWT_PARAM_RANK_OVERLAP symbols past its end
  *     and continued by Lemma 1 once the interval holds no old suffix; reads
- *     with a longer repeat fall back to one whole walk.  0 = never (256 ..
+ *     with a longer repeat fall back to one whole walk.  0 = never (32 ..
  *     2^24, default 768).  A segment whose interval is still open at its
  *     end starts once more with 16 times the overlap (at least 256).
  *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 64).
@@ -193,8 +193,12 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     the device by a persistent refinement) into a HIP graph the first time
  *     it meets an input plan and index state, and replays the graph while
  *     they stay the same (same input buffers and block cut, same index size
- *     and buffers, no reallocation in between; the symbols may change).  The
- *     first sort then runs full-width radix passes (no bucket finish).  A
+ *     and buffers, no reallocation in between; the symbols may change).  Only
+ *     appends whose blocks all hold fewer than 2^20 suffixes are captured
+ *     (larger blocks take the bucket finish, which decides on the host, and
+ *     launch costs do not matter there); the first sort of a captured block
+ *     runs full-width radix passes.  The same holds for bwt_set_append_many
+ *     with the parameter set on hs[0] (one stream, no lanes).  A
  *     block with a tied group too large for the refinement makes that call
  *     run again eagerly.  Up to 4 graphs are kept per handle.  0 (default) =
  *     no capture. */
@@ -208,6 +212,29 @@ enum {
     BWT_PARAM_GRAPH = 7
 };
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
+
+/* Autotuner for the knobs above that never change a result: the first-key
+ * width, the ComputeRanks segment length and overlap, and the radix tile
+ * shape.  It builds this input (reads/offsets as for bwt_set_append) from
+ * empty on a scratch handle with h's block size, median of three builds per
+ * setting, changing one knob at a time from h's current settings, and applies
+ * the fastest to h.  The choice is cached per GPU architecture and shape
+ * class (block size, mean and longest read length, rounded to powers of
+ * two) for the process and, when the environment variable BWTSET_TUNE_CACHE
+ * names a file, in that file; a later call of the same class applies the
+ * cached choice without timing unless `force` is set.  h's index is not
+ * changed.  out (may be NULL) receives the choice. */
+typedef struct {
+    int radix_tile;
+    int key_bits;
+    uint32_t rank_segment;
+    uint32_t rank_overlap;
+    int from_cache;      /* 1: taken from the cache, nothing timed */
+    double ms;           /* build time of the choice (median), when timed */
+    int trials;          /* settings timed */
+} bwt_tune_t;
+int bwt_set_autotune(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, uint64_t m,
+                     int force, bwt_tune_t *out);
 
 /* Last error code recorded on h (or, for h == NULL, by bwt_set_create). */
 int bwt_set_last_error(bwt_set_t h);

@@ -86,6 +86,7 @@ EXPORTED = [
     "bwt_set_enable_timing", "bwt_set_get_stats", "bwt_set_set_param",
     "bwt_set_import", "bwt_set_memory", "bwt_set_trim", "bwt_set_append_many",
     "bwt_set_block_sort_noalloc", "bwt_set_count_many", "bwt_set_append_strands",
+    "bwt_set_autotune",
 ]
 BWT_STRAND_FORWARD = 0
 BWT_STRAND_REVERSE = 1
@@ -141,6 +142,8 @@ def load(path: str = LIB_PATH):
     L.bwt_set_count_many.restype = i32
     L.bwt_set_append_strands.argtypes = [vp, vp, vp, u64, i32, vp]
     L.bwt_set_append_strands.restype = i32
+    L.bwt_set_autotune.argtypes = [vp, vp, vp, u64, i32, ctypes.POINTER(Tune)]
+    L.bwt_set_autotune.restype = i32
     L.bwt_set_compute_ranks.argtypes = [vp, vp, vp, u64, vp, vp]
     L.bwt_set_compute_ranks.restype = i32
     L.bwt_set_insert.argtypes = [vp, vp, vp, u64, vp]
@@ -163,6 +166,15 @@ def load(path: str = LIB_PATH):
     if path == LIB_PATH:
         _lib = L
     return L
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("radix_tile", ctypes.c_int), ("key_bits", ctypes.c_int),
+                ("rank_segment", ctypes.c_uint32), ("rank_overlap", ctypes.c_uint32),
+                ("from_cache", ctypes.c_int), ("ms", ctypes.c_double), ("trials", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class BwtSetError(RuntimeError):
@@ -280,6 +292,17 @@ class BwtSet:
         self._check(load().bwt_set_append_strands(self._h, _ptr(reads), _ptr(offsets), m,
                                                   int(mode), _stream(stream)),
                     "bwt_set_append_strands")
+
+    def autotune(self, reads, offsets, force: bool = False) -> dict:
+        """Pick the fastest tuning knobs for this input's shape class (see
+        bwt_set_autotune) and apply them; returns the choice."""
+        reads = _as_reads(reads)
+        offsets = _as_offsets(offsets)
+        t = Tune()
+        self._check(load().bwt_set_autotune(self._h, _ptr(reads), _ptr(offsets),
+                                            _len(offsets) - 1, 1 if force else 0,
+                                            ctypes.byref(t)), "bwt_set_autotune")
+        return t.as_dict()
 
     def rank(self, c: str, k: int) -> int:
         r = load().bwt_set_rank(self._h, c.encode("ascii"), int(k))

@@ -14,7 +14,13 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <chrono>
+#include <cstdlib>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -85,7 +91,7 @@ constexpr int MISC_STATS = 16;   // running totals of ComputeRanks: segment retr
                                  // reads, then (words 18-19, 64-bit) symbols of queued reads
 constexpr int BK_TABLES = 6;     // bucket starts, ends, tie counts, sizes; oversized list, offsets
 constexpr uint32_t BK_PART = 3 * 4096 + 16;  // tile partials of the bucket scans
-constexpr uint32_t MIN_SEG_LEN = 256;
+constexpr uint32_t MIN_SEG_LEN = 32;   // shortest ComputeRanks segment
 constexpr int MAX_LANES = 4;
 constexpr uint32_t BUCKET_TARGET = 32;  // suffixes per bucket the bucket count aims at
 constexpr uint32_t BUCKET_MIN_BLOCK = 1u << 20;  // smallest block that takes the bucket finish
@@ -190,6 +196,8 @@ struct bwt_set {
 };
 
 namespace {
+
+constexpr size_t MAX_GRAPHS = 4;   // executable graphs kept per handle
 
 void drop_graphs(bwt_set *h) {
     for (auto &g : h->graphs)
@@ -1353,6 +1361,93 @@ int append_many(bwt_set *d, bwt_set **hs, const uint8_t *const *reads,
     HIPCHK(d, hipMemcpyAsync(d->btab, tab.data(), tab.size(), hipMemcpyHostToDevice, s));
     HIPCHK(d, hipStreamSynchronize(s));  // tab is pageable host memory
 
+    // 6-7 captured (BWT_PARAM_GRAPH on hs[0]): the staging and every device
+    // block in one graph on one stream, replayed while the batch's plan and
+    // the sets' index states stay the same
+    if (d->graph && (max_nblk < BUCKET_MIN_BLOCK || !d->sort_buckets)) {
+        std::vector<uint64_t> key = {0xba7c4ull, na, M, (uint64_t)d->key_bits,
+                                     (uint64_t)d->radix_cfg, d->seg_len, d->seg_overlap,
+                                     g_alloc_gen.load(), maxlen, total_reads, total_syms,
+                                     blocks.size(), (uint64_t)(uintptr_t)d};
+        for (uint32_t a = 0; a < na; ++a) {
+            const bwt_set *h = hs[act[a]];
+            key.insert(key.end(), {(uint64_t)(uintptr_t)h, (uint64_t)h->cur, h->n, h->m,
+                                   (uint64_t)(uintptr_t)dreads[a], (uint64_t)(uintptr_t)doff[a],
+                                   m[act[a]], sym_base[a]});
+        }
+        for (const HostUnit &u : units) key.insert(key.end(), {u.set, u.j0, u.j1, u.nsuf});
+        bwt_set::GraphEntry *ge = nullptr;
+        for (auto &g : d->graphs)
+            if (g.key == key) ge = &g;
+        if (!ge && (d->cap_stream || hipStreamCreateWithFlags(&d->cap_stream,
+                                                              hipStreamNonBlocking) == hipSuccess)) {
+            hipStream_t cs = d->cap_stream;
+            const bool timing = d->timer.on;
+            d->timer.on = false;
+            d->capturing = true;
+            bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                Workspace &w = d->ws;
+                const uint64_t tiles = div_up(w.cap, RADIX_MIN_TILE) + 1;
+                const GatherUnit *gdev = reinterpret_cast<const GatherUnit *>(d->btab + gu_at);
+                ok = launch_zero_u32(reinterpret_cast<uint32_t *>(w.status_radix),
+                                     (uint32_t)(tiles * 256 * 2), cs) == hipSuccess &&
+                     launch_zero_u32(reinterpret_cast<uint32_t *>(w.status_scan),
+                                     (uint32_t)(tiles * 8 * 2), cs) == hipSuccess &&
+                     launch_zero_u32(w.misc, MISC_HIST, cs) == hipSuccess &&
+                     launch_gather_offsets(gdev, (uint32_t)units.size(), total_reads, total_syms,
+                                           d->stage_off, cs) == hipSuccess &&
+                     launch_gather_reads(gdev, (uint32_t)units.size(), total_syms,
+                                         d->stage_reads, cs) == hipSuccess;
+                const BatchInput gin{d->stage_reads, d->stage_off, d->btab, maxlen};
+                for (size_t b = 0; ok && b < blocks.size(); ++b)
+                    ok = run_block(d, cs, blocks[b], units, gin) == BWT_OK;
+                hipGraph_t g = nullptr;
+                const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess && g;
+                ok = ok && ended;
+                hipGraphExec_t exec = nullptr;
+                if (ok) ok = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+                if (g) (void)hipGraphDestroy(g);
+                if (ok) {
+                    if (d->graphs.size() >= MAX_GRAPHS) {
+                        (void)hipGraphExecDestroy(d->graphs.front().exec);
+                        d->graphs.erase(d->graphs.begin());
+                    }
+                    d->graphs.push_back({std::move(key), exec, 0});
+                    d->graph_captures += 1;
+                    ge = &d->graphs.back();
+                }
+            }
+            if (!ok) (void)hipGetLastError();
+            d->capturing = false;
+            d->timer.on = timing;
+            d->broken = false;
+            d->last_error = BWT_OK;
+        }
+        if (ge) {
+            HIPCHK(d, hipGraphLaunch(ge->exec, s));
+            HIPCHK(d, hipStreamSynchronize(s));
+            uint32_t e = 0;
+            if ((rc = read_u32(d, s, d->ws.misc + MISC_ERR, &e))) return rc;
+            d->graph_replays += 1;
+            if (e == 0) {
+                for (uint32_t a = 0; a < na; ++a) {
+                    bwt_set *h = hs[act[a]];
+                    const uint64_t K = res[4 * a + 3];
+                    h->cur = other[a][(K - 1) & 1];
+                    h->n = n_run[a];
+                    h->m += m[act[a]];
+                }
+                return BWT_OK;
+            }
+            if (!(e & REFINE_REDO)) {
+                rc = check_err(d, s);
+                return fail(d, rc ? rc : BWT_EHIP);
+            }
+            d->graph_redos += 1;   // a tied group needs prefix doubling: run eagerly
+        }
+    }
+
     // 6. staging: every unit's reads, in schedule order, into one input
     {
         Scope sc(d, s, BWT_STAGE_PLAN);
@@ -1674,8 +1769,6 @@ std::vector<uint64_t> graph_key(const bwt_set *h, const Plan &P) {
     return k;
 }
 
-constexpr size_t MAX_GRAPHS = 4;
-
 // Captures the blocks of a planned append into an executable graph (or finds
 // the one captured for the same key).  Returns the entry, or null when
 // capture failed (the caller then runs the append eagerly).
@@ -1765,7 +1858,9 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
     if ((rc = ensure_ws(h, max_block(P)))) return rc;
     int src = h->cur;
     bool done = false;
-    if (h->graph) {
+    // capture is for launch-bound appends: blocks that take the bucket finish
+    // (which decides on the host) run eagerly, where launches cost little
+    if (h->graph && (max_block(P) < BUCKET_MIN_BLOCK || !h->sort_buckets)) {
         // a captured schedule: every buffer it names exists before capture
         const uint64_t nt = div_up(records_for(n_final), INS_TILE_RECS);
         if ((rc = ensure_buf(h, h->first_new, h->first_new_cap, nt + 2))) return rc;
@@ -1864,6 +1959,170 @@ int bwt_set_rank_many(bwt_set_t h, const uint8_t *cs, const uint64_t *ks, uint64
     hipStream_t s = stream ? (hipStream_t)stream : h->stream;
     IndexBuf &B = h->buf[h->cur];
     HIPCHK(h, launch_rank_many(B.recs, B.sbc, B.meta, cs, ks, out, count, s));
+    return BWT_OK;
+}
+
+}  // extern "C"
+
+// ---- autotuning -------------------------------------------------------------
+// The tuning knobs never change a result, only the time: the tuner builds the
+// caller's input from empty on a scratch handle with candidate settings and
+// keeps the fastest, one knob at a time (first-key width, ComputeRanks
+// segments, radix tile shape).  Results are cached per GPU architecture and
+// shape class (block size, mean and longest read length) in the process and,
+// when BWTSET_TUNE_CACHE names a file, in that file as lines of
+// "<class> <radix tile> <key bits> <segment> <overlap>".
+namespace {
+
+struct TuneSet {
+    int radix_cfg, key_bits;
+    uint32_t seg_len, seg_overlap;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneSet> g_tune;
+bool g_tune_loaded = false;
+
+int log2_ceil(uint64_t v) {
+    int b = 0;
+    while (b < 63 && (1ull << b) < v) ++b;
+    return b;
+}
+
+std::string tune_class(int dev, uint64_t M, const Plan &P, uint64_t m) {
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    } else {
+        (void)hipGetLastError();
+    }
+    const uint64_t blk = std::min<uint64_t>(M, P.total_suffixes);
+    const uint64_t mean = m ? (P.total_suffixes - m) / m : 0;
+    std::ostringstream k;
+    k << arch << "/b" << log2_ceil(blk) << "/r" << log2_ceil(mean + 1) << "/x"
+      << log2_ceil(P.maxlen + 1);
+    return k.str();
+}
+
+void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = getenv("BWTSET_TUNE_CACHE");
+    if (!f || !*f) return;
+    std::ifstream in(f);
+    std::string cls;
+    TuneSet t;
+    while (in >> cls >> t.radix_cfg >> t.key_bits >> t.seg_len >> t.seg_overlap) g_tune[cls] = t;
+}
+
+void tune_store(const std::string &cls, const TuneSet &t) {
+    g_tune[cls] = t;
+    const char *f = getenv("BWTSET_TUNE_CACHE");
+    if (!f || !*f) return;
+    std::ofstream out(f, std::ios::app);
+    out << cls << ' ' << t.radix_cfg << ' ' << t.key_bits << ' ' << t.seg_len << ' '
+        << t.seg_overlap << '\n';
+}
+
+void tune_apply(bwt_set *h, const TuneSet &t) {
+    h->radix_cfg = t.radix_cfg;
+    h->key_bits = t.key_bits;
+    h->seg_len = t.seg_len;
+    h->seg_overlap = t.seg_overlap;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bwt_set_autotune(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, uint64_t m,
+                     int force, bwt_tune_t *out) {
+    if (!h) return BWT_EINVAL;
+    if (h->broken) return fail(h, BWT_ESTATE);
+    if (m == 0 || !reads || !offsets) return fail(h, BWT_EINVAL);
+    int rc = set_device(h);
+    if (rc) return rc;
+    Plan P;
+    if ((rc = plan_input(h, h->stream, reads, offsets, m, h->M, P))) return rc;
+    const std::string cls = tune_class(h->device, h->M, P, m);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(cls);
+    if (it != g_tune.end() && !force) {
+        tune_apply(h, it->second);
+        if (out) *out = bwt_tune_t{it->second.radix_cfg, it->second.key_bits,
+                                   it->second.seg_len, it->second.seg_overlap, 1, 0.0, 0};
+        return BWT_OK;
+    }
+    bwt_set *t = bwt_set_create("ACGT");
+    if (!t) return fail(h, BWT_ENOMEM);
+    t->M = h->M;
+    t->sort_buckets = h->sort_buckets;
+    int trials = 0;
+    // median of three builds from empty (after one warm-up build)
+    auto time_it = [&](const TuneSet &c, double *ms) -> int {
+        tune_apply(t, c);
+        double v[3];
+        for (int r = -1; r < 3; ++r) {
+            int e = bwt_set_reset(t);
+            if (e) return e;
+            auto t0 = std::chrono::steady_clock::now();
+            if ((e = bwt_set_append(t, reads, offsets, m, nullptr))) return e;
+            auto t1 = std::chrono::steady_clock::now();
+            if (r >= 0) v[r] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        }
+        std::sort(v, v + 3);
+        *ms = v[1];
+        ++trials;
+        return BWT_OK;
+    };
+    TuneSet best{h->radix_cfg, h->key_bits, h->seg_len, h->seg_overlap};
+    double best_ms = 0;
+    rc = time_it(best, &best_ms);
+    auto consider = [&](TuneSet c) -> int {
+        double ms;
+        int e = time_it(c, &ms);
+        if (e) return e;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        return BWT_OK;
+    };
+    const uint64_t mean = (P.total_suffixes - m) / m;
+    for (int kb : {64, 48, 40, 32}) {
+        if (rc) break;
+        if (kb == best.key_bits) continue;
+        TuneSet c = best;
+        c.key_bits = kb;
+        rc = consider(c);
+    }
+    {
+        std::vector<std::pair<uint32_t, uint32_t>> segs = {{768, 64}, {1024, 128}, {0, 0}};
+        if (mean <= 512) segs.insert(segs.end(), {{32, 16}, {64, 16}, {128, 32}});
+        for (auto so : segs) {
+            if (rc) break;
+            if (so.first == best.seg_len && so.second == best.seg_overlap) continue;
+            TuneSet c = best;
+            c.seg_len = so.first;
+            c.seg_overlap = so.second;
+            rc = consider(c);
+        }
+    }
+    for (int cfg : {3, 0, 1, 5}) {
+        if (rc) break;
+        if (cfg == best.radix_cfg) continue;
+        TuneSet c = best;
+        c.radix_cfg = cfg;
+        rc = consider(c);
+    }
+    bwt_set_destroy(t);
+    if (rc) return fail(h, rc);
+    tune_store(cls, best);
+    tune_apply(h, best);
+    if (out) *out = bwt_tune_t{best.radix_cfg, best.key_bits, best.seg_len, best.seg_overlap, 0,
+                               best_ms, trials};
     return BWT_OK;
 }
 

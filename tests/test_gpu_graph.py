@@ -120,3 +120,85 @@ def test_incremental_appends_and_host_inputs(torch_dev, oracle_mod):
                     g.append(*_dev(torch, p, o))
             assert g.export() == want, rep
         assert g.stats()["graph_replays"] == 9
+
+
+def test_batched_replays_equal_eager_and_oracle(torch_dev, oracle_mod):
+    """A whole append_many captured once and replayed: every set's index
+    equals the eager batch's and, for a sample of sets, the oracle's; sets
+    larger than a block take several levels."""
+    torch = torch_dev
+    from paper_1410_0562_amd import bwtset
+    rng = np.random.default_rng(105)
+    sets = []
+    for k in range(40):
+        m = int(rng.integers(50, 3000))
+        sets.append(synth.random_reads(300 + k, m, 0, int(rng.integers(40, 250))))
+    dev = [_dev(torch, p, o) for p, o in sets]
+    M = 120_000
+    hg = [bwtset.BwtSet(block_size=M) for _ in sets]
+    he = [bwtset.BwtSet(block_size=M) for _ in sets]
+    try:
+        hg[0].set_param(bwtset.BWT_PARAM_GRAPH, 1)
+        bwtset.append_many(he, [r for r, _ in dev], [o for _, o in dev])
+        eager = [h.export() for h in he]
+        for k in (0, 7, 21, 39):
+            assert eager[k] == oracle_mod.bwt_of_codes(*oracle_mod.reads_from_packed(*sets[k])), k
+        hg[0].stats(reset=True)
+        for rep in range(4):
+            _log("batched replay %d" % rep)
+            for h in hg:
+                h.reset()
+            bwtset.append_many(hg, [r for r, _ in dev], [o for _, o in dev])
+            for k, h in enumerate(hg):
+                assert h.export() == eager[k], (rep, k)
+            # eager work of the program between replays
+            he[3].reset()
+            he[3].append(*dev[3])
+            torch.cuda.synchronize()
+        st = hg[0].stats()
+        assert st["graph_replays"] == 4 and st["graph_redos"] == 0
+        assert 1 <= st["graph_captures"] <= 3
+    finally:
+        for h in hg + he:
+            h.close()
+
+
+def test_autotune_keeps_results_and_caches(torch_dev, oracle_mod, tmp_path, monkeypatch):
+    """The autotuner times settings that never change a result: after it the
+    index still equals the oracle's; a second call of the same shape class
+    comes from the cache."""
+    torch = torch_dev
+    from paper_1410_0562_amd import bwtset
+    packed, offs = synth.random_reads(106, 3000, 50, 150)
+    want = oracle_mod.bwt_of_codes(*oracle_mod.reads_from_packed(packed, offs))
+    dr, do = _dev(torch, packed, offs)
+    with bwtset.BwtSet(block_size=70_000) as h:
+        t1 = h.autotune(dr, do, force=True)
+        assert t1["from_cache"] == 0 and t1["trials"] >= 5
+        assert t1["key_bits"] in (64, 48, 40, 32) and t1["radix_tile"] in (3, 0, 1, 5)
+        h.append(dr, do)
+        assert h.export() == want
+        t2 = h.autotune(dr, do)
+        assert t2["from_cache"] == 1
+        assert (t2["key_bits"], t2["radix_tile"], t2["rank_segment"]) == \
+            (t1["key_bits"], t1["radix_tile"], t1["rank_segment"])
+        # the index was not changed by tuning
+        assert h.export() == want
+
+
+@pytest.mark.parametrize("seg,ov", [(32, 16), (64, 8), (48, 0)])
+def test_short_segments_are_exact(torch_dev, oracle_mod, seg, ov):
+    """Segments down to 32 symbols (what the tuner tries on short reads),
+    with retries, through whole appends on a growing index."""
+    torch = torch_dev
+    from paper_1410_0562_amd import bwtset
+    packed, offs = synth.short_reads(m=6000, length=100, ref_len=30_000, seed=107)
+    want = oracle_mod.bwt_of_codes(*oracle_mod.reads_from_packed(packed, offs))
+    with bwtset.BwtSet(block_size=100_000) as h:
+        h.set_param(bwtset.BWT_PARAM_RANK_SEGMENT, seg)
+        h.set_param(bwtset.BWT_PARAM_RANK_OVERLAP, ov)
+        h.enable_timing(True)
+        h.append(packed, offs)
+        st = h.stats()
+        assert h.export() == want
+        assert st["ranks_seg_symbols"] > 0
