@@ -431,6 +431,8 @@ def main():
                     help="radix pass tile shape (library default if omitted)")
     ap.add_argument("--graph", action="store_true",
                     help="capture each append in a HIP graph and replay it (BWT_PARAM_GRAPH)")
+    ap.add_argument("--host-index", action="store_true",
+                    help="keep the index in pinned host memory (BWT_PARAM_HOST_INDEX)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner on the workload first (untimed)")
     ap.add_argument("--cpu-sample-bases", type=int, default=None,
@@ -533,6 +535,8 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
     idx = bwtset.BwtSet(block_size=block)
     if args.graph and own:
         idx.set_param(bwtset.BWT_PARAM_GRAPH, 1)
+    if args.host_index and own:
+        idx.set_param(bwtset.BWT_PARAM_HOST_INDEX, 1)
     if args.key_bits is not None:
         idx.set_key_bits(args.key_bits)
     if args.radix_tile is not None:
@@ -626,7 +630,8 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
                    "reads": m, "bases": bases, "block_suffixes": block,
                    "blocks": st["blocks"] // steps, "key_bits": args.key_bits,
                    "radix_tile": args.radix_tile, "graph": bool(args.graph and own),
-                   "graph_replays": graph_replays, "autotune": tune},
+                   "graph_replays": graph_replays, "autotune": tune,
+                   "host_index": bool(args.host_index and own)},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
         "stages_ms_per_step": {s: round(st["ms"][s] / steps, 3) for s in bwtset.STAGES},

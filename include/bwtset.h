@@ -188,6 +188,15 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     bucket of equal top bits) and one wavefront finishes each bucket in
  *     registers (blocks of 2^20 suffixes or more); 0 = radix passes over the
  *     whole key. */
+/*   BWT_PARAM_HOST_INDEX: 1 = the host-memory tier (Section 5 keeps the
+ *     partial BWT in system memory; Section 6's bound is constant GPU memory):
+ *     the index records and their occurrence counters are allocated in
+ *     pinned host memory that the kernels read and write over the host link,
+ *     so an index may exceed device memory while the device holds only the
+ *     per-block workspace (bounded by the block size) and a few words per
+ *     index buffer.  Buffers move to the chosen tier as they are next
+ *     written (the next append moves the whole index).  bwt_set_memory
+ *     counts device memory only.  0 (default) = index in device memory. */
 /*   BWT_PARAM_GRAPH: 1 = bwt_set_append captures its blocks (every kernel of
  *     ConstructSA, ComputeRanks and Insert, with the tied-suffix count read on
  *     the device by a persistent refinement) into a HIP graph the first time
@@ -209,7 +218,8 @@ enum {
     BWT_PARAM_RANK_OVERLAP = 4,
     BWT_PARAM_BATCH_LANES = 5,
     BWT_PARAM_SORT_BUCKETS = 6,
-    BWT_PARAM_GRAPH = 7
+    BWT_PARAM_GRAPH = 7,
+    BWT_PARAM_HOST_INDEX = 8
 };
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
 

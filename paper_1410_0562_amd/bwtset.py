@@ -98,6 +98,7 @@ BWT_PARAM_RANK_OVERLAP = 4
 BWT_PARAM_BATCH_LANES = 5
 BWT_PARAM_SORT_BUCKETS = 6
 BWT_PARAM_GRAPH = 7
+BWT_PARAM_HOST_INDEX = 8
 
 _lib = None
 

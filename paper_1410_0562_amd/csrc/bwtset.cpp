@@ -48,6 +48,7 @@ struct IndexBuf {
     uint64_t *sbc = nullptr;
     uint64_t sbc_cap = 0;
     uint64_t *meta = nullptr;
+    bool host = false;   // recs and sbc in pinned host memory (the host-memory tier)
 };
 
 // Device scratch for one block of at most `cap` suffixes.
@@ -149,6 +150,7 @@ struct bwt_set {
     uint32_t seg_len = 768;          // ComputeRanks segment length for long reads
     uint32_t seg_overlap = 64;       // symbols a segment walk starts past its end
     bool sort_buckets = true;        // first sort: top digits + LDS bucket finish
+    bool host_index = false;         // index records and counters in pinned host memory
     uint64_t *first_new = nullptr;
     uint64_t first_new_cap = 0;
     // staging for host inputs / outputs
@@ -243,6 +245,37 @@ void dfree(T *&p) {
         (void)hipFree(p);
     }
     p = nullptr;
+}
+
+// Pinned host memory the GPU reads and writes directly (coherent, mapped
+// into the device's address space): the host-memory tier of the index.
+template <class T>
+hipError_t halloc(T **p, uint64_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    g_alloc_gen.fetch_add(1);
+    return hipHostMalloc((void **)p, count * sizeof(T), hipHostMallocDefault);
+}
+
+template <class T>
+void hfree(T *&p) {
+    if (p) {
+        g_alloc_gen.fetch_add(1);
+        (void)hipHostFree(p);
+    }
+    p = nullptr;
+}
+
+// Frees an index buffer's records and counters wherever they live.
+void free_index_data(IndexBuf &b) {
+    if (b.host) {
+        hfree(b.recs);
+        hfree(b.sbc);
+    } else {
+        dfree(b.recs);
+        dfree(b.sbc);
+    }
+    b.rec_cap = b.sbc_cap = 0;
 }
 
 bool is_device_ptr(const void *p) {
@@ -373,11 +406,17 @@ void timer_collect(bwt_set *h) {
 // ---- memory ---------------------------------------------------------------
 int ensure_index(bwt_set *h, IndexBuf &b, uint64_t n) {
     uint64_t nr = records_for(n), ns = superblocks_for(n);
+    if (b.host != h->host_index) {
+        // the buffer moves to the tier the handle now uses
+        free_index_data(b);
+        b.host = h->host_index;
+    }
     if (b.rec_cap < nr) {
         uint64_t cap = std::max<uint64_t>(nr, b.rec_cap + b.rec_cap / 2);
-        dfree(b.recs);
+        if (b.host) hfree(b.recs);
+        else dfree(b.recs);
         b.rec_cap = 0;
-        if (dalloc(&b.recs, cap) != hipSuccess) {
+        if ((b.host ? halloc(&b.recs, cap) : dalloc(&b.recs, cap)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(h, BWT_ENOMEM);
         }
@@ -385,9 +424,10 @@ int ensure_index(bwt_set *h, IndexBuf &b, uint64_t n) {
     }
     if (b.sbc_cap < ns) {
         uint64_t cap = std::max<uint64_t>(ns, 4);
-        dfree(b.sbc);
+        if (b.host) hfree(b.sbc);
+        else dfree(b.sbc);
         b.sbc_cap = 0;
-        if (dalloc(&b.sbc, cap * 4) != hipSuccess) {
+        if ((b.host ? halloc(&b.sbc, cap * 4) : dalloc(&b.sbc, cap * 4)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(h, BWT_ENOMEM);
         }
@@ -1676,8 +1716,7 @@ void bwt_set_destroy(bwt_set_t h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (auto &b : h->buf) {
-        dfree(b.recs);
-        dfree(b.sbc);
+        free_index_data(b);
         dfree(b.meta);
     }
     free_ws(h->ws);
@@ -2275,8 +2314,8 @@ int bwt_set_memory(bwt_set_t h, uint64_t *bytes) {
     if (!h || !bytes) return BWT_EINVAL;
     uint64_t b = 0;
     for (auto &x : h->buf) {
-        if (x.recs) b += x.rec_cap * sizeof(Rec);
-        if (x.sbc) b += x.sbc_cap * 4 * 8;
+        if (x.recs && !x.host) b += x.rec_cap * sizeof(Rec);
+        if (x.sbc && !x.host) b += x.sbc_cap * 4 * 8;
         if (x.meta) b += META_WORDS * 8;
     }
     const Workspace &w = h->ws;
@@ -2299,10 +2338,8 @@ int bwt_set_trim(bwt_set_t h) {
     for (int b = 0; b < 3; ++b) {
         if (b == h->cur) continue;
         IndexBuf &x = h->buf[b];
-        dfree(x.recs);
-        dfree(x.sbc);
+        free_index_data(x);
         dfree(x.meta);
-        x.rec_cap = x.sbc_cap = 0;
     }
     free_ws(h->ws);
     dfree(h->first_new);
@@ -2374,6 +2411,10 @@ int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
     case BWT_PARAM_RANK_OVERLAP:
         if (value < 0 || value > (1 << 24)) return fail(h, BWT_EINVAL);
         h->seg_overlap = (uint32_t)value;
+        return BWT_OK;
+    case BWT_PARAM_HOST_INDEX:
+        if (value != 0 && value != 1) return fail(h, BWT_EINVAL);
+        h->host_index = value != 0;
         return BWT_OK;
     case BWT_PARAM_GRAPH:
         if (value != 0 && value != 1) return fail(h, BWT_EINVAL);
