@@ -431,6 +431,10 @@ def main():
                     help="radix pass tile shape (library default if omitted)")
     ap.add_argument("--graph", action="store_true",
                     help="capture each append in a HIP graph and replay it (BWT_PARAM_GRAPH)")
+    ap.add_argument("--host-input", action="store_true",
+                    help="pass the reads from host memory (the host-to-device copy is timed)")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="with --host-input: copy all reads before the first block")
     ap.add_argument("--host-index", action="store_true",
                     help="keep the index in pinned host memory (BWT_PARAM_HOST_INDEX)")
     ap.add_argument("--autotune", action="store_true",
@@ -527,8 +531,11 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         packed, offs = synth.uniform_reads(m=nreads or 10_000)
     bases = int(offs[-1]) - int(offs[0])
     m = len(offs) - 1
-    dev_reads = torch.from_numpy(packed).cuda()
-    dev_offs = torch.from_numpy(offs.view(np.int64)).cuda()
+    if args.host_input and own:
+        dev_reads, dev_offs = packed, offs          # host buffers: staged by the library
+    else:
+        dev_reads = torch.from_numpy(packed).cuda()
+        dev_offs = torch.from_numpy(offs.view(np.int64)).cuda()
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
@@ -537,6 +544,8 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         idx.set_param(bwtset.BWT_PARAM_GRAPH, 1)
     if args.host_index and own:
         idx.set_param(bwtset.BWT_PARAM_HOST_INDEX, 1)
+    if args.no_pipeline and own:
+        idx.set_param(bwtset.BWT_PARAM_PIPELINE, 0)
     if args.key_bits is not None:
         idx.set_key_bits(args.key_bits)
     if args.radix_tile is not None:
@@ -631,7 +640,9 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
                    "blocks": st["blocks"] // steps, "key_bits": args.key_bits,
                    "radix_tile": args.radix_tile, "graph": bool(args.graph and own),
                    "graph_replays": graph_replays, "autotune": tune,
-                   "host_index": bool(args.host_index and own)},
+                   "host_index": bool(args.host_index and own),
+                   "host_input": bool(args.host_input and own),
+                   "pipeline": not (args.no_pipeline and own)},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kinfo.items()},
         "stages_ms_per_step": {s: round(st["ms"][s] / steps, 3) for s in bwtset.STAGES},

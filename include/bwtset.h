@@ -188,6 +188,13 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     bucket of equal top bits) and one wavefront finishes each bucket in
  *     registers (blocks of 2^20 suffixes or more); 0 = radix passes over the
  *     whole key. */
+/*   BWT_PARAM_PIPELINE: 1 (default) = reads in host memory are streamed to
+ *     the device block by block (the paper's stage pipeline with multiple
+ *     buffering, Results and Figure 1): a second host thread copies block
+ *     k+1's reads into one of two pinned slots and a copy stream sends them
+ *     to one of two device slots while block k runs, events ordering the two
+ *     streams.  0 = all host reads are copied to the device before the first
+ *     block.  Not used by captured appends (BWT_PARAM_GRAPH). */
 /*   BWT_PARAM_HOST_INDEX: 1 = the host-memory tier (Section 5 keeps the
  *     partial BWT in system memory; Section 6's bound is constant GPU memory):
  *     the index records and their occurrence counters are allocated in
@@ -219,7 +226,8 @@ enum {
     BWT_PARAM_BATCH_LANES = 5,
     BWT_PARAM_SORT_BUCKETS = 6,
     BWT_PARAM_GRAPH = 7,
-    BWT_PARAM_HOST_INDEX = 8
+    BWT_PARAM_HOST_INDEX = 8,
+    BWT_PARAM_PIPELINE = 9
 };
 int bwt_set_set_param(bwt_set_t h, int param, int64_t value);
 

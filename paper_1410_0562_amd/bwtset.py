@@ -99,6 +99,7 @@ BWT_PARAM_BATCH_LANES = 5
 BWT_PARAM_SORT_BUCKETS = 6
 BWT_PARAM_GRAPH = 7
 BWT_PARAM_HOST_INDEX = 8
+BWT_PARAM_PIPELINE = 9
 
 _lib = None
 

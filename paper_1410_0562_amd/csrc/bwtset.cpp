@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <chrono>
+#include <condition_variable>
 #include <cstdlib>
 #include <fstream>
 #include <map>
@@ -40,6 +41,28 @@ uint32_t next_epoch() {
     uint32_t e = g_epoch.fetch_add(1) & 0x3fffffffu;
     if (e == 0) e = g_epoch.fetch_add(1) & 0x3fffffffu;
     return e;
+}
+
+// Staging of host reads streamed block by block (append_streamed): two pinned
+// host slots, a copy stream and the events that order it with the compute
+// stream.
+struct Pipe {
+    uint8_t *pinned = nullptr;       // 2 slots of slot_bytes
+    uint64_t slot_bytes = 0;
+    hipStream_t copy = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, consumed[2] = {nullptr, nullptr};
+};
+
+void pipe_free(Pipe &p) {
+    if (p.pinned) (void)hipHostFree(p.pinned);
+    p.pinned = nullptr;
+    p.slot_bytes = 0;
+    for (auto &e : p.copied)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+    for (auto &e : p.consumed)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+    if (p.copy) (void)hipStreamDestroy(p.copy);
+    p.copy = nullptr;
 }
 
 struct IndexBuf {
@@ -151,6 +174,8 @@ struct bwt_set {
     uint32_t seg_overlap = 64;       // symbols a segment walk starts past its end
     bool sort_buckets = true;        // first sort: top digits + LDS bucket finish
     bool host_index = false;         // index records and counters in pinned host memory
+    bool pipeline = true;            // host reads streamed block by block (pipelined)
+    Pipe *pipe = nullptr;
     uint64_t *first_new = nullptr;
     uint64_t first_new_cap = 0;
     // staging for host inputs / outputs
@@ -920,16 +945,20 @@ int insert_block(bwt_set *h, hipStream_t s, const IndexBuf &src, IndexBuf &dst, 
 
 // ---- input planning -----------------------------------------------------------
 struct Plan {
-    const uint8_t *reads = nullptr;   // device
-    const uint64_t *off = nullptr;    // device, m + 1 entries
+    const uint8_t *reads = nullptr;   // device (null: host reads left in place)
+    const uint64_t *off = nullptr;    // device, m + 1 entries (null with host reads left)
     std::vector<uint64_t> cut_j;      // block boundaries (read indices), K + 1
     std::vector<uint64_t> cut_s;      // block-text position S(j) of each boundary
     uint64_t total_suffixes = 0;
     uint64_t maxlen = 0;              // longest read
+    const uint8_t *host_reads = nullptr;  // host reads left in place (stream_host)
+    std::vector<uint64_t> hoff;       // their offsets, on the host
 };
 
+// stream_host: host reads are not copied here (the caller streams them to
+// the device block by block); the plan then keeps the host offsets.
 int plan_input(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *offsets,
-               uint64_t m, uint64_t M, Plan &P) {
+               uint64_t m, uint64_t M, Plan &P, bool stream_host = false) {
     const bool off_dev = is_device_ptr(offsets);
     const bool reads_dev = is_device_ptr(reads);
     std::vector<uint64_t> hoff;
@@ -968,6 +997,11 @@ int plan_input(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *
             j = k;
         }
         P.total_suffixes = hoff[m] - o0 + m;
+        if (stream_host && !reads_dev) {
+            P.host_reads = reads;
+            P.hoff = std::move(hoff);
+            return BWT_OK;
+        }
         // device copies
         uint64_t base_sym = o0 & ~3ull;
         if (!reads_dev) {
@@ -1732,6 +1766,11 @@ void bwt_set_destroy(bwt_set_t h) {
     for (auto *l : h->lanes) bwt_set_destroy(l);
     h->lanes.clear();
     drop_graphs(h);
+    if (h->pipe) {
+        pipe_free(*h->pipe);
+        delete h->pipe;
+        h->pipe = nullptr;
+    }
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     dfree(h->res);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -1752,8 +1791,47 @@ namespace {
 // written by block b-1 (the current one for b = 0) and writes other[b & 1].
 // Nothing here waits for the device while h->capturing is set.  *src_out is
 // the buffer that holds the result.
-int enqueue_blocks(bwt_set *h, hipStream_t s, const Plan &P, const int other[2], int *src_out) {
+// One block of an append: reads/off (device; off points at the block's first
+// read, m_blk + 1 entries) ranked against src, merged into dst.
+int enqueue_block(bwt_set *h, hipStream_t s, const uint8_t *reads, const uint64_t *off,
+                  uint32_t m_blk, uint32_t n_blk, uint64_t maxlen, int src, int dst,
+                  uint64_t n_cur) {
     Workspace &w = h->ws;
+    int rc;
+    IndexBuf &S = h->buf[src];
+    if ((rc = block_prep(h, s, off, m_blk, n_blk))) return rc;
+    // ComputeRanks first: g leads the suffix sort key (an empty index ranks
+    // every suffix 0, so the first block skips it)
+    const int gbits = bits_for_value(n_cur);
+    if (gbits > 0) {
+        Scope sc(h, s, BWT_STAGE_RANKS);
+        const RankKeys kk = rank_keys(h, s, gbits, n_blk, &rc);
+        if (rc) return fail(h, rc);
+        MarkSet mk(h, 3);
+        HIPCHK(h, launch_compute_ranks(reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc, S.meta,
+                                       n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
+                                       rank_segments(h, maxlen), w.misc + MISC_ERR, s, mk.get()));
+        mk.add(0, SPAN_RANKS_K, n_blk - m_blk);
+        mk.add(1, SPAN_RANKS_SEG, 0);
+        mk.add(2, SPAN_RANKS_FB, 0);
+    }
+    uint32_t *sa = nullptr;
+    const uint64_t *gkeys = nullptr;
+    int gshift = 64;
+    if ((rc = block_sort(h, s, reads, off, m_blk, n_blk, maxlen, w.g, gbits, gbits > 0, &sa, &gkeys,
+                         &gshift)))
+        return rc;
+    if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gshift, sa, n_blk, m_blk)))
+        return rc;
+    h->timer.acc.blocks += 1;
+    return BWT_OK;
+}
+
+// The blocks of one planned append, enqueued on s: block b reads the index
+// written by block b-1 (the current one for b = 0) and writes other[b & 1].
+// Nothing here waits for the device while h->capturing is set.  *src_out is
+// the buffer that holds the result.
+int enqueue_blocks(bwt_set *h, hipStream_t s, const Plan &P, const int other[2], int *src_out) {
     int src = h->cur, rc;
     uint64_t n_cur = h->n;
     const size_t K = P.cut_j.size() - 1;
@@ -1761,38 +1839,151 @@ int enqueue_blocks(bwt_set *h, hipStream_t s, const Plan &P, const int other[2],
         const uint64_t j0 = P.cut_j[b], j1 = P.cut_j[b + 1];
         const uint32_t m_blk = (uint32_t)(j1 - j0);
         const uint32_t n_blk = (uint32_t)(P.cut_s[b + 1] - P.cut_s[b]);
-        const uint64_t *off = P.off + j0;
-        IndexBuf &S = h->buf[src];
-        if ((rc = block_prep(h, s, off, m_blk, n_blk))) return rc;
-        // ComputeRanks first: g leads the suffix sort key (an empty index
-        // ranks every suffix 0, so the first block skips it)
-        const int gbits = bits_for_value(n_cur);
-        if (gbits > 0) {
-            Scope sc(h, s, BWT_STAGE_RANKS);
-            const RankKeys kk = rank_keys(h, s, gbits, n_blk, &rc);
-            if (rc) return fail(h, rc);
-            MarkSet mk(h, 3);
-            HIPCHK(h, launch_compute_ranks(P.reads, off, w.soff, m_blk, n_blk, S.recs, S.sbc,
-                                           S.meta, n_cur >= (1ull << SB_SHIFT) ? 1 : 0, w.g, &kk,
-                                           rank_segments(h, P.maxlen), w.misc + MISC_ERR, s,
-                                           mk.get()));
-            mk.add(0, SPAN_RANKS_K, n_blk - m_blk);
-            mk.add(1, SPAN_RANKS_SEG, 0);
-            mk.add(2, SPAN_RANKS_FB, 0);
-        }
-        uint32_t *sa = nullptr;
-        const uint64_t *gkeys = nullptr;
-        int gshift = 64;
-        if ((rc = block_sort(h, s, P.reads, off, m_blk, n_blk, P.maxlen, w.g, gbits, gbits > 0, &sa,
-                             &gkeys, &gshift)))
-            return rc;
         const int dst = other[b & 1];
-        if ((rc = insert_block(h, s, S, h->buf[dst], n_cur, gkeys, gshift, sa, n_blk, m_blk)))
+        if ((rc = enqueue_block(h, s, P.reads, P.off + j0, m_blk, n_blk, P.maxlen, src, dst,
+                                n_cur)))
             return rc;
         n_cur += n_blk;
-        h->timer.acc.blocks += 1;
         src = dst;
     }
+    *src_out = src;
+    return BWT_OK;
+}
+
+// ---- pipelined blocks: host reads streamed block by block -----------------------
+// The paper's pipeline (Results, Figure 1) overlaps reading the input with
+// the GPU and CPU stages, with multiple buffering.  Here a producer thread
+// copies block k+1's reads (and its offsets, rebased) into one of two pinned
+// slots and sends them to one of two device slots on a copy stream, while the
+// blocks before it run on the compute stream; events order the two streams
+// (a slot is refilled only after the block that used it is done).
+int append_streamed(bwt_set *h, hipStream_t s, const Plan &P, const int other[2], int *src_out) {
+    Pipe &pp = *h->pipe;
+    const size_t K = P.cut_j.size() - 1;
+    const uint64_t o0 = P.hoff[0];
+    // per block: first byte of its reads, bytes, rebased offsets
+    uint64_t max_bytes = 0, max_m = 0;
+    for (size_t b = 0; b < K; ++b) {
+        const uint64_t s0 = P.hoff[P.cut_j[b]], s1 = P.hoff[P.cut_j[b + 1]];
+        max_bytes = std::max(max_bytes, (s1 + 3) / 4 - s0 / 4);
+        max_m = std::max(max_m, P.cut_j[b + 1] - P.cut_j[b]);
+    }
+    (void)o0;
+    const uint64_t rb = (max_bytes + 16 + 255) & ~255ull, ob = ((max_m + 1) * 8 + 255) & ~255ull;
+    const uint64_t slot = rb + ob;
+    int rc;
+    if ((rc = ensure_buf(h, h->stage_reads, h->stage_reads_cap, 2 * slot))) return rc;
+    if (pp.slot_bytes < slot) {
+        if (pp.pinned) (void)hipHostFree(pp.pinned);
+        pp.pinned = nullptr;
+        pp.slot_bytes = 0;
+        if (hipHostMalloc((void **)&pp.pinned, 2 * slot, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, BWT_ENOMEM);
+        }
+        pp.slot_bytes = slot;
+    }
+    if (!pp.copy && hipStreamCreateWithFlags(&pp.copy, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        pp.copy = nullptr;
+        return fail(h, BWT_EHIP);
+    }
+    for (int q = 0; q < 2; ++q) {
+        if (!pp.copied[q]) HIPCHK(h, hipEventCreateWithFlags(&pp.copied[q], hipEventDisableTiming));
+        if (!pp.consumed[q])
+            HIPCHK(h, hipEventCreateWithFlags(&pp.consumed[q], hipEventDisableTiming));
+    }
+    uint8_t *dev = h->stage_reads;
+    // host side handshake: ready = blocks staged, enqueued = blocks whose
+    // compute (and its consumed event) has been enqueued
+    std::mutex mu;
+    std::condition_variable cv;
+    size_t ready = 0, enqueued = 0;
+    bool stop = false;
+    int prc = BWT_OK;
+    std::thread producer([&] {
+        int e = BWT_OK;
+        if (hipSetDevice(h->device) != hipSuccess) e = BWT_EHIP;
+        for (size_t b = 0; b < K && e == BWT_OK; ++b) {
+            const int q = (int)(b & 1);
+            if (b >= 2) {
+                // the slot's previous block: its compute enqueued, its copy done
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop || enqueued >= b - 1; });
+                if (stop) break;
+                lk.unlock();
+                if (hipEventSynchronize(pp.copied[q]) != hipSuccess) {
+                    e = BWT_EHIP;
+                    break;
+                }
+            }
+            const uint64_t j0 = P.cut_j[b], j1 = P.cut_j[b + 1];
+            const uint64_t s0 = P.hoff[j0], s1 = P.hoff[j1];
+            const uint64_t byte0 = s0 / 4, nbytes = (s1 + 3) / 4 - byte0;
+            uint8_t *hp = pp.pinned + q * slot;
+            if (nbytes) memcpy(hp, P.host_reads + byte0, nbytes);
+            uint64_t *ho = reinterpret_cast<uint64_t *>(hp + rb);
+            for (uint64_t j = j0; j <= j1; ++j) ho[j - j0] = P.hoff[j] - 4 * byte0;
+            hipStream_t c = pp.copy;
+            bool ok = true;
+            if (b >= 2) ok = hipStreamWaitEvent(c, pp.consumed[q], 0) == hipSuccess;
+            ok = ok && (!nbytes || hipMemcpyAsync(dev + q * slot, hp, nbytes, hipMemcpyHostToDevice,
+                                                  c) == hipSuccess);
+            ok = ok && hipMemcpyAsync(dev + q * slot + rb, ho, (j1 - j0 + 1) * 8,
+                                      hipMemcpyHostToDevice, c) == hipSuccess;
+            ok = ok && hipEventRecord(pp.copied[q], c) == hipSuccess;
+            if (!ok) {
+                e = BWT_EHIP;
+                break;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            ready = b + 1;
+            cv.notify_all();
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        prc = e;
+        stop = true;
+        cv.notify_all();
+    });
+    int src = h->cur;
+    uint64_t n_cur = h->n;
+    for (size_t b = 0; b < K; ++b) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return ready > b || stop; });
+            if (ready <= b) {
+                rc = prc ? prc : BWT_EHIP;
+                break;
+            }
+        }
+        const int q = (int)(b & 1);
+        const uint32_t m_blk = (uint32_t)(P.cut_j[b + 1] - P.cut_j[b]);
+        const uint32_t n_blk = (uint32_t)(P.cut_s[b + 1] - P.cut_s[b]);
+        const int dst = other[b & 1];
+        rc = hipStreamWaitEvent(s, pp.copied[q], 0) == hipSuccess ? BWT_OK : BWT_EHIP;
+        if (!rc)
+            rc = enqueue_block(h, s, dev + q * slot,
+                               reinterpret_cast<const uint64_t *>(dev + q * slot + rb), m_blk,
+                               n_blk, P.maxlen, src, dst, n_cur);
+        if (!rc && hipEventRecord(pp.consumed[q], s) != hipSuccess) rc = BWT_EHIP;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (rc) stop = true;
+            else enqueued = b + 1;
+            cv.notify_all();
+        }
+        if (rc) break;
+        n_cur += n_blk;
+        src = dst;
+    }
+    producer.join();
+    if (rc) {
+        (void)hipStreamSynchronize(pp.copy);
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+        return fail(h, rc == BWT_EHIP ? BWT_EHIP : rc);
+    }
+    if (prc) return fail(h, prc);
     *src_out = src;
     return BWT_OK;
 }
@@ -1876,9 +2067,11 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
     if (rc) return rc;
     hipStream_t s = stream ? (hipStream_t)stream : h->stream;
     Plan P;
+    // host reads are streamed block by block (pipelined) unless captured
+    const bool stream_in = h->pipeline && !h->graph && !is_device_ptr(reads);
     {
         Scope sc(h, s, BWT_STAGE_PLAN);
-        rc = plan_input(h, s, reads, offsets, m, h->M, P);
+        rc = plan_input(h, s, reads, offsets, m, h->M, P, stream_in);
     }
     if (rc) {
         if (h->timer.on) {
@@ -1922,7 +2115,13 @@ int bwt_set_append(bwt_set_t h, const uint8_t *reads, const uint64_t *offsets, u
     }
     if (!done) {
         if ((rc = clear_err(h, s))) return rc;
-        if ((rc = enqueue_blocks(h, s, P, other, &src))) return rc;
+        if (P.host_reads) {
+            if (!h->pipe) h->pipe = new (std::nothrow) Pipe();
+            if (!h->pipe) return fail(h, BWT_ENOMEM);
+            if ((rc = append_streamed(h, s, P, other, &src))) return rc;
+        } else if ((rc = enqueue_blocks(h, s, P, other, &src))) {
+            return rc;
+        }
         HIPCHK(h, hipStreamSynchronize(s));
         if (h->timer.on) timer_collect(h);
         if ((rc = check_err(h, s))) return rc;
@@ -2335,6 +2534,7 @@ int bwt_set_trim(bwt_set_t h) {
     if (!h) return BWT_EINVAL;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     drop_graphs(h);
+    if (h->pipe) pipe_free(*h->pipe);
     for (int b = 0; b < 3; ++b) {
         if (b == h->cur) continue;
         IndexBuf &x = h->buf[b];
@@ -2411,6 +2611,10 @@ int bwt_set_set_param(bwt_set_t h, int param, int64_t value) {
     case BWT_PARAM_RANK_OVERLAP:
         if (value < 0 || value > (1 << 24)) return fail(h, BWT_EINVAL);
         h->seg_overlap = (uint32_t)value;
+        return BWT_OK;
+    case BWT_PARAM_PIPELINE:
+        if (value != 0 && value != 1) return fail(h, BWT_EINVAL);
+        h->pipeline = value != 0;
         return BWT_OK;
     case BWT_PARAM_HOST_INDEX:
         if (value != 0 && value != 1) return fail(h, BWT_EINVAL);

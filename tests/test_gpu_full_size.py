@@ -56,9 +56,12 @@ def _sha_of_index(torch, idx):
     return hashlib.sha256(host.tobytes()).hexdigest(), n
 
 
-@pytest.mark.parametrize("key,block", [("uniform_10k", 1 << 18), ("short_reads_4M", 1 << 26),
-                                       ("long_reads_250k", 1 << 27)])
-def test_plain_workload_bwt_digest(torch_dev, key, block):
+@pytest.mark.parametrize("key,block,where", [("uniform_10k", 1 << 18, "device"),
+                                             ("short_reads_4M", 1 << 26, "device"),
+                                             ("long_reads_250k", 1 << 27, "device"),
+                                             ("short_reads_4M", 1 << 26, "host, pipelined"),
+                                             ("long_reads_250k", 1 << 27, "host, pipelined")])
+def test_plain_workload_bwt_digest(torch_dev, key, block, where):
     torch = torch_dev
     from paper_1410_0562_amd import bwtset
     want = _golden(key)
@@ -70,9 +73,12 @@ def test_plain_workload_bwt_digest(torch_dev, key, block):
     else:
         packed, offs = synth.long_reads(threads=16)
     assert int(offs[-1]) == want["bases"] and len(offs) - 1 == want["strings"]
-    dev_reads = torch.from_numpy(packed).cuda()
-    dev_offs = torch.from_numpy(offs.view(np.int64)).cuda()
-    _log("%s: building %d bases, block %d" % (key, want["bases"], block))
+    if where == "device":
+        dev_reads = torch.from_numpy(packed).cuda()
+        dev_offs = torch.from_numpy(offs.view(np.int64)).cuda()
+    else:
+        dev_reads, dev_offs = packed, offs       # streamed block by block
+    _log("%s: building %d bases, block %d, input %s" % (key, want["bases"], block, where))
     with bwtset.BwtSet(block_size=block) as idx:
         idx.append(dev_reads, dev_offs)
         sha, n = _sha_of_index(torch, idx)
