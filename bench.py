@@ -198,6 +198,51 @@ def summarize_profile(root, workload, command_note):
         f.write("\n".join(table) + "\n")
 
 
+def summarize_overlap(folder, command_note, out_name):
+    """From a rocprofv3 kernel trace: how much of the time kernels of
+    different HIP streams ran at the same moment on the device (the served
+    form's batches on their own streams).  Writes profiles/<out_name>.md."""
+    rows = _csv_rows(folder, "kernel_trace.csv")
+    ev = []
+    for r in rows:
+        a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if b > a:
+            sid = (r.get("Queue_Id"), r.get("Stream_Id"))
+            ev.append((a, 1, sid))
+            ev.append((b, -1, sid))
+    ev.sort(key=lambda e: (e[0], e[1]))
+    active = {}
+    t_prev = ev[0][0]
+    busy = multi = 0
+    hist = {}
+    for t, d, sid in ev:
+        nact = sum(1 for v in active.values() if v > 0)
+        dt = t - t_prev
+        if nact >= 1:
+            busy += dt
+        if nact >= 2:
+            multi += dt
+        hist[nact] = hist.get(nact, 0) + dt
+        active[sid] = active.get(sid, 0) + d
+        t_prev = t
+    span = ev[-1][0] - ev[0][0]
+    streams = {sid for _, _, sid in ev}
+    lines = ["# Kernels of different streams running at once: %s" % out_name, "",
+             "Commands (repository root = `$R` on the GPU box):", "", "```",
+             command_note.strip(), "```", "",
+             "Kernel dispatches: %d on %d streams.  Span from the first kernel start to the last "
+             "kernel end: %.1f ms; time with at least one kernel running: %.1f ms; time with "
+             "kernels of two or more streams running at once: %.1f ms (%.1f%% of the busy time)."
+             % (len(rows), len(streams), span / 1e6, busy / 1e6, multi / 1e6,
+                100.0 * multi / max(busy, 1)), "",
+             "| streams with a kernel running | ms | share of busy time |", "|---:|---:|---:|"]
+    for k in sorted(hist):
+        if k >= 1:
+            lines.append("| %d | %.1f | %.1f%% |" % (k, hist[k] / 1e6, 100.0 * hist[k] / max(busy, 1)))
+    with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -440,7 +485,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner on the workload first (untimed)")
     ap.add_argument("--cpu-sample-bases", type=int, default=None,
-                    help="bases of the oracle's sample (default: a quarter of the workload)")
+                    help="bases of the oracle's sample (default: a sixth of the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
@@ -448,6 +493,9 @@ def main():
                     help="no GPU work: write profiles/ summaries for --workload from the "
                          "rocprofv3 runs under DIR (stats/, fetch/, write/, copy_fetch/, "
                          "copy_write/)")
+    ap.add_argument("--summarize-overlap", metavar="DIR", default=None,
+                    help="no GPU work: write profiles/served_16_tenants_overlap.md from the "
+                         "rocprofv3 kernel trace under DIR")
     ap.add_argument("--profile-commands", metavar="FILE", default=None,
                     help="with --summarize-profile: text file holding the commands that made "
                          "the runs")
@@ -467,6 +515,10 @@ def main():
     ap.add_argument("--set-reads", type=str, default=None,
                     help="batched form: MIN,MAX reads per set (default 1000,2000000)")
     args = ap.parse_args()
+    if args.summarize_overlap:
+        note = open(args.profile_commands).read() if args.profile_commands else ""
+        summarize_overlap(args.summarize_overlap, note, "served_16_tenants_overlap")
+        return
     if args.summarize_profile:
         note = open(args.profile_commands).read() if args.profile_commands else ""
         summarize_profile(args.summarize_profile, args.workload, note)
@@ -666,7 +718,7 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
     del dev_reads, dev_offs
     torch.cuda.empty_cache()
     if cpu:
-        sample = args.cpu_sample_bases or max(1, bases // 4)
+        sample = args.cpu_sample_bases or max(1, bases // 6)
         log("timing the CPU oracle on a sample of %d bases" % sample)
         out["cpu_baseline"] = cpu_baseline(packed, offs, sample, key)
     else:
