@@ -23,9 +23,10 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 // ------------------------------------------------------------ rank on B_ext
 // rank(c, k) of Eq. 2 for a base c in 0..3 (A,C,G,T), 0 <= k <= n.
-// One 64-byte record read (four 16-byte loads of the same line); `big` is
-// uniform and says whether the index reaches 2^32 symbols (then the 64-bit
-// superblock count is added).
+// One 64-byte record read (loads of the same line: the count of c, the two
+// code planes, and the terminator plane for A only); `big` is uniform and
+// says whether the index reaches 2^32 symbols (then the 64-bit superblock
+// count is added).
 __device__ __forceinline__ uint64_t match_bits(uint64_t lo, uint64_t hi, uint64_t dl, int c) {
     uint64_t a = (c & 1) ? lo : ~lo;
     uint64_t b = (c & 2) ? hi : ~hi;
@@ -36,8 +37,12 @@ __device__ __forceinline__ uint64_t rank_base(const Rec *__restrict__ recs,
                                               const uint64_t *__restrict__ sbc, uint64_t k,
                                               int c, bool big) {
     const uint4 *p = reinterpret_cast<const uint4 *>(recs + (k >> REC_SHIFT));
-    uint4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
-    uint32_t cnt = c == 0 ? q0.x : c == 1 ? q0.y : c == 2 ? q0.z : q0.w;
+    const uint32_t cnt = reinterpret_cast<const uint32_t *>(p)[c];
+    uint4 q1 = p[1], q2 = p[2];
+    // a terminator's code bits are those of A, so only A needs the terminator
+    // plane: the other bases skip its load
+    uint4 q3 = make_uint4(0u, 0u, 0u, 0u);
+    if (c == 0) q3 = p[3];
     uint64_t lo0 = q1.x | ((uint64_t)q1.y << 32), lo1 = q1.z | ((uint64_t)q1.w << 32);
     uint64_t hi0 = q2.x | ((uint64_t)q2.y << 32), hi1 = q2.z | ((uint64_t)q2.w << 32);
     uint64_t dl0 = q3.x | ((uint64_t)q3.y << 32), dl1 = q3.z | ((uint64_t)q3.w << 32);
