@@ -120,6 +120,9 @@ def test_served_workload_digests(torch_dev):
     torch = torch_dev
     from paper_1410_0562_amd.serve import BwtService
     want = _golden("served_16_tenants")
+    if len(want) < 16:
+        pytest.skip("served digests for %d of 16 tenants so far (tests/golden/make_full_size.py)"
+                    % len(want))
     _log("served: generating 512 requests on the GPU")
     tids, reqs = synth.served_requests_gpu()
     svc = BwtService(16, budget_bytes=100 << 30, workers=4, block_size=1 << 26)
