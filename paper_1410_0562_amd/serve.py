@@ -7,8 +7,11 @@ different tenants are batched: a worker takes the queued requests of up to
 ``max_batch`` idle tenants that fit the device memory budget and runs them as
 one ``bwt_set_append_many`` call, whose blocks hold the reads of several
 tenants at once (each ranked against and merged into its own index).  A pool
-of workers runs such batches side by side, each on the first tenant handle's
-own HIP stream, so their kernels also overlap on the device.  To make room,
+of workers runs such batches side by side.  Every worker leads its batches
+with a handle of its own that holds no strings, so a batch runs on that
+handle's workspace and HIP stream: tenant handles hold only their index
+buffers, and trimming them frees nothing a later batch has to allocate
+again.  To make room,
 idle tenants are first trimmed (workspace and spare buffers freed) and then
 spilled: the index is exported to pinned host memory and the device copy
 released; the next request of a spilled tenant restores it with
@@ -90,6 +93,21 @@ class BwtService:
         # workspace (about 90 bytes per suffix of a block) plus staging; a
         # batch shares one workspace
         self.per_append = int(per_append_bytes or 96 * min(self.block_size, 1 << 26))
+        # every worker leads its batches with a handle of its own that holds no
+        # strings (its input is empty): the batch runs on that handle's
+        # workspace, so tenant handles only ever hold their index buffers and
+        # trimming them frees no workspace that the next batch must allocate
+        # again; the workers' workspaces count against the budget throughout
+        self._leaders = []
+        for _ in range(workers):
+            h = bwtset.BwtSet(block_size=self.block_size)
+            h.set_param(bwtset.BWT_PARAM_BATCH_LANES, 1)
+            self._leaders.append(h)
+        self._empty_reads = np.zeros(1, dtype=np.uint8)
+        self._empty_offs = np.zeros(1, dtype=np.uint64)
+        self._free_leaders = list(self._leaders)
+        # device bytes each leader holds, as of the end of its last batch
+        self._leader_bytes = [h.memory() for h in self._leaders]
         self.lock = threading.Condition()
         self.queue = collections.deque()      # arrival order
         self.reserved = 0                     # bytes promised to batches in flight
@@ -136,6 +154,9 @@ class BwtService:
             if t.index is not None:
                 t.index.close()
                 t.index = None
+        for h in self._leaders:
+            h.close()
+        self._leaders = []
 
     def export(self, tenant: int) -> bytes:
         """The tenant's BWT (waits for its pending appends)."""
@@ -163,8 +184,9 @@ class BwtService:
 
     # ----------------------------------------------------------- scheduling
     def _resident_bytes(self) -> int:
-        return self.reserved + sum(t.index.memory() for t in self.tenants
-                                   if t.index is not None and not t.busy)
+        return (self.reserved + sum(self._leader_bytes) +
+                sum(t.index.memory() for t in self.tenants
+                    if t.index is not None and not t.busy))
 
     def _make_room(self, need: int, keep) -> bool:
         """Trim, then spill, idle tenants (least recently used first, none in
@@ -222,11 +244,13 @@ class BwtService:
         self.completed.append(req)
         req.done.set()
 
-    def _admit(self) -> list:
+    def _admit(self, lk: int) -> list:
         """The oldest queued request of each idle tenant, in arrival order, up
         to max_batch of them and as long as they fit the budget together (the
-        batch shares one workspace).  Requests of a failed tenant are failed
-        here.  Called with the lock held."""
+        batch shares the workspace of worker lk's leading handle, which the
+        first request also reserves while that handle has not yet grown it).
+        Requests of a failed tenant are failed here.  Called with the lock
+        held."""
         batch = []
         keep = set()
         seen = set()
@@ -249,7 +273,8 @@ class BwtService:
             resident = 0 if t.index is None else t.index.memory()
             restore = 0 if t.index is not None else (
                 int(len(t.spill) * 1.6) if t.spill is not None else 0)
-            need = grow + restore + (0 if batch else self.per_append)
+            need = grow + restore + (
+                0 if batch else max(0, self.per_append - self._leader_bytes[lk]))
             if t.index is not None and not t.trimmed:
                 need = max(0, need - resident)
             fits = self._make_room(need, keep | {t})
@@ -269,9 +294,10 @@ class BwtService:
             batch.append(req)
         return batch
 
-    def _run_batch(self, batch: list) -> None:
-        """Restore, then append every request of the batch (one call).
-        Outside the lock; the batch's tenants are marked busy."""
+    def _run_batch(self, batch: list, leader) -> None:
+        """Restore, then append every request of the batch (one call, led by
+        the worker's own handle).  Outside the lock; the batch's tenants are
+        marked busy."""
         ready = []
         for req in batch:
             t = self.tenants[req.tenant]
@@ -285,12 +311,10 @@ class BwtService:
             ready.append(req)
         if not ready:
             return
-        idx = [self.tenants[r.tenant].index for r in ready]
+        idx = [leader] + [self.tenants[r.tenant].index for r in ready]
         try:
-            if len(ready) == 1:
-                idx[0].append(ready[0].reads, ready[0].offsets)
-            else:
-                bwtset.append_many(idx, [r.reads for r in ready], [r.offsets for r in ready])
+            bwtset.append_many(idx, [self._empty_reads] + [r.reads for r in ready],
+                               [self._empty_offs] + [r.offsets for r in ready])
         except BaseException as e:  # noqa: BLE001
             for r in ready:
                 r.error = e
@@ -301,11 +325,14 @@ class BwtService:
     def _worker(self) -> None:
         torch = self.torch
         torch.cuda.set_device(self._device)
+        with self.lock:
+            leader = self._free_leaders.pop()
+            lk = self._leaders.index(leader)
         while True:
             with self.lock:
                 batch = []
                 while not self._stop:
-                    batch = self._admit()
+                    batch = self._admit(lk)
                     if batch:
                         break
                     self.lock.wait(timeout=0.05)
@@ -314,8 +341,10 @@ class BwtService:
                 self.stats["batches"] += 1
                 self.stats["batched_requests"] += len(batch)
             # outside the lock: other workers keep admitting meanwhile
-            self._run_batch(batch)
+            self._run_batch(batch, leader)
+            leader_bytes = leader.memory()
             with self.lock:
+                self._leader_bytes[lk] = leader_bytes
                 for req in batch:
                     t = self.tenants[req.tenant]
                     self.reserved -= req.reserved

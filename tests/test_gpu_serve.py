@@ -162,8 +162,10 @@ def test_failed_restore_keeps_the_spill_and_stops_the_tenant(torch_dev, oracle_m
         return real_import(self, B, stream)
 
     monkeypatch.setattr(bwtset.BwtSet, "import_bwt", flaky_import)
-    svc = BwtService(tenants, budget_bytes=24 << 20, workers=1, block_size=1 << 18,
-                     per_append_bytes=16 << 20)
+    # a budget below one batch's workspace: every batch runs alone, and every
+    # idle tenant is spilled before it, so each tenant's next request restores
+    svc = BwtService(tenants, budget_bytes=1 << 20, workers=1, block_size=1 << 18,
+                     per_append_bytes=1 << 20)
     try:
         handles = [svc.submit(t, p, o) for (t, p, o) in reqs]
         svc.drain(timeout=120)
