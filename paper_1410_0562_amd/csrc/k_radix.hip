@@ -60,45 +60,36 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp) {
 // One digit pass over tiles of THREADS * ITEMS keys.  Wave w of a tile owns
 // the ITEMS * 64 consecutive keys starting at w * ITEMS * 64 and takes them
 // row by row, so tile order = (wave, row, lane) and the ranking is stable.
-// Keys and then values go through the same LDS buffer to keep the tile small
-// enough for several workgroups per CU.
-template <int THREADS, int ITEMS>
-__global__ __launch_bounds__(THREADS) void radix_pass_kernel(
+// A key's rank among the equal digits of its wave is the count of that digit
+// in the wave's earlier rows plus its lower lanes in its own row: the lowest
+// lane of each group of equal digits in a row adds the group's size to the
+// wave's count with one LDS add-with-return (the rows' adds are issued back
+// to back and run in row order), and the other lanes take the earlier count
+// from that lane.  Keys and then values go through the same LDS buffer; each
+// thread keeps the destinations of its write-out slots in registers for the
+// value phase.  Full tiles (all but possibly the last) take a path with no
+// bounds tests.
+template <int THREADS, int ITEMS, bool FULL>
+__device__ __forceinline__ void radix_tile(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
     uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ hist_cur,
     uint32_t *__restrict__ hist_next, int shift_next, uint64_t *__restrict__ status,
-    uint32_t *__restrict__ counter, uint32_t ntiles, uint32_t epoch, uint32_t *__restrict__ err) {
+    uint32_t tile, uint32_t epoch, uint32_t *__restrict__ err, uint32_t (*s_wh)[256],
+    int32_t *s_gbase, uint32_t *s_next, uint32_t *s_tmp, uint64_t *s_buf) {
     constexpr int WAVES = THREADS / WAVE;
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WKEYS = ITEMS * WAVE;
-    static_assert(THREADS >= 256, "one thread per digit");
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_wh[WAVES][256];  // per-wave digit counts, then wave offsets
-    __shared__ uint32_t s_lstart[256];     // start of each digit inside the tile
-    __shared__ int32_t s_gbase[256];       // global position minus tile position
-    __shared__ uint32_t s_next[256];       // this tile's counts of the next pass's digit
-    __shared__ uint32_t s_tmp[WAVES];
-    __shared__ uint64_t s_buf[TILE];       // keys, then values
-    __shared__ uint8_t s_dig[TILE];        // digit of each staged key
-
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int d = lane; d < 256; d += WAVE) s_wh[wave][d] = 0;
-    if (tid < 256) s_next[tid] = 0;
-    const uint32_t tile = acquire_tile(counter, ntiles, &s_tile);
-    if (tile >= ntiles) {  // only if the tile counter was not zero at launch
-        if (tid == 0) atomicOr(err, 2u);
-        return;
-    }
     const uint64_t base = (uint64_t)tile * TILE;
     const uint64_t wbase = base + (uint64_t)wave * WKEYS;
+    const uint32_t cnt_tile = FULL ? (uint32_t)TILE : (uint32_t)(n - base);
 
     uint64_t k[ITEMS];
     uint32_t v[ITEMS];
-    uint32_t rk[ITEMS];
 #pragma unroll
     for (int e = 0; e < ITEMS; ++e) {
-        uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
-        bool ok = idx < n;
+        const uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
+        const bool ok = FULL || idx < n;
         k[e] = ok ? kin[idx] : 0;
         v[e] = ok ? vin[idx] : 0;
     }
@@ -115,45 +106,53 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(
         // histogram of the next pass's digit while the keys are in registers
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e) {
-            uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
-            if (idx < n) atomicAdd(&s_next[(uint32_t)(k[e] >> shift_next) & 255u], 1u);
+            const uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
+            if (FULL || idx < n) atomicAdd(&s_next[(uint32_t)(k[e] >> shift_next) & 255u], 1u);
         }
     }
     const uint64_t ltm = lanemask_lt();
+    uint32_t rk[ITEMS], lead[ITEMS], prev[ITEMS];
 #pragma unroll
     for (int e = 0; e < ITEMS; ++e) {
-        uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
-        bool ok = idx < n;
-        uint32_t d = (uint32_t)(k[e] >> shift) & 255u;
-        uint64_t peers = __ballot(ok);
+        const uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
+        const bool ok = FULL || idx < n;
+        const uint32_t d = (uint32_t)(k[e] >> shift) & 255u;
+        uint64_t peers = FULL ? ~0ull : __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bb = __ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
             peers &= bit ? bb : ~bb;
         }
-        uint32_t before = __popcll(peers & ltm);
-        uint32_t cnt = __popcll(peers);
-        uint32_t prev = ok ? s_wh[wave][d] : 0;
-        rk[e] = prev + before;
-        if (ok && before == 0) s_wh[wave][d] = prev + cnt;
+        rk[e] = __popcll(peers & ltm);
+        lead[e] = (uint32_t)__builtin_ctzll(peers | (1ull << 63));
+        prev[e] = 0;
+        if (ok && rk[e] == 0) prev[e] = atomicAdd(&s_wh[wave][d], (uint32_t)__popcll(peers));
     }
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) rk[e] += (uint32_t)__shfl((int)prev[e], (int)lead[e], WAVE);
     __syncthreads();
-    // digit totals of the tile, wave offsets, tile-local digit starts
+    // digit totals of the tile; the wave offsets then hold the tile-local
+    // digit start plus the counts of the earlier waves
     uint32_t total = 0;
+    uint32_t wc[WAVES];
     if (tid < 256) {
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) {
-            uint32_t c = s_wh[w][tid];
-            s_wh[w][tid] = total;
-            total += c;
+            wc[w] = s_wh[w][tid];
+            total += wc[w];
         }
     }
     const uint32_t lstart = block_excl_sum<THREADS>(tid < 256 ? total : 0u, s_tmp);
     const uint32_t dstart = block_excl_sum<THREADS>(tid < 256 ? dcount : 0u, s_tmp);
     if (tid < 256) {
-        s_lstart[tid] = lstart;
-        uint32_t excl = lookback(status + tid, 256u, tile, epoch, total, OpSum(), 0u, err);
+        uint32_t run = lstart;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            s_wh[w][tid] = run;
+            run += wc[w];
+        }
+        const uint32_t excl = lookback(status + tid, 256u, tile, epoch, total, OpSum(), 0u, err);
         s_gbase[tid] = (int32_t)(dstart + excl) - (int32_t)lstart;
         if (hist_next && s_next[tid])
             atomicAdd(&hist_next[(tile % HIST_COPIES) * 256 + tid], s_next[tid]);
@@ -161,40 +160,83 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(
     __syncthreads();
     // keys: stage in LDS in sorted order, then write each digit run out
     uint32_t pos[ITEMS];
+    bool bad = false;
 #pragma unroll
     for (int e = 0; e < ITEMS; ++e) {
-        uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
-        pos[e] = 0xffffffffu;
-        if (idx < n) {
-            uint32_t dd = (uint32_t)(k[e] >> shift) & 255u;
-            uint32_t q = s_lstart[dd] + s_wh[wave][dd] + rk[e];
-            if (q < (uint32_t)TILE) {
-                pos[e] = q;
-                s_buf[q] = k[e];
-                s_dig[q] = (uint8_t)dd;
-            } else {
-                atomicOr(err, 4u);
-            }
-        }
+        const uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
+        const uint32_t d = (uint32_t)(k[e] >> shift) & 255u;
+        uint32_t q = s_wh[wave][d] + rk[e];
+        bad |= q >= (uint32_t)TILE;
+        q = q < (uint32_t)TILE ? q : (uint32_t)TILE - 1;
+        pos[e] = q;
+        if (FULL || idx < n) s_buf[q] = k[e];
     }
     __syncthreads();
-    const uint32_t cnt_tile = (uint32_t)((n - base) < (uint64_t)TILE ? (n - base) : TILE);
-    for (uint32_t i = tid; i < cnt_tile; i += THREADS) {
-        int64_t dst = (int64_t)s_gbase[s_dig[i]] + (int64_t)i;
-        if ((uint64_t)dst < n) kout[dst] = s_buf[i];
-        else atomicOr(err, 4u);
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t i = (uint32_t)tid + (uint32_t)r * THREADS;
+        dst[r] = 0xffffffffu;
+        if (FULL || i < cnt_tile) {
+            const uint64_t kk = s_buf[i];
+            const uint32_t t = (uint32_t)(s_gbase[(uint32_t)(kk >> shift) & 255u] + (int32_t)i);
+            if ((uint64_t)t < n) {
+                dst[r] = t;
+                kout[t] = kk;
+            } else {
+                bad = true;
+            }
+        }
     }
     __syncthreads();
     // values through the same buffer
     uint32_t *s_val = reinterpret_cast<uint32_t *>(s_buf);
 #pragma unroll
-    for (int e = 0; e < ITEMS; ++e)
-        if (pos[e] != 0xffffffffu) s_val[pos[e]] = v[e];
-    __syncthreads();
-    for (uint32_t i = tid; i < cnt_tile; i += THREADS) {
-        int64_t dst = (int64_t)s_gbase[s_dig[i]] + (int64_t)i;
-        if ((uint64_t)dst < n) vout[dst] = s_val[i];
+    for (int e = 0; e < ITEMS; ++e) {
+        const uint64_t idx = wbase + (uint64_t)e * WAVE + lane;
+        if (FULL || idx < n) s_val[pos[e]] = v[e];
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t i = (uint32_t)tid + (uint32_t)r * THREADS;
+        if (dst[r] != 0xffffffffu) vout[dst[r]] = s_val[i];
+    }
+    if (bad) atomicOr(err, 4u);
+}
+
+// Destinations are 32-bit: a block sort runs on at most MAX_BLOCK keys.
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void radix_pass_kernel(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, uint64_t n, int shift, const uint32_t *__restrict__ hist_cur,
+    uint32_t *__restrict__ hist_next, int shift_next, uint64_t *__restrict__ status,
+    uint32_t *__restrict__ counter, uint32_t ntiles, uint32_t epoch, uint32_t *__restrict__ err) {
+    constexpr int WAVES = THREADS / WAVE;
+    constexpr int TILE = THREADS * ITEMS;
+    static_assert(THREADS >= 256, "one thread per digit");
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wh[WAVES][256];  // per-wave digit counts, then offsets
+    __shared__ int32_t s_gbase[256];       // global position minus tile position
+    __shared__ uint32_t s_next[256];       // this tile's counts of the next pass's digit
+    __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint64_t s_buf[TILE];       // keys, then values
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int d = lane; d < 256; d += WAVE) s_wh[wave][d] = 0;
+    if (tid < 256) s_next[tid] = 0;
+    const uint32_t tile = acquire_tile(counter, ntiles, &s_tile);
+    if (tile >= ntiles) {  // only if the tile counter was not zero at launch
+        if (tid == 0) atomicOr(err, 2u);
+        return;
+    }
+    if ((uint64_t)(tile + 1) * TILE <= n)
+        radix_tile<THREADS, ITEMS, true>(kin, vin, kout, vout, n, shift, hist_cur, hist_next,
+                                         shift_next, status, tile, epoch, err, s_wh, s_gbase,
+                                         s_next, s_tmp, s_buf);
+    else
+        radix_tile<THREADS, ITEMS, false>(kin, vin, kout, vout, n, shift, hist_cur, hist_next,
+                                          shift_next, status, tile, epoch, err, s_wh, s_gbase,
+                                          s_next, s_tmp, s_buf);
 }
 
 }  // namespace

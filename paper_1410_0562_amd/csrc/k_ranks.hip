@@ -260,19 +260,40 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
         __syncthreads();
     }
     const uint32_t j = blockIdx.x * blockDim.x + tid;
+    uint64_t s0 = 0;
+    uint32_t len = 0, nseg = 0;
     if (j < m_blk) {
-        const uint64_t s0 = off[j];
-        const uint32_t len = (uint32_t)(off[j + 1] - s0);
-        if (seg > 0 && (len > seg || queue_all)) {
-            const uint32_t nseg = len > seg ? (len + seg - 1) / seg : 1u;
-            const uint32_t at = atomicAdd(seg_count, nseg);
-            if (len) atomicAdd(seg_syms, (unsigned long long)len);
-            if (at + nseg > seg_cap) {
+        s0 = off[j];
+        len = (uint32_t)(off[j + 1] - s0);
+        if (seg > 0 && (len > seg || queue_all)) nseg = len > seg ? (len + seg - 1) / seg : 1u;
+    }
+    // Queue places are reserved once per wave (one atomic on the shared
+    // counter per 64 reads instead of one per read): every lane of the wave
+    // takes part, queued or not.  The queued symbols are summed in two 16-bit
+    // halves so that the wave's sums cannot overflow 32 bits.
+    {
+        const uint32_t lane = tid & (WAVE - 1);
+        const uint32_t qlen = nseg ? len : 0u;
+        const uint32_t incl = wave_incl_sum(nseg);
+        const uint32_t sum_lo = wave_incl_sum(qlen & 0xffffu);
+        const uint32_t sum_hi = wave_incl_sum(qlen >> 16);
+        uint32_t base = 0;
+        if (lane == WAVE - 1 && incl) {
+            base = atomicAdd(seg_count, incl);
+            atomicAdd(seg_syms, (unsigned long long)sum_lo + ((unsigned long long)sum_hi << 16));
+        }
+        base = __shfl(base, WAVE - 1, WAVE);
+        if (nseg) {
+            const uint32_t at = base + incl - nseg;
+            if ((uint64_t)at + nseg > seg_cap) {
                 atomicOr(err, 128u);
             } else {
                 for (uint32_t s = 0; s < nseg; ++s) seg_list[at + s] = ((uint64_t)j << 32) | s;
             }
-        } else {
+        }
+    }
+    if (j < m_blk && nseg == 0) {
+        {
             SymReader sym{reads, 0, 0};
             walk_read<KEYS>(src.at(j), sym, s0, len, soff[j], o, count ? s_h : nullptr);
         }
