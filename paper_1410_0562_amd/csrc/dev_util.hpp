@@ -100,6 +100,21 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
     return v;
 }
 
+// The same sum with DPP moves instead of LDS-crossbar shuffles: shifts by 1,
+// 2, 4 and 8 lanes inside each row of 16 (lanes shifted in from outside the
+// row read 0), then the last lane of rows 0 and 2 added to rows 1 and 3
+// (row_bcast:15 on row mask 0xA), then lane 31 added to rows 2 and 3
+// (row_bcast:31 on row mask 0xC).  All 64 lanes of the wave must be active.
+__device__ __forceinline__ uint32_t wave_incl_sum_dpp(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
     int l = lane_id();
 #pragma unroll

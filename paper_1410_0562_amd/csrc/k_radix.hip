@@ -40,21 +40,29 @@ __global__ __launch_bounds__(256) void radix_hist1_kernel(const uint64_t *__rest
     if (h[tid]) atomicAdd(&hist[(blockIdx.x % HIST_COPIES) * 256 + tid], h[tid]);
 }
 
-// Block-wide exclusive sum over THREADS threads (every thread calls it);
-// tmp holds THREADS/64 words.  Contains barriers.
+// Block-wide exclusive sums of two values at once over THREADS threads
+// (every thread calls it, with all lanes active); tmp holds 2 * THREADS/64
+// words.  One barrier: tmp must not be written again before the next one.
 template <int THREADS>
-__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp) {
+__device__ __forceinline__ void block_excl_sum2(uint32_t a, uint32_t b, uint32_t *tmp,
+                                                uint32_t &ea, uint32_t &eb) {
     constexpr int W = THREADS / WAVE;
     const int tid = threadIdx.x, w = tid >> 6;
-    uint32_t inc = wave_incl_sum(v);
-    if ((tid & 63) == 63) tmp[w] = inc;
+    const uint32_t ia = wave_incl_sum_dpp(a), ib = wave_incl_sum_dpp(b);
+    if ((tid & 63) == 63) {
+        tmp[w] = ia;
+        tmp[W + w] = ib;
+    }
     __syncthreads();
-    uint32_t before = 0;
+    uint32_t ba = 0, bb = 0;
 #pragma unroll
     for (int k = 0; k < W; ++k)
-        if (k < w) before += tmp[k];
-    __syncthreads();
-    return before + inc - v;
+        if (k < w) {
+            ba += tmp[k];
+            bb += tmp[W + k];
+        }
+    ea = ba + ia - a;
+    eb = bb + ib - b;
 }
 
 // One digit pass over tiles of THREADS * ITEMS keys.  Wave w of a tile owns
@@ -143,8 +151,8 @@ __device__ __forceinline__ void radix_tile(
             total += wc[w];
         }
     }
-    const uint32_t lstart = block_excl_sum<THREADS>(tid < 256 ? total : 0u, s_tmp);
-    const uint32_t dstart = block_excl_sum<THREADS>(tid < 256 ? dcount : 0u, s_tmp);
+    uint32_t lstart, dstart;
+    block_excl_sum2<THREADS>(tid < 256 ? total : 0u, tid < 256 ? dcount : 0u, s_tmp, lstart, dstart);
     if (tid < 256) {
         uint32_t run = lstart;
 #pragma unroll
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(THREADS) void radix_pass_kernel(
     __shared__ uint32_t s_wh[WAVES][256];  // per-wave digit counts, then offsets
     __shared__ int32_t s_gbase[256];       // global position minus tile position
     __shared__ uint32_t s_next[256];       // this tile's counts of the next pass's digit
-    __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint32_t s_tmp[2 * WAVES];
     __shared__ uint64_t s_buf[TILE];       // keys, then values
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int d = lane; d < 256; d += WAVE) s_wh[wave][d] = 0;
