@@ -88,17 +88,19 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&x)[E],
 // quad (DPP quad_perm); 4 is a mirror inside each half-row of 8 followed by a
 // reversal inside each quad (two DPP moves); 8 is a rotation by 8 inside a
 // row of 16 (DPP row_ror:8); 16 and 32 go through the LDS crossbar.
+// Every lane reads a valid source lane in these patterns, so the DPP moves
+// need no initial destination value (mov_dpp, all rows and banks written).
 template <int J>
 __device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
     if constexpr (J == 1) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
     } else if constexpr (J == 2) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
     } else if constexpr (J == 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);
     } else if constexpr (J == 4) {
-        const int m = __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, false);
+        const int m = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);
+        return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, true);
     } else {
         return (uint32_t)__shfl_xor((int)v, J, 64);
     }
