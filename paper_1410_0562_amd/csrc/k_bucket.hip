@@ -415,29 +415,36 @@ __global__ __launch_bounds__(256) void bucket_scan_down_kernel(
 constexpr uint32_t BT_T = 2048;
 constexpr uint32_t BT_WIN = BT_T + BUCKET_CAP;
 
-// Sorts up to four rows of whole consecutive buckets held in LDS (row r:
+// Rows of packed buckets sorted together by one wave.  One: with more rows
+// at once the compare masks of every row are live together and the scalar
+// registers spill into vector lanes, which costs more VALU than the overlap
+// of the rows' exchanges saves (1 row: 16.3 ms of bucket finish on the
+// 250k long-read workload, 2: 16.9, 4: 17.7).
+constexpr int PACK_ROWS = 1;
+
+// Sorts up to PACK_ROWS rows of whole consecutive buckets held in LDS (row r:
 // window offsets rst[r] .. rst[r] + rlen[r] - 1, first bucket rid[r]; rlen 0
 // = no row), one row per register, into kout / vout at t0 + offset.  Tied
 // suffixes get their flag in s_f, and the last lane of each bucket with ties
 // writes the bucket's tie count.
 __device__ __forceinline__ void sort_packed_rows(
-    const uint64_t *__restrict__ s_k, const uint32_t *__restrict__ s_v, const uint32_t (&rst)[4],
-    const uint32_t (&rlen)[4], const uint32_t (&rid)[4], uint64_t *__restrict__ kout,
+    const uint64_t *__restrict__ s_k, const uint32_t *__restrict__ s_v, const uint32_t (&rst)[PACK_ROWS],
+    const uint32_t (&rlen)[PACK_ROWS], const uint32_t (&rid)[PACK_ROWS], uint64_t *__restrict__ kout,
     uint32_t *__restrict__ vout, uint32_t t0, int bshift, int kshort, uint8_t *__restrict__ s_f,
     uint32_t *__restrict__ tcnt) {
     const int lane = lane_id();
     const uint32_t l = (uint32_t)lane;
-    uint64_t c[4];
+    uint64_t c[PACK_ROWS];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < PACK_ROWS; ++r) {
         const uint64_t base = (uint64_t)rid[r] << bshift;
         c[r] = l < rlen[r] ? ((s_k[rst[r] + l] - base) << 6) | (uint64_t)l
                            : ~0ull;  // a real key never has all length bits set
     }
-    wave_sort_rows<4, 64>(c, lane);
+    wave_sort_rows<PACK_ROWS, 64>(c, lane);
     const uint64_t le = lanemask_lt() | (1ull << lane);  // lanes up to this one
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < PACK_ROWS; ++r) {
         const bool ok = l < rlen[r];
         const uint64_t k = ok ? ((uint64_t)rid[r] << bshift) + (c[r] >> 6) : ~0ull;
         if (ok) {
@@ -598,7 +605,7 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     const uint32_t tend = s_end - t0;  // may exceed the window (oversized)
     // Each wave takes a quarter of the owned buckets in order and packs runs
     // of whole consecutive buckets of at most 64 suffixes into rows of at
-    // most 64 lanes; four rows are sorted at once.  A row's words are
+    // most 64 lanes; PACK_ROWS rows are sorted at once.  A row's words are
     // (key - first bucket's base) << 6 | lane, so one sort orders its
     // buckets apart and each bucket inside (buckets id0 .. id0 + span - 1 fit
     // one word).  Larger buckets are sorted one at a time; oversized ones are
@@ -606,7 +613,7 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
     const uint32_t span = bshift > 58 ? 0u : bshift >= 27 ? (1u << (58 - bshift)) : 0xffffffffu;
     {
         const uint32_t jb0 = nbk * (uint32_t)wave / 4, jb1 = nbk * (uint32_t)(wave + 1) / 4;
-        uint32_t rst[4] = {0, 0, 0, 0}, rlen[4] = {0, 0, 0, 0}, rid[4] = {0, 0, 0, 0};
+        uint32_t rst[PACK_ROWS] = {}, rlen[PACK_ROWS] = {}, rid[PACK_ROWS] = {};
         uint32_t nr = 0;
         uint32_t cst = 0, clen = 0, cid = 0;  // the open row (none while clen == 0)
         for (uint32_t jb = jb0; jb < jb1; jb += 64) {
@@ -626,15 +633,22 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
                 const bool small = span != 0 && z <= 64;
                 if (clen && (!small || clen + z > 64 || id - cid >= span)) {
                     // close the open row
-                    rst[3] = rst[2]; rst[2] = rst[1]; rst[1] = rst[0]; rst[0] = cst;
-                    rlen[3] = rlen[2]; rlen[2] = rlen[1]; rlen[1] = rlen[0]; rlen[0] = clen;
-                    rid[3] = rid[2]; rid[2] = rid[1]; rid[1] = rid[0]; rid[0] = cid;
+#pragma unroll
+                    for (int r = PACK_ROWS - 1; r > 0; --r) {
+                        rst[r] = rst[r - 1];
+                        rlen[r] = rlen[r - 1];
+                        rid[r] = rid[r - 1];
+                    }
+                    rst[0] = cst;
+                    rlen[0] = clen;
+                    rid[0] = cid;
                     clen = 0;
-                    if (++nr == 4) {
+                    if (++nr == PACK_ROWS) {
                         sort_packed_rows(s_k, s_v, rst, rlen, rid, kout, vout, t0, bshift, kshort,
                                          s_f, tcnt);
                         nr = 0;
-                        rlen[0] = rlen[1] = rlen[2] = rlen[3] = 0;
+#pragma unroll
+                        for (int r = 0; r < PACK_ROWS; ++r) rlen[r] = 0;
                     }
                 }
                 if (small) {
@@ -656,9 +670,15 @@ __global__ __launch_bounds__(256) void bucket_tile_sort_kernel(
             }
         }
         if (clen) {
-            rst[3] = rst[2]; rst[2] = rst[1]; rst[1] = rst[0]; rst[0] = cst;
-            rlen[3] = rlen[2]; rlen[2] = rlen[1]; rlen[1] = rlen[0]; rlen[0] = clen;
-            rid[3] = rid[2]; rid[2] = rid[1]; rid[1] = rid[0]; rid[0] = cid;
+#pragma unroll
+            for (int r = PACK_ROWS - 1; r > 0; --r) {
+                rst[r] = rst[r - 1];
+                rlen[r] = rlen[r - 1];
+                rid[r] = rid[r - 1];
+            }
+            rst[0] = cst;
+            rlen[0] = clen;
+            rid[0] = cid;
             ++nr;
         }
         if (nr)
