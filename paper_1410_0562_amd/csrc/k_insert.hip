@@ -319,42 +319,65 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
     const uint64_t r_lo = o0 >> REC_SHIFT;
     const uint32_t nr_old = nold ? (uint32_t)(((o0 + nold - 1) >> REC_SHIFT) - r_lo + 1) : 0u;
     // a consistent split never trips these; they keep a broken one in bounds
-    if (a1 < a0 || a1 - a0 > INS_TILE_SYMS || nr_old > INS_TILE_RECS + 1 ||
-        (nr_old && r_lo + nr_old > nrec_in)) {
+    if (a1 < a0 || a0 > q0 || o0 > J.n_ext || a1 - a0 > INS_TILE_SYMS ||
+        nr_old > INS_TILE_RECS + 1 || (nr_old && r_lo + nr_old > nrec_in)) {
         if (lane == 0) atomicOr(err, 32u);
         return;
     }
+    // Every load the tile needs depends only on a0 and a1, so all of them
+    // go out here, before any result is used: the old records' planes, the
+    // first eight rows of new symbols, the B_int samples and partial chunks
+    // and the rank at o0 for the counts at the tile start, and the
+    // superblock base of this lane's output record.
+    const uint64_t A = sa0 + a0;
+    const int cb = lane & 3;
+    uint64_t ow[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        // at most (INS_TILE_RECS + 1) * 6 = 102 words: two per lane
+        const uint32_t k = (uint32_t)lane + 64u * e;
+        ow[e] = k < nr_old * 6
+                    ? reinterpret_cast<const uint64_t *>(orecs + r_lo + k / 6)[2 + k % 6]
+                    : 0ull;
+    }
+    constexpr int NB = 8;
+    uint64_t gk[NB];
+    uint32_t vv[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        const uint64_t i = a0 + (uint64_t)e * 64 + lane;
+        gk[e] = i < a1 ? gkeys[sa0 + i] : 0ull;
+        vv[e] = i < a1 ? vals[sa0 + i] : 0u;
+    }
+    const uint64_t x = (A & ~63ull) + lane;
+    const uint64_t y = (sa0 & ~63ull) + lane;
+    const uint32_t vx = x < A ? vals[x] : (6u << POS_BITS);
+    const uint32_t vy = y < sa0 ? vals[y] : (6u << POS_BITS);
+    const uint64_t sA = bint_sample(bcnt, A >> CHUNK_SHIFT, cb);
+    const uint64_t s0 = bint_sample(bcnt, sa0 >> CHUNK_SHIFT, cb);
+    const uint64_t rb = rank_base(orecs, osbc, o0, cb, true);
+    const uint64_t r = (uint64_t)(lane >> 2);
+    const uint64_t R = R0 + r;
+    const uint64_t sbase = r < nrec ? nsbc[((R * REC_SYMS) >> SB_SHIFT) * 4 + cb] : 0ull;
+
     L.bm[lane] = 0;
-    {
-        // at most (INS_TILE_RECS + 1) * 6 = 102 words: two per lane, both
-        // loads issued before the stores
-        uint64_t ow[2];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const uint32_t k = (uint32_t)lane + 64u * e;
-            ow[e] = k < nr_old * 6
-                        ? reinterpret_cast<const uint64_t *>(orecs + r_lo + k / 6)[2 + k % 6]
-                        : 0ull;
-        }
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const uint32_t k = (uint32_t)lane + 64u * e;
-            if (k < nr_old * 6) L.old[k] = ow[e];
-        }
+    for (int e = 0; e < 2; ++e) {
+        const uint32_t k = (uint32_t)lane + 64u * e;
+        if (k < nr_old * 6) L.old[k] = ow[e];
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    // the tile's new symbols, eight per lane at a time, their loads issued
-    // before any is used
-    for (uint64_t i0 = a0; i0 < a1; i0 += 8 * 64) {
-        constexpr int NB = 8;
-        uint64_t gk[NB];
-        uint32_t vv[NB];
+    // the tile's new symbols, eight rows of 64 at a time (the first rows are
+    // already loaded; later ones, if any, have their loads issued together)
+    for (uint64_t i0 = a0; i0 < a1; i0 += NB * 64) {
+        if (i0 != a0) {
 #pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            const uint64_t i = i0 + (uint64_t)e * 64 + lane;
-            gk[e] = i < a1 ? gkeys[sa0 + i] : 0ull;
-            vv[e] = i < a1 ? vals[sa0 + i] : 0u;
+            for (int e = 0; e < NB; ++e) {
+                const uint64_t i = i0 + (uint64_t)e * 64 + lane;
+                gk[e] = i < a1 ? gkeys[sa0 + i] : 0ull;
+                vv[e] = i < a1 ? vals[sa0 + i] : 0u;
+            }
         }
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
@@ -372,21 +395,15 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
         // counts at the tile start: old part by a rank on B_ext, new part from
         // the sampled B_int counts plus the < 64 symbols since the sample
         // (taken at the unit's first slot too, and subtracted)
-        const uint64_t A = sa0 + a0;
-        const uint64_t x = (A & ~63ull) + lane;
-        const int c = x < A ? code_at(vals, x) : 6;
+        const int c = (int)(vx >> POS_BITS), d = (int)(vy >> POS_BITS);
         const uint32_t cA = __popcll(__ballot(c == 0)), cC = __popcll(__ballot(c == 1));
         const uint32_t cG = __popcll(__ballot(c == 2)), cT = __popcll(__ballot(c == 3));
-        const uint64_t y = (sa0 & ~63ull) + lane;
-        const int d = y < sa0 ? code_at(vals, y) : 6;
         const uint32_t dA = __popcll(__ballot(d == 0)), dC = __popcll(__ballot(d == 1));
         const uint32_t dG = __popcll(__ballot(d == 2)), dT = __popcll(__ballot(d == 3));
         if (lane < 4) {
             const uint32_t part = lane == 0 ? cA : lane == 1 ? cC : lane == 2 ? cG : cT;
             const uint32_t part0 = lane == 0 ? dA : lane == 1 ? dC : lane == 2 ? dG : dT;
-            L.base[lane] = (bint_sample(bcnt, A >> CHUNK_SHIFT, lane) + part) -
-                           (bint_sample(bcnt, sa0 >> CHUNK_SHIFT, lane) + part0) +
-                           rank_base(orecs, osbc, o0, lane, true);
+            L.base[lane] = (sA + part) - (s0 + part0) + rb;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -457,12 +474,10 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
 #pragma unroll
     for (int c = 0; c < 4; ++c)
         rec_before[c] = (uint64_t)__shfl((long long)before[c], first, 64);
-    const uint64_t r = (uint64_t)(lane >> 2);
     if (r < nrec) {
-        const uint64_t R = R0 + r;
         const uint64_t cabs = k == 0 ? rec_before[0] : k == 1 ? rec_before[1] : k == 2 ? rec_before[2] : rec_before[3];
         uint32_t *out = reinterpret_cast<uint32_t *>(nrecs) + R * 16;
-        out[k] = (uint32_t)(cabs - nsbc[((R * REC_SYMS) >> SB_SHIFT) * 4 + k]);
+        out[k] = (uint32_t)(cabs - sbase);
         out[4 + k] = lo_w;
         out[8 + k] = hi_w;
         out[12 + k] = dl_w;
