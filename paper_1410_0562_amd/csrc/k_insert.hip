@@ -411,7 +411,8 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
     // this lane's 32 output rows: q0 + 32 * lane .. + 31
     const uint32_t word = L.bm[lane];
     const uint32_t nnew = (uint32_t)__popc(word);
-    uint32_t nb = wave_incl_sum(nnew) - nnew;              // new symbols before this lane
+    // (every lane of the wave is active from here: its exits are wave-uniform)
+    uint32_t nb = wave_incl_sum_dpp(nnew) - nnew;          // new symbols before this lane
     uint64_t ob = o0 + 32ull * lane - nb - r_lo * REC_SYMS;  // old row, relative to record r_lo
     const uint64_t ql = q0 + 32ull * lane;
     const uint32_t nvalid = ql < q1 ? (q1 - ql < 32 ? (uint32_t)(q1 - ql) : 32u) : 0u;
@@ -467,7 +468,7 @@ __device__ __forceinline__ void insert_tile(const InsJob &J, uint64_t t, InsLds 
     for (int c = 0; c < 4; ++c) {
         const uint32_t a = (c & 1) ? lo_w : ~lo_w, b = (c & 2) ? hi_w : ~hi_w;
         const uint32_t m = (uint32_t)__popc(a & b & ~dl_w & vmask);
-        before[c] = L.base[c] + (wave_incl_sum(m) - m);
+        before[c] = L.base[c] + (wave_incl_sum_dpp(m) - m);
     }
     const int first = lane & ~3, k = lane & 3;
     uint64_t rec_before[4];
