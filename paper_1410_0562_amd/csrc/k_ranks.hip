@@ -244,8 +244,8 @@ __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t
 // segments wait for this launch to end.
 // In key mode with o.hist set, the digit counts of the keys of the walked
 // reads are gathered in LDS and added once per workgroup to one of the
-// HIST_COPIES copies (the keys of queued reads are counted by
-// count_long_keys_kernel once they are final).
+// HIST_COPIES copies (the keys of queued reads are counted by the segment
+// and whole-read kernels that write them).
 template <class Src, bool KEYS>
 __global__ __launch_bounds__(256) void compute_ranks_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
@@ -304,48 +304,25 @@ __global__ __launch_bounds__(256) void compute_ranks_kernel(
     }
 }
 
-// Digit counts (bit o.hshift) of the final keys of the reads that were cut
-// into segments: the workgroups stride over the queued segments (j, s); a
-// segment owns the positions of symbols [s * seg, min(len, s * seg + seg)) of
-// read j and, if it is the last one, the terminator position.
-__global__ __launch_bounds__(256) void count_long_keys_kernel(
-    const uint64_t *__restrict__ off, const uint32_t *__restrict__ soff, uint32_t m_blk,
-    uint32_t seg, const uint64_t *__restrict__ seg_list, const uint32_t *__restrict__ seg_count,
-    const uint64_t *__restrict__ keys, int hshift, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t s_h[256];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t nq = *seg_count;
-    if (blockIdx.x >= nq) return;
-    s_h[tid] = 0;
-    __syncthreads();
-    for (uint32_t t = blockIdx.x; t < nq; t += gridDim.x) {
-        const uint64_t e_js = seg_list[t];
-        const uint32_t j = (uint32_t)(e_js >> 32), sg = (uint32_t)e_js;
-        if (j >= m_blk) continue;  // only if the queue overflowed (already flagged)
-        const uint32_t len = (uint32_t)(off[j + 1] - off[j]);
-        const uint64_t gb = soff[j];
-        const uint32_t a = sg * seg;
-        if (sg > 0 && a >= len) continue;  // (an empty read is queued as segment 0)
-        const uint32_t b = a + seg < len ? a + seg : len;
-        const uint32_t cnt = b - a + (b == len ? 1u : 0u);  // positions gb + a ...
-        for (uint32_t q = tid; q < cnt; q += 256)
-            atomicAdd(&s_h[(uint32_t)(keys[gb + a + q] >> hshift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (s_h[tid]) atomicAdd(&hist[(blockIdx.x % HIST_COPIES) * 256 + tid], s_h[tid]);
-}
+// Key mode: a key whose length field has every bit set never occurs (the
+// field holds at most kfirst); a segment that hands its read to the
+// whole-read walk fills its positions with it.
+constexpr uint64_t NO_KEY = ~0ull;
 
-// One lane per queued segment (j, s) of a long read: symbols [a, b) with
-// a = s * seg, b = min(len, a + seg); the walk starts at e = min(len, b + ov).
+// Queued segment t, (j, s) of a long read: symbols [a, b) with a = s * seg,
+// b = min(len, a + seg); the walk starts at e = min(len, b + ov).  Its keys
+// are written only once its interval has closed at its first own position,
+// after which the walk is exact, so every key it writes is final (the
+// whole-read walk of a read that falls back writes the same values there):
+// sh (key mode, may be null) counts their digits at bit o.hshift.
 template <class Src, bool KEYS>
-__global__ __launch_bounds__(256) void rank_segments_kernel(
-    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, Out o, uint32_t seg, uint32_t ov,
-    const uint64_t *__restrict__ seg_list, const uint32_t *__restrict__ seg_count,
-    uint32_t *__restrict__ fb_flag, uint32_t *__restrict__ fb_list,
-    uint32_t *__restrict__ fb_count, uint32_t *__restrict__ stats, uint32_t *__restrict__ err) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= *seg_count) return;
+__device__ void rank_segment(const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+                             const uint32_t *__restrict__ soff, uint32_t m_blk, Src src,
+                             const Out &o, uint32_t seg, uint32_t ov,
+                             const uint64_t *__restrict__ seg_list, uint32_t t,
+                             uint32_t *__restrict__ fb_flag, uint32_t *__restrict__ fb_list,
+                             uint32_t *__restrict__ fb_count, uint32_t *__restrict__ stats,
+                             uint32_t *__restrict__ err, uint32_t *sh) {
     const uint64_t e_js = seg_list[t];
     const uint32_t j = (uint32_t)(e_js >> 32), s = (uint32_t)e_js;
     if (j >= m_blk) {  // only if the queue overflowed (already flagged)
@@ -392,6 +369,7 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
             lo = hi = lf.m_ext;  // exact start at the terminator suffix
             if (b == len) {
                 buf.push(KEYS ? (lo + W.goff) << o.gshift : lo + W.goff);
+                if (KEYS && sh) atomicAdd(&sh[(uint32_t)(buf.r0 >> o.hshift) & 255u], 1u);
                 if (((gb + len) & 7) == 0) buf.flush(dst, gb + len, o.vec);
             }
         } else {
@@ -418,7 +396,9 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
                         if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
                     }
                     const uint32_t tt = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
-                    buf.push(((lo + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | tt);
+                    const uint64_t key = ((lo + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | tt;
+                    buf.push(key);
+                    if (sh) atomicAdd(&sh[(uint32_t)(key >> o.hshift) & 255u], 1u);
                 } else {
                     buf.push(lo + W.goff);
                 }
@@ -428,7 +408,11 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
         if (!open) break;
         if (attempt > 0 || e == len) {
             // a repeat longer than the retry's overlap: the whole read is
-            // walked exactly
+            // walked exactly.  Nothing of this segment has been written or
+            // counted; its positions get NO_KEY so that the whole-read walk
+            // can tell the counted keys of the read's other segments.
+            if constexpr (KEYS)
+                for (uint32_t q = a; q < b; ++q) o.keys[gb + q] = NO_KEY;
             if (atomicExch(&fb_flag[j], 1u) == 0u) {
                 fb_list[atomicAdd(fb_count, 1u)] = j;
                 atomicAdd(stats + 1, 1u);
@@ -447,19 +431,71 @@ __global__ __launch_bounds__(256) void rank_segments_kernel(
     }
 }
 
+// One lane per queued segment.  In key mode with o.hist set, the digit
+// counts of the keys written are gathered in LDS and added once per
+// workgroup to one of the HIST_COPIES copies.
+template <class Src, bool KEYS>
+__global__ __launch_bounds__(256) void rank_segments_kernel(
+    const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ soff, uint32_t m_blk, Src src, Out o, uint32_t seg, uint32_t ov,
+    const uint64_t *__restrict__ seg_list, const uint32_t *__restrict__ seg_count,
+    uint32_t *__restrict__ fb_flag, uint32_t *__restrict__ fb_list,
+    uint32_t *__restrict__ fb_count, uint32_t *__restrict__ stats, uint32_t *__restrict__ err) {
+    __shared__ uint32_t s_h[KEYS ? 256 : 1];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nq = *seg_count;
+    if (blockIdx.x * blockDim.x >= nq) return;  // the whole workgroup
+    const bool count = KEYS && o.hist != nullptr;
+    if (count) {
+        s_h[tid] = 0;
+        __syncthreads();
+    }
+    const uint32_t t = blockIdx.x * blockDim.x + tid;
+    if (t < nq)
+        rank_segment<Src, KEYS>(reads, off, soff, m_blk, src, o, seg, ov, seg_list, t, fb_flag,
+                                fb_list, fb_count, stats, err, count ? s_h : nullptr);
+    if (count) {
+        __syncthreads();
+        if (s_h[tid]) atomicAdd(&o.hist[(blockIdx.x % HIST_COPIES) * 256 + tid], s_h[tid]);
+    }
+}
+
 // Whole-read walks for the reads whose segments could not close their
-// interval within the overlap.
+// interval within the overlap.  In key mode with o.hist set, the keys its
+// other segments wrote (every position not NO_KEY) were counted already:
+// their digits are taken off before the walk counts every key of the read.
 template <class Src, bool KEYS>
 __global__ __launch_bounds__(256) void rank_fallback_kernel(
     const uint8_t *__restrict__ reads, const uint64_t *__restrict__ off,
     const uint32_t *__restrict__ soff, Src src, Out o, const uint32_t *__restrict__ fb_list,
     const uint32_t *__restrict__ fb_count) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= *fb_count) return;
-    const uint32_t j = fb_list[t];
-    const uint64_t s0 = off[j];
-    SymReader sym{reads, 0, 0};
-    walk_read<KEYS>(src.at(j), sym, s0, (uint32_t)(off[j + 1] - s0), soff[j], o, nullptr);
+    __shared__ uint32_t s_h[KEYS ? 256 : 1];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nf = *fb_count;
+    if (blockIdx.x * blockDim.x >= nf) return;  // the whole workgroup
+    const bool count = KEYS && o.hist != nullptr;
+    if (count) {
+        s_h[tid] = 0;
+        __syncthreads();
+    }
+    const uint32_t t = blockIdx.x * blockDim.x + tid;
+    if (t < nf) {
+        const uint32_t j = fb_list[t];
+        const uint64_t s0 = off[j];
+        const uint32_t len = (uint32_t)(off[j + 1] - s0);
+        const uint64_t gb = soff[j];
+        if (count)
+            for (uint32_t q = 0; q <= len; ++q) {
+                const uint64_t key = o.keys[gb + q];
+                if (key != NO_KEY) atomicSub(&s_h[(uint32_t)(key >> o.hshift) & 255u], 1u);
+            }
+        SymReader sym{reads, 0, 0};
+        walk_read<KEYS>(src.at(j), sym, s0, len, gb, o, count ? s_h : nullptr);
+    }
+    if (count) {
+        __syncthreads();
+        if (s_h[tid]) atomicAdd(&o.hist[(blockIdx.x % HIST_COPIES) * 256 + tid], s_h[tid]);
+    }
 }
 
 __global__ void zero_kernel(uint32_t *p, uint32_t n) {
@@ -504,9 +540,6 @@ hipError_t compute_ranks(const uint8_t *reads, const uint64_t *off, const uint32
     if (seg > 0) {
         rank_fallback_kernel<Src, KEYS><<<(unsigned)div_up(m_blk, 256), 256, 0, s>>>(
             reads, off, soff, src, o, sg.fb_list, sg.counters + 1);
-        if (KEYS && o.hist)
-            count_long_keys_kernel<<<cap < 2048 ? cap : 2048, 256, 0, s>>>(
-                off, soff, m_blk, seg, sg.seg_list, sg.counters, o.keys, o.hshift, o.hist);
     }
     Marks::end(mk, 2, s);
     return hipGetLastError();
