@@ -18,6 +18,7 @@ under "also".
 import argparse
 import hashlib
 import json
+import subprocess
 import os
 import platform
 import sys
@@ -487,6 +488,9 @@ def main():
     ap.add_argument("--cpu-sample-bases", type=int, default=None,
                     help="bases of the oracle's sample (default: a sixth of the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-random", action="store_true",
+                    help="run bench_random_reads (dependent random reads per second, the "
+                         "ceiling of the LF walks) and print its table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     ap.add_argument("--summarize-profile", metavar="DIR", default=None,
@@ -540,6 +544,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_random:
+        from paper_1410_0562_amd import build as hipbuild
+        if not os.path.exists(hipbuild.RANDOM_READS_BIN):
+            print("bench_random_reads is not built; run __graft_entry__.build()", file=sys.stderr)
+            sys.exit(2)
+        sys.exit(subprocess.run([hipbuild.RANDOM_READS_BIN]).returncode)
 
     if args.calibrate_copy:
         # a plain copy of known size: the HBM byte counters read on it give the
@@ -666,6 +677,10 @@ def run_plain(args, torch, bwtset, synth, workload, steps, warmup, cpu=True):
         kinfo[name] = {"ms_per_step": ms / steps, "launches_per_step": launches / steps,
                        "avg_launch_ms": ms / launches, "bytes_per_launch": nbytes / launches,
                        "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        if name in ("compute_ranks_kernel", "rank_segments_kernel") and ms > 0:
+            # each LF step is one dependent read of a random 64-byte record:
+            # compare with `bench.py --calibrate-random`
+            kinfo[name]["lf_steps_G_per_s"] = nbytes / RANKS_BYTES_PER_STEP / (ms * 1e-3) / 1e9
     if kinfo:
         dom = max(kinfo, key=lambda k: kinfo[k]["ms_per_step"])
         d = kinfo[dom]

@@ -61,7 +61,27 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         os.unlink(tmp)
         raise RuntimeError("link failed:\n" + out.stdout.decode(errors="replace"))
     os.replace(tmp, LIB)
+    build_random_reads(hipcc, verbose)
     return LIB
+
+
+# The random-read rate benchmark beside bench.py (the ceiling of the LF walks).
+RANDOM_READS_SRC = os.path.join(os.path.dirname(HERE), "bench_random_reads.hip")
+RANDOM_READS_BIN = os.path.join(os.path.dirname(HERE), "bench_random_reads")
+
+
+def build_random_reads(hipcc: str, verbose: bool = False) -> str:
+    cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=" + ARCH,
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           RANDOM_READS_SRC, "-o", RANDOM_READS_BIN + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if out.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s" % (RANDOM_READS_SRC,
+                                                      out.stdout.decode(errors="replace")))
+    os.replace(RANDOM_READS_BIN + ".tmp", RANDOM_READS_BIN)
+    return RANDOM_READS_BIN
 
 
 def _wait(item):
