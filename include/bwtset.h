@@ -178,7 +178,8 @@ int bwt_set_set_block_size(bwt_set_t h, uint64_t M);
  *     and continued by Lemma 1 once the interval holds no old suffix; reads
  *     with a longer repeat fall back to one whole walk.  0 = never (32 ..
  *     2^24, default 768).  A segment whose interval is still open at its
- *     end starts once more with 16 times the overlap (at least 256).
+ *     end starts again with 4 times the overlap (at least 256), then with
+ *     16 times (at least 1024), before its read is walked whole.
  *   BWT_PARAM_RANK_OVERLAP: see above (0 .. 2^24, default 64).
  *   BWT_PARAM_BATCH_LANES: blocks of one level of a batch (bwt_set_append_many
  *     on this handle as hs[0]) that run side by side, each on its own stream

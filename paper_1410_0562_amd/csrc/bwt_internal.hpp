@@ -261,9 +261,12 @@ struct RankSegments {
                                  // and (64-bit, words 2-3) symbols ranked by segment walks
 };
 // A segment whose FM-index interval is still open at its end starts again
-// with its overlap times RETRY_FACTOR (at least RETRY_MIN_OVERLAP).
-constexpr uint32_t RETRY_FACTOR = 16;
-constexpr uint32_t RETRY_MIN_OVERLAP = 256;
+// with its overlap times RETRY_FACTOR1 (at least RETRY_MIN1), then times
+// RETRY_FACTOR2 (at least RETRY_MIN2); after that its read is walked whole.
+// The short first retry keeps the usual case (a chance agreement of noisy
+// reads a little longer than the overlap) from stretching its launch.
+constexpr uint32_t RETRY_FACTOR1 = 4, RETRY_MIN1 = 256;
+constexpr uint32_t RETRY_FACTOR2 = 16, RETRY_MIN2 = 1024;
 // Key mode (kk != null): instead of g, the walks write the first sort key of
 // every block position, g << gshift | its next kfirst symbols << 5 | their
 // count (what launch_block_keys builds), and its sort value (see below).

@@ -348,8 +348,9 @@ __device__ void rank_segment(const uint8_t *__restrict__ reads, const uint64_t *
     vb.cnt = 0;
     const int top = 2 * (o.kfirst - 1);
     // First attempt with overlap ov; a segment whose interval is still open at
-    // b (a repeat longer than ov) starts once more, RETRY_FACTOR times further
-    // out, before its read is handed to the whole-read walk.  Nothing of the
+    // b (a repeat longer than ov) starts again RETRY_FACTOR1, then
+    // RETRY_FACTOR2, times further out before its read is handed to the
+    // whole-read walk.  Nothing of the
     // segment has been written when the interval is found open (that happens
     // at its first position), so a restart only resets the walk.
     uint32_t ovs = ov;
@@ -406,7 +407,7 @@ __device__ void rank_segment(const uint8_t *__restrict__ reads, const uint64_t *
             }
         }
         if (!open) break;
-        if (attempt > 0 || e == len) {
+        if (attempt > 1 || e == len) {
             // a repeat longer than the retry's overlap: the whole read is
             // walked exactly.  Nothing of this segment has been written or
             // counted; its positions get NO_KEY so that the whole-read walk
@@ -419,8 +420,9 @@ __device__ void rank_segment(const uint8_t *__restrict__ reads, const uint64_t *
             }
             return;
         }
-        ovs = ov < RETRY_MIN_OVERLAP / RETRY_FACTOR ? RETRY_MIN_OVERLAP
-              : ov > (1u << 24) ? (1u << 28) : ov * RETRY_FACTOR;
+        const uint32_t f = attempt == 0 ? RETRY_FACTOR1 : RETRY_FACTOR2;
+        const uint32_t mn = attempt == 0 ? RETRY_MIN1 : RETRY_MIN2;
+        ovs = ov > (1u << 24) ? (1u << 28) : (ov * f > mn ? ov * f : mn);
         atomicAdd(stats, 1u);
     }
     buf.flush(dst, gb + a, false);

@@ -457,8 +457,9 @@ def test_segmented_compute_ranks(B, torch_dev, oracle_mod, seg, ov):
                                                   (300, 0, True)])
 def test_segment_retry_and_fallback(B, torch_dev, oracle_mod, seg, ov, exact_copies):
     """Segments whose FM-index interval is still open at their end start
-    again with a 16x longer overlap (at least 256); a read with a repeat
-    longer than that (an exact copy of an old string) is walked whole.  Noisy
+    again with a 4x longer overlap (at least 256), then a 16x one (at least
+    1024); a read with a repeat longer than that (an exact copy of an old
+    string) is walked whole.  Noisy
     copies of one region (5% substitutions) make the first attempts of short
     overlaps fail; the ranks are exact either way, and the statistics show
     that both paths ran."""
