@@ -32,65 +32,51 @@ namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // The values of one lane are written in descending order; they are kept in
-// an 8-entry shift register and written as one aligned 64-byte chunk when the
-// register covers indices [8q, 8q + 8), so the writes are whole half-lines
-// instead of single words spread over the cache (partial chunks at both ends
-// of a walk are written word by word).
-struct GBuf {
-    uint64_t r0, r1, r2, r3, r4, r5, r6, r7;  // r0 = lowest index held
+// an N-entry shift register and written as one aligned chunk of 128 bytes
+// when the register covers indices [Nq, Nq + N), so the writes are whole
+// cache lines instead of single words spread over the cache (partial chunks
+// at both ends of a walk are written word by word).  Plain stores: under the
+// walks' random reads, non-temporal stores of the same chunks cut the rate
+// of reads that the memory system sustains, and 128-byte chunks cost less
+// than 64-byte ones (measured with dependent random reads beside streaming
+// stores of each kind).
+template <class T, int N>
+struct OutBuf {
+    static_assert(N * sizeof(T) == 128, "one cache line per chunk");
+    static constexpr int SIZE = N;
+    T r[N];  // r[0] = lowest index held
     uint32_t cnt;
-    __device__ void push(uint64_t v) {
-        r7 = r6; r6 = r5; r5 = r4; r4 = r3; r3 = r2; r2 = r1; r1 = r0; r0 = v;
-        cnt = cnt < 8 ? cnt + 1 : 8;
-    }
-    // write the held values to g[idx .. idx + cnt)
-    __device__ void flush(uint64_t *__restrict__ g, uint64_t idx, bool vec) {
-        if (cnt == 8 && vec) {
-            // streaming stores: the output is not read again by this kernel
-            u32x4 *q = reinterpret_cast<u32x4 *>(g + idx);
-            __builtin_nontemporal_store(u32x4{(uint32_t)r0, (uint32_t)(r0 >> 32), (uint32_t)r1, (uint32_t)(r1 >> 32)}, q + 0);
-            __builtin_nontemporal_store(u32x4{(uint32_t)r2, (uint32_t)(r2 >> 32), (uint32_t)r3, (uint32_t)(r3 >> 32)}, q + 1);
-            __builtin_nontemporal_store(u32x4{(uint32_t)r4, (uint32_t)(r4 >> 32), (uint32_t)r5, (uint32_t)(r5 >> 32)}, q + 2);
-            __builtin_nontemporal_store(u32x4{(uint32_t)r6, (uint32_t)(r6 >> 32), (uint32_t)r7, (uint32_t)(r7 >> 32)}, q + 3);
-        } else {
-            if (cnt > 0) g[idx] = r0;
-            if (cnt > 1) g[idx + 1] = r1;
-            if (cnt > 2) g[idx + 2] = r2;
-            if (cnt > 3) g[idx + 3] = r3;
-            if (cnt > 4) g[idx + 4] = r4;
-            if (cnt > 5) g[idx + 5] = r5;
-            if (cnt > 6) g[idx + 6] = r6;
-            if (cnt > 7) g[idx + 7] = r7;
-        }
-        cnt = 0;
-    }
-};
-
-// The same for 4-byte values: 16 of them make one aligned 64-byte chunk.
-struct VBuf {
-    uint32_t r[16];  // r[0] = lowest index held
-    uint32_t cnt;
-    __device__ void push(uint32_t v) {
+    __device__ void push(T v) {
 #pragma unroll
-        for (int q = 15; q > 0; --q) r[q] = r[q - 1];
+        for (int q = N - 1; q > 0; --q) r[q] = r[q - 1];
         r[0] = v;
-        cnt = cnt < 16 ? cnt + 1 : 16;
+        cnt = cnt < (uint32_t)N ? cnt + 1 : (uint32_t)N;
     }
-    __device__ void flush(uint32_t *__restrict__ p, uint64_t idx, bool vec) {
-        if (cnt == 16 && vec) {
+    // write the held values to p[idx .. idx + cnt)
+    __device__ void flush(T *__restrict__ p, uint64_t idx, bool vec) {
+        if (cnt == (uint32_t)N && vec) {
             u32x4 *q = reinterpret_cast<u32x4 *>(p + idx);
-            __builtin_nontemporal_store(u32x4{r[0], r[1], r[2], r[3]}, q + 0);
-            __builtin_nontemporal_store(u32x4{r[4], r[5], r[6], r[7]}, q + 1);
-            __builtin_nontemporal_store(u32x4{r[8], r[9], r[10], r[11]}, q + 2);
-            __builtin_nontemporal_store(u32x4{r[12], r[13], r[14], r[15]}, q + 3);
+            if constexpr (sizeof(T) == 8) {
+#pragma unroll
+                for (int c = 0; c < N / 2; ++c)
+                    q[c] = u32x4{(uint32_t)r[2 * c], (uint32_t)(r[2 * c] >> 32),
+                                 (uint32_t)r[2 * c + 1], (uint32_t)(r[2 * c + 1] >> 32)};
+            } else {
+#pragma unroll
+                for (int c = 0; c < N / 4; ++c)
+                    q[c] = u32x4{r[4 * c], r[4 * c + 1], r[4 * c + 2], r[4 * c + 3]};
+            }
         } else {
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
+            for (int q = 0; q < N; ++q)
                 if ((uint32_t)q < cnt) p[idx + q] = r[q];
         }
         cnt = 0;
     }
 };
+using GBuf = OutBuf<uint64_t, 16>;  // g values or sort keys
+using VBuf = OutBuf<uint32_t, 32>;  // sort values
+constexpr uint64_t GMASK = GBuf::SIZE - 1, VMASK = VBuf::SIZE - 1;
 
 // Where the walks write.  g mode (keys == nullptr): g[p] for every block
 // position p.  Key mode: the first sort key of p, g << gshift | the next
@@ -101,7 +87,7 @@ struct Out {
     uint64_t *keys;
     uint32_t *vals;
     int gshift, kfirst;
-    bool vec, vvec;  // 64-byte aligned arrays: whole chunks may be written
+    bool vec, vvec;  // 128-byte aligned arrays: whole chunks may be written
     uint32_t *hist;  // key mode: counts of the key digit at bit hshift (or null)
     int hshift;
 };
@@ -211,15 +197,15 @@ __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t
     uint64_t i = W.lf.m_ext;
     uint32_t k = len;
     buf.push(KEYS ? (i + W.goff) << o.gshift : i + W.goff);  // terminator: no symbols
-    if (KEYS && sh) atomicAdd(&sh[(uint32_t)(buf.r0 >> o.hshift) & 255u], 1u);
-    if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
+    if (KEYS && sh) atomicAdd(&sh[(uint32_t)(buf.r[0] >> o.hshift) & 255u], 1u);
+    if (((gb + k) & GMASK) == 0) buf.flush(dst, gb + k, o.vec);
     while (k > 0) {
         --k;
         const int c = sym.get(s0 + k);
         i = W.lf.step(W.recs, W.sbc, i, c);
         if constexpr (KEYS) {
             vb.push((uint32_t)(gb + k + 1) | ((uint32_t)c << POS_BITS));
-            if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
+            if (((gb + k + 1) & VMASK) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
             if (o.kfirst > 0) win = (win >> 2) | ((uint64_t)c << top);
             const uint32_t t = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
             const uint64_t key = ((i + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | t;
@@ -228,7 +214,7 @@ __device__ void walk_read(const Walker &W, SymReader &sym, uint64_t s0, uint32_t
         } else {
             buf.push(i + W.goff);
         }
-        if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
+        if (((gb + k) & GMASK) == 0) buf.flush(dst, gb + k, o.vec);
     }
     buf.flush(dst, gb, false);  // what is left below the last aligned index
     if constexpr (KEYS) {
@@ -370,8 +356,8 @@ __device__ void rank_segment(const uint8_t *__restrict__ reads, const uint64_t *
             lo = hi = lf.m_ext;  // exact start at the terminator suffix
             if (b == len) {
                 buf.push(KEYS ? (lo + W.goff) << o.gshift : lo + W.goff);
-                if (KEYS && sh) atomicAdd(&sh[(uint32_t)(buf.r0 >> o.hshift) & 255u], 1u);
-                if (((gb + len) & 7) == 0) buf.flush(dst, gb + len, o.vec);
+                if (KEYS && sh) atomicAdd(&sh[(uint32_t)(buf.r[0] >> o.hshift) & 255u], 1u);
+                if (((gb + len) & GMASK) == 0) buf.flush(dst, gb + len, o.vec);
             }
         } else {
             lo = 0;             // the empty prefix: every row of B_ext
@@ -394,7 +380,7 @@ __device__ void rank_segment(const uint8_t *__restrict__ reads, const uint64_t *
                 if constexpr (KEYS) {
                     if (k + 1 < b || k + 1 == len) {
                         vb.push((uint32_t)(gb + k + 1) | ((uint32_t)c << POS_BITS));
-                        if (((gb + k + 1) & 15) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
+                        if (((gb + k + 1) & VMASK) == 0) vb.flush(o.vals, gb + k + 1, o.vvec);
                     }
                     const uint32_t tt = len - k < (uint32_t)o.kfirst ? len - k : (uint32_t)o.kfirst;
                     const uint64_t key = ((lo + W.goff) << o.gshift) | (win << KEY_LEN_BITS) | tt;
@@ -403,7 +389,7 @@ __device__ void rank_segment(const uint8_t *__restrict__ reads, const uint64_t *
                 } else {
                     buf.push(lo + W.goff);
                 }
-                if (((gb + k) & 7) == 0) buf.flush(dst, gb + k, o.vec);
+                if (((gb + k) & GMASK) == 0) buf.flush(dst, gb + k, o.vec);
             }
         }
         if (!open) break;
@@ -559,14 +545,14 @@ hipError_t compute_ranks_any(const uint8_t *reads, const uint64_t *off, const ui
         o.vals = kk->vals;
         o.gshift = kk->gshift;
         o.kfirst = kk->kfirst;
-        o.vec = (reinterpret_cast<uintptr_t>(o.keys) & 63) == 0;
-        o.vvec = (reinterpret_cast<uintptr_t>(o.vals) & 63) == 0;
+        o.vec = (reinterpret_cast<uintptr_t>(o.keys) & 127) == 0;
+        o.vvec = (reinterpret_cast<uintptr_t>(o.vals) & 127) == 0;
         o.hist = kk->hist;
         o.hshift = kk->hshift;
         return compute_ranks<Src, true>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s, mk);
     }
     o.g = g;
-    o.vec = (reinterpret_cast<uintptr_t>(g) & 63) == 0;
+    o.vec = (reinterpret_cast<uintptr_t>(g) & 127) == 0;
     return compute_ranks<Src, false>(reads, off, soff, m_blk, n_blk, src, o, sg, err, s, mk);
 }
 
