@@ -219,3 +219,31 @@ def test_queued_requests_share_one_batch(torch_dev, oracle_mod):
     assert summ["mean_batch"] > 1.5, summ
     for t in range(tenants):
         assert out[t] == _oracle_of(oracle_mod, reqs, t), t
+
+
+def test_batches_run_on_the_workers_own_handles(torch_dev, oracle_mod):
+    """Every batch is led by a handle of its worker that holds no strings, so
+    the block workspace lives on the workers' handles and a tenant's handle
+    holds only its index buffers (trimming a tenant frees nothing a later
+    batch has to allocate again)."""
+    from paper_1410_0562_amd.serve import BwtService
+    tenants = 4
+    reqs = _requests(11, tenants, 16)
+    svc = BwtService(tenants, budget_bytes=64 << 30, workers=2, block_size=1 << 20)
+    try:
+        for (t, p, o) in reqs:
+            svc.submit(t, p, o)
+        svc.drain(timeout=120)
+        lead = max(h.memory() for h in svc._leaders)
+        held = [t.index.memory() for t in svc.tenants if t.index is not None]
+        assert held and lead > 0
+        # the workspace of a block of up to 2^20 suffixes is far larger than
+        # the few-million-symbol indices of these tenants
+        assert max(held) * 4 < lead, (held, lead)
+        out = [svc.export(t) for t in range(tenants)]
+        assert svc.latency_summary()["errors"] == 0
+    finally:
+        svc.close()
+    for t in range(tenants):
+        assert out[t] == _oracle_of(oracle_mod, reqs, t), t
+
