@@ -139,7 +139,7 @@ def summarize_profile(root, workload, command_note):
     rows = _csv_rows(os.path.join(root, "stats"), "kernel_stats.csv")
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = ["# Kernel time per kernel, %s" % key, "",
-             "Commands (repository root = `$R` on the GPU box):", "", "```", command_note.strip(),
+             "Commands (`$R` = the repository root where they ran):", "", "```", command_note.strip(),
              "```", "", "| kernel | calls | total ms | avg us | min us | max us | % |",
              "|---|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
@@ -172,7 +172,7 @@ def summarize_profile(root, workload, command_note):
                       "+ WRITE_SIZE x %.3f (KiB x 1024), the factors being what a plain 1 GiB "
                       "device copy reads on the same counters" % (f_scale, w_scale)}
     table = ["# HBM traffic per kernel launch, %s" % key, "",
-             "Commands (repository root = `$R` on the GPU box; each counter in a run of its own):",
+             "Commands (`$R` = the repository root where they ran; each counter in a run of its own):",
              "", "```", command_note.strip(), "```", "",
              "Scale: a plain 1 GiB device copy reads FETCH_SIZE x 1024 x %.3f and WRITE_SIZE x "
              "1024 x %.3f bytes per launch." % (f_scale, w_scale), "",
@@ -229,7 +229,7 @@ def summarize_overlap(folder, command_note, out_name):
     span = ev[-1][0] - ev[0][0]
     streams = {sid for _, _, sid in ev}
     lines = ["# Kernels of different streams running at once: %s" % out_name, "",
-             "Commands (repository root = `$R` on the GPU box):", "", "```",
+             "Commands (`$R` = the repository root where they ran):", "", "```",
              command_note.strip(), "```", "",
              "Kernel dispatches: %d on %d streams.  Span from the first kernel start to the last "
              "kernel end: %.1f ms; time with at least one kernel running: %.1f ms; time with "
