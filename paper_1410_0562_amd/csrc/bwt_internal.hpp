@@ -132,7 +132,7 @@ struct Marks {
 // one atomic word: hist[(pass * HIST_COPIES + copy) * 256 + digit].  Pass p
 // sums the copies of its counts into digit starts (hist_cur = pass p's copies)
 // and adds the next pass's counts.
-constexpr int HIST_COPIES = 16;
+constexpr int HIST_COPIES = 8;
 constexpr uint32_t HIST_WORDS = 8 * HIST_COPIES * 256;
 hipError_t launch_radix_hist1(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
                               hipStream_t s);
