@@ -166,6 +166,33 @@ def test_compute_ranks_vs_oracle(B, torch_dev, oracle_mod):
     assert np.array_equal(g.cpu().numpy().astype(np.uint64), want)
 
 
+@pytest.mark.parametrize("shift", [3, 16])
+def test_compute_ranks_into_an_offset_buffer(B, torch_dev, oracle_mod, shift):
+    """The walks write g in whole 128-byte chunks only where the output is
+    128-byte aligned, word by word elsewhere: g written into a view that
+    starts `shift` words into a buffer (24 bytes: unaligned; 128: aligned) is
+    the oracle's, short and segmented reads alike, and the words around the
+    view are left as they were."""
+    torch = torch_dev
+    old = synth.random_reads(71, 600, 50, 3000)
+    new = synth.random_reads(72, 400, 0, 2500)
+    ca, oa2 = _oracle_inputs(oracle_mod, *old)
+    T_old, _ = oracle_mod.concat_text(ca, oa2)
+    cb, ob2 = _oracle_inputs(oracle_mod, *new)
+    T, _ = oracle_mod.concat_text(cb, ob2)
+    want = oracle_mod.compute_ranks(T_old, T)
+    guard = -7
+    buf = torch.full((len(T) + shift + 40,), guard, dtype=torch.int64, device="cuda")
+    g = buf[shift:shift + len(T)]
+    with B.BwtSet() as idx:
+        idx.set_param(B.BWT_PARAM_RANK_SEGMENT, 512)
+        idx.append(*old)
+        idx.compute_ranks(*new, g)
+    h = buf.cpu().numpy()
+    assert np.array_equal(h[shift:shift + len(T)].astype(np.uint64), want)
+    assert (h[:shift] == guard).all() and (h[shift + len(T):] == guard).all()
+
+
 def test_insert_vs_oracle(B, torch_dev, oracle_mod):
     torch = torch_dev
     packed, offs = synth.random_reads(37, 5000, 20, 180)
